@@ -1,0 +1,249 @@
+/*
+ * hdg.h - C ABI of the MI355X (gfx950) library for the statically condensed,
+ * matrix-free hybridizable discontinuous Galerkin (HDG) operator of
+ * Huismann, Stiller & Froehlich, "Linearizing the hybridizable discontinuous
+ * Galerkin method: A linearly scaling operator" (arXiv:2007.11891).
+ *
+ * Problem (paper, equation (helmholtz_equation)):
+ *     lambda u - laplace u = f  in the box [0, sum h_1] x [0, sum h_2] x [0, sum h_3],
+ *     u = g_D on the whole boundary,
+ * discretised on a Cartesian mesh of n1 x n2 x n3 cuboids with per-axis
+ * widths, Lagrange polynomials of degree p on Gauss-Lobatto-Legendre (GLL)
+ * points (lumped GLL mass matrix), penalty tau_{i,e} = 2 tau_hat / h_{i,e}
+ * (section "LDG operator structure in three dimensions").  After static
+ * condensation only the face trace u~ remains: K u~ = F (equation
+ * (hdg_system)), K = sum_e Q_e^T K_e Q_e with K_e the Schur complement of
+ * equation (hdg_operator).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers: arguments documented "device" are device pointers of the GPU the
+ * context was created on; "host" pointers are read during the call only.
+ * The caller owns every buffer it passes; the library never frees or keeps
+ * them.  Buffers must not overlap unless stated.
+ *
+ * Streams: all device work is enqueued on the stream given to hdg_create
+ * (a hipStream_t passed as void*, NULL = the null stream), in call order.
+ * Entry points that need a host decision (the solvers) synchronise that
+ * stream; all others return without waiting.
+ *
+ * Errors: every entry point returns hdg_status.  Arguments are validated
+ * before any work is enqueued; on error nothing is enqueued and
+ * hdg_last_error() returns a message (thread-local, valid until the next
+ * call on the same thread).  HIP failures return HDG_EHIP.
+ *
+ * Layouts (n_p = p + 1):
+ *   Volume vectors (length n_vol = n1 n2 n3 n_p^3): element
+ *     e = i + n1 (j + n2 k), then node q1 + n_p (q2 + n_p q3), q1 fastest
+ *     (the paper's Kronecker ordering, equation (tp_definition)).
+ *   Trace vectors: faces normal to x1, then x2, then x3, interior faces only
+ *     ("free" part, length n_free), followed by the boundary faces ("tail",
+ *     length n_all - n_free).  Interior faces of axis a sit on planes
+ *     m = 1..n_a-1 and are ordered with x1 fastest over (plane, element
+ *     indices of the two other axes):
+ *         a=0: (m-1) + (n1-1)(j + n2 k)
+ *         a=1: i + n1((m-1) + (n2-1) k)
+ *         a=2: i + n1(j + n2 (m-1))
+ *     The tail holds, for a = 0, 1, 2, the plane m = 0 then m = n_a, each
+ *     ordered t_b + n_b t_c over the two tangential element indices (b < c).
+ *     Within a face: n_p x n_p nodes, q_b + n_p q_c (lower axis fastest).
+ *   Bases of trace vectors: HDG_BASIS_NODAL holds nodal values (u~) or
+ *     nodal residuals; HDG_BASIS_EIGEN holds the transformed unknowns of the
+ *     section "Product factorization of the HDG operator":
+ *     u^ = (S^T M x S^T M) u~ per face, and F^ = (S^T x S^T) F for residuals,
+ *     where S^T M S = I, S^T L S = Lambda (equation
+ *     (generalized_eigenvalue_decomposition)).  K^ = T^T K T, T = S x S.
+ */
+#ifndef HDG_H
+#define HDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hdg_ctx hdg_ctx;
+
+typedef enum {
+  HDG_OK = 0,
+  HDG_EINVAL = -1,       /* invalid argument */
+  HDG_EHIP = -2,         /* a HIP runtime call failed */
+  HDG_ENOMEM = -3,       /* device or host allocation failed */
+  HDG_ENOCONV = -4,      /* solver stopped at maxit; info is filled */
+  HDG_EUNSUPPORTED = -5  /* valid request this build does not implement */
+} hdg_status;
+
+typedef enum { HDG_F64 = 0, HDG_F32 = 1 } hdg_dtype;
+typedef enum { HDG_BASIS_NODAL = 0, HDG_BASIS_EIGEN = 1 } hdg_basis;
+
+/* Face transforms of the section "Product factorization of the HDG operator"
+ * and of the transformed solver listing, applied per face as A x A:
+ *   HDG_TO_EIGEN_UNKNOWN   u^ = (S^T M x S^T M) u~
+ *   HDG_TO_EIGEN_RESIDUAL  F^ = (S^T x S^T) F
+ *   HDG_TO_NODAL_UNKNOWN   u~ = (S x S) u^
+ *   HDG_TO_NODAL_RESIDUAL  F  = (M S x M S) F^                              */
+typedef enum {
+  HDG_TO_EIGEN_UNKNOWN = 0,
+  HDG_TO_EIGEN_RESIDUAL = 1,
+  HDG_TO_NODAL_UNKNOWN = 2,
+  HDG_TO_NODAL_RESIDUAL = 3
+} hdg_transform;
+
+/* Solver options.  The CG runs on K^_ff in the eigen-face basis with the
+ * diagonal (Jacobi) preconditioner of K^ (the paper's HDG-trans solver,
+ * section "Summary of solution method"); x0 = 0. */
+typedef struct {
+  double rtol;        /* stop when ||r||_2 <= rtol ||F^||_2 (eigen basis)   */
+  int maxit;          /* iteration cap (FP64 CG, or per inner FP32 solve)   */
+  int precond;        /* 0: none, 1: Jacobi                                  */
+  int mixed;          /* 0: FP64 CG; 1: FP32 inner CG + FP64 defect correction */
+  double inner_rtol;  /* mixed: relative reduction asked of each inner solve */
+  int max_outer;      /* mixed: cap on defect-correction steps              */
+  int check_every;    /* iterations per host convergence poll (>= 1)        */
+} hdg_solve_opts;
+
+typedef struct {
+  int iters;          /* CG iterations (FP64, or FP32 inner summed)          */
+  int outer_iters;    /* defect-correction steps (mixed), else 0            */
+  double rel_res;     /* final ||F^ - K^ u^||_2 / ||F^||_2, recomputed in FP64 */
+  double rhs_norm;    /* ||F^||_2                                            */
+  double t_ms;        /* wall time of the solve on the stream               */
+} hdg_solve_info;
+
+/* Fill *opts with defaults: rtol 1e-10, maxit 20000, Jacobi, FP64,
+ * inner_rtol 1e-4, max_outer 12, check_every 25. */
+void hdg_default_opts(hdg_solve_opts* opts);
+
+/* Create a context for one mesh (paper section "LDG operator structure in
+ * three dimensions": Cartesian cuboids, per-axis widths, tau_{i,e}).
+ *   n_elem      host int[3], elements per axis, each >= 1
+ *   h1, h2, h3  host double arrays of n_elem[0..2] widths, each > 0
+ *   p           polynomial degree, 1 <= p <= 16
+ *   tau_hat     penalty scale tau_hat > 0
+ *   lambda_host host double[n1 n2 n3] per-element lambda >= 0, or NULL to
+ *               use lambda_const >= 0 everywhere
+ *   stream      hipStream_t (as void*) used for all work of this context
+ * The one-time setup (GLL points, 1D matrices, the generalized
+ * eigendecomposition S, Lambda and B_S of equation (hdgbs), and the
+ * diagonal of K^) runs in FP64: the 1D part on the host, the diagonal on the
+ * GPU.  On success *out owns device memory until hdg_destroy. */
+hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2,
+                      const double* h3, int p, double tau_hat,
+                      const double* lambda_host, double lambda_const,
+                      void* stream, hdg_ctx** out);
+
+/* Release the context and its device memory (synchronises its stream). */
+hdg_status hdg_destroy(hdg_ctx* ctx);
+
+/* Thread-local message of the last failed call. */
+const char* hdg_last_error(void);
+
+/* Vector lengths: trace unknowns (free), whole trace, volume nodes. */
+hdg_status hdg_sizes(const hdg_ctx* ctx, int64_t* n_free, int64_t* n_all,
+                     int64_t* n_vol);
+
+/* Replace the per-element lambda field (device double[n_elem], >= 0, not
+ * checked on the device) and rebuild the diagonal preconditioner. */
+hdg_status hdg_set_lambda(hdg_ctx* ctx, const double* lambda_dev);
+
+/* Host-only: the 1D tables the context uses, for degree p and tau_hat
+ * (equations (element_matrices), (generalized_eigenvalue_decomposition),
+ * (hdgbs)).  Each output is a host array, row-major, or NULL to skip:
+ * x, w [n_p] GLL points and weights; D [n_p*n_p] with D_ij = int phi_i phi_j';
+ * S [n_p*n_p] (S_ij = S[i*n_p+j], columns = eigenvectors); Lam [n_p]
+ * ascending; BS [n_p*2] with BS[k*2+s]; H [1], the diagonal value of
+ * G + C^T M^-1 C.  Touches no GPU. */
+hdg_status hdg_tables(int p, double tau_hat, double* x, double* w, double* D,
+                      double* S, double* Lam, double* BS, double* H);
+
+/* Physical coordinates of the volume nodes (device double[n_vol*3], xyz
+ * interleaved) and of the trace nodes (device double[n_all*3]); either may
+ * be NULL.  Synchronous (computed on the host, copied on the stream). */
+hdg_status hdg_coords(hdg_ctx* ctx, double* vol_xyz, double* trace_xyz);
+
+/* y = K_ff x (paper: Alg. "HDG_Op_3D", nodal basis, or the transformed
+ * Alg. with product factorization, eigen basis), on the free trace:
+ * x, y device arrays of n_free values of type dtype, not overlapping.
+ * Boundary (Dirichlet) unknowns are zero.  The element loop applies the
+ * transformed operator; in the nodal basis the face transforms of the
+ * product-factorization section wrap it. */
+hdg_status hdg_apply(hdg_ctx* ctx, const void* x, void* y, hdg_dtype dtype,
+                     hdg_basis basis);
+
+/* Per-face transform (see hdg_transform) of n_faces consecutive faces
+ * (n_faces * n_p^2 FP64 values, device); in == out is allowed. */
+hdg_status hdg_face_transform(hdg_ctx* ctx, hdg_transform kind,
+                              const double* in, double* out, int64_t n_faces);
+
+/* Right-hand side of the condensed system with the Dirichlet lift,
+ *     F_f = F(f)_f - K_fD g_D,   F(f)_e = -R_e^T A_e^-1 [M_e f_e; 0]
+ * (derived from eliminating u, q in the element system; the printed solver
+ * listing has the opposite sign), evaluated by fast diagonalisation:
+ * F^_e = -B^_e^T D_Z^-1 (S_e^T M_e f_e - B^_e u^_D,e).
+ *   f        device double[n_vol] nodal forcing
+ *   trace    device double[n_all] nodal trace; only the tail (g_D) is read;
+ *            NULL means g_D = 0
+ *   F_free   device double[n_free] output in the requested basis */
+hdg_status hdg_rhs(hdg_ctx* ctx, const double* f, const double* trace,
+                   double* F_free, hdg_basis basis);
+
+/* Solve K_ff u_f = F_f by preconditioned CG in the eigen-face basis
+ * (transformed solver listing: transform, pCG on K^, transform back).
+ *   F_free   device double[n_free], nodal residual basis
+ *   u_free   device double[n_free], output nodal trace unknowns
+ * Returns HDG_ENOCONV (info filled, u_free = last iterate) when the cap is
+ * reached.  Synchronises the stream.  opts NULL = defaults. */
+hdg_status hdg_solve(hdg_ctx* ctx, const double* F_free, double* u_free,
+                     const hdg_solve_opts* opts, hdg_solve_info* info);
+
+/* Whole solution process for forcing f and Dirichlet data: RHS, CG in the
+ * eigen basis, back transform, recovery of u per element.
+ *   f        device double[n_vol]
+ *   trace    device double[n_all] in: tail = g_D (nodal); out: free part =
+ *            nodal solution trace (tail unchanged)
+ *   u_vol    device double[n_vol] output, or NULL to skip the recovery */
+hdg_status hdg_solve_forcing(hdg_ctx* ctx, const double* f, double* trace,
+                             double* u_vol, const hdg_solve_opts* opts,
+                             hdg_solve_info* info);
+
+/* Recovery of u in every element from the trace (paper: last loop of the
+ * primal solver listing, sign read from the element system):
+ *     u_e = S_e D_Z^-1 (S_e^T M_e f_e - B^_e u^_e)
+ *   f      device double[n_vol];  trace device double[n_all] nodal (free
+ *   part and g_D tail);  u_vol device double[n_vol] output. */
+hdg_status hdg_reconstruct(hdg_ctx* ctx, const double* f, const double* trace,
+                           double* u_vol);
+
+/* Adjoint of u(lambda, f) for a scalar loss J(u) (not in the paper; derived
+ * from equation (hdg_operator_factorized) and the recovery formula).  Given
+ * the forward solution (trace, u not needed) and r = dJ/du:
+ *     j^ = -B^^T D_Z^-1 S_e^T r_e,   K^_ff mu^ = j^ (same CG),
+ *     a_E = D_Z^-1 (S_e^T r_e - B^_e mu^_e),  u_E = D_Z^-1 (S_e^T M_e f_e - B^_e u^_e)
+ *     dJ/dlambda_e = -d0_e sum a_E u_E,   dJ/df_e = M_e S_e a_E.
+ *   f, trace   the forward inputs/solution (device, as in hdg_solve_forcing)
+ *   dJdu       device double[n_vol]
+ *   dJdlambda  device double[n_elem] output
+ *   dJdf       device double[n_vol] output
+ * The adjoint CG uses opts (NULL = defaults); info describes it. */
+hdg_status hdg_adjoint(hdg_ctx* ctx, const double* f, const double* trace,
+                       const double* dJdu, double* dJdlambda, double* dJdf,
+                       const hdg_solve_opts* opts, hdg_solve_info* info);
+
+/* Diagonal of K^_ff (eigen basis), device double[n_free] output. */
+hdg_status hdg_diagonal(hdg_ctx* ctx, double* diag_free);
+
+/* Timing helper: launch the internal kernel `which` `reps` times
+ * back-to-back on the context stream between two HIP events and return the
+ * mean time per launch in *ms.  which: 0 = FP64 eigen-basis element apply
+ * (x -> y), 1 = FP32 eigen-basis element apply, 2 = FP64 CG iteration
+ * (fused apply + update), 3 = FP32 CG iteration.  x, y device buffers of
+ * n_free values of the matching type (x read, y scratch).  Synchronises. */
+hdg_status hdg_time_kernel(hdg_ctx* ctx, int which, const void* x, void* y,
+                           int reps, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HDG_H */

@@ -1,0 +1,878 @@
+// Host side of the C ABI declared in include/hdg.h: context lifetime, argument
+// validation, device buffers, and the solver drivers (FP64 preconditioned CG
+// and FP32-inner / FP64-outer defect correction) around the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hdg.h"
+#include "hdg_internal.hpp"
+
+using namespace hdg;
+
+namespace {
+
+thread_local std::string g_err;
+
+hdg_status fail(hdg_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(HDG_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),      \
+                  __FILE__, __LINE__);                                                 \
+  } while (0)
+
+template <typename T>
+hdg_status dalloc(T** p, int64_t n) {
+  *p = nullptr;
+  if (n <= 0) n = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)n);
+  if (e != hipSuccess) return fail(HDG_ENOMEM, "hipMalloc of %lld bytes failed: %s",
+                                   (long long)(sizeof(T) * n), hipGetErrorString(e));
+  return HDG_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+#define ST_TRY(expr)                  \
+  do {                                \
+    hdg_status _s = (expr);           \
+    if (_s != HDG_OK) return _s;      \
+  } while (0)
+
+int vec_blocks_for(int64_t n) {
+  int64_t nb = (n + 1023) / 1024;
+  nb = std::min<int64_t>(std::max<int64_t>(nb, 1), 2048);
+  return (int)nb;
+}
+
+template <typename T>
+hdg_status alloc_work(hdg_ctx* c, CgWork<T>& w) {
+  if (w.x) return HDG_OK;
+  const int64_t n = c->n_free;
+  w.n = n;
+  int epb = 1;
+  elem_threads(c->np, &epb);
+  w.apply_blocks = (int)std::max<int64_t>(1, (c->n_elem + epb - 1) / epb);
+  w.update_blocks = vec_blocks_for(n);
+  ST_TRY(dalloc(&w.x, n));
+  ST_TRY(dalloc(&w.r, n));
+  ST_TRY(dalloc(&w.p[0], n));
+  ST_TRY(dalloc(&w.p[1], n));
+  ST_TRY(dalloc(&w.qa, n));
+  ST_TRY(dalloc(&w.qb, n));
+  ST_TRY(dalloc(&w.partials, 2 * (int64_t)std::max(w.apply_blocks, w.update_blocks) + 64));
+  ST_TRY(dalloc(&w.sc, 1));
+  HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(CgScalars), c->stream));
+  if (n > 0) {
+    HIP_TRY(hipMemsetAsync(w.qa, 0, sizeof(T) * n, c->stream));
+    HIP_TRY(hipMemsetAsync(w.qb, 0, sizeof(T) * n, c->stream));
+  }
+  return HDG_OK;
+}
+
+template <typename T>
+void free_work(CgWork<T>& w) {
+  if (w.graph) (void)hipGraphExecDestroy(w.graph);
+  w.graph = nullptr;
+  dfree(w.x);
+  dfree(w.r);
+  dfree(w.p[0]);
+  dfree(w.p[1]);
+  dfree(w.qa);
+  dfree(w.qb);
+  dfree(w.partials);
+  dfree(w.sc);
+}
+
+template <typename T>
+T* dinv_of(hdg_ctx* c);
+template <>
+double* dinv_of<double>(hdg_ctx* c) { return c->d_tmp[3]; }
+template <>
+float* dinv_of<float>(hdg_ctx* c) { return c->d_dinv32; }
+
+// Capture `iters` CG iterations (fused apply + update) into a graph.
+template <typename T>
+hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters) {
+  if (w.graph && w.graph_iters == iters) return HDG_OK;
+  if (w.graph) {
+    (void)hipGraphExecDestroy(w.graph);
+    w.graph = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t err = hipSuccess;
+  for (int it = 0; it < iters && err == hipSuccess; ++it) {
+    err = launch_cg_apply<T>(c, w, c->cap_stream);
+    if (err == hipSuccess) err = launch_cg_update<T>(c, w, c->cap_stream);
+  }
+  hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+  if (err != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(HDG_EHIP, "kernel launch during capture failed: %s", hipGetErrorString(err));
+  }
+  HIP_TRY(e2);
+  hipError_t e3 = hipGraphInstantiate(&w.graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIP_TRY(e3);
+  w.graph_iters = iters;
+  return HDG_OK;
+}
+
+// Preconditioned CG on K^_ff w.x = b (eigen basis, precision T).  The
+// iterations run as captured graphs of `check_every` iterations; the host
+// keeps one graph in flight ahead of the convergence check, so a converged
+// solve costs at most one extra graph of no-op kernels.
+template <typename T>
+hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
+                  int check_every, int* iters_out, int* done_out) {
+  *iters_out = 0;
+  *done_out = 1;
+  if (w.n == 0) return HDG_OK;
+  w.dinv = dinv_of<T>(c);
+  CgScalars* hs = c->h_scal;
+  HIP_TRY(hipStreamSynchronize(c->stream));   // the upload slot is reused below
+  hs[2] = CgScalars{};
+  hs[2].rr_stop = rtol * rtol;
+  hs[2].maxit = std::max(1, maxit);
+  HIP_TRY(hipMemcpyAsync(w.sc, &hs[2], sizeof(CgScalars), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(launch_cg_init<T>(c, w, b, c->stream));
+  check_every = std::max(1, check_every);
+  ST_TRY(build_graph<T>(c, w, check_every));
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 2; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } guard{ev};
+  const int max_chunks = (std::max(1, maxit) + check_every - 1) / check_every + 1;
+  int done = 0, iters = 0;
+  for (int k = 0; k < max_chunks; ++k) {
+    HIP_TRY(hipGraphLaunch(w.graph, c->stream));
+    HIP_TRY(hipMemcpyAsync(&hs[k & 1], w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipEventRecord(ev[k & 1], c->stream));
+    if (k >= 1) {
+      HIP_TRY(hipEventSynchronize(ev[(k - 1) & 1]));
+      if (hs[(k - 1) & 1].done) break;
+    }
+  }
+  HIP_TRY(launch_cg_finalize<T>(c, w, c->stream));
+  HIP_TRY(hipMemcpyAsync(&hs[0], w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  done = hs[0].done;
+  iters = hs[0].iter;
+  *iters_out = iters;
+  *done_out = done;
+  if (done == 3) return fail(HDG_ENOCONV, "CG breakdown after %d iterations", iters);
+  return HDG_OK;
+}
+
+hdg_status validate_opts(const hdg_solve_opts* o) {
+  if (!(o->rtol > 0.0) || o->maxit < 1 || (o->precond != 0 && o->precond != 1) ||
+      (o->mixed != 0 && o->mixed != 1) || o->check_every < 1 ||
+      (o->mixed && (!(o->inner_rtol > 0.0) || o->inner_rtol >= 1.0 || o->max_outer < 1)))
+    return fail(HDG_EINVAL, "invalid solver options");
+  if (o->precond == 0) return fail(HDG_EUNSUPPORTED, "only the Jacobi preconditioner is built");
+  return HDG_OK;
+}
+
+// ||F^ - K^ x||^2 (FP64) into *rr; r written to c->d_tmp[2].
+hdg_status residual64(hdg_ctx* c, const double* b, const double* x, double* rr) {
+  CgWork<double>& w = c->w64;
+  HIP_TRY(launch_elem_apply<double>(c, x, nullptr, w.qa, w.qb, c->stream));
+  HIP_TRY(launch_residual64(b, w.qa, w.qb, c->d_tmp[2], c->n_free, w.partials, c->d_cnt,
+                            c->d_red, w.update_blocks, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->h_red, c->d_red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *rr = *c->h_red;
+  return HDG_OK;
+}
+
+hdg_status norm2_64(hdg_ctx* c, const double* v, double* out) {
+  HIP_TRY(launch_dot64(v, v, c->n_free, c->w64.partials, c->d_cnt, c->d_red,
+                       c->w64.update_blocks, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->h_red, c->d_red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *out = *c->h_red;
+  return HDG_OK;
+}
+
+// Solve K^_ff x = b in the eigen basis; the solution is returned in x_out
+// (FP64, free length).  b must not alias the CG workspace.
+hdg_status solve_eigen(hdg_ctx* c, const double* b, double* x_out, const hdg_solve_opts* o,
+                       hdg_solve_info* info) {
+  hdg_solve_info inf{};
+  auto t0 = std::chrono::steady_clock::now();
+  ST_TRY(alloc_work(c, c->w64));
+  double bb = 0.0;
+  ST_TRY(norm2_64(c, b, &bb));
+  inf.rhs_norm = std::sqrt(bb);
+  hdg_status result = HDG_OK;
+  if (c->n_free == 0 || bb == 0.0) {
+    if (c->n_free) HIP_TRY(launch_fill64(x_out, 0.0, c->n_free, c->stream));
+    inf.rel_res = 0.0;
+  } else if (!o->mixed) {
+    int it = 0, done = 0;
+    ST_TRY(run_cg<double>(c, c->w64, b, o->rtol, o->maxit, o->check_every, &it, &done));
+    inf.iters = it;
+    HIP_TRY(hipMemcpyAsync(x_out, c->w64.x, sizeof(double) * c->n_free,
+                           hipMemcpyDeviceToDevice, c->stream));
+    if (done == 2) result = HDG_ENOCONV;
+  } else {
+    ST_TRY(alloc_work(c, c->w32));
+    // FP32 right-hand side buffer: reuse p-ping-pong of nothing; keep a
+    // dedicated FP32 vector in d_vol_tmp-independent storage
+    float* b32 = reinterpret_cast<float*>(c->d_tmp[1]);   // n_free floats fit in n_free doubles
+    double* xacc = x_out;
+    HIP_TRY(launch_fill64(xacc, 0.0, c->n_free, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->d_tmp[2], b, sizeof(double) * c->n_free, hipMemcpyDeviceToDevice,
+                           c->stream));
+    double rr = bb;
+    int outer = 0, inner_total = 0;
+    while (std::sqrt(rr) > o->rtol * inf.rhs_norm && outer < o->max_outer) {
+      const double rn = std::sqrt(rr);
+      HIP_TRY(launch_cast_scale_64_32(c->d_tmp[2], b32, 1.0 / rn, c->n_free, c->stream));
+      int it = 0, done = 0;
+      ST_TRY(run_cg<float>(c, c->w32, b32, o->inner_rtol, o->maxit, o->check_every, &it, &done));
+      inner_total += it;
+      HIP_TRY(launch_axpy_32_64(c->w32.x, xacc, rn, c->n_free, c->stream));
+      ST_TRY(residual64(c, b, xacc, &rr));
+      ++outer;
+    }
+    inf.iters = inner_total;
+    inf.outer_iters = outer;
+    if (std::sqrt(rr) > o->rtol * inf.rhs_norm) result = HDG_ENOCONV;
+  }
+  if (c->n_free && bb != 0.0) {
+    double rr = 0.0;
+    ST_TRY(residual64(c, b, x_out, &rr));
+    inf.rel_res = std::sqrt(rr) / inf.rhs_norm;
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  inf.t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  if (result == HDG_ENOCONV)
+    return fail(HDG_ENOCONV, "solver stopped after %d iterations at relative residual %.3e",
+                inf.iters, inf.rel_res);
+  return result;
+}
+
+int64_t n_bdry_faces(const hdg_ctx* c) { return c->n_faces - c->n_free_faces; }
+
+// Eigen-basis Dirichlet data of a nodal trace (tail) into c->d_tmp[0]'s
+// boundary scratch; returns the pointer (or null for a null trace).
+hdg_status eigen_boundary(hdg_ctx* c, const double* trace, const double** out) {
+  *out = nullptr;
+  if (!trace || n_bdry_faces(c) == 0) return HDG_OK;
+  const int npf = c->np * c->np;
+  HIP_TRY(launch_face_transform<double>(c->np, c->d_mats64 + npf, trace + c->n_free, nullptr,
+                                        c->d_vol_tmp, n_bdry_faces(c), c->stream));
+  *out = c->d_vol_tmp;
+  return HDG_OK;
+}
+
+const double* mat64(const hdg_ctx* c, int kind) {
+  // storage order: St, StM, S, MS
+  const int npf = c->np * c->np;
+  switch (kind) {
+    case HDG_TO_EIGEN_UNKNOWN: return c->d_mats64 + npf;      // S^T M
+    case HDG_TO_EIGEN_RESIDUAL: return c->d_mats64;           // S^T
+    case HDG_TO_NODAL_UNKNOWN: return c->d_mats64 + 2 * npf;  // S
+    default: return c->d_mats64 + 3 * npf;                    // M S
+  }
+}
+const float* mat32(const hdg_ctx* c, int kind) {
+  const int npf = c->np * c->np;
+  switch (kind) {
+    case HDG_TO_EIGEN_UNKNOWN: return c->d_mats32 + npf;
+    case HDG_TO_EIGEN_RESIDUAL: return c->d_mats32;
+    case HDG_TO_NODAL_UNKNOWN: return c->d_mats32 + 2 * npf;
+    default: return c->d_mats32 + 3 * npf;
+  }
+}
+
+hdg_status upload_lambda_and_diag(hdg_ctx* c) {
+  HIP_TRY(launch_diag(c, c->d_diag, c->stream));
+  HIP_TRY(launch_recip_64_32(c->d_diag, c->d_dinv32, c->d_tmp[3], c->n_free, c->stream));
+  return HDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hdg_default_opts(hdg_solve_opts* o) {
+  if (!o) return;
+  o->rtol = 1e-10;
+  o->maxit = 20000;
+  o->precond = 1;
+  o->mixed = 0;
+  o->inner_rtol = 1e-4;
+  o->max_outer = 12;
+  o->check_every = 25;
+}
+
+const char* hdg_last_error(void) { return g_err.c_str(); }
+
+hdg_status hdg_tables(int p, double tau_hat, double* x, double* w, double* D, double* S,
+                      double* Lam, double* BS, double* H) {
+  if (p < 1 || p > 16) return fail(HDG_EINVAL, "p must be in [1, 16], got %d", p);
+  if (!(tau_hat > 0.0)) return fail(HDG_EINVAL, "tau_hat must be > 0");
+  Tables1D t = make_tables(p, tau_hat);
+  const int n = t.np;
+  if (x) std::memcpy(x, t.x.data(), sizeof(double) * n);
+  if (w) std::memcpy(w, t.w.data(), sizeof(double) * n);
+  if (D) std::memcpy(D, t.D.data(), sizeof(double) * n * n);
+  if (S) std::memcpy(S, t.S.data(), sizeof(double) * n * n);
+  if (Lam) std::memcpy(Lam, t.Lam.data(), sizeof(double) * n);
+  if (BS) std::memcpy(BS, t.BS.data(), sizeof(double) * n * 2);
+  if (H) *H = t.H;
+  return HDG_OK;
+}
+
+hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, const double* h3,
+                      int p, double tau_hat, const double* lambda_host, double lambda_const,
+                      void* stream, hdg_ctx** out) {
+  if (!out) return fail(HDG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!n_elem) return fail(HDG_EINVAL, "n_elem is NULL");
+  const double* hs[3] = {h1, h2, h3};
+  for (int a = 0; a < 3; ++a) {
+    if (n_elem[a] < 1 || n_elem[a] > (1 << 20))
+      return fail(HDG_EINVAL, "n_elem[%d] = %d out of range", a, n_elem[a]);
+    if (!hs[a]) return fail(HDG_EINVAL, "width array %d is NULL", a);
+    for (int i = 0; i < n_elem[a]; ++i)
+      if (!(hs[a][i] > 0.0) || !std::isfinite(hs[a][i]))
+        return fail(HDG_EINVAL, "width h%d[%d] must be finite and > 0", a + 1, i);
+  }
+  if (p < 1 || p > 16) return fail(HDG_EINVAL, "p must be in [1, 16], got %d", p);
+  if (!(tau_hat > 0.0) || !std::isfinite(tau_hat)) return fail(HDG_EINVAL, "tau_hat must be > 0");
+  const int64_t ne = (int64_t)n_elem[0] * n_elem[1] * n_elem[2];
+  if (lambda_host) {
+    for (int64_t e = 0; e < ne; ++e)
+      if (!(lambda_host[e] >= 0.0) || !std::isfinite(lambda_host[e]))
+        return fail(HDG_EINVAL, "lambda[%lld] must be finite and >= 0", (long long)e);
+  } else if (!(lambda_const >= 0.0) || !std::isfinite(lambda_const)) {
+    return fail(HDG_EINVAL, "lambda_const must be finite and >= 0");
+  }
+
+  hdg_ctx* c = new (std::nothrow) hdg_ctx();
+  if (!c) return fail(HDG_ENOMEM, "host allocation failed");
+  auto cleanup = [&](hdg_status st) {
+    hdg_destroy(c);
+    return st;
+  };
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  if (hipGetDevice(&c->device) != hipSuccess) return cleanup(fail(HDG_EHIP, "no HIP device"));
+  for (int a = 0; a < 3; ++a) c->n[a] = n_elem[a];
+  c->p = p;
+  c->np = p + 1;
+  c->tau = tau_hat;
+  c->n_elem = ne;
+  const int n1 = n_elem[0], n2 = n_elem[1], n3 = n_elem[2];
+  const int64_t nf0 = (int64_t)(n1 - 1) * n2 * n3, nf1 = (int64_t)n1 * (n2 - 1) * n3,
+                nf2 = (int64_t)n1 * n2 * (n3 - 1);
+  c->n_free_faces = nf0 + nf1 + nf2;
+  const int64_t tb[3] = {(int64_t)n2 * n3, (int64_t)n1 * n3, (int64_t)n1 * n2};
+  c->n_faces = c->n_free_faces + 2 * (tb[0] + tb[1] + tb[2]);
+  const int64_t npf = (int64_t)c->np * c->np;
+  c->n_free = c->n_free_faces * npf;
+  c->n_all = c->n_faces * npf;
+  c->n_vol = ne * npf * c->np;
+  c->tab = make_tables(p, tau_hat);
+  for (int a = 0; a < 3; ++a) c->h_host[a].assign(hs[a], hs[a] + n_elem[a]);
+  c->lam_host.resize(ne);
+  for (int64_t e = 0; e < ne; ++e) c->lam_host[e] = lambda_host ? lambda_host[e] : lambda_const;
+
+  // element tables
+  for (int k = 0; k < c->np; ++k) {
+    c->et64.bs0[k] = c->tab.BS[2 * k];
+    c->et64.bs1[k] = c->tab.BS[2 * k + 1];
+    c->et64.lam[k] = c->tab.Lam[k];
+    c->et32.bs0[k] = (float)c->tab.BS[2 * k];
+    c->et32.bs1[k] = (float)c->tab.BS[2 * k + 1];
+    c->et32.lam[k] = (float)c->tab.Lam[k];
+  }
+  c->et64.H = c->tab.H;
+  c->et32.H = (float)c->tab.H;
+
+  hdg_status st;
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(fail(HDG_EHIP, "stream creation failed"));
+  for (int a = 0; a < 3; ++a)
+    if ((st = dalloc(&c->d_h[a], n_elem[a])) != HDG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_lam, ne)) != HDG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_mats64, 4 * npf)) != HDG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_mats32, 4 * npf)) != HDG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_diag, c->n_free)) != HDG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_dinv32, c->n_free)) != HDG_OK) return cleanup(st);
+  for (int t = 0; t < 4; ++t)
+    if ((st = dalloc(&c->d_tmp[t], c->n_free)) != HDG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_vol_tmp, std::max<int64_t>(n_bdry_faces(c) * npf, 1))) != HDG_OK)
+    return cleanup(st);
+  if ((st = dalloc(&c->d_red, 16)) != HDG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_cnt, 16)) != HDG_OK) return cleanup(st);
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_scal), 4 * sizeof(CgScalars),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_red), 8 * sizeof(double),
+                    hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(HDG_ENOMEM, "pinned host allocation failed"));
+
+  std::vector<double> mats(4 * npf);
+  std::copy(c->tab.St.begin(), c->tab.St.end(), mats.begin());
+  std::copy(c->tab.StM.begin(), c->tab.StM.end(), mats.begin() + npf);
+  std::copy(c->tab.S.begin(), c->tab.S.end(), mats.begin() + 2 * npf);
+  std::copy(c->tab.MS.begin(), c->tab.MS.end(), mats.begin() + 3 * npf);
+  std::vector<float> mats32(mats.begin(), mats.end());
+
+  auto h2d = [&](void* dst, const void* src, size_t bytes) -> hdg_status {
+    if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(HDG_EHIP, "host-to-device copy failed");
+    return HDG_OK;
+  };
+  for (int a = 0; a < 3; ++a)
+    if ((st = h2d(c->d_h[a], hs[a], sizeof(double) * n_elem[a])) != HDG_OK) return cleanup(st);
+  if ((st = h2d(c->d_lam, c->lam_host.data(), sizeof(double) * ne)) != HDG_OK) return cleanup(st);
+  if ((st = h2d(c->d_mats64, mats.data(), sizeof(double) * mats.size())) != HDG_OK)
+    return cleanup(st);
+  if ((st = h2d(c->d_mats32, mats32.data(), sizeof(float) * mats32.size())) != HDG_OK)
+    return cleanup(st);
+  if (hipMemset(c->d_cnt, 0, 16 * sizeof(unsigned)) != hipSuccess)
+    return cleanup(fail(HDG_EHIP, "memset failed"));
+
+  MeshDev& m = c->mesh;
+  m.n1 = n1;
+  m.n2 = n2;
+  m.n3 = n3;
+  m.n_elem = ne;
+  m.foff[0] = 0;
+  m.foff[1] = nf0;
+  m.foff[2] = nf0 + nf1;
+  int64_t off = c->n_free_faces;
+  for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 2; ++s) {
+      m.boff[2 * a + s] = off;
+      off += tb[a];
+    }
+  m.n_free_faces = c->n_free_faces;
+  m.h1 = c->d_h[0];
+  m.h2 = c->d_h[1];
+  m.h3 = c->d_h[2];
+  m.lam = c->d_lam;
+
+  if ((st = upload_lambda_and_diag(c)) != HDG_OK) return cleanup(st);
+  if ((st = alloc_work(c, c->w64)) != HDG_OK) return cleanup(st);
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return cleanup(fail(HDG_EHIP, "setup kernels failed: %s", hipGetErrorString(hipGetLastError())));
+  *out = c;
+  return HDG_OK;
+}
+
+hdg_status hdg_destroy(hdg_ctx* c) {
+  if (!c) return HDG_OK;
+  (void)hipStreamSynchronize(c->stream);
+  free_work(c->w64);
+  free_work(c->w32);
+  for (auto& h : c->d_h) dfree(h);
+  dfree(c->d_lam);
+  dfree(c->d_mats64);
+  dfree(c->d_mats32);
+  dfree(c->d_diag);
+  dfree(c->d_dinv32);
+  for (auto& t : c->d_tmp) dfree(t);
+  dfree(c->d_vol_tmp);
+  dfree(c->d_red);
+  dfree(c->d_cnt);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->h_scal) (void)hipHostFree(c->h_scal);
+  if (c->h_red) (void)hipHostFree(c->h_red);
+  delete c;
+  return HDG_OK;
+}
+
+hdg_status hdg_sizes(const hdg_ctx* c, int64_t* n_free, int64_t* n_all, int64_t* n_vol) {
+  if (!c) return fail(HDG_EINVAL, "ctx is NULL");
+  if (n_free) *n_free = c->n_free;
+  if (n_all) *n_all = c->n_all;
+  if (n_vol) *n_vol = c->n_vol;
+  return HDG_OK;
+}
+
+hdg_status hdg_set_lambda(hdg_ctx* c, const double* lambda_dev) {
+  if (!c || !lambda_dev) return fail(HDG_EINVAL, "NULL argument");
+  HIP_TRY(hipMemcpyAsync(c->d_lam, lambda_dev, sizeof(double) * c->n_elem,
+                         hipMemcpyDeviceToDevice, c->stream));
+  return upload_lambda_and_diag(c);
+}
+
+hdg_status hdg_coords(hdg_ctx* c, double* vol_xyz, double* trace_xyz) {
+  if (!c) return fail(HDG_EINVAL, "ctx is NULL");
+  const int np = c->np;
+  std::vector<double> X[3];
+  for (int a = 0; a < 3; ++a) {
+    X[a].assign(c->n[a] + 1, 0.0);
+    for (int i = 0; i < c->n[a]; ++i) X[a][i + 1] = X[a][i] + c->h_host[a][i];
+  }
+  auto coord = [&](int a, int el, int q) {
+    return X[a][el] + c->h_host[a][el] * 0.5 * (c->tab.x[q] + 1.0);
+  };
+  if (vol_xyz) {
+    std::vector<double> v((size_t)c->n_vol * 3);
+    size_t o = 0;
+    for (int k = 0; k < c->n[2]; ++k)
+      for (int j = 0; j < c->n[1]; ++j)
+        for (int i = 0; i < c->n[0]; ++i)
+          for (int q3 = 0; q3 < np; ++q3)
+            for (int q2 = 0; q2 < np; ++q2)
+              for (int q1 = 0; q1 < np; ++q1) {
+                v[o++] = coord(0, i, q1);
+                v[o++] = coord(1, j, q2);
+                v[o++] = coord(2, k, q3);
+              }
+    HIP_TRY(hipMemcpyAsync(vol_xyz, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  if (trace_xyz) {
+    std::vector<double> t((size_t)c->n_all * 3);
+    const MeshDev& m = c->mesh;
+    auto put = [&](int64_t fid, int a, int plane, int eb, int ec) {
+      const int b = (a == 0) ? 1 : 0, cax = (a == 2) ? 1 : 2;
+      for (int qc = 0; qc < np; ++qc)
+        for (int qb = 0; qb < np; ++qb) {
+          const size_t g = (size_t)(fid * np * np + qb + np * qc) * 3;
+          t[g + a] = X[a][plane];
+          t[g + b] = coord(b, eb, qb);
+          t[g + cax] = coord(cax, ec, qc);
+        }
+    };
+    const int n1 = c->n[0], n2 = c->n[1], n3 = c->n[2];
+    for (int k = 0; k < n3; ++k)
+      for (int j = 0; j < n2; ++j)
+        for (int pl = 0; pl <= n1; ++pl) {
+          int64_t fid = (pl >= 1 && pl <= n1 - 1)
+                            ? m.foff[0] + (pl - 1) + (int64_t)(n1 - 1) * (j + (int64_t)n2 * k)
+                            : m.boff[pl == 0 ? 0 : 1] + j + (int64_t)n2 * k;
+          put(fid, 0, pl, j, k);
+        }
+    for (int k = 0; k < n3; ++k)
+      for (int pl = 0; pl <= n2; ++pl)
+        for (int i = 0; i < n1; ++i) {
+          int64_t fid = (pl >= 1 && pl <= n2 - 1)
+                            ? m.foff[1] + i + (int64_t)n1 * ((pl - 1) + (int64_t)(n2 - 1) * k)
+                            : m.boff[2 + (pl == 0 ? 0 : 1)] + i + (int64_t)n1 * k;
+          put(fid, 1, pl, i, k);
+        }
+    for (int pl = 0; pl <= n3; ++pl)
+      for (int j = 0; j < n2; ++j)
+        for (int i = 0; i < n1; ++i) {
+          int64_t fid = (pl >= 1 && pl <= n3 - 1)
+                            ? m.foff[2] + i + (int64_t)n1 * (j + (int64_t)n2 * (pl - 1))
+                            : m.boff[4 + (pl == 0 ? 0 : 1)] + i + (int64_t)n1 * j;
+          put(fid, 2, pl, i, j);
+        }
+    HIP_TRY(hipMemcpyAsync(trace_xyz, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return HDG_OK;
+}
+
+hdg_status hdg_face_transform(hdg_ctx* c, hdg_transform kind, const double* in, double* out,
+                              int64_t n_faces) {
+  if (!c || !in || !out) return fail(HDG_EINVAL, "NULL argument");
+  if (kind < 0 || kind > 3) return fail(HDG_EINVAL, "unknown transform %d", (int)kind);
+  if (n_faces < 0 || n_faces > c->n_faces) return fail(HDG_EINVAL, "n_faces out of range");
+  HIP_TRY(launch_face_transform<double>(c->np, mat64(c, kind), in, nullptr, out, n_faces,
+                                        c->stream));
+  return HDG_OK;
+}
+
+hdg_status hdg_apply(hdg_ctx* c, const void* x, void* y, hdg_dtype dtype, hdg_basis basis) {
+  if (!c || !x || !y) return fail(HDG_EINVAL, "NULL argument");
+  if (x == y) return fail(HDG_EINVAL, "x and y must not overlap");
+  if (dtype != HDG_F64 && dtype != HDG_F32) return fail(HDG_EINVAL, "unknown dtype");
+  if (basis != HDG_BASIS_NODAL && basis != HDG_BASIS_EIGEN) return fail(HDG_EINVAL, "unknown basis");
+  if (c->n_free == 0) return HDG_OK;
+  const int64_t nff = c->n_free_faces;
+  if (dtype == HDG_F64) {
+    CgWork<double>& w = c->w64;
+    const double* xin = static_cast<const double*>(x);
+    double* yout = static_cast<double*>(y);
+    if (basis == HDG_BASIS_NODAL) {
+      HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_EIGEN_UNKNOWN), xin, nullptr,
+                                            c->d_tmp[0], nff, c->stream));
+      xin = c->d_tmp[0];
+    }
+    HIP_TRY(launch_elem_apply<double>(c, xin, nullptr, w.qa, w.qb, c->stream));
+    if (basis == HDG_BASIS_NODAL)
+      HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_NODAL_RESIDUAL), w.qa, w.qb,
+                                            yout, nff, c->stream));
+    else
+      HIP_TRY(launch_combine<double>(w.qa, w.qb, yout, c->n_free, c->stream));
+  } else {
+    ST_TRY(alloc_work(c, c->w32));
+    CgWork<float>& w = c->w32;
+    const float* xin = static_cast<const float*>(x);
+    float* yout = static_cast<float*>(y);
+    if (basis == HDG_BASIS_NODAL) {
+      float* tmp = reinterpret_cast<float*>(c->d_tmp[0]);
+      HIP_TRY(launch_face_transform<float>(c->np, mat32(c, HDG_TO_EIGEN_UNKNOWN), xin, nullptr,
+                                           tmp, nff, c->stream));
+      xin = tmp;
+    }
+    HIP_TRY(launch_elem_apply<float>(c, xin, nullptr, w.qa, w.qb, c->stream));
+    if (basis == HDG_BASIS_NODAL)
+      HIP_TRY(launch_face_transform<float>(c->np, mat32(c, HDG_TO_NODAL_RESIDUAL), w.qa, w.qb,
+                                           yout, nff, c->stream));
+    else
+      HIP_TRY(launch_combine<float>(w.qa, w.qb, yout, c->n_free, c->stream));
+  }
+  return HDG_OK;
+}
+
+hdg_status hdg_rhs(hdg_ctx* c, const double* f, const double* trace, double* F_free,
+                   hdg_basis basis) {
+  if (!c || !f || !F_free) return fail(HDG_EINVAL, "NULL argument");
+  if (basis != HDG_BASIS_NODAL && basis != HDG_BASIS_EIGEN) return fail(HDG_EINVAL, "unknown basis");
+  if (c->n_free == 0) return HDG_OK;
+  const double* xb = nullptr;
+  ST_TRY(eigen_boundary(c, trace, &xb));
+  CgWork<double>& w = c->w64;
+  HIP_TRY(launch_volume(c, VOL_RHS, 1, f, nullptr, xb, nullptr, nullptr, w.qa, w.qb, nullptr,
+                        nullptr, c->stream));
+  if (basis == HDG_BASIS_EIGEN)
+    HIP_TRY(launch_combine<double>(w.qa, w.qb, F_free, c->n_free, c->stream));
+  else
+    HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_NODAL_RESIDUAL), w.qa, w.qb,
+                                          F_free, c->n_free_faces, c->stream));
+  return HDG_OK;
+}
+
+hdg_status hdg_solve(hdg_ctx* c, const double* F_free, double* u_free, const hdg_solve_opts* opts,
+                     hdg_solve_info* info) {
+  if (!c || !F_free || !u_free) return fail(HDG_EINVAL, "NULL argument");
+  hdg_solve_opts o;
+  hdg_default_opts(&o);
+  if (opts) o = *opts;
+  ST_TRY(validate_opts(&o));
+  if (c->n_free == 0) {
+    if (info) *info = hdg_solve_info{};
+    return HDG_OK;
+  }
+  double* bhat = c->d_tmp[0];
+  HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_EIGEN_RESIDUAL), F_free, nullptr,
+                                        bhat, c->n_free_faces, c->stream));
+  double* xhat = c->d_tmp[1];
+  if (o.mixed) xhat = u_free;   // d_tmp[1] holds the FP32 right-hand side in mixed mode
+  hdg_status st = solve_eigen(c, bhat, xhat, &o, info);
+  if (st != HDG_OK && st != HDG_ENOCONV) return st;
+  HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_NODAL_UNKNOWN), xhat, nullptr,
+                                        u_free, c->n_free_faces, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return st;
+}
+
+hdg_status hdg_solve_forcing(hdg_ctx* c, const double* f, double* trace, double* u_vol,
+                             const hdg_solve_opts* opts, hdg_solve_info* info) {
+  if (!c || !f || !trace) return fail(HDG_EINVAL, "NULL argument");
+  hdg_solve_opts o;
+  hdg_default_opts(&o);
+  if (opts) o = *opts;
+  ST_TRY(validate_opts(&o));
+  const double* xb = nullptr;
+  ST_TRY(eigen_boundary(c, trace, &xb));
+  CgWork<double>& w = c->w64;
+  double* bhat = c->d_tmp[0];
+  double* xhat = trace;   // eigen-basis solution staged in the free part of trace
+  hdg_status st = HDG_OK;
+  if (c->n_free > 0) {
+    HIP_TRY(launch_volume(c, VOL_RHS, 1, f, nullptr, xb, nullptr, nullptr, w.qa, w.qb, nullptr,
+                          nullptr, c->stream));
+    HIP_TRY(launch_combine<double>(w.qa, w.qb, bhat, c->n_free, c->stream));
+    st = solve_eigen(c, bhat, xhat, &o, info);
+    if (st != HDG_OK && st != HDG_ENOCONV) return st;
+  } else if (info) {
+    *info = hdg_solve_info{};
+  }
+  if (u_vol)
+    HIP_TRY(launch_volume(c, VOL_RECON, 1, f, xhat, xb, nullptr, nullptr, nullptr, nullptr, u_vol,
+                          nullptr, c->stream));
+  if (c->n_free > 0)
+    HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_NODAL_UNKNOWN), xhat, nullptr,
+                                          trace, c->n_free_faces, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return st;
+}
+
+hdg_status hdg_reconstruct(hdg_ctx* c, const double* f, const double* trace, double* u_vol) {
+  if (!c || !f || !trace || !u_vol) return fail(HDG_EINVAL, "NULL argument");
+  const double* xb = nullptr;
+  ST_TRY(eigen_boundary(c, trace, &xb));
+  double* xhat = c->d_tmp[0];
+  if (c->n_free > 0)
+    HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_EIGEN_UNKNOWN), trace, nullptr,
+                                          xhat, c->n_free_faces, c->stream));
+  HIP_TRY(launch_volume(c, VOL_RECON, 1, f, c->n_free ? xhat : nullptr, xb, nullptr, nullptr,
+                        nullptr, nullptr, u_vol, nullptr, c->stream));
+  return HDG_OK;
+}
+
+hdg_status hdg_adjoint(hdg_ctx* c, const double* f, const double* trace, const double* dJdu,
+                       double* dJdlambda, double* dJdf, const hdg_solve_opts* opts,
+                       hdg_solve_info* info) {
+  if (!c || !f || !trace || !dJdu || !dJdlambda || !dJdf) return fail(HDG_EINVAL, "NULL argument");
+  hdg_solve_opts o;
+  hdg_default_opts(&o);
+  if (opts) o = *opts;
+  ST_TRY(validate_opts(&o));
+  const double* xb = nullptr;
+  ST_TRY(eigen_boundary(c, trace, &xb));
+  CgWork<double>& w = c->w64;
+  // d_tmp[0]: eigen-basis forward trace; d_tmp[2] is the residual scratch,
+  // d_tmp[1] the FP32 rhs in mixed mode, so the adjoint rhs and solution use
+  // the qa/qb-free slots below.
+  double* xhat = c->d_tmp[0];
+  if (c->n_free > 0)
+    HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_EIGEN_UNKNOWN), trace, nullptr,
+                                          xhat, c->n_free_faces, c->stream));
+  std::vector<double*> extra(2, nullptr);
+  hdg_status st = HDG_OK;
+  double* jhat = nullptr;
+  double* muhat = nullptr;
+  if (c->n_free > 0) {
+    ST_TRY(dalloc(&jhat, c->n_free));
+    st = dalloc(&muhat, c->n_free);
+    if (st != HDG_OK) {
+      dfree(jhat);
+      return st;
+    }
+    hipError_t e = launch_volume(c, VOL_RHS, 0, dJdu, nullptr, nullptr, nullptr, nullptr, w.qa,
+                                 w.qb, nullptr, nullptr, c->stream);
+    if (e == hipSuccess) e = launch_combine<double>(w.qa, w.qb, jhat, c->n_free, c->stream);
+    if (e != hipSuccess) {
+      dfree(jhat);
+      dfree(muhat);
+      return fail(HDG_EHIP, "adjoint rhs failed: %s", hipGetErrorString(e));
+    }
+    st = solve_eigen(c, jhat, muhat, &o, info);
+    if (st != HDG_OK && st != HDG_ENOCONV) {
+      dfree(jhat);
+      dfree(muhat);
+      return st;
+    }
+  } else if (info) {
+    *info = hdg_solve_info{};
+  }
+  hipError_t e = launch_volume(c, VOL_ADJ, 1, f, c->n_free ? xhat : nullptr, xb, dJdu, muhat,
+                               nullptr, nullptr, dJdf, dJdlambda, c->stream);
+  hipError_t e2 = hipStreamSynchronize(c->stream);
+  dfree(jhat);
+  dfree(muhat);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(HDG_EHIP, "adjoint gradient kernel failed: %s",
+                hipGetErrorString(e != hipSuccess ? e : e2));
+  return st;
+}
+
+hdg_status hdg_diagonal(hdg_ctx* c, double* diag_free) {
+  if (!c || !diag_free) return fail(HDG_EINVAL, "NULL argument");
+  if (c->n_free == 0) return HDG_OK;
+  HIP_TRY(hipMemcpyAsync(diag_free, c->d_diag, sizeof(double) * c->n_free,
+                         hipMemcpyDeviceToDevice, c->stream));
+  return HDG_OK;
+}
+
+hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int reps, double* ms) {
+  if (!c || !x || !ms || reps < 1) return fail(HDG_EINVAL, "invalid argument");
+  (void)y;
+  if (which < 0 || which > 7) return fail(HDG_EINVAL, "unknown kernel id %d", which);
+  if (c->n_free == 0) {
+    *ms = 0.0;
+    return HDG_OK;
+  }
+  const bool f32 = (which == 1 || which == 3 || which == 6 || which == 7);
+  if (f32) ST_TRY(alloc_work(c, c->w32));
+  // CG-state kernels need an initialised run that never finishes
+  if (which >= 2) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    CgScalars& init = c->h_scal[2];
+    init = CgScalars{};
+    init.rr_stop = 0.0;
+    init.maxit = 1 << 30;
+    if (f32) {
+      c->w32.dinv = c->d_dinv32;
+      HIP_TRY(hipMemcpyAsync(c->w32.sc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(launch_cg_init<float>(c, c->w32, static_cast<const float*>(x), c->stream));
+    } else {
+      c->w64.dinv = c->d_tmp[3];
+      HIP_TRY(hipMemcpyAsync(c->w64.sc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(launch_cg_init<double>(c, c->w64, static_cast<const double*>(x), c->stream));
+    }
+  }
+  auto launch = [&]() -> hipError_t {
+    switch (which) {
+      case 0: return launch_elem_apply<double>(c, static_cast<const double*>(x), nullptr,
+                                               c->w64.qa, c->w64.qb, c->stream);
+      case 1: return launch_elem_apply<float>(c, static_cast<const float*>(x), nullptr,
+                                              c->w32.qa, c->w32.qb, c->stream);
+      case 2: {
+        hipError_t e = launch_cg_apply<double>(c, c->w64, c->stream);
+        return e == hipSuccess ? launch_cg_update<double>(c, c->w64, c->stream) : e;
+      }
+      case 3: {
+        hipError_t e = launch_cg_apply<float>(c, c->w32, c->stream);
+        return e == hipSuccess ? launch_cg_update<float>(c, c->w32, c->stream) : e;
+      }
+      case 4: return launch_cg_apply<double>(c, c->w64, c->stream);
+      case 5: return launch_cg_update<double>(c, c->w64, c->stream);
+      case 6: return launch_cg_apply<float>(c, c->w32, c->stream);
+      default: return launch_cg_update<float>(c, c->w32, c->stream);
+    }
+  };
+  HIP_TRY(launch());   // warm-up
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, c->stream));
+  hipError_t err = hipSuccess;
+  for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
+  HIP_TRY(hipEventRecord(e1, c->stream));
+  HIP_TRY(hipEventSynchronize(e1));
+  float t = 0.f;
+  HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(err);
+  *ms = (double)t / reps;
+  return HDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,171 @@
+// Internal declarations shared by the host API and the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "setup1d.hpp"
+
+namespace hdg {
+
+constexpr int kMaxNP = 17;     // p <= 16
+
+// Per-degree 1D data the element kernels need, passed by value.
+template <typename T>
+struct ElemTab {
+  T bs0[kMaxNP];   // B_S[k][0]
+  T bs1[kMaxNP];   // B_S[k][1]
+  T lam[kMaxNP];   // Lambda_k
+  T H;             // diagonal of G + C^T M^-1 C
+};
+
+// Mesh description on the device.  Face ids follow the canonical layout:
+// free faces of axis 0, 1, 2 then the boundary tail (see include/hdg.h).
+struct MeshDev {
+  int n1, n2, n3;
+  int64_t n_elem;
+  int64_t foff[3];     // first free face id of each axis
+  int64_t boff[6];     // first boundary face id of (axis, side)
+  int64_t n_free_faces;
+  const double* h1;
+  const double* h2;
+  const double* h3;
+  const double* lam;   // per element
+};
+
+// Device-resident scalars of one CG run (one cache line each group).
+struct CgScalars {
+  double rho;        // r.z of the current residual
+  double alpha;      // alpha of the current iteration (written by the apply)
+  double alpha_x;    // alpha applied to x in the next apply (written by the update)
+  double beta;       // beta for the next search direction
+  double rr;         // ||r||^2 of the current residual
+  double rr_stop;    // convergence threshold on ||r||^2
+  double pq;
+  double pad0;
+  int iter;          // completed iterations
+  int maxit;
+  int done;          // 0 running, 1 converged, 2 iteration cap, 3 breakdown
+  int pad1;
+  unsigned cnt_apply;   // last-block counters
+  unsigned cnt_update;
+  unsigned cnt_misc;
+  unsigned pad2;
+};
+
+// Workspace of one CG solve in precision T (free-trace vectors).
+template <typename T>
+struct CgWork {
+  T* x = nullptr;
+  T* r = nullptr;
+  T* p[2] = {nullptr, nullptr};
+  T* qa = nullptr;       // contribution of the element below each face
+  T* qb = nullptr;       // contribution of the element above each face
+  T* dinv = nullptr;
+  double* partials = nullptr;  // 2 doubles per block
+  CgScalars* sc = nullptr;
+  int64_t n = 0;
+  int apply_blocks = 0;
+  int update_blocks = 0;
+  hipGraphExec_t graph = nullptr;
+  int graph_iters = 0;
+};
+
+struct KernelConfig {
+  int epb = 1;      // elements per block of the element kernels
+};
+
+}  // namespace hdg
+
+struct hdg_ctx {
+  int n[3] = {0, 0, 0};
+  int p = 0, np = 0;
+  double tau = 0.0;
+  int64_t n_elem = 0, n_free = 0, n_all = 0, n_vol = 0;
+  int64_t n_free_faces = 0, n_faces = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;   // private stream for graph capture
+  int device = 0;
+  hdg::Tables1D tab;
+  hdg::MeshDev mesh{};
+  std::vector<double> h_host[3];
+  std::vector<double> lam_host;
+  // device buffers
+  double* d_h[3] = {nullptr, nullptr, nullptr};
+  double* d_lam = nullptr;
+  double* d_mats64 = nullptr;   // St, StM, S, MS (4 n_p^2 doubles)
+  float* d_mats32 = nullptr;
+  hdg::ElemTab<double> et64{};
+  hdg::ElemTab<float> et32{};
+  double* d_diag = nullptr;     // diag of K^_ff (FP64)
+  float* d_dinv32 = nullptr;
+  hdg::CgWork<double> w64;
+  hdg::CgWork<float> w32;
+  // FP64 free-length scratch: [0] eigen-basis rhs / trace, [1] FP64 solution or FP32
+  // inner rhs (mixed), [2] FP64 residual, [3] inverse diagonal (FP64)
+  double* d_tmp[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* d_vol_tmp = nullptr;
+  double* d_red = nullptr;      // small reduction scratch
+  unsigned* d_cnt = nullptr;
+  hdg::CgScalars* h_scal = nullptr;   // pinned host slots: [0..1] polling, [2] upload
+  double* h_red = nullptr;            // pinned host scalar for reductions
+};
+
+namespace hdg {
+
+// ---- kernel launchers (defined in the .hip translation units) -------------
+// element apply in the eigen basis, output split into qa/qb.
+template <typename T>
+hipError_t launch_elem_apply(const hdg_ctx* c, const T* x_free, const T* x_bdry,
+                             T* qa, T* qb, hipStream_t s);
+// fused CG apply (see kernels_cg.hip)
+template <typename T>
+hipError_t launch_cg_apply(const hdg_ctx* c, CgWork<T>& w, hipStream_t s);
+template <typename T>
+hipError_t launch_cg_update(const hdg_ctx* c, CgWork<T>& w, hipStream_t s);
+template <typename T>
+hipError_t launch_cg_init(const hdg_ctx* c, CgWork<T>& w, const T* b, hipStream_t s);
+template <typename T>
+hipError_t launch_cg_finalize(const hdg_ctx* c, CgWork<T>& w, hipStream_t s);
+
+// y = qa + qb (optionally scaled); or y = b - (qa + qb) with the squared norm
+// reduced into red[0] (FP64)
+template <typename T>
+hipError_t launch_combine(const T* qa, const T* qb, T* y, int64_t n, hipStream_t s);
+hipError_t launch_residual64(const double* b, const double* qa, const double* qb, double* r,
+                             int64_t n, double* partials, unsigned* cnt, double* out,
+                             int nblocks, hipStream_t s);
+
+// per-face transform A x A of n_faces faces; optional second input added first
+template <typename T>
+hipError_t launch_face_transform(int np, const T* A, const T* in, const T* in2, T* out,
+                                 int64_t n_faces, hipStream_t s);
+
+// diagonal of K^_ff
+hipError_t launch_diag(const hdg_ctx* c, double* diag, hipStream_t s);
+
+// volume-source element kernel (RHS / recovery / adjoint)
+enum VolMode { VOL_RHS = 0, VOL_RECON = 1, VOL_ADJ = 2 };
+hipError_t launch_volume(const hdg_ctx* c, int mode, int src_is_forcing,
+                         const double* f, const double* x_free, const double* x_bdry,
+                         const double* r2, const double* mu_free,
+                         double* qa, double* qb, double* out_vol, double* out_elem,
+                         hipStream_t s);
+
+// misc vector kernels
+hipError_t launch_cast_scale_64_32(const double* in, float* out, double scale, int64_t n,
+                                   hipStream_t s);
+hipError_t launch_axpy_32_64(const float* in, double* out, double scale, int64_t n,
+                             hipStream_t s);
+hipError_t launch_fill64(double* out, double v, int64_t n, hipStream_t s);
+hipError_t launch_fill32(float* out, float v, int64_t n, hipStream_t s);
+hipError_t launch_recip_64_32(const double* diag, float* dinv32, double* dinv64, int64_t n,
+                              hipStream_t s);
+hipError_t launch_dot64(const double* a, const double* b, int64_t n, double* partials,
+                        unsigned* cnt, double* out, int nblocks, hipStream_t s);
+
+int elem_threads(int np, int* epb);
+
+}  // namespace hdg

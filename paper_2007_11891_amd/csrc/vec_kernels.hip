@@ -1,0 +1,429 @@
+// Vector kernels of the preconditioned CG on the free trace, face transforms,
+// and the diagonal of the transformed operator.
+//
+// CG (paper: section "Summary of solution method", solver HDG-trans): the
+// iteration is split into two launches.  The fused element apply (see
+// elem_kernels.hip) forms p = z + beta p_old with z = D^-1 r on the fly,
+// applies x += alpha_old p_old on the faces it owns, and reduces p.q from
+// element-local quadratic forms; its last block sets alpha = rho / p.q.
+// The update below forms q = qa + qb, r -= alpha q, and reduces r.z and r.r;
+// its last block sets beta, advances the iteration counter and raises the
+// done flag.  All reductions are block partials summed in a fixed order.
+#include "device_common.hpp"
+
+namespace hdg {
+
+constexpr int kVecThreads = 256;
+
+static inline int vec_blocks(int64_t n, int cap = 2048) {
+  int64_t nb = (n + kVecThreads * 4 - 1) / (kVecThreads * 4);
+  if (nb > cap) nb = cap;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+// ------------------------------------------------------------------ CG ----
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+cg_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb, T* __restrict__ r,
+                 const T* __restrict__ dinv, double* partials, CgScalars* sc) {
+  __shared__ double s_red[kVecThreads / 64];
+  if (sc->done) return;
+  const T alpha = (T)sc->alpha;
+  double rz = 0.0, rr = 0.0;
+  T rz_t = 0, rr_t = 0;
+  for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * kVecThreads) {
+    const T q = qa[g] + qb[g];
+    const T rn = r[g] - alpha * q;
+    r[g] = rn;
+    const T z = dinv[g] * rn;
+    rz_t += rn * z;
+    rr_t += rn * rn;
+  }
+  rz = (double)rz_t;
+  rr = (double)rr_t;
+  const double brz = block_sum<kVecThreads>(rz, s_red);
+  const double brr = block_sum<kVecThreads>(rr, s_red);
+  if (threadIdx.x == 0) {
+    store_partial(partials + 2 * blockIdx.x, brz);
+    store_partial(partials + 2 * blockIdx.x + 1, brr);
+  }
+  if (arrive_last(&sc->cnt_update, gridDim.x)) {
+    const double trz = sum_partials<kVecThreads>(partials, gridDim.x, 2, 0, s_red);
+    const double trr = sum_partials<kVecThreads>(partials, gridDim.x, 2, 1, s_red);
+    if (threadIdx.x == 0) {
+      const double rho_old = sc->rho;
+      sc->beta = trz / rho_old;
+      sc->rho = trz;
+      sc->rr = trr;
+      sc->alpha_x = sc->alpha;
+      sc->iter = sc->iter + 1;
+      if (trr <= sc->rr_stop) sc->done = 1;
+      else if (sc->iter >= sc->maxit) sc->done = 2;
+      else if (!isfinite(trr) || !isfinite(sc->beta)) sc->done = 3;
+    }
+  }
+}
+
+// r = b, p_old = 0, x = 0, rho = b.D^-1 b, rr = b.b; rr_stop scaled by rr.
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+cg_init_kernel(int64_t n, const T* __restrict__ b, T* __restrict__ r, T* __restrict__ x,
+               T* __restrict__ p1, const T* __restrict__ dinv, double* partials, CgScalars* sc) {
+  __shared__ double s_red[kVecThreads / 64];
+  T rz_t = 0, rr_t = 0;
+  for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * kVecThreads) {
+    const T v = b[g];
+    r[g] = v;
+    x[g] = 0;
+    p1[g] = 0;
+    rz_t += v * dinv[g] * v;
+    rr_t += v * v;
+  }
+  const double brz = block_sum<kVecThreads>((double)rz_t, s_red);
+  const double brr = block_sum<kVecThreads>((double)rr_t, s_red);
+  if (threadIdx.x == 0) {
+    store_partial(partials + 2 * blockIdx.x, brz);
+    store_partial(partials + 2 * blockIdx.x + 1, brr);
+  }
+  if (arrive_last(&sc->cnt_misc, gridDim.x)) {
+    const double trz = sum_partials<kVecThreads>(partials, gridDim.x, 2, 0, s_red);
+    const double trr = sum_partials<kVecThreads>(partials, gridDim.x, 2, 1, s_red);
+    if (threadIdx.x == 0) {
+      sc->rho = trz;
+      sc->rr = trr;
+      sc->rr_stop = sc->rr_stop * trr;   // host stored rtol^2
+      sc->beta = 0.0;
+      sc->alpha = 0.0;
+      sc->alpha_x = 0.0;
+      sc->iter = 0;
+      sc->done = (trr <= sc->rr_stop || trr == 0.0) ? 1 : 0;
+      if (!isfinite(trr)) sc->done = 3;
+    }
+  }
+}
+
+// x += alpha_x p_last after the loop stopped.
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+cg_finalize_kernel(int64_t n, T* __restrict__ x, const T* __restrict__ p0,
+                   const T* __restrict__ p1, const CgScalars* sc) {
+  const T a = (T)sc->alpha_x;
+  // the last apply ran at iteration iter-1 and wrote p[(iter - 1) & 1]
+  const T* p = (sc->iter & 1) ? p0 : p1;
+  for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * kVecThreads)
+    x[g] += a * p[g];
+}
+
+template <typename T>
+hipError_t launch_cg_update(const hdg_ctx*, CgWork<T>& w, hipStream_t s) {
+  hipLaunchKernelGGL((cg_update_kernel<T>), dim3(w.update_blocks), dim3(kVecThreads), 0, s, w.n,
+                     w.qa, w.qb, w.r, w.dinv, w.partials, w.sc);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_cg_init(const hdg_ctx*, CgWork<T>& w, const T* b, hipStream_t s) {
+  hipLaunchKernelGGL((cg_init_kernel<T>), dim3(w.update_blocks), dim3(kVecThreads), 0, s, w.n, b,
+                     w.r, w.x, w.p[1], w.dinv, w.partials, w.sc);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_cg_finalize(const hdg_ctx*, CgWork<T>& w, hipStream_t s) {
+  hipLaunchKernelGGL((cg_finalize_kernel<T>), dim3(w.update_blocks), dim3(kVecThreads), 0, s, w.n,
+                     w.x, w.p[0], w.p[1], w.sc);
+  return hipGetLastError();
+}
+
+template hipError_t launch_cg_update<double>(const hdg_ctx*, CgWork<double>&, hipStream_t);
+template hipError_t launch_cg_update<float>(const hdg_ctx*, CgWork<float>&, hipStream_t);
+template hipError_t launch_cg_init<double>(const hdg_ctx*, CgWork<double>&, const double*,
+                                           hipStream_t);
+template hipError_t launch_cg_init<float>(const hdg_ctx*, CgWork<float>&, const float*,
+                                          hipStream_t);
+template hipError_t launch_cg_finalize<double>(const hdg_ctx*, CgWork<double>&, hipStream_t);
+template hipError_t launch_cg_finalize<float>(const hdg_ctx*, CgWork<float>&, hipStream_t);
+
+// ------------------------------------------------------------ combine ----
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+combine_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb, T* __restrict__ y) {
+  for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * kVecThreads)
+    y[g] = qa[g] + qb[g];
+}
+
+template <typename T>
+hipError_t launch_combine(const T* qa, const T* qb, T* y, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((combine_kernel<T>), dim3(vec_blocks(n, 8192)), dim3(kVecThreads), 0, s, n,
+                     qa, qb, y);
+  return hipGetLastError();
+}
+template hipError_t launch_combine<double>(const double*, const double*, double*, int64_t,
+                                           hipStream_t);
+template hipError_t launch_combine<float>(const float*, const float*, float*, int64_t,
+                                          hipStream_t);
+
+// r = b - (qa + qb); out[0] = ||r||^2 (FP64)
+__global__ void __launch_bounds__(kVecThreads)
+residual64_kernel(int64_t n, const double* __restrict__ b, const double* __restrict__ qa,
+                  const double* __restrict__ qb, double* __restrict__ r, double* partials,
+                  unsigned* cnt, double* out) {
+  __shared__ double s_red[kVecThreads / 64];
+  double acc = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * kVecThreads) {
+    const double v = b[g] - (qa[g] + qb[g]);
+    r[g] = v;
+    acc += v * v;
+  }
+  const double bs = block_sum<kVecThreads>(acc, s_red);
+  if (threadIdx.x == 0) store_partial(partials + blockIdx.x, bs);
+  if (arrive_last(cnt, gridDim.x)) {
+    const double t = sum_partials<kVecThreads>(partials, gridDim.x, 1, 0, s_red);
+    if (threadIdx.x == 0) out[0] = t;
+  }
+}
+
+hipError_t launch_residual64(const double* b, const double* qa, const double* qb, double* r,
+                             int64_t n, double* partials, unsigned* cnt, double* out,
+                             int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(residual64_kernel, dim3(nblocks), dim3(kVecThreads), 0, s, n, b, qa, qb, r,
+                     partials, cnt, out);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kVecThreads)
+dot64_kernel(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+             double* partials, unsigned* cnt, double* out) {
+  __shared__ double s_red[kVecThreads / 64];
+  double acc = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * kVecThreads)
+    acc += a[g] * b[g];
+  const double bs = block_sum<kVecThreads>(acc, s_red);
+  if (threadIdx.x == 0) store_partial(partials + blockIdx.x, bs);
+  if (arrive_last(cnt, gridDim.x)) {
+    const double t = sum_partials<kVecThreads>(partials, gridDim.x, 1, 0, s_red);
+    if (threadIdx.x == 0) out[0] = t;
+  }
+}
+
+hipError_t launch_dot64(const double* a, const double* b, int64_t n, double* partials,
+                        unsigned* cnt, double* out, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(dot64_kernel, dim3(nblocks), dim3(kVecThreads), 0, s, n, a, b, partials, cnt,
+                     out);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- misc ----
+__global__ void cast_scale_kernel(int64_t n, const double* __restrict__ in, float* __restrict__ out,
+                                  double scale) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x)
+    out[g] = (float)(in[g] * scale);
+}
+hipError_t launch_cast_scale_64_32(const double* in, float* out, double scale, int64_t n,
+                                   hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(cast_scale_kernel, dim3(vec_blocks(n, 8192)), dim3(kVecThreads), 0, s, n, in,
+                     out, scale);
+  return hipGetLastError();
+}
+
+__global__ void axpy_32_64_kernel(int64_t n, const float* __restrict__ in, double* __restrict__ out,
+                                  double scale) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x)
+    out[g] += scale * (double)in[g];
+}
+hipError_t launch_axpy_32_64(const float* in, double* out, double scale, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(axpy_32_64_kernel, dim3(vec_blocks(n, 8192)), dim3(kVecThreads), 0, s, n, in,
+                     out, scale);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void fill_kernel(int64_t n, T* __restrict__ out, T v) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x)
+    out[g] = v;
+}
+hipError_t launch_fill64(double* out, double v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((fill_kernel<double>), dim3(vec_blocks(n, 8192)), dim3(kVecThreads), 0, s, n,
+                     out, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill32(float* out, float v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((fill_kernel<float>), dim3(vec_blocks(n, 8192)), dim3(kVecThreads), 0, s, n,
+                     out, v);
+  return hipGetLastError();
+}
+
+__global__ void recip_kernel(int64_t n, const double* __restrict__ diag, float* __restrict__ d32,
+                             double* __restrict__ d64) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const double v = 1.0 / diag[g];
+    d64[g] = v;
+    d32[g] = (float)v;
+  }
+}
+hipError_t launch_recip_64_32(const double* diag, float* dinv32, double* dinv64, int64_t n,
+                              hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(recip_kernel, dim3(vec_blocks(n, 8192)), dim3(kVecThreads), 0, s, n, diag,
+                     dinv32, dinv64);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ face transform ----
+// out_face = (A x A) (in_face [+ in2_face]) on n_p x n_p faces, A row-major
+// (out[a] = sum_b A[a*n_p+b] in[b]) applied along both tangential axes.
+template <typename T, int NP>
+__global__ void __launch_bounds__(320)
+face_transform_kernel(const T* __restrict__ A, const T* __restrict__ in, const T* __restrict__ in2,
+                      T* __restrict__ out, int64_t n_faces) {
+  constexpr int NF = NP * NP;
+  constexpr int FPB = (256 / NF) > 0 ? 256 / NF : 1;
+  __shared__ T s_in[FPB][NF];
+  __shared__ T s_t[FPB][NF];
+  const int slot = threadIdx.x / NF;
+  const int lt = threadIdx.x - slot * NF;
+  const int64_t f = (int64_t)blockIdx.x * FPB + slot;
+  const bool active = slot < FPB && f < n_faces;
+  if (active) {
+    T v = in[f * NF + lt];
+    if (in2) v += in2[f * NF + lt];
+    s_in[slot][lt] = v;
+  }
+  __syncthreads();
+  const int qa = lt % NP, qb = lt / NP;
+  if (active) {
+    // along the first tangential axis: t[a, c] = sum_b A[a,b] in[b, c]
+    T acc = 0;
+#pragma unroll
+    for (int b = 0; b < NP; ++b) acc += A[qa * NP + b] * s_in[slot][b + NP * qb];
+    s_t[slot][lt] = acc;
+  }
+  __syncthreads();
+  if (active) {
+    // along the second tangential axis: out[a, c] = sum_d A[c,d] t[a, d]
+    T acc = 0;
+#pragma unroll
+    for (int dd = 0; dd < NP; ++dd) acc += A[qb * NP + dd] * s_t[slot][qa + NP * dd];
+    out[f * NF + lt] = acc;
+  }
+}
+
+template <typename T, int NP>
+static hipError_t launch_ft_np(const T* A, const T* in, const T* in2, T* out, int64_t n_faces,
+                               hipStream_t s) {
+  constexpr int NF = NP * NP;
+  constexpr int FPB = (256 / NF) > 0 ? 256 / NF : 1;
+  const int64_t nb = (n_faces + FPB - 1) / FPB;
+  if (nb == 0) return hipSuccess;
+  constexpr int NTH = (FPB * NF + 63) / 64 * 64;
+  hipLaunchKernelGGL((face_transform_kernel<T, NP>), dim3((unsigned)nb), dim3(NTH), 0, s, A, in,
+                     in2, out, n_faces);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_face_transform(int np, const T* A, const T* in, const T* in2, T* out,
+                                 int64_t n_faces, hipStream_t s) {
+  switch (np) {
+#define HDG_CASE(N) \
+  case N: return launch_ft_np<T, N>(A, in, in2, out, n_faces, s);
+    HDG_CASE(2) HDG_CASE(3) HDG_CASE(4) HDG_CASE(5) HDG_CASE(6) HDG_CASE(7) HDG_CASE(8)
+    HDG_CASE(9) HDG_CASE(10) HDG_CASE(11) HDG_CASE(12) HDG_CASE(13) HDG_CASE(14)
+    HDG_CASE(15) HDG_CASE(16) HDG_CASE(17)
+#undef HDG_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_face_transform<double>(int, const double*, const double*, const double*,
+                                                  double*, int64_t, hipStream_t);
+template hipError_t launch_face_transform<float>(int, const float*, const float*, const float*,
+                                                 float*, int64_t, hipStream_t);
+
+// ------------------------------------------------------------ diagonal ----
+// diag(K^) at a free face node: sum over the two adjacent elements of
+//   d_a H - d_a^2 sum_q BS[q,s]^2 / (lambda d0 + d_a Lam[q] + d_b Lam[qb] + d_c Lam[qc])
+// with s = 1 for the element below the face and s = 0 for the one above
+// (paper: equation (hdg_op_east_east_transformed) and the diagonal
+// preconditioner that follows it).
+__global__ void __launch_bounds__(256)
+diag_kernel(const MeshDev m, const ElemTab<double> tab, int np, double* __restrict__ diag) {
+  const int nf = np * np;
+  const int64_t n = m.n_free_faces * nf;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t fid = g / nf;
+    const int lt = (int)(g - fid * nf);
+    const int qb = lt % np, qc = lt / np;
+    int a, pl, ti, tj, tk;   // axis, plane, element indices (one replaced by plane)
+    if (fid < m.foff[1]) {
+      a = 0;
+      int64_t loc = fid - m.foff[0];
+      pl = (int)(loc % (m.n1 - 1)) + 1;
+      loc /= (m.n1 - 1);
+      tj = (int)(loc % m.n2);
+      tk = (int)(loc / m.n2);
+      ti = 0;
+    } else if (fid < m.foff[2]) {
+      a = 1;
+      int64_t loc = fid - m.foff[1];
+      ti = (int)(loc % m.n1);
+      loc /= m.n1;
+      pl = (int)(loc % (m.n2 - 1)) + 1;
+      tk = (int)(loc / (m.n2 - 1));
+      tj = 0;
+    } else {
+      a = 2;
+      int64_t loc = fid - m.foff[2];
+      ti = (int)(loc % m.n1);
+      loc /= m.n1;
+      tj = (int)(loc % m.n2);
+      pl = (int)(loc / m.n2) + 1;
+      tk = 0;
+    }
+    double acc = 0.0;
+    for (int side = 0; side < 2; ++side) {
+      // side 0: element below (its high face, s = 1); side 1: element above (s = 0)
+      const int ei = (a == 0) ? pl - 1 + side : ti;
+      const int ej = (a == 1) ? pl - 1 + side : tj;
+      const int ek = (a == 2) ? pl - 1 + side : tk;
+      const int64_t e = ei + (int64_t)m.n1 * (ej + (int64_t)m.n2 * ek);
+      const double h1 = m.h1[ei], h2 = m.h2[ej], h3 = m.h3[ek];
+      const double d0 = h1 * h2 * h3 * 0.125;
+      const double dd[3] = {d0 * 4.0 / (h1 * h1), d0 * 4.0 / (h2 * h2), d0 * 4.0 / (h3 * h3)};
+      const int b = (a == 0) ? 1 : 0;
+      const int c = (a == 2) ? 1 : 2;
+      const double base = d0 * m.lam[e] + dd[b] * tab.lam[qb] + dd[c] * tab.lam[qc];
+      const double* bs = (side == 0) ? tab.bs1 : tab.bs0;
+      double sum = 0.0;
+      for (int q = 0; q < np; ++q) sum += bs[q] * bs[q] / (base + dd[a] * tab.lam[q]);
+      acc += dd[a] * tab.H - dd[a] * dd[a] * sum;
+    }
+    diag[g] = acc;
+  }
+}
+
+hipError_t launch_diag(const hdg_ctx* c, double* diag, hipStream_t s) {
+  const int64_t n = c->n_free;
+  if (n == 0) return hipSuccess;
+  int64_t nb = (n + 255) / 256;
+  if (nb > 65535) nb = 65535;
+  hipLaunchKernelGGL(diag_kernel, dim3((unsigned)nb), dim3(256), 0, s, c->mesh, c->et64, c->np,
+                     diag);
+  return hipGetLastError();
+}
+
+}  // namespace hdg

@@ -1,0 +1,329 @@
+"""ctypes binding of the C ABI in ``include/hdg.h``.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libhdg.so`` built next to this file.  PyTorch provides device
+memory (CUDA/HIP tensors) and the stream; there is no CPU fallback, and a
+missing library raises at first use.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdg.so")
+
+HDG_OK = 0
+STATUS_NAMES = {0: "HDG_OK", -1: "HDG_EINVAL", -2: "HDG_EHIP", -3: "HDG_ENOMEM",
+                -4: "HDG_ENOCONV", -5: "HDG_EUNSUPPORTED"}
+F64, F32 = 0, 1
+NODAL, EIGEN = 0, 1
+TO_EIGEN_UNKNOWN, TO_EIGEN_RESIDUAL, TO_NODAL_UNKNOWN, TO_NODAL_RESIDUAL = 0, 1, 2, 3
+
+# every symbol include/hdg.h declares
+EXPORTS = (
+    "hdg_default_opts", "hdg_create", "hdg_destroy", "hdg_last_error", "hdg_sizes",
+    "hdg_set_lambda", "hdg_tables", "hdg_coords", "hdg_apply", "hdg_face_transform",
+    "hdg_rhs", "hdg_solve", "hdg_solve_forcing", "hdg_reconstruct", "hdg_adjoint",
+    "hdg_diagonal", "hdg_time_kernel",
+)
+
+
+class HdgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("maxit", ctypes.c_int), ("precond", ctypes.c_int),
+                ("mixed", ctypes.c_int), ("inner_rtol", ctypes.c_double),
+                ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int),
+                ("rel_res", ctypes.c_double), ("rhs_norm", ctypes.c_double),
+                ("t_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhdg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -m paper_2007_11891_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "hdg_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
+        "hdg_create": (ctypes.c_int, [ip, dp, dp, dp, ctypes.c_int, ctypes.c_double, dp,
+                                      ctypes.c_double, vp, ctypes.POINTER(vp)]),
+        "hdg_destroy": (ctypes.c_int, [vp]),
+        "hdg_last_error": (ctypes.c_char_p, []),
+        "hdg_sizes": (ctypes.c_int, [vp, i64p, i64p, i64p]),
+        "hdg_set_lambda": (ctypes.c_int, [vp, vp]),
+        "hdg_tables": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp, dp, dp]),
+        "hdg_coords": (ctypes.c_int, [vp, vp, vp]),
+        "hdg_apply": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, ctypes.c_int]),
+        "hdg_face_transform": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int64]),
+        "hdg_rhs": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int]),
+        "hdg_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                     ctypes.POINTER(SolveInfo)]),
+        "hdg_solve_forcing": (ctypes.c_int, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                             ctypes.POINTER(SolveInfo)]),
+        "hdg_reconstruct": (ctypes.c_int, [vp, vp, vp, vp]),
+        "hdg_adjoint": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                       ctypes.POINTER(SolveInfo)]),
+        "hdg_diagonal": (ctypes.c_int, [vp, vp]),
+        "hdg_time_kernel": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int, dp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, allow_noconv: bool = False):
+    if status == HDG_OK or (allow_noconv and status == -4):
+        return status
+    msg = load_library().hdg_last_error()
+    raise HdgError(status, msg.decode() if msg else "")
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    load_library().hdg_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def tables(p: int, tau: float) -> dict:
+    """1D tables of the library (host-only call): GLL x, w, D, S, Lambda, B_S, H."""
+    lib = load_library()
+    n = p + 1
+    arrs = {k: np.zeros(s) for k, s in (("x", n), ("w", n), ("D", n * n), ("S", n * n),
+                                          ("Lam", n), ("BS", 2 * n), ("H", 1))}
+    ptr = {k: v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for k, v in arrs.items()}
+    _check(lib.hdg_tables(p, float(tau), ptr["x"], ptr["w"], ptr["D"], ptr["S"], ptr["Lam"],
+                          ptr["BS"], ptr["H"]))
+    arrs["D"] = arrs["D"].reshape(n, n)
+    arrs["S"] = arrs["S"].reshape(n, n)
+    arrs["BS"] = arrs["BS"].reshape(n, 2)
+    arrs["H"] = float(arrs["H"][0])
+    return arrs
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t, n: int, dtype, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Sizes:
+    n_free: int
+    n_all: int
+    n_vol: int
+
+
+class HdgContext:
+    """One Cartesian mesh / degree / lambda field on the current GPU."""
+
+    def __init__(self, n: Sequence[int], widths: Sequence[np.ndarray], p: int, tau: float,
+                 lam, device=None):
+        torch = _torch()
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU")
+        self._lib = lib
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.n = tuple(int(v) for v in n)
+        self.p = int(p)
+        self.n_elem = self.n[0] * self.n[1] * self.n[2]
+        self._widths = [np.ascontiguousarray(w, dtype=np.float64) for w in widths]
+        nn = (ctypes.c_int * 3)(*self.n)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lam_arr = np.asarray(lam, dtype=np.float64)
+        lam_ptr, lam_const = None, 0.0
+        if lam_arr.ndim == 0:
+            lam_const = float(lam_arr)
+        else:
+            lam_arr = np.ascontiguousarray(lam_arr)
+            if lam_arr.size != self.n_elem:
+                raise ValueError("lambda must have one value per element")
+            lam_ptr = lam_arr.ctypes.data_as(dp)
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device)
+            self._stream = stream
+            h = ctypes.c_void_p()
+            _check(lib.hdg_create(nn, *(w.ctypes.data_as(dp) for w in self._widths), self.p,
+                                  float(tau), lam_ptr, lam_const,
+                                  ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        nf, na, nv = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.hdg_sizes(self._h, ctypes.byref(nf), ctypes.byref(na), ctypes.byref(nv)))
+        self.sizes = Sizes(nf.value, na.value, nv.value)
+
+    # -- lifetime -------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hdg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- helpers --------------------------------------------------------------
+    def _empty(self, n, dtype=None):
+        torch = _torch()
+        return torch.empty(n, dtype=dtype or torch.float64, device=self.device)
+
+    def zeros_trace(self):
+        return _torch().zeros(self.sizes.n_all, dtype=_torch().float64, device=self.device)
+
+    # -- entry points -----------------------------------------------------------
+    def coords(self):
+        v = self._empty(self.sizes.n_vol * 3)
+        t = self._empty(self.sizes.n_all * 3)
+        _check(self._lib.hdg_coords(self._h, ctypes.c_void_p(v.data_ptr()),
+                                    ctypes.c_void_p(t.data_ptr())))
+        return v.view(-1, 3), t.view(-1, 3)
+
+    def set_lambda(self, lam):
+        torch = _torch()
+        _check(self._lib.hdg_set_lambda(self._h, _dptr(lam, self.n_elem, torch.float64, "lambda")))
+
+    def apply(self, x, y=None, basis: str = "eigen"):
+        torch = _torch()
+        dt = x.dtype
+        if dt not in (torch.float64, torch.float32):
+            raise TypeError("x must be float64 or float32")
+        if y is None:
+            y = self._empty(self.sizes.n_free, dt)
+        n = self.sizes.n_free
+        _check(self._lib.hdg_apply(self._h, _dptr(x, n, dt, "x"), _dptr(y, n, dt, "y"),
+                                   F64 if dt == torch.float64 else F32,
+                                   EIGEN if basis == "eigen" else NODAL))
+        return y
+
+    def face_transform(self, kind: int, x, n_faces: int, out=None):
+        torch = _torch()
+        m = n_faces * (self.p + 1) ** 2
+        if out is None:
+            out = self._empty(m)
+        _check(self._lib.hdg_face_transform(self._h, int(kind), _dptr(x, m, torch.float64, "in"),
+                                            _dptr(out, m, torch.float64, "out"), int(n_faces)))
+        return out
+
+    def rhs(self, f, trace=None, basis: str = "nodal"):
+        torch = _torch()
+        out = self._empty(self.sizes.n_free)
+        tp = None if trace is None else _dptr(trace, self.sizes.n_all, torch.float64, "trace")
+        _check(self._lib.hdg_rhs(self._h, _dptr(f, self.sizes.n_vol, torch.float64, "f"), tp,
+                                 _dptr(out, self.sizes.n_free, torch.float64, "F"),
+                                 EIGEN if basis == "eigen" else NODAL))
+        return out
+
+    def solve(self, F_free, opts: Optional[SolveOpts] = None, u_free=None):
+        torch = _torch()
+        if u_free is None:
+            u_free = self._empty(self.sizes.n_free)
+        info = SolveInfo()
+        o = opts or default_opts()
+        st = self._lib.hdg_solve(self._h, _dptr(F_free, self.sizes.n_free, torch.float64, "F"),
+                                 _dptr(u_free, self.sizes.n_free, torch.float64, "u"),
+                                 ctypes.byref(o), ctypes.byref(info))
+        _check(st)
+        return u_free, info.as_dict()
+
+    def solve_forcing(self, f, trace, u_vol=None, want_volume: bool = True,
+                      opts: Optional[SolveOpts] = None, allow_noconv: bool = False):
+        """Solve with forcing f; trace: in = Dirichlet tail, out = nodal solution."""
+        torch = _torch()
+        if want_volume and u_vol is None:
+            u_vol = self._empty(self.sizes.n_vol)
+        info = SolveInfo()
+        o = opts or default_opts()
+        st = self._lib.hdg_solve_forcing(
+            self._h, _dptr(f, self.sizes.n_vol, torch.float64, "f"),
+            _dptr(trace, self.sizes.n_all, torch.float64, "trace"),
+            _dptr(u_vol, self.sizes.n_vol, torch.float64, "u_vol") if want_volume else None,
+            ctypes.byref(o), ctypes.byref(info))
+        _check(st, allow_noconv=allow_noconv)
+        return trace, u_vol, info.as_dict()
+
+    def reconstruct(self, f, trace, u_vol=None):
+        torch = _torch()
+        if u_vol is None:
+            u_vol = self._empty(self.sizes.n_vol)
+        _check(self._lib.hdg_reconstruct(self._h, _dptr(f, self.sizes.n_vol, torch.float64, "f"),
+                                         _dptr(trace, self.sizes.n_all, torch.float64, "trace"),
+                                         _dptr(u_vol, self.sizes.n_vol, torch.float64, "u_vol")))
+        return u_vol
+
+    def adjoint(self, f, trace, dJdu, opts: Optional[SolveOpts] = None):
+        torch = _torch()
+        dl = self._empty(self.n_elem)
+        df = self._empty(self.sizes.n_vol)
+        info = SolveInfo()
+        o = opts or default_opts()
+        _check(self._lib.hdg_adjoint(
+            self._h, _dptr(f, self.sizes.n_vol, torch.float64, "f"),
+            _dptr(trace, self.sizes.n_all, torch.float64, "trace"),
+            _dptr(dJdu, self.sizes.n_vol, torch.float64, "dJdu"),
+            _dptr(dl, self.n_elem, torch.float64, "dJdlambda"),
+            _dptr(df, self.sizes.n_vol, torch.float64, "dJdf"), ctypes.byref(o), ctypes.byref(info)))
+        return dl, df, info.as_dict()
+
+    def diagonal(self):
+        torch = _torch()
+        d = self._empty(self.sizes.n_free)
+        _check(self._lib.hdg_diagonal(self._h, _dptr(d, self.sizes.n_free, torch.float64, "diag")))
+        return d
+
+    def time_kernel(self, which: int, x, reps: int = 100) -> float:
+        ms = ctypes.c_double()
+        _check(self._lib.hdg_time_kernel(self._h, int(which), ctypes.c_void_p(x.data_ptr()),
+                                         None, int(reps), ctypes.byref(ms)))
+        return ms.value

@@ -1,0 +1,64 @@
+"""Shared helpers of the GPU tests: building matching oracle / library
+problems from one seeded description, and error norms."""
+import numpy as np
+
+import oracle
+import workloads as W
+
+
+def rel_err(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+def max_rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def perturbed_mesh(n, seed):
+    rng = np.random.default_rng(seed)
+    return [W.perturbed_widths(v, rng) for v in n]
+
+
+def gpu_ctx(n, widths, p, tau, lam):
+    import paper_2007_11891_amd as pkg
+    return pkg.HdgContext(n, widths, p, tau, lam)
+
+
+def to_dev(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+def to_host(t):
+    return t.detach().cpu().numpy()
+
+
+def canonical_oracle_S(std):
+    """S of the generalized eigenproblem with each column's first entry of
+    magnitude > 1e-8 made positive and eigenvalues ascending."""
+    from oracle.fastdiag import eigen_1d
+    S, lam = eigen_1d(std)
+    order = np.argsort(lam)
+    S, lam = S[:, order], lam[order]
+    for c in range(S.shape[1]):
+        col = S[:, c]
+        idx = np.nonzero(np.abs(col) > 1e-8)[0][0]
+        if col[idx] < 0:
+            S[:, c] = -col
+    return S, lam
+
+
+def face_T(S, layout, n_faces):
+    """Block-diagonal per-face S x S acting on n_faces consecutive faces."""
+    npn = S.shape[0]
+    blk = np.kron(S, S)   # node q_b + n_p q_c: S acts on both axes
+    T = np.zeros((n_faces * npn * npn, n_faces * npn * npn))
+    for f in range(n_faces):
+        sl = slice(f * npn * npn, (f + 1) * npn * npn)
+        T[sl, sl] = blk
+    return T

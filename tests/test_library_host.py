@@ -1,0 +1,94 @@
+"""Host-side checks of the HIP library (no GPU needed).
+
+The library must load and export every symbol ``include/hdg.h`` declares; its
+host-only 1D setup (GLL points, derivative matrix, generalized
+eigendecomposition, B_S) is compared with the oracle's independent
+construction and with the invariants of the paper's equations.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.basis import standard_matrices
+from oracle.fastdiag import b_s
+import paper_2007_11891_amd as pkg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("libhdg.so not built (python -m paper_2007_11891_amd.build)")
+    return pkg.load_library()
+
+
+def test_header_declares_exactly_the_exported_names():
+    with open(os.path.join(ROOT, "include", "hdg.h")) as fh:
+        text = fh.read()
+    declared = set(re.findall(r"\b(hdg_[a-z_0-9]+)\s*\(", text))
+    assert declared == set(pkg.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in pkg.EXPORTS:
+        assert hasattr(lib, name), name
+
+
+def test_default_options():
+    o = pkg.default_opts()
+    assert o.rtol == 1e-10 and o.precond == 1 and o.mixed == 0 and o.check_every >= 1
+
+
+def test_create_rejects_invalid_arguments_without_gpu_work():
+    lib = _lib()
+    n = (ctypes.c_int * 3)(2, 2, 2)
+    h = (ctypes.c_double * 2)(0.5, 0.5)
+    bad = (ctypes.c_double * 2)(0.5, -0.5)
+    out = ctypes.c_void_p()
+    dp = ctypes.POINTER(ctypes.c_double)
+    hp = ctypes.cast(h, dp)
+    cases = [
+        (n, hp, hp, hp, 0, 1.0, None, 1.0),            # p = 0
+        (n, hp, hp, hp, 17, 1.0, None, 1.0),           # p = 17
+        (n, hp, hp, hp, 3, 0.0, None, 1.0),            # tau = 0
+        (n, hp, hp, hp, 3, 1.0, None, -1.0),           # lambda < 0
+        (n, hp, ctypes.cast(bad, dp), hp, 3, 1.0, None, 1.0),   # negative width
+        ((ctypes.c_int * 3)(0, 2, 2), hp, hp, hp, 3, 1.0, None, 1.0),
+    ]
+    for args in cases:
+        st = lib.hdg_create(*args, None, ctypes.byref(out))
+        assert st == -1, args
+        assert out.value is None
+        assert lib.hdg_last_error()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 7, 10, 16])
+def test_library_tables_match_oracle(p):
+    _lib()
+    tau = 1.3
+    t = pkg.tables(p, tau)
+    s = standard_matrices(p, tau)
+    assert np.abs(t["x"] - s["x"]).max() < 1e-15
+    assert np.abs(t["w"] - s["w"]).max() < 1e-15
+    assert np.abs(t["D"] - s["D"]).max() < 1e-12 * max(1.0, np.abs(s["D"]).max())
+    S, lam = t["S"], t["Lam"]
+    n = p + 1
+    # generalized eigendecomposition (equation generalized_eigenvalue_decomposition)
+    assert np.abs(S.T @ s["M"] @ S - np.eye(n)).max() < 1e-13
+    assert np.abs(S.T @ s["L"] @ S - np.diag(lam)).max() < 1e-13 * np.abs(lam).max()
+    assert np.all(np.diff(lam) >= 0)
+    # B_S of equation (hdgbs) with the library's S
+    assert np.abs(t["BS"] - b_s(s, S)).max() < 1e-12 * max(1.0, np.abs(t["BS"]).max())
+    H = s["G"] + s["C"].T @ np.linalg.inv(s["M"]) @ s["C"]
+    assert np.abs(H - t["H"] * np.eye(2)).max() < 1e-13 * abs(t["H"])
+
+
+def test_tables_reject_bad_degree():
+    _lib()
+    with pytest.raises(pkg.HdgError):
+        pkg.tables(0, 1.0)
