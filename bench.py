@@ -1,0 +1,204 @@
+"""Benchmark of the condensed-HDG hot path on one MI355X.
+
+Workload (default): Cartesian 16^3 mesh of the unit cube with per-axis widths
+perturbed by U[0.7, 1.3] and renormalised (seed 2), p = 7, lambda = 10,
+tau = 1, forcing f ~ U[-1, 1] i.i.d. per node, homogeneous Dirichlet data.
+
+One step = the whole hot path on that input, all data resident on the GPU:
+right-hand side with Dirichlet lift, transform to the eigen-face basis,
+Jacobi-preconditioned CG on the transformed condensed operator to a relative
+residual of 1e-10 (one operator application per iteration), transform back,
+and recovery of u in every element.
+
+value = N_tr(free) x (operator applications in the step) / step time, i.e.
+trace-DOF/s of the condensed operator as the CG drives it.  The JSON line also
+carries the isolated apply rate, FP64 and mixed-precision time-to-1e-10, the
+roofline of the dominant kernel (the fused CG apply) timed with HIP events on
+its own stream, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(prob, budget_s: float):
+    """Oracle apply (dense Schur complement per element, then K_e x_e) on a
+    bounded sample of elements of the same workload, scaled to trace-DOF/s."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    o = oracle.HdgOracle(prob.n, prob.widths, prob.p, prob.tau, prob.lam, cache_limit=1)
+    rng = np.random.default_rng(0)
+    x = rng.uniform(-1, 1, o.layout.n_all)
+    x[o.layout.n_free:] = 0.0
+    order = rng.permutation(o.layout.n_elem)
+    t0 = time.perf_counter()
+    m = 0
+    for e in order:
+        mp = o.tmap(int(e))
+        _ = o.K_e(int(e)) @ x[mp]
+        m += 1
+        if time.perf_counter() - t0 > budget_s and m >= 2:
+            break
+    dt = time.perf_counter() - t0
+    per_apply_s = dt / m * o.layout.n_elem
+    return {"value": o.layout.n_free / per_apply_s, "unit": "trace-DOF/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{m} of {o.layout.n_elem} elements (dense element Schur complement + "
+                      f"matvec), {dt:.1f} s; scaled to one full apply = {per_apply_s:.0f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=16)
+    ap.add_argument("--p", type=int, default=7)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              f"path is a design note, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    import paper_2007_11891_amd as pkg
+
+    torch.cuda.set_device(0)
+    prob = W.perturbed(n=args.n, p=args.p, lam=10.0, seed=2)
+    log(f"[bench] workload perturbed n={prob.n} p={prob.p} lam=10 tau=1")
+    ctx = pkg.HdgContext(prob.n, prob.widths, prob.p, prob.tau, prob.lam)
+    nf, na, nv = ctx.sizes.n_free, ctx.sizes.n_all, ctx.sizes.n_vol
+    dev = torch.device("cuda", 0)
+    f = torch.as_tensor(prob.f_values, device=dev)
+    trace = torch.zeros(na, dtype=torch.float64, device=dev)
+    u_vol = torch.empty(nv, dtype=torch.float64, device=dev)
+    opts = pkg.default_opts(rtol=1e-10)
+
+    def step():
+        trace.zero_()
+        return ctx.solve_forcing(f, trace, u_vol=u_vol, opts=opts)
+
+    for _ in range(args.warmup):
+        _, _, info = step()
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, info = step()
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    iters = infos[-1]["iters"]
+    applies = statistics.mean(i["iters"] for i in infos)
+    value = nf * applies / (elapsed / args.steps)
+    log(f"[bench] step {ms_per_step:.3f} ms, CG iters {iters}, rel_res {infos[-1]['rel_res']:.2e}")
+
+    # ---- isolated kernels, HIP events on the context stream ----------------
+    x64 = torch.as_tensor(W.random_trace(nf, 1), device=dev)
+    x32 = x64.float()
+    reps = 200
+    t_apply64 = ctx.time_kernel(0, x64, reps)
+    t_apply32 = ctx.time_kernel(1, x32, reps)
+    t_cg_apply = ctx.time_kernel(4, x64, reps)
+    t_cg_update = ctx.time_kernel(5, x64, reps)
+    t_cg_iter = ctx.time_kernel(2, x64, reps)
+    t_cg_iter32 = ctx.time_kernel(3, x32, reps)
+    log(f"[bench] apply64 {t_apply64*1e3:.2f} us apply32 {t_apply32*1e3:.2f} us "
+        f"cg_apply {t_cg_apply*1e3:.2f} us cg_update {t_cg_update*1e3:.2f} us "
+        f"cg_iter {t_cg_iter*1e3:.2f} us cg_iter32 {t_cg_iter32*1e3:.2f} us")
+    cg_apply_bytes = 56 * nf        # x r/w, r, D^-1, p_old read; p, q written once
+    achieved = cg_apply_bytes / (t_cg_apply * 1e-3) / 1e9
+    roofline = {"kernel": "elem_apply_kernel<double,8,1> (fused CG apply)", "bound": "hbm",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": cg_apply_bytes, "avg_launch_us": round(t_cg_apply * 1e3, 3)}
+    apply_bytes = 16 * nf
+    apply_only = {"trace_dof_per_s_fp64": nf / (t_apply64 * 1e-3),
+                  "trace_dof_per_s_fp32": nf / (t_apply32 * 1e-3),
+                  "avg_launch_us_fp64": round(t_apply64 * 1e3, 3),
+                  "avg_launch_us_fp32": round(t_apply32 * 1e3, 3),
+                  "algorithmic_GBs_fp64": round(apply_bytes / (t_apply64 * 1e-3) / 1e9, 1),
+                  "algorithmic_GBs_fp32": round(apply_bytes / 2 / (t_apply32 * 1e-3) / 1e9, 1)}
+
+    # ---- time-to-1e-10: FP64 vs mixed precision ------------------------------
+    mixed = None
+    if not args.no_mixed:
+        def solve_time(o, reps=3):
+            ts, last = [], None
+            for _ in range(reps):
+                trace.zero_()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, _, inf = ctx.solve_forcing(f, trace, want_volume=False, opts=o)
+                torch.cuda.synchronize()
+                ts.append(1e3 * (time.perf_counter() - t))
+                last = inf
+            return statistics.median(ts), last, trace.clone()
+        t64, i64, u64 = solve_time(pkg.default_opts(rtol=1e-10))
+        tmx, imx, umx = solve_time(pkg.default_opts(rtol=1e-10, mixed=1))
+        diff = float(torch.linalg.norm(umx - u64) / torch.linalg.norm(u64))
+        mixed = {"fp64_ms": round(t64, 3), "mixed_ms": round(tmx, 3),
+                 "speedup": round(t64 / tmx, 3), "fp64_iters": i64["iters"],
+                 "mixed_inner_iters": imx["iters"], "mixed_outer": imx["outer_iters"],
+                 "fp64_rel_res": i64["rel_res"], "mixed_rel_res": imx["rel_res"],
+                 "mixed_vs_fp64_rel_diff": diff}
+        log(f"[bench] time-to-1e-10 fp64 {t64:.2f} ms ({i64['iters']} it), mixed {tmx:.2f} ms "
+            f"({imx['iters']} inner, {imx['outer_iters']} outer), diff {diff:.1e}")
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle) ...")
+        cpu = cpu_baseline(prob, args.cpu_budget)
+        log(f"[bench] cpu baseline {cpu['value']:.3e} trace-DOF/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": "trace-DOF/s of condensed HDG apply; time-to-1e-10 CG, mixed vs FP64",
+        "value": value, "unit": "trace-DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"perturbed Cartesian {prob.n[0]}x{prob.n[1]}x{prob.n[2]}, "
+                               f"p={prob.p}, lambda=10, tau=1, f~U[-1,1], g_D=0; step = RHS + "
+                               f"Jacobi-PCG to 1e-10 + recovery",
+                   "n_elem": prob.n_elem, "p": prob.p, "n_trace_free": nf, "n_trace_all": na,
+                   "n_vol": nv, "cg_iters": iters, "rel_res": infos[-1]["rel_res"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "apply_only": apply_only,
+        "cg_iteration_us": {"fp64": round(t_cg_iter * 1e3, 3), "fp32": round(t_cg_iter32 * 1e3, 3),
+                            "fused_apply_fp64": round(t_cg_apply * 1e3, 3),
+                            "update_fp64": round(t_cg_update * 1e3, 3)},
+        "mixed_precision": mixed,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -54,40 +54,57 @@ __device__ inline double block_sum(double v, double* sbuf) {
   }
 }
 
-__device__ inline void store_partial(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline double load_partial(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Every block calls this once after thread 0 stored its partial(s); returns
-// true in all threads of the block that arrives last.  That block resets the
-// counter for the next launch.
-__device__ inline bool arrive_last(unsigned* cnt, unsigned nblocks) {
-  __shared__ int s_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(cnt, 1u);
-    s_last = (prev == nblocks - 1) ? 1 : 0;
-    if (s_last) {
-      __threadfence();
-      __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Deterministic sum of nparts partials written by an earlier launch, with
+// stride `stride` and offset `off`, by a whole block of NT threads.  Every
+// block that calls it gets the same value (same order, same tree); the result
+// is broadcast to all threads through sbuf.
+template <int NT>
+__device__ inline double sum_partials(const double* __restrict__ parts, int nparts, int stride,
+                                      int off, double* sbuf) {
+  // up to 4 loads per thread in flight, then a fixed-order combine
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i0 = threadIdx.x; i0 < nparts; i0 += 4 * NT) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * NT;
+      if (i < nparts) v[u] += parts[(size_t)i * stride + off];
     }
   }
+  double t = block_sum<NT>((v[0] + v[1]) + (v[2] + v[3]), sbuf);
+  __shared__ double s_bcast;
+  if (threadIdx.x == 0) s_bcast = t;
   __syncthreads();
-  return s_last != 0;
+  t = s_bcast;
+  __syncthreads();
+  return t;
 }
 
-// Deterministic sum of nparts partials with stride `stride` (offset `off`),
-// performed by the whole (last) block of NT threads; valid in thread 0.
+// Two partial arrays summed in one pass (same order as two sum_partials).
 template <int NT>
-__device__ inline double sum_partials(const double* parts, int nparts, int stride, int off,
-                                      double* sbuf) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += NT) v += load_partial(parts + (size_t)i * stride + off);
-  return block_sum<NT>(v, sbuf);
+__device__ inline void sum_partials2(const double* __restrict__ pa, const double* __restrict__ pb,
+                                     int nparts, double* sbuf, double* ra, double* rb) {
+  double va[4] = {0.0, 0.0, 0.0, 0.0}, vb[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i0 = threadIdx.x; i0 < nparts; i0 += 4 * NT) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * NT;
+      if (i < nparts) {
+        va[u] += pa[i];
+        vb[u] += pb[i];
+      }
+    }
+  }
+  double ta = block_sum<NT>((va[0] + va[1]) + (va[2] + va[3]), sbuf);
+  double tb = block_sum<NT>((vb[0] + vb[1]) + (vb[2] + vb[3]), sbuf);
+  __shared__ double s_bc2[2];
+  if (threadIdx.x == 0) {
+    s_bc2[0] = ta;
+    s_bc2[1] = tb;
+  }
+  __syncthreads();
+  *ra = s_bc2[0];
+  *rb = s_bc2[1];
+  __syncthreads();
 }
 
 // Face id of the face of element (i,j,k) normal to axis a on side s (0 low,

@@ -32,7 +32,9 @@ struct ApplyIO {
   T* p0;
   T* p1;
   T* x;
-  double* partials;
+  double* partials;  // pq[2][pmax] | rz[2][pmax] | rr[2][pmax]
+  int pmax;
+  int n_upd;         // number of update-kernel partials
   CgScalars* sc;
 };
 
@@ -64,15 +66,42 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io) {
 
   T beta = 0, alpha_x = 0;
   int iter = 0;
+  bool finish = false;     // converged / capped: only the last x update remains
   if constexpr (MODE == 1) {
-    if (io.sc->done) return;               // uniform over the grid
-    beta = (T)io.sc->beta;
-    alpha_x = (T)io.sc->alpha_x;
-    iter = io.sc->iter;
+    // scalar reads of slot A (a struct copy here costs a large serialisation)
+    if (io.sc->A.done) return;             // uniform over the grid
+    iter = io.sc->A.iter;
+    const double rho_prev = io.sc->A.rho;
+    const double rtol2 = io.sc->A.rtol2;
+    const int maxit = io.sc->A.maxit;
+    double rr_stop = io.sc->A.rr_stop;
+    alpha_x = (T)io.sc->A.alpha;
+    const int k2 = iter & 1;
+    const double* prz = io.partials + (size_t)(2 + k2) * io.pmax;
+    const double* prr = io.partials + (size_t)(4 + k2) * io.pmax;
+    double rho, rr;
+    sum_partials2<NT>(prz, prr, io.n_upd, s_red, &rho, &rr);
+    if (iter == 0) rr_stop = rtol2 * rr;
+    const double b = (iter == 0) ? 0.0 : rho / rho_prev;
+    int done = 0;
+    if (!isfinite(rr) || !isfinite(b)) done = 3;
+    else if (rr <= rr_stop) done = 1;
+    else if (iter >= maxit) done = 2;
+    finish = done != 0;
+    beta = (T)b;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      io.sc->B.rho = rho;
+      io.sc->B.rr = rr;
+      io.sc->B.rr_stop = rr_stop;
+      io.sc->B.iter = iter;
+      io.sc->B.maxit = maxit;
+      io.sc->B.rtol2 = rtol2;
+      io.sc->B.done = done;
+    }
   }
+  // search directions ping-pong: iteration k reads p_{k-1} and writes p_k
   const T* p_in = (MODE == 1) ? ((iter & 1) ? io.p0 : io.p1) : nullptr;
   T* p_out = (MODE == 1) ? ((iter & 1) ? io.p1 : io.p0) : nullptr;
-
   const int tid = threadIdx.x;
   const int slot = tid / NF;
   const int lt = tid - slot * NF;
@@ -106,10 +135,10 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io) {
             v = io.x_free[g];
           } else {
             const T pin = p_in[g];
-            v = io.dinv[g] * io.r[g] + beta * pin;
-            if (s == 1) {             // the element below the face owns it
-              p_out[g] = v;
-              io.x[g] += alpha_x * pin;
+            if (s == 1) io.x[g] += alpha_x * pin;   // the element below the face owns it
+            if (!finish) {
+              v = io.dinv[g] * io.r[g] + beta * pin;
+              if (s == 1) p_out[g] = v;
             }
           }
         } else if (MODE == 0 && io.x_bdry != nullptr) {
@@ -118,6 +147,9 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io) {
         xf[2 * a + s] = v;
         s_face[slot][2 * a + s][lt] = v;
       }
+  }
+  if constexpr (MODE == 1) {
+    if (finish) return;                    // uniform: every block took the same decision
   }
   __syncthreads();
 
@@ -192,23 +224,10 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io) {
   }
 
   if constexpr (MODE == 1) {
-    // p.q = sum_e p_e^T K_e p_e: element-local quadratic forms.
+    // p.q = sum_e p_e^T K_e p_e: element-local quadratic forms, one partial
+    // per block, summed by every block of the update kernel.
     const double bs = block_sum<NT>(dot, s_red);
-    if (tid == 0) store_partial(io.partials + blockIdx.x, bs);
-    if (arrive_last(&io.sc->cnt_apply, gridDim.x)) {
-      const double pq = sum_partials<NT>(io.partials, gridDim.x, 1, 0, s_red);
-      if (tid == 0) {
-        io.sc->pq = pq;
-        const double alpha = io.sc->rho / pq;
-        if (!(pq > 0.0) || !isfinite(alpha)) {
-          io.sc->done = 3;
-          io.sc->alpha = 0.0;
-          io.sc->alpha_x = 0.0;
-        } else {
-          io.sc->alpha = alpha;
-        }
-      }
-    }
+    if (tid == 0) io.partials[(size_t)(iter & 1) * io.pmax + blockIdx.x] = bs;
   }
 }
 
@@ -266,6 +285,8 @@ hipError_t launch_cg_apply(const hdg_ctx* c, CgWork<T>& w, hipStream_t s) {
   io.p1 = w.p[1];
   io.x = w.x;
   io.partials = w.partials;
+  io.pmax = w.pmax;
+  io.n_upd = w.update_blocks;
   io.sc = w.sc;
   return launch_apply_dispatch<T, 1>(c, tab_of<T>(c), io, s);
 }

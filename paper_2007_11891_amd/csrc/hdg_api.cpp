@@ -63,7 +63,7 @@ void dfree(T*& p) {
   } while (0)
 
 int vec_blocks_for(int64_t n) {
-  int64_t nb = (n + 1023) / 1024;
+  int64_t nb = (n + 1023) / 1024;   // 256 threads x 4 elements per thread
   nb = std::min<int64_t>(std::max<int64_t>(nb, 1), 2048);
   return (int)nb;
 }
@@ -83,9 +83,11 @@ hdg_status alloc_work(hdg_ctx* c, CgWork<T>& w) {
   ST_TRY(dalloc(&w.p[1], n));
   ST_TRY(dalloc(&w.qa, n));
   ST_TRY(dalloc(&w.qb, n));
-  ST_TRY(dalloc(&w.partials, 2 * (int64_t)std::max(w.apply_blocks, w.update_blocks) + 64));
+  w.pmax = std::max(w.apply_blocks, w.update_blocks);
+  ST_TRY(dalloc(&w.partials, 6 * (int64_t)w.pmax));
   ST_TRY(dalloc(&w.sc, 1));
   HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(CgScalars), c->stream));
+  HIP_TRY(hipMemsetAsync(w.partials, 0, sizeof(double) * 6 * (size_t)w.pmax, c->stream));
   if (n > 0) {
     HIP_TRY(hipMemsetAsync(w.qa, 0, sizeof(T) * n, c->stream));
     HIP_TRY(hipMemsetAsync(w.qb, 0, sizeof(T) * n, c->stream));
@@ -156,8 +158,9 @@ hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
   CgScalars* hs = c->h_scal;
   HIP_TRY(hipStreamSynchronize(c->stream));   // the upload slot is reused below
   hs[2] = CgScalars{};
-  hs[2].rr_stop = rtol * rtol;
-  hs[2].maxit = std::max(1, maxit);
+  hs[2].A.rtol2 = rtol * rtol;
+  hs[2].A.maxit = std::max(1, maxit);
+  hs[2].A.rho = 1.0;
   HIP_TRY(hipMemcpyAsync(w.sc, &hs[2], sizeof(CgScalars), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(launch_cg_init<T>(c, w, b, c->stream));
   check_every = std::max(1, check_every);
@@ -171,8 +174,10 @@ hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
         if (e[i]) (void)hipEventDestroy(e[i]);
     }
   } guard{ev};
-  const int max_chunks = (std::max(1, maxit) + check_every - 1) / check_every + 1;
-  int done = 0, iters = 0;
+  // the apply that detects convergence also applies the last x update, so
+  // one more graph may be needed after the cap; +2 chunks of slack
+  const int max_chunks = (std::max(1, maxit) + check_every - 1) / check_every + 2;
+  bool seen_done = false;
   for (int k = 0; k < max_chunks; ++k) {
     HIP_TRY(hipGraphLaunch(w.graph, c->stream));
     HIP_TRY(hipMemcpyAsync(&hs[k & 1], w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost,
@@ -180,17 +185,19 @@ hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
     HIP_TRY(hipEventRecord(ev[k & 1], c->stream));
     if (k >= 1) {
       HIP_TRY(hipEventSynchronize(ev[(k - 1) & 1]));
-      if (hs[(k - 1) & 1].done) break;
+      if (hs[(k - 1) & 1].A.done) {
+        seen_done = true;
+        break;
+      }
     }
   }
-  HIP_TRY(launch_cg_finalize<T>(c, w, c->stream));
   HIP_TRY(hipMemcpyAsync(&hs[0], w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  done = hs[0].done;
-  iters = hs[0].iter;
-  *iters_out = iters;
+  const int done = hs[0].A.done;
+  *iters_out = hs[0].A.iter;
   *done_out = done;
-  if (done == 3) return fail(HDG_ENOCONV, "CG breakdown after %d iterations", iters);
+  if (!seen_done && !done) return fail(HDG_EHIP, "CG did not report completion");
+  if (done == 3) return fail(HDG_ENOCONV, "CG breakdown after %d iterations", hs[0].A.iter);
   return HDG_OK;
 }
 
@@ -207,8 +214,8 @@ hdg_status validate_opts(const hdg_solve_opts* o) {
 hdg_status residual64(hdg_ctx* c, const double* b, const double* x, double* rr) {
   CgWork<double>& w = c->w64;
   HIP_TRY(launch_elem_apply<double>(c, x, nullptr, w.qa, w.qb, c->stream));
-  HIP_TRY(launch_residual64(b, w.qa, w.qb, c->d_tmp[2], c->n_free, w.partials, c->d_cnt,
-                            c->d_red, w.update_blocks, c->stream));
+  HIP_TRY(launch_residual64(b, w.qa, w.qb, c->d_tmp[2], c->n_free, w.partials, c->d_red,
+                            w.update_blocks, c->stream));
   HIP_TRY(hipMemcpyAsync(c->h_red, c->d_red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   *rr = *c->h_red;
@@ -216,8 +223,8 @@ hdg_status residual64(hdg_ctx* c, const double* b, const double* x, double* rr) 
 }
 
 hdg_status norm2_64(hdg_ctx* c, const double* v, double* out) {
-  HIP_TRY(launch_dot64(v, v, c->n_free, c->w64.partials, c->d_cnt, c->d_red,
-                       c->w64.update_blocks, c->stream));
+  HIP_TRY(launch_dot64(v, v, c->n_free, c->w64.partials, c->d_red, c->w64.update_blocks,
+                       c->stream));
   HIP_TRY(hipMemcpyAsync(c->h_red, c->d_red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   *out = *c->h_red;
@@ -825,8 +832,9 @@ hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int re
     HIP_TRY(hipStreamSynchronize(c->stream));
     CgScalars& init = c->h_scal[2];
     init = CgScalars{};
-    init.rr_stop = 0.0;
-    init.maxit = 1 << 30;
+    init.A.rtol2 = 0.0;
+    init.A.maxit = 1 << 30;
+    init.A.rho = 1.0;
     if (f32) {
       c->w32.dinv = c->d_dinv32;
       HIP_TRY(hipMemcpyAsync(c->w32.sc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
@@ -836,6 +844,9 @@ hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int re
       HIP_TRY(hipMemcpyAsync(c->w64.sc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
       HIP_TRY(launch_cg_init<double>(c, c->w64, static_cast<const double*>(x), c->stream));
     }
+    // prime the state with one apply so that an update has a p.q to consume
+    if (f32) HIP_TRY(launch_cg_apply<float>(c, c->w32, c->stream));
+    else HIP_TRY(launch_cg_apply<double>(c, c->w64, c->stream));
   }
   auto launch = [&]() -> hipError_t {
     switch (which) {

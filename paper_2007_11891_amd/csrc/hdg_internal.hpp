@@ -35,24 +35,27 @@ struct MeshDev {
   const double* lam;   // per element
 };
 
-// Device-resident scalars of one CG run (one cache line each group).
-struct CgScalars {
-  double rho;        // r.z of the current residual
-  double alpha;      // alpha of the current iteration (written by the apply)
-  double alpha_x;    // alpha applied to x in the next apply (written by the update)
-  double beta;       // beta for the next search direction
-  double rr;         // ||r||^2 of the current residual
-  double rr_stop;    // convergence threshold on ||r||^2
-  double pq;
-  double pad0;
-  int iter;          // completed iterations
+// Device-resident state of one CG run.  The fused apply reads slot A and
+// its block 0 writes slot B; the update reads B and its block 0 writes A.
+// Because the two kernels strictly alternate, no slot is read and written by
+// the same launch.  Reductions are block partials that every block of the
+// consuming kernel sums in the same fixed order (no fences, deterministic).
+struct CgState {
+  double rho;        // A: rho_{k-1} (previous r.z);  B: rho_k
+  double alpha;      // A: alpha_{k-1};  B: unused
+  double rr_stop;    // absolute threshold on ||r||^2 (set at iteration 0)
+  double rtol2;      // rtol^2 from the host
+  double rr;         // last ||r||^2 seen (diagnostic)
+  double pq;         // last p.q (diagnostic)
+  int iter;          // A: k (iterations completed);  B: k
   int maxit;
   int done;          // 0 running, 1 converged, 2 iteration cap, 3 breakdown
-  int pad1;
-  unsigned cnt_apply;   // last-block counters
-  unsigned cnt_update;
-  unsigned cnt_misc;
-  unsigned pad2;
+  int pad;
+};
+
+struct CgScalars {
+  CgState A;
+  CgState B;
 };
 
 // Workspace of one CG solve in precision T (free-trace vectors).
@@ -64,7 +67,8 @@ struct CgWork {
   T* qa = nullptr;       // contribution of the element below each face
   T* qb = nullptr;       // contribution of the element above each face
   T* dinv = nullptr;
-  double* partials = nullptr;  // 2 doubles per block
+  double* partials = nullptr;  // pq[2][pmax] | rz[2][pmax] | rr[2][pmax]
+  int pmax = 0;                // partial slots per buffer
   CgScalars* sc = nullptr;
   int64_t n = 0;
   int apply_blocks = 0;
@@ -127,16 +131,14 @@ template <typename T>
 hipError_t launch_cg_update(const hdg_ctx* c, CgWork<T>& w, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_init(const hdg_ctx* c, CgWork<T>& w, const T* b, hipStream_t s);
-template <typename T>
-hipError_t launch_cg_finalize(const hdg_ctx* c, CgWork<T>& w, hipStream_t s);
 
 // y = qa + qb (optionally scaled); or y = b - (qa + qb) with the squared norm
 // reduced into red[0] (FP64)
 template <typename T>
 hipError_t launch_combine(const T* qa, const T* qb, T* y, int64_t n, hipStream_t s);
 hipError_t launch_residual64(const double* b, const double* qa, const double* qb, double* r,
-                             int64_t n, double* partials, unsigned* cnt, double* out,
-                             int nblocks, hipStream_t s);
+                             int64_t n, double* partials, double* out, int nblocks,
+                             hipStream_t s);
 
 // per-face transform A x A of n_faces faces; optional second input added first
 template <typename T>
@@ -164,7 +166,7 @@ hipError_t launch_fill32(float* out, float v, int64_t n, hipStream_t s);
 hipError_t launch_recip_64_32(const double* diag, float* dinv32, double* dinv64, int64_t n,
                               hipStream_t s);
 hipError_t launch_dot64(const double* a, const double* b, int64_t n, double* partials,
-                        unsigned* cnt, double* out, int nblocks, hipStream_t s);
+                        double* out, int nblocks, hipStream_t s);
 
 int elem_threads(int np, int* epb);
 

@@ -14,63 +14,101 @@
 namespace hdg {
 
 constexpr int kVecThreads = 256;
+constexpr int kUnroll = 4;
 
 static inline int vec_blocks(int64_t n, int cap = 2048) {
-  int64_t nb = (n + kVecThreads * 4 - 1) / (kVecThreads * 4);
+  int64_t nb = (n + kVecThreads * kUnroll - 1) / (kVecThreads * kUnroll);
   if (nb > cap) nb = cap;
   if (nb < 1) nb = 1;
   return (int)nb;
 }
 
 // ------------------------------------------------------------------ CG ----
+// Update of iteration k: alpha_k = rho_k / (p_k . q_k) with p.q summed from
+// the apply's partials; r -= alpha q with q = qa + qb; partials of r.z and
+// r.r for the next apply.  Block 0 publishes slot A for the next apply.
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
 cg_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb, T* __restrict__ r,
-                 const T* __restrict__ dinv, double* partials, CgScalars* sc) {
+                 const T* __restrict__ dinv, double* __restrict__ partials, int pmax, int n_apply,
+                 CgScalars* sc) {
   __shared__ double s_red[kVecThreads / 64];
-  if (sc->done) return;
-  const T alpha = (T)sc->alpha;
-  double rz = 0.0, rr = 0.0;
-  T rz_t = 0, rr_t = 0;
-  for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
-       g += (int64_t)gridDim.x * kVecThreads) {
-    const T q = qa[g] + qb[g];
-    const T rn = r[g] - alpha * q;
-    r[g] = rn;
-    const T z = dinv[g] * rn;
-    rz_t += rn * z;
-    rr_t += rn * rn;
-  }
-  rz = (double)rz_t;
-  rr = (double)rr_t;
-  const double brz = block_sum<kVecThreads>(rz, s_red);
-  const double brr = block_sum<kVecThreads>(rr, s_red);
-  if (threadIdx.x == 0) {
-    store_partial(partials + 2 * blockIdx.x, brz);
-    store_partial(partials + 2 * blockIdx.x + 1, brr);
-  }
-  if (arrive_last(&sc->cnt_update, gridDim.x)) {
-    const double trz = sum_partials<kVecThreads>(partials, gridDim.x, 2, 0, s_red);
-    const double trr = sum_partials<kVecThreads>(partials, gridDim.x, 2, 1, s_red);
-    if (threadIdx.x == 0) {
-      const double rho_old = sc->rho;
-      sc->beta = trz / rho_old;
-      sc->rho = trz;
-      sc->rr = trr;
-      sc->alpha_x = sc->alpha;
-      sc->iter = sc->iter + 1;
-      if (trr <= sc->rr_stop) sc->done = 1;
-      else if (sc->iter >= sc->maxit) sc->done = 2;
-      else if (!isfinite(trr) || !isfinite(sc->beta)) sc->done = 3;
+  // scalar reads of slot B (a struct copy here costs a large serialisation)
+  const int done = sc->B.done;
+  if (done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->A.done = done;
+      sc->A.rr = sc->B.rr;
     }
+    return;
+  }
+  const int k = sc->B.iter;
+  const double rho = sc->B.rho;
+  const double pq = sum_partials<kVecThreads>(partials + (size_t)(k & 1) * pmax, n_apply, 1, 0,
+                                              s_red);
+  const double alpha = rho / pq;
+  if (!(pq > 0.0) || !isfinite(alpha)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->A.done = 3;
+      sc->A.alpha = 0.0;
+      sc->A.pq = pq;
+    }
+    return;
+  }
+  const T a = (T)alpha;
+  T rz_t = 0, rr_t = 0;
+  // kUnroll independent elements per thread: all loads issued before use
+  const int64_t stride = (int64_t)gridDim.x * kVecThreads;
+  for (int64_t g0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g0 < n;
+       g0 += kUnroll * stride) {
+    T va[kUnroll], vb[kUnroll], vr[kUnroll], vd[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t g = g0 + u * stride;
+      if (g < n) {
+        va[u] = qa[g];
+        vb[u] = qb[g];
+        vr[u] = r[g];
+        vd[u] = dinv[g];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t g = g0 + u * stride;
+      if (g < n) {
+        const T rn = vr[u] - a * (va[u] + vb[u]);
+        r[g] = rn;
+        rz_t += rn * (vd[u] * rn);
+        rr_t += rn * rn;
+      }
+    }
+  }
+  const double brz = block_sum<kVecThreads>((double)rz_t, s_red);
+  const double brr = block_sum<kVecThreads>((double)rr_t, s_red);
+  const int k1 = (k + 1) & 1;
+  if (threadIdx.x == 0) {
+    partials[(size_t)(2 + k1) * pmax + blockIdx.x] = brz;
+    partials[(size_t)(4 + k1) * pmax + blockIdx.x] = brr;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // rho_k becomes the previous rho of iteration k+1
+    sc->A.rho = rho;
+    sc->A.alpha = alpha;
+    sc->A.pq = pq;
+    sc->A.rr_stop = sc->B.rr_stop;
+    sc->A.rr = sc->B.rr;
+    sc->A.iter = k + 1;
+    sc->A.done = 0;
   }
 }
 
-// r = b, p_old = 0, x = 0, rho = b.D^-1 b, rr = b.b; rr_stop scaled by rr.
+// r = b, x = 0, p_{-1} = 0, and the partials of b.D^-1 b and b.b that the
+// first apply sums (they play the role of the update of iteration -1).
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
 cg_init_kernel(int64_t n, const T* __restrict__ b, T* __restrict__ r, T* __restrict__ x,
-               T* __restrict__ p1, const T* __restrict__ dinv, double* partials, CgScalars* sc) {
+               T* __restrict__ p1, const T* __restrict__ dinv, double* __restrict__ partials,
+               int pmax) {
   __shared__ double s_red[kVecThreads / 64];
   T rz_t = 0, rr_t = 0;
   for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
@@ -79,61 +117,27 @@ cg_init_kernel(int64_t n, const T* __restrict__ b, T* __restrict__ r, T* __restr
     r[g] = v;
     x[g] = 0;
     p1[g] = 0;
-    rz_t += v * dinv[g] * v;
+    rz_t += v * (dinv[g] * v);
     rr_t += v * v;
   }
   const double brz = block_sum<kVecThreads>((double)rz_t, s_red);
   const double brr = block_sum<kVecThreads>((double)rr_t, s_red);
   if (threadIdx.x == 0) {
-    store_partial(partials + 2 * blockIdx.x, brz);
-    store_partial(partials + 2 * blockIdx.x + 1, brr);
-  }
-  if (arrive_last(&sc->cnt_misc, gridDim.x)) {
-    const double trz = sum_partials<kVecThreads>(partials, gridDim.x, 2, 0, s_red);
-    const double trr = sum_partials<kVecThreads>(partials, gridDim.x, 2, 1, s_red);
-    if (threadIdx.x == 0) {
-      sc->rho = trz;
-      sc->rr = trr;
-      sc->rr_stop = sc->rr_stop * trr;   // host stored rtol^2
-      sc->beta = 0.0;
-      sc->alpha = 0.0;
-      sc->alpha_x = 0.0;
-      sc->iter = 0;
-      sc->done = (trr <= sc->rr_stop || trr == 0.0) ? 1 : 0;
-      if (!isfinite(trr)) sc->done = 3;
-    }
+    partials[(size_t)2 * pmax + blockIdx.x] = brz;
+    partials[(size_t)4 * pmax + blockIdx.x] = brr;
   }
 }
 
-// x += alpha_x p_last after the loop stopped.
 template <typename T>
-__global__ void __launch_bounds__(kVecThreads)
-cg_finalize_kernel(int64_t n, T* __restrict__ x, const T* __restrict__ p0,
-                   const T* __restrict__ p1, const CgScalars* sc) {
-  const T a = (T)sc->alpha_x;
-  // the last apply ran at iteration iter-1 and wrote p[(iter - 1) & 1]
-  const T* p = (sc->iter & 1) ? p0 : p1;
-  for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
-       g += (int64_t)gridDim.x * kVecThreads)
-    x[g] += a * p[g];
-}
-
-template <typename T>
-hipError_t launch_cg_update(const hdg_ctx*, CgWork<T>& w, hipStream_t s) {
+hipError_t launch_cg_update(const hdg_ctx* c, CgWork<T>& w, hipStream_t s) {
   hipLaunchKernelGGL((cg_update_kernel<T>), dim3(w.update_blocks), dim3(kVecThreads), 0, s, w.n,
-                     w.qa, w.qb, w.r, w.dinv, w.partials, w.sc);
+                     w.qa, w.qb, w.r, w.dinv, w.partials, w.pmax, w.apply_blocks, w.sc);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_cg_init(const hdg_ctx*, CgWork<T>& w, const T* b, hipStream_t s) {
   hipLaunchKernelGGL((cg_init_kernel<T>), dim3(w.update_blocks), dim3(kVecThreads), 0, s, w.n, b,
-                     w.r, w.x, w.p[1], w.dinv, w.partials, w.sc);
-  return hipGetLastError();
-}
-template <typename T>
-hipError_t launch_cg_finalize(const hdg_ctx*, CgWork<T>& w, hipStream_t s) {
-  hipLaunchKernelGGL((cg_finalize_kernel<T>), dim3(w.update_blocks), dim3(kVecThreads), 0, s, w.n,
-                     w.x, w.p[0], w.p[1], w.sc);
+                     w.r, w.x, w.p[1], w.dinv, w.partials, w.pmax);
   return hipGetLastError();
 }
 
@@ -143,8 +147,6 @@ template hipError_t launch_cg_init<double>(const hdg_ctx*, CgWork<double>&, cons
                                            hipStream_t);
 template hipError_t launch_cg_init<float>(const hdg_ctx*, CgWork<float>&, const float*,
                                           hipStream_t);
-template hipError_t launch_cg_finalize<double>(const hdg_ctx*, CgWork<double>&, hipStream_t);
-template hipError_t launch_cg_finalize<float>(const hdg_ctx*, CgWork<float>&, hipStream_t);
 
 // ------------------------------------------------------------ combine ----
 template <typename T>
@@ -167,11 +169,18 @@ template hipError_t launch_combine<double>(const double*, const double*, double*
 template hipError_t launch_combine<float>(const float*, const float*, float*, int64_t,
                                           hipStream_t);
 
+// out[0] = sum of n partials (one block, fixed order)
+__global__ void __launch_bounds__(kVecThreads)
+reduce_partials_kernel(const double* __restrict__ parts, int n, double* __restrict__ out) {
+  __shared__ double s_red[kVecThreads / 64];
+  const double v = sum_partials<kVecThreads>(parts, n, 1, 0, s_red);
+  if (threadIdx.x == 0) out[0] = v;
+}
+
 // r = b - (qa + qb); out[0] = ||r||^2 (FP64)
 __global__ void __launch_bounds__(kVecThreads)
 residual64_kernel(int64_t n, const double* __restrict__ b, const double* __restrict__ qa,
-                  const double* __restrict__ qb, double* __restrict__ r, double* partials,
-                  unsigned* cnt, double* out) {
+                  const double* __restrict__ qb, double* __restrict__ r, double* partials) {
   __shared__ double s_red[kVecThreads / 64];
   double acc = 0.0;
   for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
@@ -181,40 +190,35 @@ residual64_kernel(int64_t n, const double* __restrict__ b, const double* __restr
     acc += v * v;
   }
   const double bs = block_sum<kVecThreads>(acc, s_red);
-  if (threadIdx.x == 0) store_partial(partials + blockIdx.x, bs);
-  if (arrive_last(cnt, gridDim.x)) {
-    const double t = sum_partials<kVecThreads>(partials, gridDim.x, 1, 0, s_red);
-    if (threadIdx.x == 0) out[0] = t;
-  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
 hipError_t launch_residual64(const double* b, const double* qa, const double* qb, double* r,
-                             int64_t n, double* partials, unsigned* cnt, double* out,
-                             int nblocks, hipStream_t s) {
+                             int64_t n, double* partials, double* out, int nblocks,
+                             hipStream_t s) {
   hipLaunchKernelGGL(residual64_kernel, dim3(nblocks), dim3(kVecThreads), 0, s, n, b, qa, qb, r,
-                     partials, cnt, out);
+                     partials);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kVecThreads), 0, s, partials, nblocks,
+                     out);
   return hipGetLastError();
 }
 
 __global__ void __launch_bounds__(kVecThreads)
 dot64_kernel(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
-             double* partials, unsigned* cnt, double* out) {
+             double* partials) {
   __shared__ double s_red[kVecThreads / 64];
   double acc = 0.0;
   for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
        g += (int64_t)gridDim.x * kVecThreads)
     acc += a[g] * b[g];
   const double bs = block_sum<kVecThreads>(acc, s_red);
-  if (threadIdx.x == 0) store_partial(partials + blockIdx.x, bs);
-  if (arrive_last(cnt, gridDim.x)) {
-    const double t = sum_partials<kVecThreads>(partials, gridDim.x, 1, 0, s_red);
-    if (threadIdx.x == 0) out[0] = t;
-  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
 
 hipError_t launch_dot64(const double* a, const double* b, int64_t n, double* partials,
-                        unsigned* cnt, double* out, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(dot64_kernel, dim3(nblocks), dim3(kVecThreads), 0, s, n, a, b, partials, cnt,
+                        double* out, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(dot64_kernel, dim3(nblocks), dim3(kVecThreads), 0, s, n, a, b, partials);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kVecThreads), 0, s, partials, nblocks,
                      out);
   return hipGetLastError();
 }
