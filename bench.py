@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the isolated kernel timings (for counter collection)")
+    ap.add_argument("--reps", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -99,6 +102,17 @@ def main():
     trace = torch.zeros(na, dtype=torch.float64, device=dev)
     u_vol = torch.empty(nv, dtype=torch.float64, device=dev)
     opts = pkg.default_opts(rtol=1e-10)
+
+    if args.kernels_only:
+        x64 = torch.as_tensor(W.random_trace(nf, 1), device=dev)
+        y64 = torch.empty_like(x64)
+        for which, name in ((0, "apply64"), (1, "apply32"), (4, "cg_apply64"),
+                            (5, "cg_update64"), (8, "copy64")):
+            xin = x64.float() if which == 1 else x64
+            ms = ctx.time_kernel(which, xin, args.reps, y=y64 if which == 8 else None)
+            log(f"[bench] {name} {ms * 1e3:.3f} us")
+        ctx.close()
+        return
 
     def step():
         trace.zero_()

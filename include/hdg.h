@@ -237,8 +237,10 @@ hdg_status hdg_diagonal(hdg_ctx* ctx, double* diag_free);
  * back-to-back on the context stream between two HIP events and return the
  * mean time per launch in *ms.  which: 0 = FP64 eigen-basis element apply
  * (x -> y), 1 = FP32 eigen-basis element apply, 2 = FP64 CG iteration
- * (fused apply + update), 3 = FP32 CG iteration.  x, y device buffers of
- * n_free values of the matching type (x read, y scratch).  Synchronises. */
+ * (fused apply + update), 3 = FP32 CG iteration, 4 / 5 = FP64 fused CG
+ * apply / update alone, 6 / 7 = the same in FP32, 8 = plain FP64 copy
+ * x -> y (reference traffic).  x, y device buffers of n_free values of the
+ * matching type (x read; y written only by 8).  Synchronises. */
 hdg_status hdg_time_kernel(hdg_ctx* ctx, int which, const void* x, void* y,
                            int reps, double* ms);
 

@@ -62,9 +62,12 @@ void dfree(T*& p) {
     if (_s != HDG_OK) return _s;      \
   } while (0)
 
+// Blocks of the CG vector kernels: 256 threads x 4 elements per thread, at
+// most 256 blocks so that the apply blocks that re-sum the update partials
+// read few values.
 int vec_blocks_for(int64_t n) {
-  int64_t nb = (n + 1023) / 1024;   // 256 threads x 4 elements per thread
-  nb = std::min<int64_t>(std::max<int64_t>(nb, 1), 2048);
+  int64_t nb = (n + 1023) / 1024;
+  nb = std::min<int64_t>(std::max<int64_t>(nb, 1), 256);
   return (int)nb;
 }
 
@@ -73,9 +76,7 @@ hdg_status alloc_work(hdg_ctx* c, CgWork<T>& w) {
   if (w.x) return HDG_OK;
   const int64_t n = c->n_free;
   w.n = n;
-  int epb = 1;
-  elem_threads(c->np, &epb);
-  w.apply_blocks = (int)std::max<int64_t>(1, (c->n_elem + epb - 1) / epb);
+  w.apply_blocks = std::max(1, elem_apply_blocks(c->np, c->n_elem));
   w.update_blocks = vec_blocks_for(n);
   ST_TRY(dalloc(&w.x, n));
   ST_TRY(dalloc(&w.r, n));
@@ -382,6 +383,7 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
   if (p < 1 || p > 16) return fail(HDG_EINVAL, "p must be in [1, 16], got %d", p);
   if (!(tau_hat > 0.0) || !std::isfinite(tau_hat)) return fail(HDG_EINVAL, "tau_hat must be > 0");
   const int64_t ne = (int64_t)n_elem[0] * n_elem[1] * n_elem[2];
+  if (ne > (int64_t)1 << 28) return fail(HDG_EINVAL, "more than 2^28 elements");
   if (lambda_host) {
     for (int64_t e = 0; e < ne; ++e)
       if (!(lambda_host[e] >= 0.0) || !std::isfinite(lambda_host[e]))
@@ -433,9 +435,12 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
   hdg_status st;
   if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return cleanup(fail(HDG_EHIP, "stream creation failed"));
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 3; ++a) {
     if ((st = dalloc(&c->d_h[a], n_elem[a])) != HDG_OK) return cleanup(st);
+    if ((st = dalloc(&c->d_g[a], n_elem[a])) != HDG_OK) return cleanup(st);
+  }
   if ((st = dalloc(&c->d_lam, ne)) != HDG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_info, ne)) != HDG_OK) return cleanup(st);
   if ((st = dalloc(&c->d_mats64, 4 * npf)) != HDG_OK) return cleanup(st);
   if ((st = dalloc(&c->d_mats32, 4 * npf)) != HDG_OK) return cleanup(st);
   if ((st = dalloc(&c->d_diag, c->n_free)) != HDG_OK) return cleanup(st);
@@ -464,8 +469,12 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
       return fail(HDG_EHIP, "host-to-device copy failed");
     return HDG_OK;
   };
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 3; ++a) {
     if ((st = h2d(c->d_h[a], hs[a], sizeof(double) * n_elem[a])) != HDG_OK) return cleanup(st);
+    std::vector<double> g(n_elem[a]);
+    for (int i = 0; i < n_elem[a]; ++i) g[i] = (2.0 / hs[a][i]) * (2.0 / hs[a][i]);
+    if ((st = h2d(c->d_g[a], g.data(), sizeof(double) * n_elem[a])) != HDG_OK) return cleanup(st);
+  }
   if ((st = h2d(c->d_lam, c->lam_host.data(), sizeof(double) * ne)) != HDG_OK) return cleanup(st);
   if ((st = h2d(c->d_mats64, mats.data(), sizeof(double) * mats.size())) != HDG_OK)
     return cleanup(st);
@@ -489,9 +498,42 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
       off += tb[a];
     }
   m.n_free_faces = c->n_free_faces;
+  {
+    // per-element face ids and metric factors
+    std::vector<ElemInfo> info((size_t)ne);
+    for (int k = 0; k < n3; ++k)
+      for (int j = 0; j < n2; ++j)
+        for (int i = 0; i < n1; ++i) {
+          ElemInfo& ei = info[(size_t)i + (size_t)n1 * (j + (size_t)n2 * k)];
+          for (int s = 0; s < 2; ++s) {
+            const int pl0 = i + s, pl1 = j + s, pl2 = k + s;
+            ei.fid[0 + s] = (int)((pl0 >= 1 && pl0 <= n1 - 1)
+                                      ? m.foff[0] + (pl0 - 1) + (int64_t)(n1 - 1) * (j + (int64_t)n2 * k)
+                                      : m.boff[0 + (pl0 == 0 ? 0 : 1)] + j + (int64_t)n2 * k);
+            ei.fid[2 + s] = (int)((pl1 >= 1 && pl1 <= n2 - 1)
+                                      ? m.foff[1] + i + (int64_t)n1 * ((pl1 - 1) + (int64_t)(n2 - 1) * k)
+                                      : m.boff[2 + (pl1 == 0 ? 0 : 1)] + i + (int64_t)n1 * k);
+            ei.fid[4 + s] = (int)((pl2 >= 1 && pl2 <= n3 - 1)
+                                      ? m.foff[2] + i + (int64_t)n1 * (j + (int64_t)n2 * (pl2 - 1))
+                                      : m.boff[4 + (pl2 == 0 ? 0 : 1)] + i + (int64_t)n1 * j);
+          }
+          ei.pad[0] = ei.pad[1] = 0;
+          const double d0 = hs[0][i] * hs[1][j] * hs[2][k] * 0.125;
+          ei.d[0] = d0;
+          ei.d[1] = d0 * (2.0 / hs[0][i]) * (2.0 / hs[0][i]);
+          ei.d[2] = d0 * (2.0 / hs[1][j]) * (2.0 / hs[1][j]);
+          ei.d[3] = d0 * (2.0 / hs[2][k]) * (2.0 / hs[2][k]);
+        }
+    if ((st = h2d(c->d_info, info.data(), sizeof(ElemInfo) * info.size())) != HDG_OK)
+      return cleanup(st);
+  }
+  m.info = c->d_info;
   m.h1 = c->d_h[0];
   m.h2 = c->d_h[1];
   m.h3 = c->d_h[2];
+  m.g1 = c->d_g[0];
+  m.g2 = c->d_g[1];
+  m.g3 = c->d_g[2];
   m.lam = c->d_lam;
 
   if ((st = upload_lambda_and_diag(c)) != HDG_OK) return cleanup(st);
@@ -508,7 +550,9 @@ hdg_status hdg_destroy(hdg_ctx* c) {
   free_work(c->w64);
   free_work(c->w32);
   for (auto& h : c->d_h) dfree(h);
+  for (auto& g : c->d_g) dfree(g);
   dfree(c->d_lam);
+  dfree(c->d_info);
   dfree(c->d_mats64);
   dfree(c->d_mats32);
   dfree(c->d_diag);
@@ -819,8 +863,8 @@ hdg_status hdg_diagonal(hdg_ctx* c, double* diag_free) {
 
 hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int reps, double* ms) {
   if (!c || !x || !ms || reps < 1) return fail(HDG_EINVAL, "invalid argument");
-  (void)y;
-  if (which < 0 || which > 7) return fail(HDG_EINVAL, "unknown kernel id %d", which);
+  if (which < 0 || which > 8) return fail(HDG_EINVAL, "unknown kernel id %d", which);
+  if (which == 8 && (!y || y == x)) return fail(HDG_EINVAL, "copy needs a distinct y");
   if (c->n_free == 0) {
     *ms = 0.0;
     return HDG_OK;
@@ -865,7 +909,9 @@ hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int re
       case 4: return launch_cg_apply<double>(c, c->w64, c->stream);
       case 5: return launch_cg_update<double>(c, c->w64, c->stream);
       case 6: return launch_cg_apply<float>(c, c->w32, c->stream);
-      default: return launch_cg_update<float>(c, c->w32, c->stream);
+      case 7: return launch_cg_update<float>(c, c->w32, c->stream);
+      default: return launch_copy64(static_cast<const double*>(x), static_cast<double*>(y),
+                                    c->n_free, c->stream);
     }
   };
   HIP_TRY(launch());   // warm-up

@@ -21,6 +21,16 @@ struct ElemTab {
   T H;             // diagonal of G + C^T M^-1 C
 };
 
+// Per-element data precomputed at set-up: the six face ids (axis a, side s
+// at index 2a+s; ids >= n_free_faces are boundary faces) and the metric
+// factors d0..d3 (paper, section "LDG operator structure in three
+// dimensions").  64 bytes, read with scalar loads.
+struct ElemInfo {
+  int fid[6];
+  int pad[2];
+  double d[4];
+};
+
 // Mesh description on the device.  Face ids follow the canonical layout:
 // free faces of axis 0, 1, 2 then the boundary tail (see include/hdg.h).
 struct MeshDev {
@@ -32,7 +42,11 @@ struct MeshDev {
   const double* h1;
   const double* h2;
   const double* h3;
+  const double* g1;    // (2/h1)^2 per element index along x1 (likewise g2, g3)
+  const double* g2;
+  const double* g3;
   const double* lam;   // per element
+  const ElemInfo* info; // per element
 };
 
 // Device-resident state of one CG run.  The fused apply reads slot A and
@@ -98,6 +112,8 @@ struct hdg_ctx {
   std::vector<double> lam_host;
   // device buffers
   double* d_h[3] = {nullptr, nullptr, nullptr};
+  double* d_g[3] = {nullptr, nullptr, nullptr};   // (2/h)^2 per axis
+  hdg::ElemInfo* d_info = nullptr;
   double* d_lam = nullptr;
   double* d_mats64 = nullptr;   // St, StM, S, MS (4 n_p^2 doubles)
   float* d_mats32 = nullptr;
@@ -162,12 +178,14 @@ hipError_t launch_cast_scale_64_32(const double* in, float* out, double scale, i
 hipError_t launch_axpy_32_64(const float* in, double* out, double scale, int64_t n,
                              hipStream_t s);
 hipError_t launch_fill64(double* out, double v, int64_t n, hipStream_t s);
+hipError_t launch_copy64(const double* in, double* out, int64_t n, hipStream_t s);
 hipError_t launch_fill32(float* out, float v, int64_t n, hipStream_t s);
 hipError_t launch_recip_64_32(const double* diag, float* dinv32, double* dinv64, int64_t n,
                               hipStream_t s);
 hipError_t launch_dot64(const double* a, const double* b, int64_t n, double* partials,
                         double* out, int nblocks, hipStream_t s);
 
-int elem_threads(int np, int* epb);
+// grid size of the element apply kernels (number of partials they write)
+int elem_apply_blocks(int np, int64_t n_elem);
 
 }  // namespace hdg

@@ -224,6 +224,19 @@ hipError_t launch_dot64(const double* a, const double* b, int64_t n, double* par
 }
 
 // --------------------------------------------------------------- misc ----
+// Plain copy (reference kernel of known traffic for counter calibration).
+__global__ void copy64_kernel(int64_t n, const double* __restrict__ in, double* __restrict__ out) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x)
+    out[g] = in[g];
+}
+hipError_t launch_copy64(const double* in, double* out, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy64_kernel, dim3(vec_blocks(n, 8192)), dim3(kVecThreads), 0, s, n, in,
+                     out);
+  return hipGetLastError();
+}
+
 __global__ void cast_scale_kernel(int64_t n, const double* __restrict__ in, float* __restrict__ out,
                                   double scale) {
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;

@@ -322,8 +322,10 @@ class HdgContext:
         _check(self._lib.hdg_diagonal(self._h, _dptr(d, self.sizes.n_free, torch.float64, "diag")))
         return d
 
-    def time_kernel(self, which: int, x, reps: int = 100) -> float:
+    def time_kernel(self, which: int, x, reps: int = 100, y=None) -> float:
+        """Mean launch time (ms) of an internal kernel, HIP events on the context stream."""
         ms = ctypes.c_double()
+        yp = None if y is None else ctypes.c_void_p(y.data_ptr())
         _check(self._lib.hdg_time_kernel(self._h, int(which), ctypes.c_void_p(x.data_ptr()),
-                                         None, int(reps), ctypes.byref(ms)))
+                                         yp, int(reps), ctypes.byref(ms)))
         return ms.value
