@@ -230,6 +230,17 @@ hdg_status hdg_adjoint(hdg_ctx* ctx, const double* f, const double* trace,
                        const double* dJdu, double* dJdlambda, double* dJdf,
                        const hdg_solve_opts* opts, hdg_solve_info* info);
 
+/* Tile shape of the element kernels: elements per work unit = the largest
+ * count that fits 256 threads and 60 KB of LDS, shifted right by `variant`
+ * (0, 1 or 2).  Synchronises the stream; invalidates captured CG graphs. */
+hdg_status hdg_set_tile(hdg_ctx* ctx, int variant);
+
+/* Autotuner: times one fused FP64 CG iteration (apply + update) for every
+ * tile variant on this context's mesh (`reps` launches each, HIP events on
+ * the context stream), selects the fastest and returns it in *chosen
+ * (times_ms: host double[3] or NULL).  Synchronises the stream. */
+hdg_status hdg_autotune(hdg_ctx* ctx, int reps, int* chosen, double* times_ms);
+
 /* Diagonal of K^_ff (eigen basis), device double[n_free] output. */
 hdg_status hdg_diagonal(hdg_ctx* ctx, double* diag_free);
 
@@ -243,6 +254,83 @@ hdg_status hdg_diagonal(hdg_ctx* ctx, double* diag_free);
  * matching type (x read; y written only by 8).  Synchronises. */
 hdg_status hdg_time_kernel(hdg_ctx* ctx, int which, const void* x, void* y,
                            int reps, double* ms);
+
+/* ------------------------------------------------------------------------
+ * Batched solves.  Many independent problems, each the paper's Dirichlet
+ * problem on the unit cube [0,1]^3 with a uniform n1 x n2 x n3 mesh
+ * (h_a = 1 / n_a), its own degree p and constant lambda, homogeneous
+ * Dirichlet data, solved together by the HDG-trans CG (section "Summary of
+ * solution method") in one persistent launch: all problems iterate in
+ * lockstep phases, each keeps its own reductions and stops on its own
+ * convergence test.  The right-hand sides, the persistent CG and the
+ * recovery are replayed from one captured HIP graph (if the runtime cannot
+ * capture the cooperative launch, the graph is split around it).
+ *
+ * Layout: the per-problem vectors of the single-problem entry points are
+ * concatenated in problem order (volume vectors by n_vol, free traces by
+ * n_free, see hdg_batch_sizes).
+ * ---------------------------------------------------------------------- */
+typedef struct hdg_batch hdg_batch;
+
+typedef struct {
+  int iters;          /* CG iterations of this problem                         */
+  int status;         /* HDG_OK, HDG_ENOCONV (iteration cap) or HDG_EHIP
+                         (CG breakdown: p.q <= 0 or not finite)                */
+  double rel_res;     /* ||r||_2 / ||F^||_2 of the CG recursion (eigen basis)  */
+} hdg_batch_result;
+
+/* Create a batch of `count` >= 1 problems.
+ *   n_elem3   host int[count][3], elements per axis, each in [1, 4096]
+ *   p         host int[count], degrees in [1, 10]
+ *   lambda    host double[count], lambda >= 0 per problem
+ *   tau_hat   penalty scale > 0 (all problems)
+ *   stream    hipStream_t (as void*) for all work of the batch
+ * Tile variants start at 0 for every degree.  *out owns device memory until
+ * hdg_batch_destroy. */
+hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const double* lambda,
+                            double tau_hat, void* stream, hdg_batch** out);
+hdg_status hdg_batch_destroy(hdg_batch* batch);
+
+/* Per-problem sizes (host int64[count] each, either may be NULL) and the
+ * totals (host int64, may be NULL). */
+hdg_status hdg_batch_sizes(const hdg_batch* batch, int64_t* n_free, int64_t* n_vol,
+                           int64_t* total_free, int64_t* total_vol);
+
+/* Tile variant (as in hdg_set_tile) of the work units of every problem of
+ * degree p (p = 0: all degrees); hdg_batch_tiles reports the current
+ * variant per degree into host int[17] (index p, -1 where no problem has
+ * that degree).  set_tile synchronises the stream and drops the graph. */
+hdg_status hdg_batch_set_tile(hdg_batch* batch, int p, int variant);
+hdg_status hdg_batch_tiles(const hdg_batch* batch, int* variants);
+
+/* Autotuner: starting from variant 0 everywhere, tries variants 1 and 2 for
+ * one degree at a time (degrees by decreasing share of the work) and keeps
+ * a change when the persistent CG, timed over `iters` iterations (best of
+ * `reps` launches), gets faster.  variants: host int[17] or NULL, as in
+ * hdg_batch_tiles.  Synchronises the stream. */
+hdg_status hdg_batch_autotune(hdg_batch* batch, int iters, int reps, int* variants);
+
+/* Mean time in *ms of one persistent CG launch of exactly `iters`
+ * iterations for every problem (right-hand side of ones in the eigen basis,
+ * no convergence test), over `reps` launches timed with HIP events on the
+ * batch stream.  Overwrites the batch's internal right-hand side.
+ * Synchronises the stream. */
+hdg_status hdg_batch_time_cg(hdg_batch* batch, int iters, int reps, double* ms);
+
+/* Solve every problem: F from f (nodal, as hdg_rhs with zero Dirichlet
+ * data), CG in the eigen basis to opts->rtol (FP64 only; opts->mixed must
+ * be 0; NULL = defaults), then the nodal trace and, when u_vol is not NULL,
+ * the volume solution (as hdg_reconstruct).
+ *   f          device double[total_vol]
+ *   trace_free device double[total_free] output (the boundary trace is 0)
+ *   u_vol      device double[total_vol] output or NULL
+ *   results    host hdg_batch_result[count] output or NULL
+ *   t_ms       host double output or NULL: GPU time of the whole pipeline
+ * Returns HDG_ENOCONV if any problem stopped unconverged, HDG_EHIP if the
+ * persistent kernel reported a failed grid barrier.  Synchronises. */
+hdg_status hdg_batch_solve_forcing(hdg_batch* batch, const double* f, double* trace_free,
+                                   double* u_vol, const hdg_solve_opts* opts,
+                                   hdg_batch_result* results, double* t_ms);
 
 #ifdef __cplusplus
 }

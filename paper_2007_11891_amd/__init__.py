@@ -7,6 +7,7 @@ The computation lives in the HIP library ``libhdg.so`` (C ABI in
 ``torch.autograd.Function`` for the adjoint, and the build script.
 """
 from .hdg import (  # noqa: F401
-    HdgContext, HdgError, SolveOpts, default_opts, load_library, tables, LIB_PATH, EXPORTS,
+    HdgBatch, HdgContext, HdgError, SolveOpts, default_opts, load_library, tables, LIB_PATH,
+    EXPORTS,
     TO_EIGEN_UNKNOWN, TO_EIGEN_RESIDUAL, TO_NODAL_UNKNOWN, TO_NODAL_RESIDUAL,
 )

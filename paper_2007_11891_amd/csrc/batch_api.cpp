@@ -1,0 +1,589 @@
+// Host side of the batched solver (include/hdg.h, "Batched solves"): one
+// single-problem context per problem supplies the mesh records, the 1D
+// tables, the Jacobi diagonal and the right-hand-side / recovery kernels; the
+// batch owns the concatenated CG vectors, the work-unit schedule of the
+// persistent kernel and the captured graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/hdg.h"
+#include "batch.hpp"
+#include "hdg_internal.hpp"
+#include "host_util.hpp"
+
+using namespace hdg;
+
+struct hdg_batch {
+  int count = 0;
+  double tau = 0.0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int device = 0;
+  std::vector<hdg_ctx*> sub;
+  std::vector<int64_t> off, voff;   // free-trace and volume offsets
+  int64_t total_free = 0, total_vol = 0;
+  int variant[kMaxNP + 1];          // tile variant per degree p (index p)
+  BatchTabs tabs{};
+  // concatenated FP64 vectors (total_free each)
+  double* d_b = nullptr;
+  double* d_x = nullptr;
+  double* d_r = nullptr;
+  double* d_p0 = nullptr;
+  double* d_p1 = nullptr;
+  double* d_qa = nullptr;
+  double* d_qb = nullptr;
+  double* d_dinv = nullptr;
+  // schedule
+  int nblocks = 0;
+  int n_units = 0, n_chunks = 0, max_units = 0;
+  std::vector<BatchProbDev> probs;
+  BatchProbDev* d_probs = nullptr;
+  int* d_unit_prob = nullptr;       // [max_units]
+  int* d_chunk_prob = nullptr;      // [n_chunks]
+  int* d_unit_range = nullptr;      // [nblocks + 1]
+  int* d_chunk_range = nullptr;     // [nblocks + 1]
+  double* d_ppq = nullptr;          // [2][max_units]
+  double* d_prz = nullptr;          // [2][n_chunks]
+  double* d_prr = nullptr;
+  BatchState* d_A = nullptr;
+  BatchState* d_B = nullptr;
+  GridBar* d_bar = nullptr;
+  BatchState* h_A = nullptr;        // pinned copies read after a solve
+  GridBar* h_bar = nullptr;
+  // probs array state on the device
+  double probs_rtol2 = -1.0;
+  int probs_maxit = -1;
+  // captured pipeline
+  hipGraphExec_t graph_pre = nullptr;    // full pipeline, or RHS + reset (split)
+  hipGraphExec_t graph_post = nullptr;   // recovery (split mode only)
+  bool split = false;
+  const double* g_f = nullptr;
+  double* g_trace = nullptr;
+  double* g_uvol = nullptr;
+  int g_max_iters = -1;
+};
+
+namespace {
+
+// Relative cost of one work unit in the apply phase: a unit keeps a whole
+// block busy for a time that grows with the column length n_p, whatever the
+// number of elements in it.
+double unit_cost(int np) { return 8.0 + np; }
+
+// Contiguous ranges of items (in order) with about equal summed cost:
+// item i goes to the block holding the midpoint of its cost interval.
+void balance(const std::vector<double>& cost, int nb, std::vector<int>& range) {
+  range.assign(nb + 1, (int)cost.size());
+  double total = 0.0;
+  for (double c : cost) total += c;
+  const double per = total > 0.0 ? total / nb : 1.0;
+  double acc = 0.0;
+  int next = 0;   // first block whose start is not yet set
+  for (int i = 0; i < (int)cost.size(); ++i) {
+    const double mid = acc + 0.5 * cost[i];
+    acc += cost[i];
+    const int blk = std::min(nb - 1, (int)(mid / per));
+    while (next <= blk) range[next++] = i;
+  }
+  while (next < nb) range[next++] = (int)cost.size();
+  range[0] = 0;
+}
+
+hdg_status build_schedule(hdg_batch* b) {
+  const int chunk = batch_chunk();
+  std::vector<int> unit_prob, chunk_prob;
+  std::vector<double> ucost, ccost;
+  for (int i = 0; i < b->count; ++i) {
+    const hdg_ctx* c = b->sub[i];
+    BatchProbDev& P = b->probs[i];
+    P.variant = b->variant[c->p];
+    const int epb = tile_epb(c->np, P.variant);
+    P.unit_begin = (int)unit_prob.size();
+    P.n_units = (int)((c->n_elem + epb - 1) / epb);
+    for (int u = 0; u < P.n_units; ++u) {
+      unit_prob.push_back(i);
+      ucost.push_back(unit_cost(c->np));
+    }
+    P.chunk_begin = (int)chunk_prob.size();
+    P.n_chunks = (int)std::max<int64_t>(1, (c->n_free + chunk - 1) / chunk);
+    for (int k = 0; k < P.n_chunks; ++k) {
+      chunk_prob.push_back(i);
+      ccost.push_back(1.0);
+    }
+  }
+  if ((int)unit_prob.size() > b->max_units || (int)chunk_prob.size() != b->n_chunks)
+    return fail(HDG_EINVAL, "internal: schedule exceeds its buffers");
+  b->n_units = (int)unit_prob.size();
+  std::vector<int> urange, crange;
+  balance(ucost, b->nblocks, urange);
+  balance(ccost, b->nblocks, crange);
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  HIP_TRY(hipMemcpy(b->d_unit_prob, unit_prob.data(), sizeof(int) * unit_prob.size(),
+                    hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_chunk_prob, chunk_prob.data(), sizeof(int) * chunk_prob.size(),
+                    hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_unit_range, urange.data(), sizeof(int) * urange.size(),
+                    hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_chunk_range, crange.data(), sizeof(int) * crange.size(),
+                    hipMemcpyHostToDevice));
+  b->probs_maxit = -1;   // force a re-upload of the problem records
+  return HDG_OK;
+}
+
+hdg_status upload_probs(hdg_batch* b, double rtol2, int maxit) {
+  if (b->probs_rtol2 == rtol2 && b->probs_maxit == maxit) return HDG_OK;
+  for (auto& P : b->probs) {
+    P.rtol2 = rtol2;
+    P.maxit = maxit;
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  HIP_TRY(hipMemcpy(b->d_probs, b->probs.data(), sizeof(BatchProbDev) * b->probs.size(),
+                    hipMemcpyHostToDevice));
+  b->probs_rtol2 = rtol2;
+  b->probs_maxit = maxit;
+  return HDG_OK;
+}
+
+BatchArgs make_args(const hdg_batch* b, int max_iters) {
+  BatchArgs a{};
+  a.probs = b->d_probs;
+  a.n_probs = b->count;
+  a.max_iters = max_iters;
+  a.unit_prob = b->d_unit_prob;
+  a.chunk_prob = b->d_chunk_prob;
+  a.unit_range = b->d_unit_range;
+  a.chunk_range = b->d_chunk_range;
+  a.n_units_total = b->n_units;
+  a.n_chunks_total = b->n_chunks;
+  a.x = b->d_x;
+  a.r = b->d_r;
+  a.p0 = b->d_p0;
+  a.p1 = b->d_p1;
+  a.qa = b->d_qa;
+  a.qb = b->d_qb;
+  a.dinv = b->d_dinv;
+  a.b = b->d_b;
+  a.ppq = b->d_ppq;
+  a.prz = b->d_prz;
+  a.prr = b->d_prr;
+  a.A = b->d_A;
+  a.B = b->d_B;
+  a.bar = b->d_bar;
+  a.tabs = b->tabs;
+  return a;
+}
+
+void drop_graphs(hdg_batch* b) {
+  if (b->graph_pre) (void)hipGraphExecDestroy(b->graph_pre);
+  if (b->graph_post) (void)hipGraphExecDestroy(b->graph_post);
+  b->graph_pre = b->graph_post = nullptr;
+  b->g_max_iters = -1;
+}
+
+// Right-hand sides of every problem (eigen basis) into d_b.
+hipError_t enqueue_rhs(hdg_batch* b, const double* f, hipStream_t s) {
+  for (int i = 0; i < b->count; ++i) {
+    const hdg_ctx* c = b->sub[i];
+    if (c->n_free == 0) continue;
+    double* qa = b->d_qa + b->off[i];
+    double* qb = b->d_qb + b->off[i];
+    hipError_t e = launch_volume(c, VOL_RHS, 1, f + b->voff[i], nullptr, nullptr, nullptr, nullptr,
+                                 qa, qb, nullptr, nullptr, s);
+    if (e == hipSuccess) e = launch_combine<double>(qa, qb, b->d_b + b->off[i], c->n_free, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Nodal trace and (optionally) volume solution of every problem from d_x.
+hipError_t enqueue_recovery(hdg_batch* b, const double* f, double* trace, double* u_vol,
+                            hipStream_t s) {
+  for (int i = 0; i < b->count; ++i) {
+    const hdg_ctx* c = b->sub[i];
+    const double* xh = c->n_free ? b->d_x + b->off[i] : nullptr;
+    hipError_t e = hipSuccess;
+    if (u_vol)
+      e = launch_volume(c, VOL_RECON, 1, f + b->voff[i], xh, nullptr, nullptr, nullptr, nullptr,
+                        nullptr, u_vol + b->voff[i], nullptr, s);
+    if (e == hipSuccess && c->n_free)
+      e = launch_face_transform<double>(c->np, c->d_mats64 + 2 * c->np * c->np, xh, nullptr,
+                                        trace + b->off[i], c->n_free_faces, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hdg_status capture_end(hdg_batch* b, hipError_t launch_err, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+  if (launch_err != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return fail(HDG_EHIP, "graph capture failed: %s",
+                hipGetErrorString(launch_err != hipSuccess ? launch_err : e2));
+  }
+  hipError_t e3 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e3 != hipSuccess) {
+    *out = nullptr;
+    (void)hipGetLastError();
+    return fail(HDG_EHIP, "graph instantiation failed: %s", hipGetErrorString(e3));
+  }
+  return HDG_OK;
+}
+
+// Capture the pipeline: [RHS, reset, persistent CG, recovery] in one graph,
+// or, when the cooperative launch cannot be captured, [RHS, reset] and
+// [recovery] with the CG launched directly between them.
+hdg_status build_pipeline(hdg_batch* b, const double* f, double* trace, double* u_vol,
+                          int max_iters) {
+  if ((b->graph_pre || b->split) && b->g_f == f && b->g_trace == trace && b->g_uvol == u_vol &&
+      b->g_max_iters == max_iters && b->graph_pre)
+    return HDG_OK;
+  drop_graphs(b);
+  const BatchArgs args = make_args(b, max_iters);
+  if (!b->split) {
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_rhs(b, f, b->cap_stream);
+    if (e == hipSuccess) e = launch_batch_reset(b->d_A, b->d_B, b->d_bar, b->count, b->cap_stream);
+    if (e == hipSuccess) e = launch_batch_cg(args, b->nblocks, b->cap_stream);
+    if (e == hipSuccess) e = enqueue_recovery(b, f, trace, u_vol, b->cap_stream);
+    if (capture_end(b, e, &b->graph_pre) != HDG_OK) b->split = true;
+  }
+  if (b->split) {
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_rhs(b, f, b->cap_stream);
+    if (e == hipSuccess) e = launch_batch_reset(b->d_A, b->d_B, b->d_bar, b->count, b->cap_stream);
+    ST_TRY(capture_end(b, e, &b->graph_pre));
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    e = enqueue_recovery(b, f, trace, u_vol, b->cap_stream);
+    ST_TRY(capture_end(b, e, &b->graph_post));
+  }
+  b->g_f = f;
+  b->g_trace = trace;
+  b->g_uvol = u_vol;
+  b->g_max_iters = max_iters;
+  return HDG_OK;
+}
+
+hdg_status check_barrier(hdg_batch* b) {
+  HIP_TRY(hipMemcpyAsync(b->h_bar, b->d_bar, sizeof(GridBar), hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (b->h_bar->err)
+    return fail(HDG_EHIP, "persistent CG: grid barrier timed out (blocks not co-resident)");
+  return HDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hdg_status hdg_batch_destroy(hdg_batch* b) {
+  if (!b) return HDG_OK;
+  if (b->stream || b->cap_stream) (void)hipStreamSynchronize(b->stream);
+  drop_graphs(b);
+  for (hdg_ctx* c : b->sub) hdg_destroy(c);
+  for (double** p : {&b->d_b, &b->d_x, &b->d_r, &b->d_p0, &b->d_p1, &b->d_qa, &b->d_qb,
+                     &b->d_dinv, &b->d_ppq, &b->d_prz, &b->d_prr})
+    dfree(*p);
+  dfree(b->d_probs);
+  dfree(b->d_unit_prob);
+  dfree(b->d_chunk_prob);
+  dfree(b->d_unit_range);
+  dfree(b->d_chunk_range);
+  dfree(b->d_A);
+  dfree(b->d_B);
+  dfree(b->d_bar);
+  if (b->h_A) (void)hipHostFree(b->h_A);
+  if (b->h_bar) (void)hipHostFree(b->h_bar);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  delete b;
+  return HDG_OK;
+}
+
+hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const double* lambda,
+                            double tau_hat, void* stream, hdg_batch** out) {
+  if (!out) return fail(HDG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || count > (1 << 16)) return fail(HDG_EINVAL, "count must be in [1, 65536]");
+  if (!n_elem3 || !p || !lambda) return fail(HDG_EINVAL, "NULL argument");
+  if (!(tau_hat > 0.0) || !std::isfinite(tau_hat)) return fail(HDG_EINVAL, "tau_hat must be > 0");
+  for (int i = 0; i < count; ++i) {
+    for (int a = 0; a < 3; ++a)
+      if (n_elem3[3 * i + a] < 1 || n_elem3[3 * i + a] > 4096)
+        return fail(HDG_EINVAL, "problem %d: n_elem[%d] = %d out of [1, 4096]", i, a,
+                    n_elem3[3 * i + a]);
+    if (p[i] < 1 || p[i] > 10)
+      return fail(HDG_EINVAL, "problem %d: batched degrees must be in [1, 10], got %d", i, p[i]);
+    if (!(lambda[i] >= 0.0) || !std::isfinite(lambda[i]))
+      return fail(HDG_EINVAL, "problem %d: lambda must be finite and >= 0", i);
+  }
+  hdg_batch* b = new (std::nothrow) hdg_batch();
+  if (!b) return fail(HDG_ENOMEM, "host allocation failed");
+  auto cleanup = [&](hdg_status st) {
+    hdg_batch_destroy(b);
+    return st;
+  };
+  b->count = count;
+  b->tau = tau_hat;
+  b->stream = reinterpret_cast<hipStream_t>(stream);
+  for (int& v : b->variant) v = 0;
+  if (hipGetDevice(&b->device) != hipSuccess) return cleanup(fail(HDG_EHIP, "no HIP device"));
+  if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(fail(HDG_EHIP, "stream creation failed"));
+  b->sub.assign(count, nullptr);
+  b->off.assign(count, 0);
+  b->voff.assign(count, 0);
+  hdg_status st;
+  for (int i = 0; i < count; ++i) {
+    const int* ne = n_elem3 + 3 * i;
+    std::vector<double> h[3];
+    for (int a = 0; a < 3; ++a) h[a].assign(ne[a], 1.0 / ne[a]);
+    if ((st = hdg_create(ne, h[0].data(), h[1].data(), h[2].data(), p[i], tau_hat, nullptr,
+                         lambda[i], stream, &b->sub[i])) != HDG_OK)
+      return cleanup(st);
+    b->off[i] = b->total_free;
+    b->voff[i] = b->total_vol;
+    b->total_free += b->sub[i]->n_free;
+    b->total_vol += b->sub[i]->n_vol;
+  }
+  if (b->total_free > ((int64_t)1 << 40)) return cleanup(fail(HDG_EINVAL, "batch too large"));
+  for (double** ptr : {&b->d_b, &b->d_x, &b->d_r, &b->d_p0, &b->d_p1, &b->d_qa, &b->d_qb,
+                       &b->d_dinv})
+    if ((st = dalloc(ptr, b->total_free)) != HDG_OK) return cleanup(st);
+  // Jacobi inverse diagonals of the single-problem contexts
+  for (int i = 0; i < count; ++i) {
+    const hdg_ctx* c = b->sub[i];
+    if (c->n_free && hipMemcpyAsync(b->d_dinv + b->off[i], c->d_tmp[3], sizeof(double) * c->n_free,
+                                    hipMemcpyDeviceToDevice, b->stream) != hipSuccess)
+      return cleanup(fail(HDG_EHIP, "diagonal copy failed"));
+  }
+  // persistent grid: every block resident (cooperative launch)
+  int per_cu = 0, n_cu = 0;
+  if (batch_occupancy(&per_cu) != hipSuccess || per_cu < 1)
+    return cleanup(fail(HDG_EHIP, "occupancy query of the persistent kernel failed"));
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
+    return cleanup(fail(HDG_EHIP, "device attribute query failed"));
+  b->nblocks = std::min(per_cu, 2) * n_cu;
+  // buffers sized for the largest schedule (variant 2 has the most units)
+  const int chunk = batch_chunk();
+  int64_t units = 0, chunks = 0;
+  for (int i = 0; i < count; ++i) {
+    const hdg_ctx* c = b->sub[i];
+    units += (c->n_elem + tile_epb(c->np, 2) - 1) / tile_epb(c->np, 2);
+    chunks += std::max<int64_t>(1, (c->n_free + chunk - 1) / chunk);
+  }
+  if (units > (1 << 30) || chunks > (1 << 30)) return cleanup(fail(HDG_EINVAL, "batch too large"));
+  b->max_units = (int)units;
+  b->n_chunks = (int)chunks;
+  if ((st = dalloc(&b->d_probs, count)) != HDG_OK || (st = dalloc(&b->d_unit_prob, units)) != HDG_OK ||
+      (st = dalloc(&b->d_chunk_prob, chunks)) != HDG_OK ||
+      (st = dalloc(&b->d_unit_range, b->nblocks + 1)) != HDG_OK ||
+      (st = dalloc(&b->d_chunk_range, b->nblocks + 1)) != HDG_OK ||
+      (st = dalloc(&b->d_ppq, 2 * units)) != HDG_OK || (st = dalloc(&b->d_prz, 2 * chunks)) != HDG_OK ||
+      (st = dalloc(&b->d_prr, 2 * chunks)) != HDG_OK || (st = dalloc(&b->d_A, count)) != HDG_OK ||
+      (st = dalloc(&b->d_B, count)) != HDG_OK || (st = dalloc(&b->d_bar, 1)) != HDG_OK)
+    return cleanup(st);
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->h_A), sizeof(BatchState) * count,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&b->h_bar), sizeof(GridBar), hipHostMallocDefault) !=
+          hipSuccess)
+    return cleanup(fail(HDG_ENOMEM, "pinned host allocation failed"));
+  b->probs.resize(count);
+  for (int i = 0; i < count; ++i) {
+    const hdg_ctx* c = b->sub[i];
+    BatchProbDev& P = b->probs[i];
+    P = BatchProbDev{};
+    P.info = c->d_info;
+    P.lam = c->d_lam;
+    P.n_elem = (int)c->n_elem;
+    P.nff = (int)c->n_free_faces;
+    P.np = c->np;
+    P.off = b->off[i];
+    P.n = c->n_free;
+    // per-degree tables (one tau_hat for the whole batch)
+    const int o = batch_tab_off(c->np);
+    for (int k = 0; k < c->np; ++k) {
+      b->tabs.v[o + k] = c->et64.bs0[k];
+      b->tabs.v[o + c->np + k] = c->et64.bs1[k];
+      b->tabs.v[o + 2 * c->np + k] = c->et64.lam[k];
+    }
+    b->tabs.v[o + 3 * c->np] = c->et64.H;
+  }
+  if ((st = build_schedule(b)) != HDG_OK) return cleanup(st);
+  if (hipStreamSynchronize(b->stream) != hipSuccess)
+    return cleanup(fail(HDG_EHIP, "batch setup failed: %s", hipGetErrorString(hipGetLastError())));
+  *out = b;
+  return HDG_OK;
+}
+
+hdg_status hdg_batch_sizes(const hdg_batch* b, int64_t* n_free, int64_t* n_vol,
+                           int64_t* total_free, int64_t* total_vol) {
+  if (!b) return fail(HDG_EINVAL, "batch is NULL");
+  for (int i = 0; i < b->count; ++i) {
+    if (n_free) n_free[i] = b->sub[i]->n_free;
+    if (n_vol) n_vol[i] = b->sub[i]->n_vol;
+  }
+  if (total_free) *total_free = b->total_free;
+  if (total_vol) *total_vol = b->total_vol;
+  return HDG_OK;
+}
+
+hdg_status hdg_batch_set_tile(hdg_batch* b, int p, int variant) {
+  if (!b) return fail(HDG_EINVAL, "batch is NULL");
+  if (p < 0 || p > 10) return fail(HDG_EINVAL, "degree %d out of [0, 10]", p);
+  if (variant < 0 || variant >= kNumTileVariants)
+    return fail(HDG_EINVAL, "tile variant must be in [0, %d)", kNumTileVariants);
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  if (p == 0) {
+    for (int& v : b->variant) v = variant;
+  } else {
+    b->variant[p] = variant;
+  }
+  drop_graphs(b);
+  return build_schedule(b);
+}
+
+hdg_status hdg_batch_tiles(const hdg_batch* b, int* variants) {
+  if (!b || !variants) return fail(HDG_EINVAL, "NULL argument");
+  for (int q = 0; q <= kMaxNP - 1; ++q) variants[q] = -1;
+  for (const hdg_ctx* c : b->sub) variants[c->p] = b->variant[c->p];
+  return HDG_OK;
+}
+
+hdg_status hdg_batch_time_cg(hdg_batch* b, int iters, int reps, double* ms) {
+  if (!b || !ms || iters < 1 || reps < 1) return fail(HDG_EINVAL, "invalid argument");
+  ST_TRY(upload_probs(b, 0.0, iters));   // never converges, stops at the cap
+  HIP_TRY(launch_fill64(b->d_b, 1.0, b->total_free, b->stream));
+  const BatchArgs args = make_args(b, iters + 1);
+  HIP_TRY(launch_batch_reset(b->d_A, b->d_B, b->d_bar, b->count, b->stream));
+  HIP_TRY(launch_batch_cg(args, b->nblocks, b->stream));   // warm-up
+  ST_TRY(check_barrier(b));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float total = 0.f;
+  hipError_t err = hipSuccess;
+  for (int r = 0; r < reps && err == hipSuccess; ++r) {
+    err = launch_batch_reset(b->d_A, b->d_B, b->d_bar, b->count, b->stream);
+    if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
+    if (err == hipSuccess) err = launch_batch_cg(args, b->nblocks, b->stream);
+    if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    total += t;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(err);
+  ST_TRY(check_barrier(b));
+  *ms = (double)total / reps;
+  return HDG_OK;
+}
+
+hdg_status hdg_batch_autotune(hdg_batch* b, int iters, int reps, int* variants) {
+  if (!b || iters < 1 || reps < 1) return fail(HDG_EINVAL, "invalid argument");
+  // degrees by decreasing share of the work (elements x n_p^3)
+  double work[kMaxNP + 1] = {0};
+  for (const hdg_ctx* c : b->sub) work[c->p] += (double)c->n_elem * c->np * c->np * c->np;
+  std::vector<int> degs;
+  for (int q = 1; q <= 10; ++q)
+    if (work[q] > 0.0) degs.push_back(q);
+  std::sort(degs.begin(), degs.end(), [&](int x, int y) { return work[x] > work[y]; });
+  auto measure = [&](double* best) -> hdg_status {
+    double m = 1e300;
+    for (int r = 0; r < reps; ++r) {
+      double t = 0.0;
+      ST_TRY(hdg_batch_time_cg(b, iters, 1, &t));
+      m = std::min(m, t);
+    }
+    *best = m;
+    return HDG_OK;
+  };
+  ST_TRY(hdg_batch_set_tile(b, 0, 0));
+  double best = 0.0;
+  ST_TRY(measure(&best));
+  for (int q : degs) {
+    int keep = b->variant[q];
+    for (int v = 1; v < kNumTileVariants; ++v) {
+      ST_TRY(hdg_batch_set_tile(b, q, v));
+      double t = 0.0;
+      ST_TRY(measure(&t));
+      if (t < best) {
+        best = t;
+        keep = v;
+      }
+    }
+    ST_TRY(hdg_batch_set_tile(b, q, keep));
+  }
+  if (variants) ST_TRY(hdg_batch_tiles(b, variants));
+  return HDG_OK;
+}
+
+hdg_status hdg_batch_solve_forcing(hdg_batch* b, const double* f, double* trace_free,
+                                   double* u_vol, const hdg_solve_opts* opts,
+                                   hdg_batch_result* results, double* t_ms) {
+  if (!b || !f || !trace_free) return fail(HDG_EINVAL, "NULL argument");
+  hdg_solve_opts o;
+  hdg_default_opts(&o);
+  if (opts) o = *opts;
+  if (!(o.rtol > 0.0) || o.maxit < 1 || o.check_every < 1 || (o.precond != 0 && o.precond != 1))
+    return fail(HDG_EINVAL, "invalid solver options");
+  if (o.precond == 0) return fail(HDG_EUNSUPPORTED, "only the Jacobi preconditioner is built");
+  if (o.mixed) return fail(HDG_EUNSUPPORTED, "the batched solver runs in FP64 only");
+  ST_TRY(upload_probs(b, o.rtol * o.rtol, o.maxit));
+  // the apply that detects the stop also applies the last x update: one more pass
+  ST_TRY(build_pipeline(b, f, trace_free, u_vol, o.maxit + 1));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  hipError_t err = hipEventRecord(e0, b->stream);
+  if (err == hipSuccess) err = hipGraphLaunch(b->graph_pre, b->stream);
+  if (b->split) {
+    if (err == hipSuccess) err = launch_batch_cg(make_args(b, o.maxit + 1), b->nblocks, b->stream);
+    if (err == hipSuccess) err = hipGraphLaunch(b->graph_post, b->stream);
+  }
+  if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(b->h_A, b->d_A, sizeof(BatchState) * b->count, hipMemcpyDeviceToHost,
+                         b->stream);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(b->h_bar, b->d_bar, sizeof(GridBar), hipMemcpyDeviceToHost, b->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(b->stream);
+  float t = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(err);
+  if (t_ms) *t_ms = t;
+  if (b->h_bar->err)
+    return fail(HDG_EHIP, "persistent CG: grid barrier timed out (blocks not co-resident)");
+  hdg_status overall = HDG_OK;
+  int bad = -1;
+  for (int i = 0; i < b->count; ++i) {
+    const BatchState& s = b->h_A[i];
+    hdg_batch_result r{};
+    r.iters = s.iter;
+    r.status = s.done == 1 ? HDG_OK : (s.done == 2 ? HDG_ENOCONV : HDG_EHIP);
+    const double rr0 = s.rr_stop / (o.rtol * o.rtol);
+    r.rel_res = rr0 > 0.0 ? std::sqrt(s.rr / rr0) : 0.0;
+    if (s.done == 0) r.status = HDG_EHIP;   // never finished: should not happen
+    if (r.status != HDG_OK && bad < 0) bad = i;
+    if (results) results[i] = r;
+  }
+  if (bad >= 0) {
+    const int d = b->h_A[bad].done;
+    overall = d == 2 ? HDG_ENOCONV : HDG_EHIP;
+    fail(overall, "problem %d stopped after %d iterations (%s)", bad, b->h_A[bad].iter,
+         d == 2 ? "iteration cap" : (d == 3 ? "CG breakdown" : "not finished"));
+  }
+  return overall;
+}
+
+}  // extern "C"

@@ -1,0 +1,240 @@
+// One work unit of the condensed HDG operator in the eigen-face basis (paper:
+// algorithm "HDG_Op_3D" for the transformed basis, section "Product
+// factorization of the HDG operator"), shared by the single-problem element
+// kernels and the batched persistent solver.  Per element e with transformed
+// faces x_{a,s} (axis a, side s) and metric factors d_0..d_3:
+//
+//   F[q1,q2,q3] = d1 sum_s BS[q1,s] x_{0,s}[q2,q3] + d2 sum_s BS[q2,s] x_{1,s}[q1,q3]
+//               + d3 sum_s BS[q3,s] x_{2,s}[q1,q2]
+//   u[q]        = F[q] / (lambda d0 + d1 Lam[q1] + d2 Lam[q2] + d3 Lam[q3])
+//   r_{0,s}[q2,q3] = d1 H x_{0,s} - d1 sum_q1 BS[q1,s] u[q1,q2,q3]   (same for axes 1, 2)
+//
+// The inverse eigenvalues are recomputed instead of stored (the paper stored
+// them; its roofline discussion notes that their n_p^3 loads cap the
+// intensity).  One thread per face-node column (q1,q2) walks q3 and keeps the
+// axis-2 reduction in registers; faces normal to x1, x2 and the element's u
+// go through LDS (u with an odd row pitch, so the axis-0 reduction is free of
+// bank conflicts).  For n_p >= 6 an element is owned by whole wavefronts (the
+// element record is wave-uniform and arrives through scalar loads); for
+// n_p <= 5 several elements share a wavefront.  Each interior face receives
+// one contribution from the element below it (qa) and one from the element
+// above it (qb): plain stores, no atomics, deterministic sums.
+#pragma once
+#include "device_common.hpp"
+
+namespace hdg {
+
+// ---- tile shapes ------------------------------------------------------------
+template <int NP>
+__host__ __device__ constexpr bool is_group() { return NP >= 6; }
+template <int NP>  // threads per element
+__host__ __device__ constexpr int tpe() { return is_group<NP>() ? round_up64(NP * NP) : NP * NP; }
+template <int NP>
+__host__ __device__ constexpr int upitch() { return NP | 1; }
+template <int NP>  // LDS words of one element (FP64 sizing)
+__host__ __device__ constexpr int lds_elem_words() {
+  return 4 * NP * NP + upitch<NP>() * NP * NP + 1;
+}
+// largest elements-per-unit for 256 threads and 60 KB of LDS
+template <int NP>
+__host__ __device__ constexpr int epb_max() {
+  constexpr int by_threads = (256 / tpe<NP>()) > 0 ? 256 / tpe<NP>() : 1;
+  constexpr int by_lds = (60000 / (8 * lds_elem_words<NP>())) > 0 ? 60000 / (8 * lds_elem_words<NP>()) : 1;
+  constexpr int e = by_threads < by_lds ? by_threads : by_lds;
+  return (is_group<NP>() && e > 4) ? 4 : e;
+}
+// tile variant v = 0, 1, 2: epb_max, epb_max/2, epb_max/4 elements per unit
+constexpr int kTileVariants = 3;
+template <int NP, int V>
+__host__ __device__ constexpr int epb_var() {
+  return (epb_max<NP>() >> V) > 0 ? (epb_max<NP>() >> V) : 1;
+}
+template <int NP, int EPB>
+__host__ __device__ constexpr int unit_threads() { return round_up64(EPB * tpe<NP>()); }
+
+// a / b through the hardware reciprocal, two Newton steps and one residual
+// correction (within about one ulp; no IEEE division sequence).
+__device__ inline double div_fast(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  double e = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  const double q = a * r;
+  return __builtin_fma(r, __builtin_fma(-b, q, a), q);
+}
+__device__ inline float div_fast(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// Pointers of one problem (already offset into batched storage).
+template <typename T>
+struct UnitIO {
+  const ElemInfo* info;
+  const double* lam;
+  int n_elem;
+  int nff;                 // number of free faces
+  // plain apply
+  const T* x_free;
+  const T* x_bdry;         // may be null
+  T* qa;
+  T* qb;
+  // fused CG apply
+  const T* r;
+  const T* dinv;
+  const T* p_in;
+  T* p_out;
+  T* x;
+  T beta;
+  T alpha_x;
+  bool finish;             // only the last x update remains
+};
+
+// 1D data of one degree seen through pointers (the batched solver keeps the
+// tables of all its degrees in its kernel arguments); apply_unit takes either
+// this or an ElemTab by value.
+template <typename T>
+struct TabRef {
+  const T* bs0;
+  const T* bs1;
+  const T* lam;
+  T H;
+};
+
+template <typename T, int NP, int EPB>
+struct UnitSmem {
+  T face[EPB][4][NP * NP];
+  T u[EPB][upitch<NP>() * NP * NP + 1];
+};
+
+// Processes elements [unit EPB, unit EPB + EPB).  Every thread of the block
+// calls it; threads beyond EPB * tpe idle.  Returns the thread's share of the
+// element-local quadratic forms p_e^T K_e p_e (MODE 1).
+template <typename T, int NP, int EPB, int MODE, typename Tab>
+__device__ inline double apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
+                                    int unit) {
+  constexpr int NF = NP * NP;
+  constexpr int TPE = tpe<NP>();
+  constexpr int P = upitch<NP>();
+  int slot, col;
+  if constexpr (is_group<NP>()) {
+    slot = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / TPE));   // wave-uniform
+    col = (int)(threadIdx.x % TPE);
+  } else {
+    slot = (int)(threadIdx.x / NF);
+    col = (int)(threadIdx.x % NF);
+  }
+  const bool colok = col < NF;
+  const int q1 = col % NP, q2 = col / NP;
+  const int e = unit * EPB + slot;
+  const bool active = slot < EPB && e < io.n_elem;
+  const int sl = slot < EPB ? slot : 0;
+  double dot = 0.0;
+
+  T d[4] = {0, 0, 0, 0};
+  int fid[6];
+  T xf[6];
+  if (active) {
+    const ElemInfo* ei = io.info + e;
+    d[0] = (T)(ei->d[0] * io.lam[e]);
+    d[1] = (T)ei->d[1];
+    d[2] = (T)ei->d[2];
+    d[3] = (T)ei->d[3];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      fid[f] = ei->fid[f];
+      T v = 0;
+      if (colok) {
+        if (fid[f] < io.nff) {
+          const int64_t g = (int64_t)fid[f] * NF + col;
+          if constexpr (MODE == 0) {
+            v = io.x_free[g];
+          } else {
+            const T pin = io.p_in[g];
+            if (f & 1) io.x[g] += io.alpha_x * pin;   // the element below owns the face
+            if (!io.finish) {
+              v = io.dinv[g] * io.r[g] + io.beta * pin;
+              if (f & 1) io.p_out[g] = v;
+            }
+          }
+        } else if (MODE == 0 && io.x_bdry != nullptr) {
+          v = io.x_bdry[(int64_t)(fid[f] - io.nff) * NF + col];
+        }
+        if (f < 4) sm.face[sl][f][col] = v;
+      }
+      xf[f] = v;
+    }
+  }
+  if constexpr (MODE == 1) {
+    if (io.finish) return 0.0;             // uniform over the unit's problem
+  }
+  __syncthreads();
+
+  // expansion into the element eigenspace, division, axis-2 reduction
+  T r2lo = 0, r2hi = 0;
+  if (active && colok) {
+    const T* f0lo = sm.face[sl][0];
+    const T* f0hi = sm.face[sl][1];
+    const T* f1lo = sm.face[sl][2];
+    const T* f1hi = sm.face[sl][3];
+    const T c0 = d[1] * tab.bs0[q1], c1 = d[1] * tab.bs1[q1];
+    const T c2 = d[2] * tab.bs0[q2], c3 = d[2] * tab.bs1[q2];
+    const T x2lo = d[3] * xf[4], x2hi = d[3] * xf[5];
+    const T dij = d[0] + d[1] * tab.lam[q1] + d[2] * tab.lam[q2];
+#pragma unroll
+    for (int q3 = 0; q3 < NP; ++q3) {
+      T F = c0 * f0lo[q2 + NP * q3];
+      F += c1 * f0hi[q2 + NP * q3];
+      F += c2 * f1lo[q1 + NP * q3];
+      F += c3 * f1hi[q1 + NP * q3];
+      F += tab.bs0[q3] * x2lo;
+      F += tab.bs1[q3] * x2hi;
+      const T u = div_fast(F, dij + d[3] * tab.lam[q3]);
+      sm.u[sl][q1 + P * (q2 + NP * q3)] = u;
+      r2lo += tab.bs0[q3] * u;
+      r2hi += tab.bs1[q3] * u;
+    }
+  }
+  __syncthreads();
+
+  // reductions back to the faces and the face-diagonal term
+  if (active && colok) {
+    T out[6];
+    {
+      // axis 0: face node (q2,q3) = col
+      const T* u = sm.u[sl] + P * col;
+      T lo = 0, hi = 0;
+#pragma unroll
+      for (int a = 0; a < NP; ++a) {
+        lo += tab.bs0[a] * u[a];
+        hi += tab.bs1[a] * u[a];
+      }
+      out[0] = d[1] * (tab.H * xf[0] - lo);
+      out[1] = d[1] * (tab.H * xf[1] - hi);
+    }
+    {
+      // axis 1: face node (q1,q3) = col
+      const T* u = sm.u[sl] + q1 + P * NP * q2;
+      T lo = 0, hi = 0;
+#pragma unroll
+      for (int b = 0; b < NP; ++b) {
+        lo += tab.bs0[b] * u[P * b];
+        hi += tab.bs1[b] * u[P * b];
+      }
+      out[2] = d[2] * (tab.H * xf[2] - lo);
+      out[3] = d[2] * (tab.H * xf[3] - hi);
+    }
+    out[4] = d[3] * (tab.H * xf[4] - r2lo);
+    out[5] = d[3] * (tab.H * xf[5] - r2hi);
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      if (fid[f] >= io.nff) continue;
+      const int64_t g = (int64_t)fid[f] * NF + col;
+      if (f & 1) io.qa[g] = out[f];
+      else io.qb[g] = out[f];
+      if constexpr (MODE == 1) dot += (double)(xf[f] * out[f]);
+    }
+  }
+  __syncthreads();                          // LDS is reused by the next unit
+  return dot;
+}
+
+}  // namespace hdg

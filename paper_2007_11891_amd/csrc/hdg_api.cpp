@@ -15,10 +15,11 @@
 
 #include "../../include/hdg.h"
 #include "hdg_internal.hpp"
+#include "host_util.hpp"
 
 using namespace hdg;
 
-namespace {
+namespace hdg {
 
 thread_local std::string g_err;
 
@@ -32,35 +33,9 @@ hdg_status fail(hdg_status st, const char* fmt, ...) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                                  \
-  do {                                                                                 \
-    hipError_t _e = (expr);                                                            \
-    if (_e != hipSuccess)                                                              \
-      return fail(HDG_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),      \
-                  __FILE__, __LINE__);                                                 \
-  } while (0)
+}  // namespace hdg
 
-template <typename T>
-hdg_status dalloc(T** p, int64_t n) {
-  *p = nullptr;
-  if (n <= 0) n = 1;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)n);
-  if (e != hipSuccess) return fail(HDG_ENOMEM, "hipMalloc of %lld bytes failed: %s",
-                                   (long long)(sizeof(T) * n), hipGetErrorString(e));
-  return HDG_OK;
-}
-
-template <typename T>
-void dfree(T*& p) {
-  if (p) (void)hipFree(p);
-  p = nullptr;
-}
-
-#define ST_TRY(expr)                  \
-  do {                                \
-    hdg_status _s = (expr);           \
-    if (_s != HDG_OK) return _s;      \
-  } while (0)
+namespace {
 
 // Blocks of the CG vector kernels: 256 threads x 4 elements per thread, at
 // most 256 blocks so that the apply blocks that re-sum the update partials
@@ -76,15 +51,18 @@ hdg_status alloc_work(hdg_ctx* c, CgWork<T>& w) {
   if (w.x) return HDG_OK;
   const int64_t n = c->n_free;
   w.n = n;
-  w.apply_blocks = std::max(1, elem_apply_blocks(c->np, c->n_elem));
+  w.apply_blocks = std::max(1, elem_apply_blocks(c->np, c->n_elem, c->tile_variant));
   w.update_blocks = vec_blocks_for(n);
+  int max_apply = 1;
+  for (int v = 0; v < kNumTileVariants; ++v)
+    max_apply = std::max(max_apply, elem_apply_blocks(c->np, c->n_elem, v));
   ST_TRY(dalloc(&w.x, n));
   ST_TRY(dalloc(&w.r, n));
   ST_TRY(dalloc(&w.p[0], n));
   ST_TRY(dalloc(&w.p[1], n));
   ST_TRY(dalloc(&w.qa, n));
   ST_TRY(dalloc(&w.qb, n));
-  w.pmax = std::max(w.apply_blocks, w.update_blocks);
+  w.pmax = std::max(max_apply, w.update_blocks);
   ST_TRY(dalloc(&w.partials, 6 * (int64_t)w.pmax));
   ST_TRY(dalloc(&w.sc, 1));
   HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(CgScalars), c->stream));
@@ -851,6 +829,50 @@ hdg_status hdg_adjoint(hdg_ctx* c, const double* f, const double* trace, const d
     return fail(HDG_EHIP, "adjoint gradient kernel failed: %s",
                 hipGetErrorString(e != hipSuccess ? e : e2));
   return st;
+}
+
+hdg_status hdg_set_tile(hdg_ctx* c, int variant) {
+  if (!c) return fail(HDG_EINVAL, "ctx is NULL");
+  if (variant < 0 || variant >= kNumTileVariants)
+    return fail(HDG_EINVAL, "tile variant must be in [0, %d)", kNumTileVariants);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->tile_variant = variant;
+  for (CgWork<double>* w : {&c->w64}) {
+    if (w->x) w->apply_blocks = std::max(1, elem_apply_blocks(c->np, c->n_elem, variant));
+    if (w->graph) (void)hipGraphExecDestroy(w->graph);
+    w->graph = nullptr;
+  }
+  if (c->w32.x) c->w32.apply_blocks = std::max(1, elem_apply_blocks(c->np, c->n_elem, variant));
+  if (c->w32.graph) (void)hipGraphExecDestroy(c->w32.graph);
+  c->w32.graph = nullptr;
+  return HDG_OK;
+}
+
+hdg_status hdg_autotune(hdg_ctx* c, int reps, int* chosen, double* times_ms) {
+  if (!c || reps < 1) return fail(HDG_EINVAL, "invalid argument");
+  if (c->n_free == 0) {
+    if (chosen) *chosen = c->tile_variant;
+    return HDG_OK;
+  }
+  // time the fused FP64 CG iteration (apply + update) of every tile variant
+  // on this context's mesh, keep the fastest
+  double best = 1e300;
+  int best_v = 0;
+  double* x = c->d_tmp[1];
+  HIP_TRY(launch_fill64(x, 1.0, c->n_free, c->stream));
+  for (int v = 0; v < kNumTileVariants; ++v) {
+    ST_TRY(hdg_set_tile(c, v));
+    double ms = 0.0;
+    ST_TRY(hdg_time_kernel(c, 2, x, nullptr, reps, &ms));
+    if (times_ms) times_ms[v] = ms;
+    if (ms < best) {
+      best = ms;
+      best_v = v;
+    }
+  }
+  ST_TRY(hdg_set_tile(c, best_v));
+  if (chosen) *chosen = best_v;
+  return HDG_OK;
 }
 
 hdg_status hdg_diagonal(hdg_ctx* c, double* diag_free) {

@@ -100,6 +100,7 @@ struct KernelConfig {
 struct hdg_ctx {
   int n[3] = {0, 0, 0};
   int p = 0, np = 0;
+  int tile_variant = 0;           // elements per work unit: epb_max >> variant
   double tau = 0.0;
   int64_t n_elem = 0, n_free = 0, n_all = 0, n_vol = 0;
   int64_t n_free_faces = 0, n_faces = 0;
@@ -185,7 +186,10 @@ hipError_t launch_recip_64_32(const double* diag, float* dinv32, double* dinv64,
 hipError_t launch_dot64(const double* a, const double* b, int64_t n, double* partials,
                         double* out, int nblocks, hipStream_t s);
 
-// grid size of the element apply kernels (number of partials they write)
-int elem_apply_blocks(int np, int64_t n_elem);
+// grid size of the element apply kernels (number of partials they write) and
+// elements per work unit of a tile variant
+int elem_apply_blocks(int np, int64_t n_elem, int variant);
+int tile_epb(int np, int variant);
+constexpr int kNumTileVariants = 3;
 
 }  // namespace hdg

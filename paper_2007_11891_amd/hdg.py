@@ -29,7 +29,9 @@ EXPORTS = (
     "hdg_default_opts", "hdg_create", "hdg_destroy", "hdg_last_error", "hdg_sizes",
     "hdg_set_lambda", "hdg_tables", "hdg_coords", "hdg_apply", "hdg_face_transform",
     "hdg_rhs", "hdg_solve", "hdg_solve_forcing", "hdg_reconstruct", "hdg_adjoint",
-    "hdg_diagonal", "hdg_time_kernel",
+    "hdg_diagonal", "hdg_time_kernel", "hdg_set_tile", "hdg_autotune",
+    "hdg_batch_create", "hdg_batch_destroy", "hdg_batch_sizes", "hdg_batch_set_tile",
+    "hdg_batch_tiles", "hdg_batch_autotune", "hdg_batch_time_cg", "hdg_batch_solve_forcing",
 )
 
 
@@ -49,6 +51,13 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int),
                 ("rel_res", ctypes.c_double), ("rhs_norm", ctypes.c_double),
                 ("t_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchResult(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("rel_res", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -89,6 +98,18 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                        ctypes.POINTER(SolveInfo)]),
         "hdg_diagonal": (ctypes.c_int, [vp, vp]),
         "hdg_time_kernel": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int, dp]),
+        "hdg_set_tile": (ctypes.c_int, [vp, ctypes.c_int]),
+        "hdg_autotune": (ctypes.c_int, [vp, ctypes.c_int, ip, dp]),
+        "hdg_batch_create": (ctypes.c_int, [ctypes.c_int, ip, ip, dp, ctypes.c_double, vp,
+                                            ctypes.POINTER(vp)]),
+        "hdg_batch_destroy": (ctypes.c_int, [vp]),
+        "hdg_batch_sizes": (ctypes.c_int, [vp, i64p, i64p, i64p, i64p]),
+        "hdg_batch_set_tile": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
+        "hdg_batch_tiles": (ctypes.c_int, [vp, ip]),
+        "hdg_batch_autotune": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ip]),
+        "hdg_batch_time_cg": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp]),
+        "hdg_batch_solve_forcing": (ctypes.c_int, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                                   ctypes.POINTER(BatchResult), dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -322,6 +343,16 @@ class HdgContext:
         _check(self._lib.hdg_diagonal(self._h, _dptr(d, self.sizes.n_free, torch.float64, "diag")))
         return d
 
+    def set_tile(self, variant: int):
+        _check(self._lib.hdg_set_tile(self._h, int(variant)))
+
+    def autotune(self, reps: int = 20):
+        """Pick the fastest element-kernel tile variant; returns (variant, times_ms)."""
+        ch = ctypes.c_int()
+        t = (ctypes.c_double * 3)()
+        _check(self._lib.hdg_autotune(self._h, int(reps), ctypes.byref(ch), t))
+        return ch.value, list(t)
+
     def time_kernel(self, which: int, x, reps: int = 100, y=None) -> float:
         """Mean launch time (ms) of an internal kernel, HIP events on the context stream."""
         ms = ctypes.c_double()
@@ -329,3 +360,91 @@ class HdgContext:
         _check(self._lib.hdg_time_kernel(self._h, int(which), ctypes.c_void_p(x.data_ptr()),
                                          yp, int(reps), ctypes.byref(ms)))
         return ms.value
+
+
+class HdgBatch:
+    """Independent unit-cube problems (uniform meshes, constant lambda, zero
+    Dirichlet data) solved together by the persistent batched CG."""
+
+    def __init__(self, n_elem: Sequence[Sequence[int]], p: Sequence[int], lam: Sequence[float],
+                 tau: float = 1.0, device=None):
+        torch = _torch()
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU")
+        self._lib = lib
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        ne = np.ascontiguousarray(np.asarray(n_elem, dtype=np.int32).reshape(-1, 3))
+        self.count = ne.shape[0]
+        pp = np.ascontiguousarray(np.asarray(p, dtype=np.int32).reshape(-1))
+        ll = np.ascontiguousarray(np.asarray(lam, dtype=np.float64).reshape(-1))
+        if pp.size != self.count or ll.size != self.count:
+            raise ValueError("n_elem, p and lam must describe the same number of problems")
+        self.n_elem, self.p, self.lam = ne, pp, ll
+        ip = ctypes.POINTER(ctypes.c_int)
+        with torch.cuda.device(self.device):
+            self._stream = torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            _check(lib.hdg_batch_create(self.count, ne.ctypes.data_as(ip), pp.ctypes.data_as(ip),
+                                        ll.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        float(tau), ctypes.c_void_p(self._stream.cuda_stream),
+                                        ctypes.byref(h)))
+        self._h = h
+        nf = np.zeros(self.count, dtype=np.int64)
+        nv = np.zeros(self.count, dtype=np.int64)
+        tf, tv = ctypes.c_int64(), ctypes.c_int64()
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        _check(lib.hdg_batch_sizes(self._h, nf.ctypes.data_as(i64p), nv.ctypes.data_as(i64p),
+                                   ctypes.byref(tf), ctypes.byref(tv)))
+        self.n_free, self.n_vol = nf, nv
+        self.total_free, self.total_vol = tf.value, tv.value
+        self.free_off = np.concatenate([[0], np.cumsum(nf)])
+        self.vol_off = np.concatenate([[0], np.cumsum(nv)])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hdg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tile(self, p: int, variant: int):
+        _check(self._lib.hdg_batch_set_tile(self._h, int(p), int(variant)))
+
+    def tiles(self) -> dict:
+        v = (ctypes.c_int * 17)()
+        _check(self._lib.hdg_batch_tiles(self._h, v))
+        return {q: v[q] for q in range(17) if v[q] >= 0}
+
+    def autotune(self, iters: int = 20, reps: int = 3) -> dict:
+        v = (ctypes.c_int * 17)()
+        _check(self._lib.hdg_batch_autotune(self._h, int(iters), int(reps), v))
+        return {q: v[q] for q in range(17) if v[q] >= 0}
+
+    def time_cg(self, iters: int, reps: int = 3) -> float:
+        ms = ctypes.c_double()
+        _check(self._lib.hdg_batch_time_cg(self._h, int(iters), int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    def solve_forcing(self, f, trace_free=None, u_vol=None, want_volume: bool = True,
+                      opts: Optional[SolveOpts] = None, allow_noconv: bool = False):
+        """f: concatenated volume forcing; returns (trace_free, u_vol, results, t_ms)."""
+        torch = _torch()
+        if trace_free is None:
+            trace_free = torch.empty(self.total_free, dtype=torch.float64, device=self.device)
+        if want_volume and u_vol is None:
+            u_vol = torch.empty(self.total_vol, dtype=torch.float64, device=self.device)
+        res = (BatchResult * self.count)()
+        ms = ctypes.c_double()
+        o = opts or default_opts()
+        st = self._lib.hdg_batch_solve_forcing(
+            self._h, _dptr(f, self.total_vol, torch.float64, "f"),
+            _dptr(trace_free, self.total_free, torch.float64, "trace_free"),
+            _dptr(u_vol, self.total_vol, torch.float64, "u_vol") if want_volume else None,
+            ctypes.byref(o), res, ctypes.byref(ms))
+        _check(st, allow_noconv=allow_noconv)
+        return trace_free, u_vol, [r.as_dict() for r in res], ms.value

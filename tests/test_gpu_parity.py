@@ -236,3 +236,35 @@ def test_empty_and_degenerate_meshes():
     assert rel_err(y, o2.apply_free(x)) < 1e-12
     with pytest.raises((ValueError, pkg.HdgError)):
         c2.apply(to_dev(x), to_dev(np.zeros(8)))
+
+
+TILE_CASES = [((5, 3, 4), 1), ((4, 3, 3), 3), ((3, 4, 3), 5), ((3, 3, 2), 6), ((2, 3, 3), 8),
+              ((2, 2, 3), 10), ((2, 2, 2), 12)]
+
+
+@pytest.mark.parametrize("n,p", TILE_CASES)
+def test_every_tile_variant_matches_oracle(n, p):
+    """Each tile shape (elements per work unit, ragged last unit) gives the
+    assembled operator's product, and the same CG solution."""
+    import paper_2007_11891_amd as pkg
+    print(f"[tile variants] n={n} p={p}", flush=True)
+    o, c = _pair(n, p)
+    K = o.assemble_K()
+    nf = o.layout.n_free
+    x = W.random_trace(nf, 300 + p)
+    y_ref = K[:nf, :nf] @ x
+    X = o.volume_coords()
+    f = W.f_sin3(*X.T, 1.0)
+    ut_ref = o.solve(f, np.zeros(o.layout.n_all))
+    for v in range(3):
+        c.set_tile(v)
+        y = to_host(c.apply(to_dev(x), basis="nodal"))
+        assert rel_err(y, y_ref) < 1e-12, v
+        tr, _, info = c.solve_forcing(to_dev(f), c.zeros_trace(), want_volume=False,
+                                      opts=pkg.default_opts(rtol=1e-15, maxit=1500),
+                                      allow_noconv=True)
+        assert rel_err(to_host(tr)[:nf], ut_ref[:nf]) < 1e-12, (v, info)
+    chosen, times = c.autotune(reps=5)
+    assert chosen in (0, 1, 2) and all(t > 0 for t in times)
+    y = to_host(c.apply(to_dev(x), basis="nodal"))
+    assert rel_err(y, y_ref) < 1e-12

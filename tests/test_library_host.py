@@ -92,3 +92,35 @@ def test_tables_reject_bad_degree():
     _lib()
     with pytest.raises(pkg.HdgError):
         pkg.tables(0, 1.0)
+
+
+def test_batch_create_rejects_invalid_arguments_without_gpu_work():
+    lib = _lib()
+    out = ctypes.c_void_p()
+    ip = ctypes.POINTER(ctypes.c_int)
+    dp = ctypes.POINTER(ctypes.c_double)
+
+    def call(count, n, p, lam, tau=1.0):
+        na = (ctypes.c_int * len(n))(*n)
+        pa = (ctypes.c_int * len(p))(*p)
+        la = (ctypes.c_double * len(lam))(*lam)
+        return lib.hdg_batch_create(count, ctypes.cast(na, ip), ctypes.cast(pa, ip),
+                                    ctypes.cast(la, dp), tau, None, ctypes.byref(out))
+
+    cases = [
+        (0, [2, 2, 2], [3], [1.0], 1.0),              # no problems
+        (1, [2, 0, 2], [3], [1.0], 1.0),              # empty axis
+        (1, [2, 2, 5000], [3], [1.0], 1.0),           # axis too long
+        (1, [2, 2, 2], [11], [1.0], 1.0),             # degree beyond the batched kernels
+        (1, [2, 2, 2], [0], [1.0], 1.0),              # degree 0
+        (2, [2, 2, 2, 2, 2, 2], [3, 4], [1.0, -1.0], 1.0),   # lambda < 0
+        (1, [2, 2, 2], [3], [float("nan")], 1.0),     # lambda NaN
+        (1, [2, 2, 2], [3], [1.0], 0.0),              # tau = 0
+    ]
+    for count, n, p, lam, tau in cases:
+        assert call(count, n, p, lam, tau) == -1, (count, n, p, lam, tau)
+        assert out.value is None
+        assert lib.hdg_last_error()
+    assert lib.hdg_batch_create(1, None, None, None, 1.0, None, ctypes.byref(out)) == -1
+    assert lib.hdg_batch_destroy(None) == 0
+
