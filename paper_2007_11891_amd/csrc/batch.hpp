@@ -15,8 +15,15 @@ __host__ __device__ constexpr int batch_tab_off(int np) {
 }
 constexpr int kBatchMaxNP = 11;
 constexpr int kBatchTabWords = batch_tab_off(kBatchMaxNP + 1);
-struct BatchTabs {
-  double v[kBatchTabWords];
+
+// A contiguous piece of one problem's work owned by one block: element work
+// units [begin, end) in the apply phase, free-trace entries [begin, end) in
+// the vector phases (both relative to the problem).
+struct BatchSeg {
+  int prob;
+  int begin;
+  int end;
+  int pad;
 };
 
 struct BatchProbDev {
@@ -28,8 +35,8 @@ struct BatchProbDev {
   int variant;          // tile variant of the element work units
   int64_t off;          // offset of the free trace in the concatenated vectors
   int64_t n;            // free trace length
-  int unit_begin, n_units;
-  int chunk_begin, n_chunks;
+  int useg_begin, n_usegs;   // apply segments (consecutive in the global list)
+  int vseg_begin, n_vsegs;   // vector segments (consecutive in the global list)
   int maxit;
   int pad;
   double rtol2;
@@ -46,22 +53,22 @@ struct BatchState {
 };
 
 struct GridBar {
-  unsigned count;
-  unsigned gen;
-  unsigned done_count;
-  unsigned err;
+  unsigned pad0;
+  unsigned done_count;  // problems finished
+  unsigned err;         // a barrier wait timed out
+  unsigned pad;
 };
+
+constexpr int kFlagStride = 32;   // one 128-byte line per block arrival flag
 
 struct BatchArgs {
   const BatchProbDev* probs;
   int n_probs;
   int max_iters;
-  const int* unit_prob;
-  const int* chunk_prob;
-  const int* unit_range;    // [nblocks + 1]
-  const int* chunk_range;   // [nblocks + 1]
-  int n_units_total;
-  int n_chunks_total;
+  const BatchSeg* useg;
+  const int* useg_range;    // [nblocks + 1]
+  const BatchSeg* vseg;
+  const int* vseg_range;    // [nblocks + 1]
   double* x;
   double* r;
   double* p0;
@@ -70,18 +77,19 @@ struct BatchArgs {
   double* qb;
   const double* dinv;
   const double* b;
-  double* ppq;              // [2][n_units_total]
-  double* prz;              // [2][n_chunks_total]
-  double* prr;              // [2][n_chunks_total]
+  double* ppq;              // [n_useg]
+  double* prz;              // [n_vseg]
+  double* prr;              // [n_vseg]
   BatchState* A;
   BatchState* B;
   GridBar* bar;
-  BatchTabs tabs;
+  unsigned* flags;          // [2][nblocks * kFlagStride]: arrival, release lines
+  const double* tabs;       // [kBatchTabWords], written by the host before the launch
 };
 
 hipError_t batch_occupancy(int* blocks_per_cu);
-hipError_t launch_batch_reset(BatchState* A, BatchState* B, GridBar* bar, int n, hipStream_t s);
+hipError_t launch_batch_reset(BatchState* A, BatchState* B, GridBar* bar, unsigned* flags,
+                              int n_probs, int nblocks, hipStream_t s);
 hipError_t launch_batch_cg(const BatchArgs& args, int nblocks, hipStream_t s);
-int batch_chunk();
 
 }  // namespace hdg

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 #include <cmath>
 #include <new>
 #include <numeric>
@@ -28,7 +30,8 @@ struct hdg_batch {
   std::vector<int64_t> off, voff;   // free-trace and volume offsets
   int64_t total_free = 0, total_vol = 0;
   int variant[kMaxNP + 1];          // tile variant per degree p (index p)
-  BatchTabs tabs{};
+  std::vector<double> tabs;         // per-degree tables, packed as batch_tab_off
+  double* d_tabs = nullptr;
   // concatenated FP64 vectors (total_free each)
   double* d_b = nullptr;
   double* d_x = nullptr;
@@ -40,16 +43,17 @@ struct hdg_batch {
   double* d_dinv = nullptr;
   // schedule
   int nblocks = 0;
-  int n_units = 0, n_chunks = 0, max_units = 0;
+  int max_segs = 0;                 // bound on segments per phase: count + nblocks
   std::vector<BatchProbDev> probs;
   BatchProbDev* d_probs = nullptr;
-  int* d_unit_prob = nullptr;       // [max_units]
-  int* d_chunk_prob = nullptr;      // [n_chunks]
-  int* d_unit_range = nullptr;      // [nblocks + 1]
-  int* d_chunk_range = nullptr;     // [nblocks + 1]
-  double* d_ppq = nullptr;          // [2][max_units]
-  double* d_prz = nullptr;          // [2][n_chunks]
+  BatchSeg* d_useg = nullptr;       // [max_segs]
+  BatchSeg* d_vseg = nullptr;       // [max_segs]
+  int* d_useg_range = nullptr;      // [nblocks + 1]
+  int* d_vseg_range = nullptr;      // [nblocks + 1]
+  double* d_ppq = nullptr;          // [max_segs]
+  double* d_prz = nullptr;          // [max_segs]
   double* d_prr = nullptr;
+  unsigned* d_flags = nullptr;      // [2 * nblocks * kFlagStride]
   BatchState* d_A = nullptr;
   BatchState* d_B = nullptr;
   GridBar* d_bar = nullptr;
@@ -75,61 +79,100 @@ namespace {
 // number of elements in it.
 double unit_cost(int np) { return 8.0 + np; }
 
-// Contiguous ranges of items (in order) with about equal summed cost:
-// item i goes to the block holding the midpoint of its cost interval.
-void balance(const std::vector<double>& cost, int nb, std::vector<int>& range) {
-  range.assign(nb + 1, (int)cost.size());
-  double total = 0.0;
-  for (double c : cost) total += c;
-  const double per = total > 0.0 ? total / nb : 1.0;
-  double acc = 0.0;
-  int next = 0;   // first block whose start is not yet set
-  for (int i = 0; i < (int)cost.size(); ++i) {
-    const double mid = acc + 0.5 * cost[i];
-    acc += cost[i];
-    const int blk = std::min(nb - 1, (int)(mid / per));
-    while (next <= blk) range[next++] = i;
-  }
-  while (next < nb) range[next++] = (int)cost.size();
-  range[0] = 0;
-}
-
+// Splits the problems' work into per-block segments.  Apply phase: the
+// global list of work units (problem-major) is cut into nb contiguous ranges
+// of about equal cost, each range into one segment per problem it touches.
+// Vector phases: the concatenated free trace is cut into nb ranges of about
+// equal length (multiples of 64 entries), likewise; a problem without free
+// entries gets one empty segment.  Segments are listed block by block, so a
+// problem's segments are consecutive in both lists.
 hdg_status build_schedule(hdg_batch* b) {
-  const int chunk = batch_chunk();
-  std::vector<int> unit_prob, chunk_prob;
-  std::vector<double> ucost, ccost;
+  const int nb = b->nblocks;
+  std::vector<int64_t> ubeg(b->count + 1, 0);
   for (int i = 0; i < b->count; ++i) {
     const hdg_ctx* c = b->sub[i];
     BatchProbDev& P = b->probs[i];
     P.variant = b->variant[c->p];
     const int epb = tile_epb(c->np, P.variant);
-    P.unit_begin = (int)unit_prob.size();
-    P.n_units = (int)((c->n_elem + epb - 1) / epb);
-    for (int u = 0; u < P.n_units; ++u) {
-      unit_prob.push_back(i);
-      ucost.push_back(unit_cost(c->np));
-    }
-    P.chunk_begin = (int)chunk_prob.size();
-    P.n_chunks = (int)std::max<int64_t>(1, (c->n_free + chunk - 1) / chunk);
-    for (int k = 0; k < P.n_chunks; ++k) {
-      chunk_prob.push_back(i);
-      ccost.push_back(1.0);
+    ubeg[i + 1] = ubeg[i] + (c->n_elem + epb - 1) / epb;
+  }
+  // apply segments: unit u goes to the block holding the midpoint of its
+  // cost interval; ucut[k] is the first unit of block k
+  const int64_t U = ubeg[b->count];
+  std::vector<int64_t> ucut(nb + 1, U);
+  {
+    double total = 0.0;
+    for (int i = 0; i < b->count; ++i)
+      total += (double)(ubeg[i + 1] - ubeg[i]) * unit_cost(b->sub[i]->np);
+    const double per = total > 0.0 ? total / nb : 1.0;
+    double acc = 0.0;
+    int next = 1;
+    ucut[0] = 0;
+    for (int i = 0; i < b->count; ++i) {
+      const double w = unit_cost(b->sub[i]->np);
+      for (int64_t u = ubeg[i]; u < ubeg[i + 1]; ++u) {
+        const int blk = std::min(nb - 1, (int)((acc + 0.5 * w) / per));
+        while (next <= blk) ucut[next++] = u;
+        acc += w;
+      }
     }
   }
-  if ((int)unit_prob.size() > b->max_units || (int)chunk_prob.size() != b->n_chunks)
+  std::vector<BatchSeg> useg, vseg;
+  std::vector<int> urange(nb + 1), vrange(nb + 1);
+  for (auto& P : b->probs) P.n_usegs = P.n_vsegs = 0;
+  int prob = 0;
+  for (int blk = 0; blk < nb; ++blk) {
+    urange[blk] = (int)useg.size();
+    for (int64_t u = ucut[blk]; u < ucut[blk + 1];) {
+      while (ubeg[prob + 1] <= u) ++prob;
+      const int64_t e = std::min(ucut[blk + 1], ubeg[prob + 1]);
+      BatchProbDev& P = b->probs[prob];
+      if (P.n_usegs++ == 0) P.useg_begin = (int)useg.size();
+      useg.push_back(BatchSeg{prob, (int)(u - ubeg[prob]), (int)(e - ubeg[prob]), 0});
+      u = e;
+    }
+  }
+  urange[nb] = (int)useg.size();
+  // vector segments: cut points on the concatenated free trace
+  const int64_t N = b->total_free;
+  std::vector<int64_t> vcut(nb + 1);
+  for (int k = 0; k <= nb; ++k) vcut[k] = std::min<int64_t>(N, (N * k / nb + 32) / 64 * 64);
+  vcut[0] = 0;
+  vcut[nb] = N;
+  int blk = 0;
+  for (int i = 0; i < b->count; ++i) {
+    BatchProbDev& P = b->probs[i];
+    const int64_t lo0 = b->off[i], hi0 = b->off[i] + b->sub[i]->n_free;
+    int64_t lo = lo0;
+    do {
+      // block whose range holds lo (an empty problem at the very end goes to the last block)
+      while (blk + 1 < nb && vcut[blk + 1] <= lo) ++blk;
+      const int64_t hi = std::min(hi0, vcut[blk + 1]);
+      if (P.n_vsegs++ == 0) P.vseg_begin = (int)vseg.size();
+      vseg.push_back(BatchSeg{i, (int)(lo - lo0), (int)(hi - lo0), blk});
+      lo = hi;
+    } while (lo < hi0);
+  }
+  // per-block ranges (the pad field held the block while building)
+  {
+    size_t k = 0;
+    for (int bl = 0; bl <= nb; ++bl) {
+      while (k < vseg.size() && vseg[k].pad < bl) ++k;
+      vrange[bl] = (int)k;
+    }
+    vrange[nb] = (int)vseg.size();
+    for (auto& sg : vseg) sg.pad = 0;
+  }
+  if ((int)useg.size() > b->max_segs || (int)vseg.size() > b->max_segs)
     return fail(HDG_EINVAL, "internal: schedule exceeds its buffers");
-  b->n_units = (int)unit_prob.size();
-  std::vector<int> urange, crange;
-  balance(ucost, b->nblocks, urange);
-  balance(ccost, b->nblocks, crange);
+  for (const auto& P : b->probs)
+    if (P.n_usegs < 1 || P.n_vsegs < 1) return fail(HDG_EINVAL, "internal: problem without segments");
   HIP_TRY(hipStreamSynchronize(b->stream));
-  HIP_TRY(hipMemcpy(b->d_unit_prob, unit_prob.data(), sizeof(int) * unit_prob.size(),
+  HIP_TRY(hipMemcpy(b->d_useg, useg.data(), sizeof(BatchSeg) * useg.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_vseg, vseg.data(), sizeof(BatchSeg) * vseg.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_useg_range, urange.data(), sizeof(int) * urange.size(),
                     hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(b->d_chunk_prob, chunk_prob.data(), sizeof(int) * chunk_prob.size(),
-                    hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(b->d_unit_range, urange.data(), sizeof(int) * urange.size(),
-                    hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(b->d_chunk_range, crange.data(), sizeof(int) * crange.size(),
+  HIP_TRY(hipMemcpy(b->d_vseg_range, vrange.data(), sizeof(int) * vrange.size(),
                     hipMemcpyHostToDevice));
   b->probs_maxit = -1;   // force a re-upload of the problem records
   return HDG_OK;
@@ -154,12 +197,10 @@ BatchArgs make_args(const hdg_batch* b, int max_iters) {
   a.probs = b->d_probs;
   a.n_probs = b->count;
   a.max_iters = max_iters;
-  a.unit_prob = b->d_unit_prob;
-  a.chunk_prob = b->d_chunk_prob;
-  a.unit_range = b->d_unit_range;
-  a.chunk_range = b->d_chunk_range;
-  a.n_units_total = b->n_units;
-  a.n_chunks_total = b->n_chunks;
+  a.useg = b->d_useg;
+  a.useg_range = b->d_useg_range;
+  a.vseg = b->d_vseg;
+  a.vseg_range = b->d_vseg_range;
   a.x = b->d_x;
   a.r = b->d_r;
   a.p0 = b->d_p0;
@@ -174,7 +215,8 @@ BatchArgs make_args(const hdg_batch* b, int max_iters) {
   a.A = b->d_A;
   a.B = b->d_B;
   a.bar = b->d_bar;
-  a.tabs = b->tabs;
+  a.flags = b->d_flags;
+  a.tabs = b->d_tabs;
   return a;
 }
 
@@ -250,7 +292,7 @@ hdg_status build_pipeline(hdg_batch* b, const double* f, double* trace, double* 
   if (!b->split) {
     HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = enqueue_rhs(b, f, b->cap_stream);
-    if (e == hipSuccess) e = launch_batch_reset(b->d_A, b->d_B, b->d_bar, b->count, b->cap_stream);
+    if (e == hipSuccess) e = launch_batch_reset(b->d_A, b->d_B, b->d_bar, b->d_flags, b->count, b->nblocks, b->cap_stream);
     if (e == hipSuccess) e = launch_batch_cg(args, b->nblocks, b->cap_stream);
     if (e == hipSuccess) e = enqueue_recovery(b, f, trace, u_vol, b->cap_stream);
     if (capture_end(b, e, &b->graph_pre) != HDG_OK) b->split = true;
@@ -258,7 +300,7 @@ hdg_status build_pipeline(hdg_batch* b, const double* f, double* trace, double* 
   if (b->split) {
     HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = enqueue_rhs(b, f, b->cap_stream);
-    if (e == hipSuccess) e = launch_batch_reset(b->d_A, b->d_B, b->d_bar, b->count, b->cap_stream);
+    if (e == hipSuccess) e = launch_batch_reset(b->d_A, b->d_B, b->d_bar, b->d_flags, b->count, b->nblocks, b->cap_stream);
     ST_TRY(capture_end(b, e, &b->graph_pre));
     HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     e = enqueue_recovery(b, f, trace, u_vol, b->cap_stream);
@@ -292,10 +334,12 @@ hdg_status hdg_batch_destroy(hdg_batch* b) {
                      &b->d_dinv, &b->d_ppq, &b->d_prz, &b->d_prr})
     dfree(*p);
   dfree(b->d_probs);
-  dfree(b->d_unit_prob);
-  dfree(b->d_chunk_prob);
-  dfree(b->d_unit_range);
-  dfree(b->d_chunk_range);
+  dfree(b->d_useg);
+  dfree(b->d_vseg);
+  dfree(b->d_useg_range);
+  dfree(b->d_vseg_range);
+  dfree(b->d_flags);
+  dfree(b->d_tabs);
   dfree(b->d_A);
   dfree(b->d_B);
   dfree(b->d_bar);
@@ -347,6 +391,8 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
     if ((st = hdg_create(ne, h[0].data(), h[1].data(), h[2].data(), p[i], tau_hat, nullptr,
                          lambda[i], stream, &b->sub[i])) != HDG_OK)
       return cleanup(st);
+    if (b->sub[i]->n_free > INT32_MAX || b->sub[i]->n_elem > INT32_MAX)
+      return cleanup(fail(HDG_EINVAL, "problem %d too large for the batched solver", i));
     b->off[i] = b->total_free;
     b->voff[i] = b->total_vol;
     b->total_free += b->sub[i]->n_free;
@@ -370,24 +416,17 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
     return cleanup(fail(HDG_EHIP, "device attribute query failed"));
   b->nblocks = std::min(per_cu, 2) * n_cu;
-  // buffers sized for the largest schedule (variant 2 has the most units)
-  const int chunk = batch_chunk();
-  int64_t units = 0, chunks = 0;
-  for (int i = 0; i < count; ++i) {
-    const hdg_ctx* c = b->sub[i];
-    units += (c->n_elem + tile_epb(c->np, 2) - 1) / tile_epb(c->np, 2);
-    chunks += std::max<int64_t>(1, (c->n_free + chunk - 1) / chunk);
-  }
-  if (units > (1 << 30) || chunks > (1 << 30)) return cleanup(fail(HDG_EINVAL, "batch too large"));
-  b->max_units = (int)units;
-  b->n_chunks = (int)chunks;
-  if ((st = dalloc(&b->d_probs, count)) != HDG_OK || (st = dalloc(&b->d_unit_prob, units)) != HDG_OK ||
-      (st = dalloc(&b->d_chunk_prob, chunks)) != HDG_OK ||
-      (st = dalloc(&b->d_unit_range, b->nblocks + 1)) != HDG_OK ||
-      (st = dalloc(&b->d_chunk_range, b->nblocks + 1)) != HDG_OK ||
-      (st = dalloc(&b->d_ppq, 2 * units)) != HDG_OK || (st = dalloc(&b->d_prz, 2 * chunks)) != HDG_OK ||
-      (st = dalloc(&b->d_prr, 2 * chunks)) != HDG_OK || (st = dalloc(&b->d_A, count)) != HDG_OK ||
-      (st = dalloc(&b->d_B, count)) != HDG_OK || (st = dalloc(&b->d_bar, 1)) != HDG_OK)
+  // each block range splits into at most one more segment than problems it touches
+  b->max_segs = count + b->nblocks + 1;
+  const int ms = b->max_segs;
+  if ((st = dalloc(&b->d_probs, count)) != HDG_OK || (st = dalloc(&b->d_useg, ms)) != HDG_OK ||
+      (st = dalloc(&b->d_vseg, ms)) != HDG_OK ||
+      (st = dalloc(&b->d_useg_range, b->nblocks + 1)) != HDG_OK ||
+      (st = dalloc(&b->d_vseg_range, b->nblocks + 1)) != HDG_OK ||
+      (st = dalloc(&b->d_ppq, ms)) != HDG_OK || (st = dalloc(&b->d_prz, ms)) != HDG_OK ||
+      (st = dalloc(&b->d_prr, ms)) != HDG_OK || (st = dalloc(&b->d_A, count)) != HDG_OK ||
+      (st = dalloc(&b->d_B, count)) != HDG_OK || (st = dalloc(&b->d_bar, 1)) != HDG_OK ||
+      (st = dalloc(&b->d_flags, 2 * (int64_t)b->nblocks * kFlagStride)) != HDG_OK)
     return cleanup(st);
   if (hipHostMalloc(reinterpret_cast<void**>(&b->h_A), sizeof(BatchState) * count,
                     hipHostMallocDefault) != hipSuccess ||
@@ -395,6 +434,7 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
           hipSuccess)
     return cleanup(fail(HDG_ENOMEM, "pinned host allocation failed"));
   b->probs.resize(count);
+  b->tabs.assign(kBatchTabWords, 0.0);
   for (int i = 0; i < count; ++i) {
     const hdg_ctx* c = b->sub[i];
     BatchProbDev& P = b->probs[i];
@@ -409,12 +449,16 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
     // per-degree tables (one tau_hat for the whole batch)
     const int o = batch_tab_off(c->np);
     for (int k = 0; k < c->np; ++k) {
-      b->tabs.v[o + k] = c->et64.bs0[k];
-      b->tabs.v[o + c->np + k] = c->et64.bs1[k];
-      b->tabs.v[o + 2 * c->np + k] = c->et64.lam[k];
+      b->tabs[o + k] = c->et64.bs0[k];
+      b->tabs[o + c->np + k] = c->et64.bs1[k];
+      b->tabs[o + 2 * c->np + k] = c->et64.lam[k];
     }
-    b->tabs.v[o + 3 * c->np] = c->et64.H;
+    b->tabs[o + 3 * c->np] = c->et64.H;
   }
+  if ((st = dalloc(&b->d_tabs, kBatchTabWords)) != HDG_OK) return cleanup(st);
+  if (hipMemcpy(b->d_tabs, b->tabs.data(), sizeof(double) * kBatchTabWords,
+                hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(fail(HDG_EHIP, "table upload failed"));
   if ((st = build_schedule(b)) != HDG_OK) return cleanup(st);
   if (hipStreamSynchronize(b->stream) != hipSuccess)
     return cleanup(fail(HDG_EHIP, "batch setup failed: %s", hipGetErrorString(hipGetLastError())));
@@ -461,7 +505,7 @@ hdg_status hdg_batch_time_cg(hdg_batch* b, int iters, int reps, double* ms) {
   ST_TRY(upload_probs(b, 0.0, iters));   // never converges, stops at the cap
   HIP_TRY(launch_fill64(b->d_b, 1.0, b->total_free, b->stream));
   const BatchArgs args = make_args(b, iters + 1);
-  HIP_TRY(launch_batch_reset(b->d_A, b->d_B, b->d_bar, b->count, b->stream));
+  HIP_TRY(launch_batch_reset(b->d_A, b->d_B, b->d_bar, b->d_flags, b->count, b->nblocks, b->stream));
   HIP_TRY(launch_batch_cg(args, b->nblocks, b->stream));   // warm-up
   ST_TRY(check_barrier(b));
   hipEvent_t e0, e1;
@@ -470,7 +514,7 @@ hdg_status hdg_batch_time_cg(hdg_batch* b, int iters, int reps, double* ms) {
   float total = 0.f;
   hipError_t err = hipSuccess;
   for (int r = 0; r < reps && err == hipSuccess; ++r) {
-    err = launch_batch_reset(b->d_A, b->d_B, b->d_bar, b->count, b->stream);
+    err = launch_batch_reset(b->d_A, b->d_B, b->d_bar, b->d_flags, b->count, b->nblocks, b->stream);
     if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
     if (err == hipSuccess) err = launch_batch_cg(args, b->nblocks, b->stream);
     if (err == hipSuccess) err = hipEventRecord(e1, b->stream);

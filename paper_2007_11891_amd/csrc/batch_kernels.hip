@@ -2,31 +2,33 @@
 // sizes and degrees in one persistent launch.
 //
 // All problems iterate in lockstep phases separated by grid-wide barriers:
-//   apply  : every block takes its contiguous range of element work units
-//            (problem, unit); per problem it re-sums the previous update's
-//            partials (r.z, r.r) in a fixed order, decides convergence, forms
-//            p = D^-1 r + beta p_old on the unit's faces, applies the
-//            transformed operator (the same `apply_unit` as the single-problem
-//            kernels, selected by degree and tile shape) and writes one p.q
-//            partial per unit;
-//   update : every block takes its contiguous range of vector chunks; per
-//            problem it re-sums the apply partials, forms alpha and updates
-//            r, writing r.z and r.r partials per chunk.
+//   apply  : every block walks its apply segments (a problem and a range of
+//            its element work units); per segment it re-sums the previous
+//            update's partials (r.z, r.r) of that problem in a fixed order,
+//            decides convergence, forms p = D^-1 r + beta p_old on the units'
+//            faces, applies the transformed operator (the same `apply_unit`
+//            as the single-problem kernels, selected by degree and tile
+//            shape) and writes one p.q partial per segment;
+//   update : every block walks its vector segments (a problem and a range of
+//            its free trace); per segment it re-sums the problem's apply
+//            partials, forms alpha and updates r, writing one r.z and one r.r
+//            partial per segment.
 // Converged problems drop out; the kernel returns when every problem is done.
 // Per-problem state lives in two slots (A: read by apply, written by update;
-// B: the reverse), written by the block that owns the problem's first unit or
-// chunk.  Reductions are deterministic (fixed order, identical in every block).
+// B: the reverse), written by the block that owns the problem's first
+// segment of the phase.  Every reduction is a fixed-order sum, identical in
+// every block, so the result does not depend on timing.
 //
-// The grid barrier spins with a bounded count: if it is ever exceeded the
-// kernel raises an error flag and every block returns, so the grid always
-// drains.
+// Grid barrier: each block publishes an arrival epoch in its own cache line;
+// block 0 waits for all of them and then releases every block through its
+// own line.  Every wait is bounded: on a time-out the kernel raises an error
+// flag and every block returns, so the grid always drains.
 #include "batch.hpp"
 #include "elem_unit.hpp"
 
 namespace hdg {
 
 constexpr int kBT = 256;                 // threads per block
-constexpr int kChunk = kBT * 4;          // DOFs per update chunk
 constexpr unsigned kSpinLimit = 1u << 22;
 
 template <int NP>
@@ -36,55 +38,117 @@ constexpr int kBatchLdsWords =
     cmax(cmax(cmax(unit_lds_words<2>(), unit_lds_words<3>()), cmax(unit_lds_words<4>(), unit_lds_words<5>())),
          cmax(cmax(cmax(unit_lds_words<6>(), unit_lds_words<7>()), cmax(unit_lds_words<8>(), unit_lds_words<9>())),
               cmax(unit_lds_words<10>(), unit_lds_words<11>())));
-static_assert(kBatchLdsWords * 8 <= 60000, "batched LDS budget");
+static_assert(kBatchLdsWords * 8 <= 40000, "batched LDS budget");
 
-// Returns false when the barrier timed out (then every block must return).
-__device__ inline bool grid_sync(GridBar* gb, unsigned nblocks) {
+// Grid barrier.  Block i (> 0) publishes its arrival epoch in line i of
+// `arrive`; block 0 polls all arrival lines (its threads in parallel), then
+// publishes the epoch in line i of `release` for every block, which polls
+// only its own line: no word is polled by more than one block.  Ordering:
+// every wave waits for its stores, the block synchronises, one thread makes
+// them visible to the device (release fence) before the arrival store; after
+// the wait one thread invalidates stale cached data (acquire fence) before
+// the block synchronises again.  Returns false when a wait timed out (then
+// every block must return).
+__device__ inline bool grid_sync(const BatchArgs& a, unsigned epoch) {
   __shared__ int s_ok;
+  GridBar* gb = a.bar;
+  unsigned* arrive = a.flags;
+  unsigned* release = a.flags + (size_t)gridDim.x * kFlagStride;
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int ok = 1;
-    const unsigned gen = __hip_atomic_load(&gb->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();   // release this block's writes
-    const unsigned arrived =
-        __hip_atomic_fetch_add(&gb->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nblocks - 1) {
-      __hip_atomic_store(&gb->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&gb->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+  if (blockIdx.x == 0) {
+    bool ok = true;
+    for (unsigned i = threadIdx.x + 1; i < gridDim.x && ok; i += kBT) {
       unsigned spins = 0;
-      while (__hip_atomic_load(&gb->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(2);
+      while (__hip_atomic_load(arrive + (size_t)i * kFlagStride, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+        __builtin_amdgcn_s_sleep(1);
         if (++spins > kSpinLimit) {
-          __hip_atomic_store(&gb->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = false;
           break;
         }
       }
     }
-    __threadfence();   // acquire the other blocks' writes
-    if (__hip_atomic_load(&gb->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-    s_ok = ok;
+    if (!ok) __hip_atomic_store(&gb->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+    __syncthreads();
+    for (unsigned i = threadIdx.x + 1; i < gridDim.x; i += kBT)
+      __hip_atomic_store(release + (size_t)i * kFlagStride, epoch, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  } else if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(arrive + (size_t)blockIdx.x * kFlagStride, epoch, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    while (__hip_atomic_load(release + (size_t)blockIdx.x * kFlagStride, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        __hip_atomic_store(&gb->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
+  if (threadIdx.x == 0)
+    s_ok = __hip_atomic_load(&gb->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
   __syncthreads();
   return s_ok != 0;
 }
 
+// Wave-uniform copies (scalar registers) of values every lane holds equal.
+template <typename T>
+__device__ inline T* uni_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+__device__ inline double uni_f64(double x) {
+  const uint64_t v = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ inline int uni_int(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+typedef const __attribute__((address_space(4))) double cdouble;
+struct ConstTab {
+  cdouble* bs0;
+  cdouble* bs1;
+  cdouble* lam;
+  double H;
+};
+
+// Units [u0, u1) of one problem at degree NP - 1 and tile EPB.  The
+// per-degree tables (a device buffer the kernel never writes) are read as
+// constant memory, i.e. with scalar loads.  The empty asm hides the
+// pointer's origin so that the compiler cannot hoist the table loads of
+// every degree to the kernel entry, which would keep all of them live in
+// scalar registers.  (The pointer must be a plain device address: never the
+// address of a kernel argument, which would force a private copy.)
 template <int NP, int EPB>
-__device__ inline double unit_np(const UnitIO<double>& io, const BatchTabs& tabs, double* smem,
-                                 int unit) {
+__device__ inline double run_units(const UnitIO<double>& io, const double* tabs, double* smem,
+                                   int u0, int u1) {
   constexpr int o = batch_tab_off(NP);
-  const TabRef<double> tab{tabs.v + o, tabs.v + o + NP, tabs.v + o + 2 * NP, tabs.v[o + 3 * NP]};
-  return apply_unit<double, NP, EPB, 1>(io, tab, *reinterpret_cast<UnitSmem<double, NP, EPB>*>(smem),
-                                       unit);
+  const double* tp = tabs;
+  asm volatile("" : "+s"(tp));
+  cdouble* ct = (cdouble*)tp;
+  const ConstTab tab{ct + o, ct + o + NP, ct + o + 2 * NP, ct[o + 3 * NP]};
+  auto& sm = *reinterpret_cast<UnitSmem<double, NP, EPB>*>(smem);
+  double dot = 0.0;
+  for (int u = u0; u < u1; ++u) dot += apply_unit<double, NP, EPB, 1>(io, tab, sm, u);
+  return dot;
 }
 
-__device__ inline double dispatch_unit(int np, int variant, const UnitIO<double>& io,
-                                       const BatchTabs& tabs, double* smem, int unit) {
+__device__ inline double dispatch_units(int np, int variant, const UnitIO<double>& io,
+                                        const double* tabs, double* smem, int u0, int u1) {
   switch (np * 4 + variant) {
-#define HDG_UCASE(N)                                                          \
-  case N * 4 + 0: return unit_np<N, epb_var<N, 0>()>(io, tabs, smem, unit); \
-  case N * 4 + 1: return unit_np<N, epb_var<N, 1>()>(io, tabs, smem, unit); \
-  case N * 4 + 2: return unit_np<N, epb_var<N, 2>()>(io, tabs, smem, unit);
+#define HDG_UCASE(N)                                                                 \
+  case N * 4 + 0: return run_units<N, epb_var<N, 0>()>(io, tabs, smem, u0, u1);   \
+  case N * 4 + 1: return run_units<N, epb_var<N, 1>()>(io, tabs, smem, u0, u1);   \
+  case N * 4 + 2: return run_units<N, epb_var<N, 2>()>(io, tabs, smem, u0, u1);
     HDG_UCASE(2) HDG_UCASE(3) HDG_UCASE(4) HDG_UCASE(5) HDG_UCASE(6) HDG_UCASE(7)
     HDG_UCASE(8) HDG_UCASE(9) HDG_UCASE(10) HDG_UCASE(11)
 #undef HDG_UCASE
@@ -96,16 +160,14 @@ __global__ void __launch_bounds__(kBT, 2) batch_cg_kernel(BatchArgs a) {
   __shared__ double smem[kBatchLdsWords];
   __shared__ double s_red[kBT / 64];
   const int bid = blockIdx.x;
-  const unsigned nb = gridDim.x;
-  const int NU = a.n_units_total, NC = a.n_chunks_total;
+  unsigned epoch = 0;
 
   // ---- init: r = b, x = 0, p_{-1} = 0, partials of iteration 0 -----------
-  for (int c = a.chunk_range[bid]; c < a.chunk_range[bid + 1]; ++c) {
-    const BatchProbDev* P = a.probs + a.chunk_prob[c];
-    const int64_t lo = P->off + (int64_t)(c - P->chunk_begin) * kChunk;
-    const int64_t hi = (lo + kChunk < P->off + P->n) ? lo + kChunk : P->off + P->n;
+  for (int s = a.vseg_range[bid]; s < a.vseg_range[bid + 1]; ++s) {
+    const BatchSeg sg = a.vseg[s];
+    const int64_t off = a.probs[sg.prob].off;
     double rz = 0.0, rr = 0.0;
-    for (int64_t g = lo + threadIdx.x; g < hi; g += kBT) {
+    for (int64_t g = off + sg.begin + threadIdx.x; g < off + sg.end; g += kBT) {
       const double v = a.b[g];
       a.r[g] = v;
       a.x[g] = 0.0;
@@ -116,138 +178,132 @@ __global__ void __launch_bounds__(kBT, 2) batch_cg_kernel(BatchArgs a) {
     const double brz = block_sum<kBT>(rz, s_red);
     const double brr = block_sum<kBT>(rr, s_red);
     if (threadIdx.x == 0) {
-      a.prz[c] = brz;
-      a.prr[c] = brr;
+      a.prz[s] = brz;
+      a.prr[s] = brr;
     }
   }
-  if (!grid_sync(a.bar, nb)) return;
+  if (!grid_sync(a, ++epoch)) return;
 
   for (int it = 0; it < a.max_iters; ++it) {
-    const int k2 = it & 1;
     // ------------------------------ apply -----------------------------------
-    {
-      int cur = -1;
-      bool skip = true;
+    for (int s = a.useg_range[bid]; s < a.useg_range[bid + 1]; ++s) {
+      const BatchSeg sg = a.useg[s];
+      const int pb = uni_int(sg.prob);
+      const BatchProbDev* P = a.probs + pb;
+      if (a.A[pb].done != 0) continue;
+      const double rho_prev = a.A[pb].rho;
+      const double alpha_prev = a.A[pb].alpha;
+      double rr_stop = a.A[pb].rr_stop;
+      double rho, rr;
+      sum_partials2<kBT>(a.prz + P->vseg_begin, a.prr + P->vseg_begin, P->n_vsegs, s_red, &rho,
+                         &rr);
+      if (it == 0) rr_stop = P->rtol2 * rr;
+      const double bb = (it == 0) ? 0.0 : rho / rho_prev;
+      int done = 0;
+      if (!isfinite(rr) || !isfinite(bb)) done = 3;
+      else if (rr <= rr_stop) done = 1;
+      else if (it >= P->maxit) done = 2;
+      if (s == P->useg_begin && threadIdx.x == 0) {
+        a.B[pb].rho = rho;
+        a.B[pb].rr = rr;
+        a.B[pb].rr_stop = rr_stop;
+        a.B[pb].iter = it;
+        a.B[pb].done = done;
+      }
+      const int64_t off = P->off;
       UnitIO<double> io{};
-      for (int u = a.unit_range[bid]; u < a.unit_range[bid + 1]; ++u) {
-        const int pb = a.unit_prob[u];
-        const BatchProbDev* P = a.probs + pb;
-        if (pb != cur) {
-          cur = pb;
-          skip = a.A[pb].done != 0;
-          if (!skip) {
-            const double rho_prev = a.A[pb].rho;
-            const double alpha_prev = a.A[pb].alpha;
-            double rr_stop = a.A[pb].rr_stop;
-            double rho, rr;
-            sum_partials2<kBT>(a.prz + (size_t)k2 * NC + P->chunk_begin,
-                               a.prr + (size_t)k2 * NC + P->chunk_begin, P->n_chunks, s_red, &rho,
-                               &rr);
-            if (it == 0) rr_stop = P->rtol2 * rr;
-            const double bb = (it == 0) ? 0.0 : rho / rho_prev;
-            int done = 0;
-            if (!isfinite(rr) || !isfinite(bb)) done = 3;
-            else if (rr <= rr_stop) done = 1;
-            else if (it >= P->maxit) done = 2;
-            io.info = P->info;
-            io.lam = P->lam;
-            io.n_elem = P->n_elem;
-            io.nff = P->nff;
-            io.qa = a.qa + P->off;
-            io.qb = a.qb + P->off;
-            io.r = a.r + P->off;
-            io.dinv = a.dinv + P->off;
-            io.p_in = ((it & 1) ? a.p0 : a.p1) + P->off;
-            io.p_out = ((it & 1) ? a.p1 : a.p0) + P->off;
-            io.x = a.x + P->off;
-            io.beta = bb;
-            io.alpha_x = alpha_prev;
-            io.finish = done != 0;
-            if (u == P->unit_begin && threadIdx.x == 0) {
-              a.B[pb].rho = rho;
-              a.B[pb].rr = rr;
-              a.B[pb].rr_stop = rr_stop;
-              a.B[pb].iter = it;
-              a.B[pb].done = done;
-            }
-          }
-        }
-        if (skip) continue;
-        const double dot = dispatch_unit(P->np, P->variant, io, a.tabs, smem, u - P->unit_begin);
-        if (!io.finish) {
-          const double bs = block_sum<kBT>(dot, s_red);
-          if (threadIdx.x == 0) a.ppq[(size_t)k2 * NU + u] = bs;
-        }
+      io.info = uni_ptr(P->info);
+      io.lam = uni_ptr(P->lam);
+      io.n_elem = uni_int(P->n_elem);
+      io.nff = uni_int(P->nff);
+      io.qa = uni_ptr(a.qa + off);
+      io.qb = uni_ptr(a.qb + off);
+      io.r = uni_ptr(a.r + off);
+      io.dinv = uni_ptr(a.dinv + off);
+      io.p_in = uni_ptr(((it & 1) ? a.p0 : a.p1) + off);
+      io.p_out = uni_ptr(((it & 1) ? a.p1 : a.p0) + off);
+      io.x = uni_ptr(a.x + off);
+      io.beta = uni_f64(bb);
+      io.alpha_x = uni_f64(alpha_prev);
+      io.finish = done != 0;
+      const double dot = dispatch_units(uni_int(P->np), uni_int(P->variant), io, a.tabs, smem,
+                                        sg.begin, sg.end);
+      if (!io.finish) {
+        const double bs = block_sum<kBT>(dot, s_red);
+        if (threadIdx.x == 0) a.ppq[s] = bs;
       }
     }
-    if (!grid_sync(a.bar, nb)) return;
+    if (!grid_sync(a, ++epoch)) return;
     // ------------------------------ update ----------------------------------
-    {
-      int cur = -1;
-      bool skip = true;
-      double alpha = 0.0;
-      for (int c = a.chunk_range[bid]; c < a.chunk_range[bid + 1]; ++c) {
-        const int pb = a.chunk_prob[c];
-        const BatchProbDev* P = a.probs + pb;
-        if (pb != cur) {
-          cur = pb;
-          // decisions read slot B only (slot A is written in this phase)
-          const int bdone = a.B[pb].done;
-          const bool owner = (c == P->chunk_begin) && threadIdx.x == 0;
-          if (bdone == 0 && a.A[pb].done != 0) {
-            skip = true;                        // broke down in an earlier update
-          } else if (bdone) {
-            skip = true;
-            if (owner && a.A[pb].done == 0) {   // finished in this iteration's apply
-              a.A[pb].done = bdone;
-              a.A[pb].iter = a.B[pb].iter;
-              a.A[pb].rr = a.B[pb].rr;
-              a.A[pb].rr_stop = a.B[pb].rr_stop;
-              atomicAdd(&a.bar->done_count, 1u);
-            }
-          } else {
-            const double pq = sum_partials<kBT>(a.ppq + (size_t)k2 * NU + P->unit_begin,
-                                                P->n_units, 1, 0, s_red);
-            const double rho = a.B[pb].rho;
-            alpha = rho / pq;
-            if (!(pq > 0.0) || !isfinite(alpha)) {
-              skip = true;
-              if (owner) {
-                a.A[pb].done = 3;
-                a.A[pb].iter = it;
-                atomicAdd(&a.bar->done_count, 1u);
-              }
-            } else {
-              skip = false;
-              if (owner) {
-                a.A[pb].rho = rho;
-                a.A[pb].alpha = alpha;
-                a.A[pb].rr_stop = a.B[pb].rr_stop;
-                a.A[pb].rr = a.B[pb].rr;
-                a.A[pb].iter = it + 1;
-              }
-            }
-          }
+    for (int s = a.vseg_range[bid]; s < a.vseg_range[bid + 1]; ++s) {
+      const BatchSeg sg = a.vseg[s];
+      const int pb = uni_int(sg.prob);
+      const BatchProbDev* P = a.probs + pb;
+      // decisions read slot B (slot A is written in this phase)
+      const int bdone = a.B[pb].done;
+      const bool owner = (s == P->vseg_begin) && threadIdx.x == 0;
+      if (bdone == 0 && a.A[pb].done != 0) continue;   // broke down in an earlier update
+      if (bdone) {
+        if (owner && a.A[pb].done == 0) {               // finished in this iteration's apply
+          a.A[pb].done = bdone;
+          a.A[pb].iter = a.B[pb].iter;
+          a.A[pb].rr = a.B[pb].rr;
+          a.A[pb].rr_stop = a.B[pb].rr_stop;
+          atomicAdd(&a.bar->done_count, 1u);
         }
-        if (skip) continue;
-        const int64_t lo = P->off + (int64_t)(c - P->chunk_begin) * kChunk;
-        const int64_t hi = (lo + kChunk < P->off + P->n) ? lo + kChunk : P->off + P->n;
-        double rz = 0.0, rr = 0.0;
-        for (int64_t g = lo + threadIdx.x; g < hi; g += kBT) {
-          const double rn = a.r[g] - alpha * (a.qa[g] + a.qb[g]);
-          a.r[g] = rn;
-          rz += rn * (a.dinv[g] * rn);
-          rr += rn * rn;
+        continue;
+      }
+      const double pq = sum_partials<kBT>(a.ppq + P->useg_begin, P->n_usegs, 1, 0, s_red);
+      const double rho = a.B[pb].rho;
+      const double alpha = rho / pq;
+      if (!(pq > 0.0) || !isfinite(alpha)) {
+        if (owner) {
+          a.A[pb].done = 3;
+          a.A[pb].iter = it;
+          atomicAdd(&a.bar->done_count, 1u);
         }
-        const double brz = block_sum<kBT>(rz, s_red);
-        const double brr = block_sum<kBT>(rr, s_red);
-        if (threadIdx.x == 0) {
-          a.prz[(size_t)(k2 ^ 1) * NC + c] = brz;
-          a.prr[(size_t)(k2 ^ 1) * NC + c] = brr;
+        continue;
+      }
+      if (owner) {
+        a.A[pb].rho = rho;
+        a.A[pb].alpha = alpha;
+        a.A[pb].rr_stop = a.B[pb].rr_stop;
+        a.A[pb].rr = a.B[pb].rr;
+        a.A[pb].iter = it + 1;
+      }
+      const int64_t lo = P->off + sg.begin, hi = P->off + sg.end;
+      double rz = 0.0, rr = 0.0;
+      int64_t g = lo + threadIdx.x;
+      for (; g + 3 * kBT < hi; g += 4 * kBT) {
+        double rn[4], q[4], d[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          rn[k] = a.r[g + k * kBT];
+          q[k] = a.qa[g + k * kBT] + a.qb[g + k * kBT];
+          d[k] = a.dinv[g + k * kBT];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          rn[k] -= alpha * q[k];
+          a.r[g + k * kBT] = rn[k];
+          rz += rn[k] * (d[k] * rn[k]);
+          rr += rn[k] * rn[k];
         }
       }
+      for (; g < hi; g += kBT) {
+        const double rn = a.r[g] - alpha * (a.qa[g] + a.qb[g]);
+        a.r[g] = rn;
+        rz += rn * (a.dinv[g] * rn);
+        rr += rn * rn;
+      }
+      const double brz = block_sum<kBT>(rz, s_red);
+      const double brr = block_sum<kBT>(rr, s_red);
+      if (threadIdx.x == 0) {
+        a.prz[s] = brz;
+        a.prr[s] = brr;
+      }
     }
-    if (!grid_sync(a.bar, nb)) return;
+    if (!grid_sync(a, ++epoch)) return;
     if (__hip_atomic_load(&a.bar->done_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
         (unsigned)a.n_probs)
       break;
@@ -256,17 +312,21 @@ __global__ void __launch_bounds__(kBT, 2) batch_cg_kernel(BatchArgs a) {
 
 // State reset before every batched solve (a kernel, so that it can sit in the
 // captured graph next to the solver).
-__global__ void batch_reset_kernel(BatchState* A, BatchState* B, GridBar* bar, int n) {
+__global__ void batch_reset_kernel(BatchState* A, BatchState* B, GridBar* bar, unsigned* flags,
+                                   int n_probs, int n_flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
+  if (i < n_probs) {
     BatchState s{};
     s.rho = 1.0;
     A[i] = s;
     B[i] = s;
   }
+  if (i < n_flags) {
+    flags[(size_t)i * kFlagStride] = 0u;                                // arrival
+    flags[((size_t)n_flags + i) * kFlagStride] = 0u;                    // release
+  }
   if (i == 0) {
-    bar->count = 0;
-    bar->gen = 0;
+    bar->pad0 = 0;
     bar->done_count = 0;
     bar->err = 0;
   }
@@ -276,9 +336,12 @@ hipError_t batch_occupancy(int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_cg_kernel, kBT, 0);
 }
 
-hipError_t launch_batch_reset(BatchState* A, BatchState* B, GridBar* bar, int n, hipStream_t s) {
+hipError_t launch_batch_reset(BatchState* A, BatchState* B, GridBar* bar, unsigned* flags,
+                              int n_probs, int nblocks, hipStream_t s) {
+  const int n = n_probs > nblocks ? n_probs : nblocks;
   const int nb = (n + 255) / 256 > 0 ? (n + 255) / 256 : 1;
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(nb), dim3(256), 0, s, A, B, bar, n);
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(nb), dim3(256), 0, s, A, B, bar, flags, n_probs,
+                     nblocks);
   return hipGetLastError();
 }
 
@@ -288,7 +351,5 @@ hipError_t launch_batch_cg(const BatchArgs& args, int nblocks, hipStream_t s) {
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(batch_cg_kernel), dim3(nblocks),
                                     dim3(kBT), params, 0, s);
 }
-
-int batch_chunk() { return kChunk; }
 
 }  // namespace hdg

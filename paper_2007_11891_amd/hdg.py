@@ -73,6 +73,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} not found: build it with `python -m paper_2007_11891_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has loaded
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
     i64p = ctypes.POINTER(ctypes.c_int64)
