@@ -69,6 +69,135 @@ def cpu_baseline(prob, budget_s: float):
                       f"matvec), {dt:.1f} s; scaled to one full apply = {per_apply_s:.0f} s"}
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fused_cg_apply_perturbed16_p7_hbm_counters.md")
+KERNEL_SOURCES = ("paper_2007_11891_amd/csrc/elem_unit.hpp", "paper_2007_11891_amd/csrc/elem_kernels.hip",
+                  "paper_2007_11891_amd/csrc/device_common.hpp")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the sources of the fused CG apply kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the
+    summary is missing, covers another kernel, or the kernel sources changed
+    since the counters were taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(block)
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    entry = rec.get("kernels", {}).get(kernel)
+    return None if entry is None else entry.get("traffic_bytes")
+
+
+def bench_batched(pkg, W, torch, dev, reps: int = 3):
+    """256 independent unit-cube problems (n_a ~ U{4..12}, p ~ U{2..10},
+    lambda log-uniform in [1e-2, 1e2], f ~ N(0,1), seed 4) in one persistent
+    launch: RHS + CG to 1e-10 + recovery, replayed from one HIP graph."""
+    probs = W.batched()
+    b = pkg.HdgBatch([pr.n for pr in probs], [pr.p for pr in probs],
+                     [float(pr.lam[0]) for pr in probs], tau=1.0)
+    tiles = b.autotune(iters=10, reps=2)
+    f = torch.as_tensor(np.concatenate([pr.f_values for pr in probs]), device=dev)
+    tr = torch.empty(b.total_free, dtype=torch.float64, device=dev)
+    uv = torch.empty(b.total_vol, dtype=torch.float64, device=dev)
+    o = pkg.default_opts(rtol=1e-10, maxit=20000)
+    b.solve_forcing(f, tr, uv, opts=o)            # capture + warm-up
+    walls, gpus, res = [], [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, res, gms = b.solve_forcing(f, tr, uv, opts=o)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t)
+        gpus.append(gms)
+    wall = statistics.median(walls)
+    iters = np.array([r["iters"] for r in res])
+    dof_iters = float(np.sum(b.n_free * iters))
+    t1 = b.time_cg(1, reps=3)
+    t21 = b.time_cg(21, reps=3)
+    t_it = (t21 - t1) / 20.0                     # ms per CG iteration, all problems active
+    bytes_it = 104 * b.total_free                # fused apply 64 B + update 40 B per DOF
+    ach = bytes_it / (t_it * 1e-3) / 1e9
+    log(f"[bench] batched: {len(probs)} problems, {b.total_free} free DOFs, wall {wall*1e3:.1f} ms, "
+        f"max iters {iters.max()}, CG iteration {t_it*1e3:.1f} us, tiles {tiles}")
+    out = {"workload": "256 unit-cube problems, n_a~U{4..12}, p~U{2..10}, lambda~logU[1e-2,1e2], "
+                       "f~N(0,1), seed 4; RHS + CG to 1e-10 + recovery in one graph",
+           "problems": len(probs), "total_free": int(b.total_free),
+           "trace_dof_iters_per_s": dof_iters / wall, "trace_dof_per_s": b.total_free / wall,
+           "wall_ms": round(wall * 1e3, 3), "gpu_ms": round(statistics.median(gpus), 3),
+           "iters_min": int(iters.min()), "iters_max": int(iters.max()),
+           "iters_sum": int(iters.sum()), "tiles_by_p": tiles,
+           "cg_iteration_us": round(t_it * 1e3, 2),
+           "roofline": {"kernel": "batch_cg_kernel (persistent, one CG iteration of every problem)",
+                        "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                        "bytes_per_iteration": bytes_it}}
+    b.close()
+    return out
+
+
+def bench_adjoint(pkg, W, torch, dev, reps: int = 3):
+    """Adjoint gradient on 24^3, p = 6, log-normal lambda field (seed 5):
+    forward solve, then dJ/dlambda and dJ/df by the adjoint solve."""
+    prob = W.adjoint()
+    c = pkg.HdgContext(prob.n, prob.widths, prob.p, prob.tau, prob.lam)
+    c.autotune(reps=20)
+    vx, _ = c.coords()
+    vx = vx.cpu().numpy()
+    lam_nodes = np.repeat(prob.lam, (prob.p + 1) ** 3)
+    f = torch.as_tensor(W.lambda_forcing_sin3(*vx.T, lam_nodes), device=dev)
+    ustar = torch.as_tensor(W.target_with_noise(W.u_sin3(*vx.T), prob.extra["noise_seed"]),
+                            device=dev)
+    w = pkg.tables(prob.p, prob.tau)["w"]
+    wk = np.kron(w, np.kron(w, w))
+    h = prob.widths
+    Md = np.concatenate([h[0][i] * h[1][j] * h[2][k] / 8.0 * wk
+                         for k in range(prob.n[2]) for j in range(prob.n[1]) for i in range(prob.n[0])])
+    Md = torch.as_tensor(Md, device=dev)
+    o = pkg.default_opts(rtol=1e-10, maxit=20000)
+    tr = c.zeros_trace()
+    fw, ad, info, ainfo = [], [], None, None
+    for _ in range(reps + 1):
+        tr.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, uv, info = c.solve_forcing(f, tr, opts=o)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dl, df, ainfo = c.adjoint(f, tr, Md * (uv - ustar), opts=o)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fw.append(t1 - t)
+        ad.append(t2 - t1)
+    fw_ms = 1e3 * statistics.median(fw[1:])
+    ad_ms = 1e3 * statistics.median(ad[1:])
+    nf = c.sizes.n_free
+    log(f"[bench] adjoint 24^3 p6: forward {fw_ms:.2f} ms ({info['iters']} it), "
+        f"adjoint {ad_ms:.2f} ms ({ainfo['iters']} it)")
+    out = {"workload": "24^3 uniform, p=6, lambda log-normal(0,1) per element, seed 5; "
+                       "J = 1/2 |u - u*|_M^2, u* = sin sin sin + 1% noise",
+           "n_lambda": int(prob.n_elem), "n_trace_free": int(nf),
+           "forward_ms": round(fw_ms, 3), "adjoint_ms": round(ad_ms, 3),
+           "forward_iters": info["iters"], "adjoint_iters": ainfo["iters"],
+           "gradients_per_s": 1e3 / ad_ms,
+           "adjoint_trace_dof_per_s": nf * ainfo["iters"] / (ad_ms * 1e-3)}
+    c.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +211,8 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the isolated kernel timings (for counter collection)")
     ap.add_argument("--reps", type=int, default=200)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -102,6 +233,10 @@ def main():
     trace = torch.zeros(na, dtype=torch.float64, device=dev)
     u_vol = torch.empty(nv, dtype=torch.float64, device=dev)
     opts = pkg.default_opts(rtol=1e-10)
+    variant, tile_times = ctx.autotune(reps=50)      # tile shape, chosen before timing
+    tile = ctx.tile_shape()
+    log(f"[bench] tile variant {variant} ({tile['elems_per_unit']} elements / "
+        f"{tile['threads_per_unit']} threads per unit), times {[round(t * 1e3, 2) for t in tile_times]} us")
 
     if args.kernels_only:
         x64 = torch.as_tensor(W.random_trace(nf, 1), device=dev)
@@ -111,6 +246,13 @@ def main():
             xin = x64.float() if which == 1 else x64
             ms = ctx.time_kernel(which, xin, args.reps, y=y64 if which == 8 else None)
             log(f"[bench] {name} {ms * 1e3:.3f} us")
+        # plain copy of 256 MiB (larger than L2 and the infinity cache): the
+        # reference dispatch for scaling HBM byte counters
+        big = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        big2 = torch.empty_like(big)
+        for _ in range(3):
+            big2.copy_(big)
+        torch.cuda.synchronize()
         ctx.close()
         return
 
@@ -147,11 +289,14 @@ def main():
     log(f"[bench] apply64 {t_apply64*1e3:.2f} us apply32 {t_apply32*1e3:.2f} us "
         f"cg_apply {t_cg_apply*1e3:.2f} us cg_update {t_cg_update*1e3:.2f} us "
         f"cg_iter {t_cg_iter*1e3:.2f} us cg_iter32 {t_cg_iter32*1e3:.2f} us")
-    cg_apply_bytes = 56 * nf        # x r/w, r, D^-1, p_old read; p, q written once
+    # per free DOF: p_old, r, D^-1, x read; x, p, qa, qb written (8 B each)
+    cg_apply_bytes = 64 * nf
     achieved = cg_apply_bytes / (t_cg_apply * 1e-3) / 1e9
-    roofline = {"kernel": "elem_apply_kernel<double,8,1> (fused CG apply)", "bound": "hbm",
+    kname = f"elem_apply_kernel<double, {prob.p + 1}, {tile['elems_per_unit']}, 1> (fused CG apply)"
+    roofline = {"kernel": kname, "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(kname.split(" (")[0]),
                 "bytes_per_launch": cg_apply_bytes, "avg_launch_us": round(t_cg_apply * 1e3, 3)}
     apply_bytes = 16 * nf
     apply_only = {"trace_dof_per_s_fp64": nf / (t_apply64 * 1e-3),
@@ -186,6 +331,9 @@ def main():
         log(f"[bench] time-to-1e-10 fp64 {t64:.2f} ms ({i64['iters']} it), mixed {tmx:.2f} ms "
             f"({imx['iters']} inner, {imx['outer_iters']} outer), diff {diff:.1e}")
 
+    batched = None if args.no_batch else bench_batched(pkg, W, torch, dev)
+    adjoint = None if args.no_adjoint else bench_adjoint(pkg, W, torch, dev)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
@@ -209,6 +357,11 @@ def main():
                             "fused_apply_fp64": round(t_cg_apply * 1e3, 3),
                             "update_fp64": round(t_cg_update * 1e3, 3)},
         "mixed_precision": mixed,
+        "tile": {"variant": variant, "elems_per_unit": tile["elems_per_unit"],
+                 "threads_per_unit": tile["threads_per_unit"],
+                 "autotune_cg_iter_us": [round(t * 1e3, 3) for t in tile_times]},
+        "batched": batched,
+        "adjoint": adjoint,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

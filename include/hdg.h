@@ -241,6 +241,12 @@ hdg_status hdg_set_tile(hdg_ctx* ctx, int variant);
  * (times_ms: host double[3] or NULL).  Synchronises the stream. */
 hdg_status hdg_autotune(hdg_ctx* ctx, int reps, int* chosen, double* times_ms);
 
+/* Current tile shape: *variant (0..2), *elems_per_unit (elements of one
+ * work unit) and *threads_per_unit (threads of one FP64 work unit, a
+ * multiple of 64); any pointer may be NULL.  Host-only, no GPU work. */
+hdg_status hdg_tile_shape(const hdg_ctx* ctx, int* variant, int* elems_per_unit,
+                          int* threads_per_unit);
+
 /* Diagonal of K^_ff (eigen basis), device double[n_free] output. */
 hdg_status hdg_diagonal(hdg_ctx* ctx, double* diag_free);
 

@@ -186,6 +186,27 @@ int tile_epb(int np, int variant) {
   }
 }
 
+template <int NP>
+static int threads_of_variant(int v) {
+  switch (v) {
+    case 1: return unit_threads<NP, epb_var<NP, 1>()>();
+    case 2: return unit_threads<NP, epb_var<NP, 2>()>();
+    default: return unit_threads<NP, epb_var<NP, 0>()>();
+  }
+}
+
+int tile_threads(int np, int variant) {
+  switch (np) {
+#define HDG_CASE(N) \
+  case N: return threads_of_variant<N>(variant);
+    HDG_CASE(2) HDG_CASE(3) HDG_CASE(4) HDG_CASE(5) HDG_CASE(6) HDG_CASE(7) HDG_CASE(8)
+    HDG_CASE(9) HDG_CASE(10) HDG_CASE(11) HDG_CASE(12) HDG_CASE(13) HDG_CASE(14)
+    HDG_CASE(15) HDG_CASE(16) HDG_CASE(17)
+#undef HDG_CASE
+    default: return 64;
+  }
+}
+
 int elem_apply_blocks(int np, int64_t n_elem, int variant) {
   int nb = 0, upb = 0;
   grid_for(n_elem, tile_epb(np, variant), &nb, &upb);

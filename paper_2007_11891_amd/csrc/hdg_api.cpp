@@ -875,6 +875,15 @@ hdg_status hdg_autotune(hdg_ctx* c, int reps, int* chosen, double* times_ms) {
   return HDG_OK;
 }
 
+hdg_status hdg_tile_shape(const hdg_ctx* c, int* variant, int* elems_per_unit,
+                          int* threads_per_unit) {
+  if (!c) return fail(HDG_EINVAL, "ctx is NULL");
+  if (variant) *variant = c->tile_variant;
+  if (elems_per_unit) *elems_per_unit = tile_epb(c->np, c->tile_variant);
+  if (threads_per_unit) *threads_per_unit = tile_threads(c->np, c->tile_variant);
+  return HDG_OK;
+}
+
 hdg_status hdg_diagonal(hdg_ctx* c, double* diag_free) {
   if (!c || !diag_free) return fail(HDG_EINVAL, "NULL argument");
   if (c->n_free == 0) return HDG_OK;

@@ -190,6 +190,7 @@ hipError_t launch_dot64(const double* a, const double* b, int64_t n, double* par
 // elements per work unit of a tile variant
 int elem_apply_blocks(int np, int64_t n_elem, int variant);
 int tile_epb(int np, int variant);
+int tile_threads(int np, int variant);
 constexpr int kNumTileVariants = 3;
 
 }  // namespace hdg

@@ -29,7 +29,7 @@ EXPORTS = (
     "hdg_default_opts", "hdg_create", "hdg_destroy", "hdg_last_error", "hdg_sizes",
     "hdg_set_lambda", "hdg_tables", "hdg_coords", "hdg_apply", "hdg_face_transform",
     "hdg_rhs", "hdg_solve", "hdg_solve_forcing", "hdg_reconstruct", "hdg_adjoint",
-    "hdg_diagonal", "hdg_time_kernel", "hdg_set_tile", "hdg_autotune",
+    "hdg_diagonal", "hdg_time_kernel", "hdg_set_tile", "hdg_autotune", "hdg_tile_shape",
     "hdg_batch_create", "hdg_batch_destroy", "hdg_batch_sizes", "hdg_batch_set_tile",
     "hdg_batch_tiles", "hdg_batch_autotune", "hdg_batch_time_cg", "hdg_batch_solve_forcing",
 )
@@ -102,6 +102,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hdg_time_kernel": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int, dp]),
         "hdg_set_tile": (ctypes.c_int, [vp, ctypes.c_int]),
         "hdg_autotune": (ctypes.c_int, [vp, ctypes.c_int, ip, dp]),
+        "hdg_tile_shape": (ctypes.c_int, [vp, ip, ip, ip]),
         "hdg_batch_create": (ctypes.c_int, [ctypes.c_int, ip, ip, dp, ctypes.c_double, vp,
                                             ctypes.POINTER(vp)]),
         "hdg_batch_destroy": (ctypes.c_int, [vp]),
@@ -354,6 +355,11 @@ class HdgContext:
         t = (ctypes.c_double * 3)()
         _check(self._lib.hdg_autotune(self._h, int(reps), ctypes.byref(ch), t))
         return ch.value, list(t)
+
+    def tile_shape(self) -> dict:
+        v, e, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.hdg_tile_shape(self._h, ctypes.byref(v), ctypes.byref(e), ctypes.byref(t)))
+        return {"variant": v.value, "elems_per_unit": e.value, "threads_per_unit": t.value}
 
     def time_kernel(self, which: int, x, reps: int = 100, y=None) -> float:
         """Mean launch time (ms) of an internal kernel, HIP events on the context stream."""
