@@ -71,6 +71,7 @@ def cpu_baseline(prob, budget_s: float):
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fused_cg_apply_perturbed16_p7_hbm_counters.md")
 KERNEL_SOURCES = ("paper_2007_11891_amd/csrc/elem_unit.hpp", "paper_2007_11891_amd/csrc/elem_kernels.hip",
+                  "paper_2007_11891_amd/csrc/vec_kernels.hip",
                   "paper_2007_11891_amd/csrc/device_common.hpp")
 
 
@@ -289,15 +290,27 @@ def main():
     log(f"[bench] apply64 {t_apply64*1e3:.2f} us apply32 {t_apply32*1e3:.2f} us "
         f"cg_apply {t_cg_apply*1e3:.2f} us cg_update {t_cg_update*1e3:.2f} us "
         f"cg_iter {t_cg_iter*1e3:.2f} us cg_iter32 {t_cg_iter32*1e3:.2f} us")
-    # per free DOF: p_old, r, D^-1, x read; x, p, qa, qb written (8 B each)
-    cg_apply_bytes = 64 * nf
-    achieved = cg_apply_bytes / (t_cg_apply * 1e-3) / 1e9
-    kname = f"elem_apply_kernel<double, {prob.p + 1}, {tile['elems_per_unit']}, 1> (fused CG apply)"
-    roofline = {"kernel": kname, "bound": "hbm",
+    # per free DOF and CG iteration (8 B each): the fused apply reads z, p_old
+    # and writes p, qa, qb; the update reads z, qa, qb, D^-1, x, p and writes
+    # z, x.  The roofline is reported for the longer of the two kernels.
+    cg_apply_bytes = 40 * nf
+    cg_update_bytes = 64 * nf
+    apply_name = f"elem_apply_kernel<double, {prob.p + 1}, {tile['elems_per_unit']}, 1>"
+    if t_cg_apply >= t_cg_update:
+        kname, kbytes, kt, kdesc = apply_name, cg_apply_bytes, t_cg_apply, "fused CG apply"
+    else:
+        kname, kbytes, kt, kdesc = "cg_update_kernel<double>", cg_update_bytes, t_cg_update, "CG update"
+    achieved = kbytes / (kt * 1e-3) / 1e9
+    roofline = {"kernel": f"{kname} ({kdesc})", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(kname.split(" (")[0]),
-                "bytes_per_launch": cg_apply_bytes, "avg_launch_us": round(t_cg_apply * 1e3, 3)}
+                "traffic": measured_traffic(kname),
+                "bytes_per_launch": kbytes, "avg_launch_us": round(kt * 1e3, 3),
+                "other_kernel": {
+                    "kernel": "cg_update_kernel<double>" if kname == apply_name else apply_name,
+                    "achieved_GBs": round((cg_update_bytes / (t_cg_update * 1e-3) if kname == apply_name
+                                           else cg_apply_bytes / (t_cg_apply * 1e-3)) / 1e9, 1),
+                    "avg_launch_us": round((t_cg_update if kname == apply_name else t_cg_apply) * 1e3, 3)}}
     apply_bytes = 16 * nf
     apply_only = {"trace_dof_per_s_fp64": nf / (t_apply64 * 1e-3),
                   "trace_dof_per_s_fp32": nf / (t_apply32 * 1e-3),

@@ -70,7 +70,7 @@ struct BatchArgs {
   const BatchSeg* vseg;
   const int* vseg_range;    // [nblocks + 1]
   double* x;
-  double* r;
+  double* z;                // D^-1 r
   double* p0;
   double* p1;
   double* qa;

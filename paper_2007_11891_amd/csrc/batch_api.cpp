@@ -35,7 +35,7 @@ struct hdg_batch {
   // concatenated FP64 vectors (total_free each)
   double* d_b = nullptr;
   double* d_x = nullptr;
-  double* d_r = nullptr;
+  double* d_z = nullptr;
   double* d_p0 = nullptr;
   double* d_p1 = nullptr;
   double* d_qa = nullptr;
@@ -202,7 +202,7 @@ BatchArgs make_args(const hdg_batch* b, int max_iters) {
   a.vseg = b->d_vseg;
   a.vseg_range = b->d_vseg_range;
   a.x = b->d_x;
-  a.r = b->d_r;
+  a.z = b->d_z;
   a.p0 = b->d_p0;
   a.p1 = b->d_p1;
   a.qa = b->d_qa;
@@ -330,7 +330,7 @@ hdg_status hdg_batch_destroy(hdg_batch* b) {
   if (b->stream || b->cap_stream) (void)hipStreamSynchronize(b->stream);
   drop_graphs(b);
   for (hdg_ctx* c : b->sub) hdg_destroy(c);
-  for (double** p : {&b->d_b, &b->d_x, &b->d_r, &b->d_p0, &b->d_p1, &b->d_qa, &b->d_qb,
+  for (double** p : {&b->d_b, &b->d_x, &b->d_z, &b->d_p0, &b->d_p1, &b->d_qa, &b->d_qb,
                      &b->d_dinv, &b->d_ppq, &b->d_prz, &b->d_prr})
     dfree(*p);
   dfree(b->d_probs);
@@ -399,7 +399,7 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
     b->total_vol += b->sub[i]->n_vol;
   }
   if (b->total_free > ((int64_t)1 << 40)) return cleanup(fail(HDG_EINVAL, "batch too large"));
-  for (double** ptr : {&b->d_b, &b->d_x, &b->d_r, &b->d_p0, &b->d_p1, &b->d_qa, &b->d_qb,
+  for (double** ptr : {&b->d_b, &b->d_x, &b->d_z, &b->d_p0, &b->d_p1, &b->d_qa, &b->d_qb,
                        &b->d_dinv})
     if ((st = dalloc(ptr, b->total_free)) != HDG_OK) return cleanup(st);
   // Jacobi inverse diagonals of the single-problem contexts

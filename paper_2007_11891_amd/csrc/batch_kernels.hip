@@ -5,14 +5,14 @@
 //   apply  : every block walks its apply segments (a problem and a range of
 //            its element work units); per segment it re-sums the previous
 //            update's partials (r.z, r.r) of that problem in a fixed order,
-//            decides convergence, forms p = D^-1 r + beta p_old on the units'
-//            faces, applies the transformed operator (the same `apply_unit`
-//            as the single-problem kernels, selected by degree and tile
-//            shape) and writes one p.q partial per segment;
+//            decides convergence, forms p = z + beta p_old on the units'
+//            faces (z = D^-1 r), applies the transformed operator (the same
+//            `apply_unit` as the single-problem kernels, selected by degree
+//            and tile shape) and writes one p.q partial per segment;
 //   update : every block walks its vector segments (a problem and a range of
 //            its free trace); per segment it re-sums the problem's apply
-//            partials, forms alpha and updates r, writing one r.z and one r.r
-//            partial per segment.
+//            partials, forms alpha, updates z and x, and writes one r.z and
+//            one r.r partial per segment.
 // Converged problems drop out; the kernel returns when every problem is done.
 // Per-problem state lives in two slots (A: read by apply, written by update;
 // B: the reverse), written by the block that owns the problem's first
@@ -162,17 +162,18 @@ __global__ void __launch_bounds__(kBT, 2) batch_cg_kernel(BatchArgs a) {
   const int bid = blockIdx.x;
   unsigned epoch = 0;
 
-  // ---- init: r = b, x = 0, p_{-1} = 0, partials of iteration 0 -----------
+  // ---- init: z = D^-1 b, x = 0, p_{-1} = 0, partials of iteration 0 -------
   for (int s = a.vseg_range[bid]; s < a.vseg_range[bid + 1]; ++s) {
     const BatchSeg sg = a.vseg[s];
     const int64_t off = a.probs[sg.prob].off;
     double rz = 0.0, rr = 0.0;
     for (int64_t g = off + sg.begin + threadIdx.x; g < off + sg.end; g += kBT) {
       const double v = a.b[g];
-      a.r[g] = v;
+      const double zv = a.dinv[g] * v;
+      a.z[g] = zv;
       a.x[g] = 0.0;
       a.p1[g] = 0.0;
-      rz += v * (a.dinv[g] * v);
+      rz += v * zv;
       rr += v * v;
     }
     const double brz = block_sum<kBT>(rz, s_red);
@@ -192,7 +193,6 @@ __global__ void __launch_bounds__(kBT, 2) batch_cg_kernel(BatchArgs a) {
       const BatchProbDev* P = a.probs + pb;
       if (a.A[pb].done != 0) continue;
       const double rho_prev = a.A[pb].rho;
-      const double alpha_prev = a.A[pb].alpha;
       double rr_stop = a.A[pb].rr_stop;
       double rho, rr;
       sum_partials2<kBT>(a.prz + P->vseg_begin, a.prr + P->vseg_begin, P->n_vsegs, s_red, &rho,
@@ -210,6 +210,7 @@ __global__ void __launch_bounds__(kBT, 2) batch_cg_kernel(BatchArgs a) {
         a.B[pb].iter = it;
         a.B[pb].done = done;
       }
+      if (done) continue;                     // x is complete: nothing left to apply
       const int64_t off = P->off;
       UnitIO<double> io{};
       io.info = uni_ptr(P->info);
@@ -218,20 +219,14 @@ __global__ void __launch_bounds__(kBT, 2) batch_cg_kernel(BatchArgs a) {
       io.nff = uni_int(P->nff);
       io.qa = uni_ptr(a.qa + off);
       io.qb = uni_ptr(a.qb + off);
-      io.r = uni_ptr(a.r + off);
-      io.dinv = uni_ptr(a.dinv + off);
+      io.z = uni_ptr(a.z + off);
       io.p_in = uni_ptr(((it & 1) ? a.p0 : a.p1) + off);
       io.p_out = uni_ptr(((it & 1) ? a.p1 : a.p0) + off);
-      io.x = uni_ptr(a.x + off);
       io.beta = uni_f64(bb);
-      io.alpha_x = uni_f64(alpha_prev);
-      io.finish = done != 0;
       const double dot = dispatch_units(uni_int(P->np), uni_int(P->variant), io, a.tabs, smem,
                                         sg.begin, sg.end);
-      if (!io.finish) {
-        const double bs = block_sum<kBT>(dot, s_red);
-        if (threadIdx.x == 0) a.ppq[s] = bs;
-      }
+      const double bs = block_sum<kBT>(dot, s_red);
+      if (threadIdx.x == 0) a.ppq[s] = bs;
     }
     if (!grid_sync(a, ++epoch)) return;
     // ------------------------------ update ----------------------------------
@@ -272,28 +267,36 @@ __global__ void __launch_bounds__(kBT, 2) batch_cg_kernel(BatchArgs a) {
         a.A[pb].iter = it + 1;
       }
       const int64_t lo = P->off + sg.begin, hi = P->off + sg.end;
+      const double* __restrict__ pk = (it & 1) ? a.p1 : a.p0;   // p of this iteration
       double rz = 0.0, rr = 0.0;
       int64_t g = lo + threadIdx.x;
       for (; g + 3 * kBT < hi; g += 4 * kBT) {
-        double rn[4], q[4], d[4];
+        double zv[4], q[4], d[4], xv[4], pv[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          rn[k] = a.r[g + k * kBT];
+          zv[k] = a.z[g + k * kBT];
           q[k] = a.qa[g + k * kBT] + a.qb[g + k * kBT];
           d[k] = a.dinv[g + k * kBT];
+          xv[k] = a.x[g + k * kBT];
+          pv[k] = pk[g + k * kBT];
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          rn[k] -= alpha * q[k];
-          a.r[g + k * kBT] = rn[k];
-          rz += rn[k] * (d[k] * rn[k]);
-          rr += rn[k] * rn[k];
+          const double zn = zv[k] - alpha * (d[k] * q[k]);
+          a.z[g + k * kBT] = zn;
+          a.x[g + k * kBT] = xv[k] + alpha * pv[k];
+          const double rn = div_fast(zn, d[k]);
+          rz += zn * rn;
+          rr += rn * rn;
         }
       }
       for (; g < hi; g += kBT) {
-        const double rn = a.r[g] - alpha * (a.qa[g] + a.qb[g]);
-        a.r[g] = rn;
-        rz += rn * (a.dinv[g] * rn);
+        const double d = a.dinv[g];
+        const double zn = a.z[g] - alpha * (d * (a.qa[g] + a.qb[g]));
+        a.z[g] = zn;
+        a.x[g] += alpha * pk[g];
+        const double rn = div_fast(zn, d);
+        rz += zn * rn;
         rr += rn * rn;
       }
       const double brz = block_sum<kBT>(rz, s_red);

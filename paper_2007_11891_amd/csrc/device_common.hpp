@@ -26,6 +26,19 @@ __device__ inline int xcd_remap(int bid, int nb) {
   return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
 }
 
+// a / b through the hardware reciprocal, two Newton steps and one residual
+// correction (within about one ulp; no IEEE division sequence).
+__device__ inline double div_fast(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  double e = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  const double q = a * r;
+  return __builtin_fma(r, __builtin_fma(-b, q, a), q);
+}
+__device__ inline float div_fast(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -4,9 +4,11 @@
 // template parameter; the context selects one of three variants per degree.
 //
 // Fused CG apply (paper: section "Summary of solution method", solver
-// HDG-trans): forms p = z + beta p_old with z = D^-1 r on the fly, applies
-// x += alpha_old p_old on the faces it owns, and reduces p.q from
-// element-local quadratic forms into one partial per block.
+// HDG-trans): forms p = z + beta p_old on the fly (the CG carries
+// z = D^-1 r, see vec_kernels.hip), writes p on the faces it owns, and
+// reduces p.q from element-local quadratic forms into one partial per block.
+// Everything that needs no face gather (the x and residual updates) is left
+// to the streaming update kernel.
 #include "elem_unit.hpp"
 
 namespace hdg {
@@ -18,11 +20,9 @@ struct ApplyIO {
   T* qa;
   T* qb;
   // fused CG mode
-  const T* r;
-  const T* dinv;
+  const T* z;
   T* p0;
   T* p1;
-  T* x;
   double* partials;  // pq[2][pmax] | rz[2][pmax] | rr[2][pmax]
   int pmax;
   int n_upd;         // number of update-kernel partials
@@ -30,10 +30,11 @@ struct ApplyIO {
 };
 
 // CG prologue: read slot A, sum the update partials (r.z and r.r), decide
-// convergence, publish slot B from block 0.
+// convergence, publish slot B from block 0.  A finished solve skips the
+// whole launch (x is already complete).
 template <typename T, int NT>
 __device__ inline void cg_prologue(const ApplyIO<T>& io, double* s_red, int* iter, T* beta,
-                                   T* alpha_x, bool* finish, bool* skip) {
+                                   bool* skip) {
   if (io.sc->A.done) {                     // uniform over the grid
     *skip = true;
     return;
@@ -44,7 +45,6 @@ __device__ inline void cg_prologue(const ApplyIO<T>& io, double* s_red, int* ite
   const double rtol2 = io.sc->A.rtol2;
   const int maxit = io.sc->A.maxit;
   double rr_stop = io.sc->A.rr_stop;
-  *alpha_x = (T)io.sc->A.alpha;
   const int k2 = it & 1;
   double rho, rr;
   sum_partials2<NT>(io.partials + (size_t)(2 + k2) * io.pmax,
@@ -55,7 +55,7 @@ __device__ inline void cg_prologue(const ApplyIO<T>& io, double* s_red, int* ite
   if (!isfinite(rr) || !isfinite(b)) done = 3;
   else if (rr <= rr_stop) done = 1;
   else if (it >= maxit) done = 2;
-  *finish = done != 0;
+  *skip = done != 0;
   *beta = (T)b;
   *iter = it;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -88,25 +88,20 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
     u.x_free = io.x_free;
     u.x_bdry = io.x_bdry;
   } else {
-    bool skip, finish;
-    T beta, alpha_x;
-    cg_prologue<T, NT>(io, s_red, &iter, &beta, &alpha_x, &finish, &skip);
+    bool skip;
+    T beta;
+    cg_prologue<T, NT>(io, s_red, &iter, &beta, &skip);
     if (skip) return;
-    u.r = io.r;
-    u.dinv = io.dinv;
+    u.z = io.z;
     u.p_in = (iter & 1) ? io.p0 : io.p1;     // iteration k reads p_{k-1}, writes p_k
     u.p_out = (iter & 1) ? io.p1 : io.p0;
-    u.x = io.x;
     u.beta = beta;
-    u.alpha_x = alpha_x;
-    u.finish = finish;
   }
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   double dot = 0.0;
   for (int un = 0; un < units_per_block; ++un)
     dot += apply_unit<T, NP, EPB, MODE>(u, tab, sm, bid * units_per_block + un);
   if constexpr (MODE == 1) {
-    if (u.finish) return;
     // one partial per block, summed by every block of the update kernel
     const double bs = block_sum<NT>(dot, s_red);
     if (threadIdx.x == 0) io.partials[(size_t)(iter & 1) * io.pmax + blockIdx.x] = bs;
@@ -236,11 +231,9 @@ hipError_t launch_cg_apply(const hdg_ctx* c, CgWork<T>& w, hipStream_t s) {
   ApplyIO<T> io{};
   io.qa = w.qa;
   io.qb = w.qb;
-  io.r = w.r;
-  io.dinv = w.dinv;
+  io.z = w.z;
   io.p0 = w.p[0];
   io.p1 = w.p[1];
-  io.x = w.x;
   io.partials = w.partials;
   io.pmax = w.pmax;
   io.n_upd = w.update_blocks;

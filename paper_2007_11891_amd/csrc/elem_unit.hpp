@@ -52,19 +52,6 @@ __host__ __device__ constexpr int epb_var() {
 template <int NP, int EPB>
 __host__ __device__ constexpr int unit_threads() { return round_up64(EPB * tpe<NP>()); }
 
-// a / b through the hardware reciprocal, two Newton steps and one residual
-// correction (within about one ulp; no IEEE division sequence).
-__device__ inline double div_fast(double a, double b) {
-  double r = __builtin_amdgcn_rcp(b);
-  double e = __builtin_fma(-b, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-b, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  const double q = a * r;
-  return __builtin_fma(r, __builtin_fma(-b, q, a), q);
-}
-__device__ inline float div_fast(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-
 // Pointers of one problem (already offset into batched storage).
 template <typename T>
 struct UnitIO {
@@ -77,15 +64,11 @@ struct UnitIO {
   const T* x_bdry;         // may be null
   T* qa;
   T* qb;
-  // fused CG apply
-  const T* r;
-  const T* dinv;
+  // fused CG apply: p = z + beta p_old
+  const T* z;              // z = D^-1 r
   const T* p_in;
   T* p_out;
-  T* x;
   T beta;
-  T alpha_x;
-  bool finish;             // only the last x update remains
 };
 
 // 1D data of one degree seen through pointers (the batched solver keeps the
@@ -148,12 +131,8 @@ __device__ inline double apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSme
           if constexpr (MODE == 0) {
             v = io.x_free[g];
           } else {
-            const T pin = io.p_in[g];
-            if (f & 1) io.x[g] += io.alpha_x * pin;   // the element below owns the face
-            if (!io.finish) {
-              v = io.dinv[g] * io.r[g] + io.beta * pin;
-              if (f & 1) io.p_out[g] = v;
-            }
+            v = io.z[g] + io.beta * io.p_in[g];
+            if (f & 1) io.p_out[g] = v;             // the element below owns the face
           }
         } else if (MODE == 0 && io.x_bdry != nullptr) {
           v = io.x_bdry[(int64_t)(fid[f] - io.nff) * NF + col];
@@ -162,9 +141,6 @@ __device__ inline double apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSme
       }
       xf[f] = v;
     }
-  }
-  if constexpr (MODE == 1) {
-    if (io.finish) return 0.0;             // uniform over the unit's problem
   }
   __syncthreads();
 

@@ -57,7 +57,7 @@ hdg_status alloc_work(hdg_ctx* c, CgWork<T>& w) {
   for (int v = 0; v < kNumTileVariants; ++v)
     max_apply = std::max(max_apply, elem_apply_blocks(c->np, c->n_elem, v));
   ST_TRY(dalloc(&w.x, n));
-  ST_TRY(dalloc(&w.r, n));
+  ST_TRY(dalloc(&w.z, n));
   ST_TRY(dalloc(&w.p[0], n));
   ST_TRY(dalloc(&w.p[1], n));
   ST_TRY(dalloc(&w.qa, n));
@@ -79,7 +79,7 @@ void free_work(CgWork<T>& w) {
   if (w.graph) (void)hipGraphExecDestroy(w.graph);
   w.graph = nullptr;
   dfree(w.x);
-  dfree(w.r);
+  dfree(w.z);
   dfree(w.p[0]);
   dfree(w.p[1]);
   dfree(w.qa);

@@ -76,7 +76,7 @@ struct CgScalars {
 template <typename T>
 struct CgWork {
   T* x = nullptr;
-  T* r = nullptr;
+  T* z = nullptr;        // preconditioned residual D^-1 r (r itself is not stored)
   T* p[2] = {nullptr, nullptr};
   T* qa = nullptr;       // contribution of the element below each face
   T* qb = nullptr;       // contribution of the element above each face

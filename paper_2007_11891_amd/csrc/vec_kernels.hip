@@ -3,12 +3,14 @@
 //
 // CG (paper: section "Summary of solution method", solver HDG-trans): the
 // iteration is split into two launches.  The fused element apply (see
-// elem_kernels.hip) forms p = z + beta p_old with z = D^-1 r on the fly,
-// applies x += alpha_old p_old on the faces it owns, and reduces p.q from
-// element-local quadratic forms; its last block sets alpha = rho / p.q.
-// The update below forms q = qa + qb, r -= alpha q, and reduces r.z and r.r;
-// its last block sets beta, advances the iteration counter and raises the
-// done flag.  All reductions are block partials summed in a fixed order.
+// elem_kernels.hip) forms p = z + beta p_old on the fly, writes p, and
+// reduces p.q from element-local quadratic forms.  The update below forms
+// alpha = rho / p.q, q = qa + qb, z -= alpha D^-1 q, x += alpha p, and
+// reduces r.z and r.r with r = z / D^-1.  The CG carries z = D^-1 r instead
+// of r: the element kernel, whose face gather streams memory less
+// efficiently, then reads two vectors per face instead of four, and the
+// x update moves to this streaming kernel.  All reductions are block
+// partials summed in a fixed order.
 #include "device_common.hpp"
 
 namespace hdg {
@@ -25,12 +27,13 @@ static inline int vec_blocks(int64_t n, int cap = 2048) {
 
 // ------------------------------------------------------------------ CG ----
 // Update of iteration k: alpha_k = rho_k / (p_k . q_k) with p.q summed from
-// the apply's partials; r -= alpha q with q = qa + qb; partials of r.z and
-// r.r for the next apply.  Block 0 publishes slot A for the next apply.
+// the apply's partials; z -= alpha D^-1 q with q = qa + qb; x += alpha p_k;
+// partials of r.z and r.r for the next apply.  Block 0 publishes slot A.
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
-cg_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb, T* __restrict__ r,
-                 const T* __restrict__ dinv, double* __restrict__ partials, int pmax, int n_apply,
+cg_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb, T* __restrict__ z,
+                 const T* __restrict__ dinv, T* __restrict__ x, const T* __restrict__ p0,
+                 const T* __restrict__ p1, double* __restrict__ partials, int pmax, int n_apply,
                  CgScalars* sc) {
   __shared__ double s_red[kVecThreads / 64];
   // scalar reads of slot B (a struct copy here costs a large serialisation)
@@ -56,29 +59,34 @@ cg_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb, 
     return;
   }
   const T a = (T)alpha;
+  const T* __restrict__ p = (k & 1) ? p1 : p0;   // p_k, written by the apply of iteration k
   T rz_t = 0, rr_t = 0;
   // kUnroll independent elements per thread: all loads issued before use
   const int64_t stride = (int64_t)gridDim.x * kVecThreads;
   for (int64_t g0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g0 < n;
        g0 += kUnroll * stride) {
-    T va[kUnroll], vb[kUnroll], vr[kUnroll], vd[kUnroll];
+    T va[kUnroll], vb[kUnroll], vz[kUnroll], vd[kUnroll], vx[kUnroll], vp[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int64_t g = g0 + u * stride;
       if (g < n) {
         va[u] = qa[g];
         vb[u] = qb[g];
-        vr[u] = r[g];
+        vz[u] = z[g];
         vd[u] = dinv[g];
+        vx[u] = x[g];
+        vp[u] = p[g];
       }
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int64_t g = g0 + u * stride;
       if (g < n) {
-        const T rn = vr[u] - a * (va[u] + vb[u]);
-        r[g] = rn;
-        rz_t += rn * (vd[u] * rn);
+        const T zn = vz[u] - a * (vd[u] * (va[u] + vb[u]));
+        z[g] = zn;
+        x[g] = vx[u] + a * vp[u];
+        const T rn = div_fast(zn, vd[u]);
+        rz_t += zn * rn;
         rr_t += rn * rn;
       }
     }
@@ -102,11 +110,12 @@ cg_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb, 
   }
 }
 
-// r = b, x = 0, p_{-1} = 0, and the partials of b.D^-1 b and b.b that the
-// first apply sums (they play the role of the update of iteration -1).
+// z = D^-1 b (r = b), x = 0, p_{-1} = 0, and the partials of b.D^-1 b and
+// b.b that the first apply sums (they play the role of the update of
+// iteration -1).
 template <typename T>
 __global__ void __launch_bounds__(kVecThreads)
-cg_init_kernel(int64_t n, const T* __restrict__ b, T* __restrict__ r, T* __restrict__ x,
+cg_init_kernel(int64_t n, const T* __restrict__ b, T* __restrict__ z, T* __restrict__ x,
                T* __restrict__ p1, const T* __restrict__ dinv, double* __restrict__ partials,
                int pmax) {
   __shared__ double s_red[kVecThreads / 64];
@@ -114,10 +123,11 @@ cg_init_kernel(int64_t n, const T* __restrict__ b, T* __restrict__ r, T* __restr
   for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
        g += (int64_t)gridDim.x * kVecThreads) {
     const T v = b[g];
-    r[g] = v;
+    const T zv = dinv[g] * v;
+    z[g] = zv;
     x[g] = 0;
     p1[g] = 0;
-    rz_t += v * (dinv[g] * v);
+    rz_t += v * zv;
     rr_t += v * v;
   }
   const double brz = block_sum<kVecThreads>((double)rz_t, s_red);
@@ -131,13 +141,14 @@ cg_init_kernel(int64_t n, const T* __restrict__ b, T* __restrict__ r, T* __restr
 template <typename T>
 hipError_t launch_cg_update(const hdg_ctx* c, CgWork<T>& w, hipStream_t s) {
   hipLaunchKernelGGL((cg_update_kernel<T>), dim3(w.update_blocks), dim3(kVecThreads), 0, s, w.n,
-                     w.qa, w.qb, w.r, w.dinv, w.partials, w.pmax, w.apply_blocks, w.sc);
+                     w.qa, w.qb, w.z, w.dinv, w.x, w.p[0], w.p[1], w.partials, w.pmax,
+                     w.apply_blocks, w.sc);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_cg_init(const hdg_ctx*, CgWork<T>& w, const T* b, hipStream_t s) {
   hipLaunchKernelGGL((cg_init_kernel<T>), dim3(w.update_blocks), dim3(kVecThreads), 0, s, w.n, b,
-                     w.r, w.x, w.p[1], w.dinv, w.partials, w.pmax);
+                     w.z, w.x, w.p[1], w.dinv, w.partials, w.pmax);
   return hipGetLastError();
 }
 
