@@ -103,6 +103,63 @@ def measured_traffic(kernel: str):
     return None if entry is None else entry.get("traffic_bytes")
 
 
+def bench_mixed(pkg, W, torch, dev, reps: int = 3):
+    """FP32-inner / FP64-outer vs plain FP64, time to relative residual 1e-10
+    on the 32^3 unit-cube mesh, p in {4, 8, 12}, lambda in {1e-2, 1, 1e2},
+    u = sin(2 pi x) cos(3 pi y) exp(z) (Dirichlet data and forcing from it);
+    each result with its nodal error against that u and its distance to the
+    FP64 solution."""
+    rows = []
+    for p in (4, 8, 12):
+        for lam in (1e-2, 1.0, 1e2):
+            prob = W.mixed(p, lam)
+            c = pkg.HdgContext(prob.n, prob.widths, prob.p, prob.tau, lam)
+            c.autotune(reps=10)
+            vx, tx = c.coords()
+            vx, tx = vx.cpu().numpy(), tx.cpu().numpy()
+            f = torch.as_tensor(W.f_mixed(*vx.T, lam), device=dev)
+            g = torch.as_tensor(W.u_mixed(*tx.T), device=dev)
+            u_ex = torch.as_tensor(W.u_mixed(*vx.T), device=dev)
+            nf = c.sizes.n_free
+            res = {}
+            for name, o in (("fp64", pkg.default_opts(rtol=1e-10)),
+                            ("mixed", pkg.default_opts(rtol=1e-10, mixed=1))):
+                ts = []
+                for _ in range(reps + 1):
+                    tr = g.clone()
+                    tr[:nf] = 0
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    _, uv, info = c.solve_forcing(f, tr, opts=o)
+                    torch.cuda.synchronize()
+                    ts.append(1e3 * (time.perf_counter() - t))
+                res[name] = (statistics.median(ts[1:]), info, tr, uv)
+            t64, i64, tr64, uv64 = res["fp64"]
+            tmx, imx, trmx, uvmx = res["mixed"]
+            nrm = float(torch.linalg.norm(u_ex))
+            row = {"p": p, "lambda": lam, "n_trace_free": nf,
+                   "fp64_ms": round(t64, 3), "mixed_ms": round(tmx, 3),
+                   "speedup": round(t64 / tmx, 3),
+                   "fp64_iters": i64["iters"], "mixed_inner_iters": imx["iters"],
+                   "mixed_outer": imx["outer_iters"],
+                   "fp64_rel_res": i64["rel_res"], "mixed_rel_res": imx["rel_res"],
+                   "mixed_vs_fp64_trace_rel_diff":
+                       float(torch.linalg.norm(trmx - tr64) / torch.linalg.norm(tr64)),
+                   "fp64_nodal_error": float(torch.linalg.norm(uv64 - u_ex)) / nrm,
+                   "mixed_nodal_error": float(torch.linalg.norm(uvmx - u_ex)) / nrm}
+            log(f"[bench] mixed 32^3 p={p} lam={lam:g}: fp64 {t64:.2f} ms ({i64['iters']} it), "
+                f"mixed {tmx:.2f} ms ({imx['iters']} inner, {imx['outer_iters']} outer), "
+                f"x{t64 / tmx:.2f}")
+            rows.append(row)
+            c.close()
+            del f, g, u_ex, res
+            torch.cuda.empty_cache()
+    sp = [r["speedup"] for r in rows]
+    return {"workload": "32^3 unit cube, u = sin(2 pi x) cos(3 pi y) exp(z); time to rel. residual "
+                        "1e-10 (FP32 inner CG to 1e-4 + FP64 defect correction vs FP64 CG)",
+            "geomean_speedup": round(float(np.exp(np.mean(np.log(sp)))), 3), "cases": rows}
+
+
 def bench_batched(pkg, W, torch, dev, reps: int = 3):
     """256 independent unit-cube problems (n_a ~ U{4..12}, p ~ U{2..10},
     lambda log-uniform in [1e-2, 1e2], f ~ N(0,1), seed 4) in one persistent
@@ -237,13 +294,14 @@ def main():
     variant, tile_times = ctx.autotune(reps=50)      # tile shape, chosen before timing
     tile = ctx.tile_shape()
     log(f"[bench] tile variant {variant} ({tile['elems_per_unit']} elements / "
-        f"{tile['threads_per_unit']} threads per unit), times {[round(t * 1e3, 2) for t in tile_times]} us")
+        f"{tile['threads_per_unit']} threads per unit), CG form {tile['cg_variant']}, "
+        f"times {[round(t * 1e3, 2) for t in tile_times]} us")
 
     if args.kernels_only:
         x64 = torch.as_tensor(W.random_trace(nf, 1), device=dev)
         y64 = torch.empty_like(x64)
         for which, name in ((0, "apply64"), (1, "apply32"), (4, "cg_apply64"),
-                            (5, "cg_update64"), (8, "copy64")):
+                            (5, "cg_update64"), (9, "cg_onekernel64"), (8, "copy64")):
             xin = x64.float() if which == 1 else x64
             ms = ctx.time_kernel(which, xin, args.reps, y=y64 if which == 8 else None)
             log(f"[bench] {name} {ms * 1e3:.3f} us")
@@ -287,16 +345,24 @@ def main():
     t_cg_update = ctx.time_kernel(5, x64, reps)
     t_cg_iter = ctx.time_kernel(2, x64, reps)
     t_cg_iter32 = ctx.time_kernel(3, x32, reps)
+    t_one = ctx.time_kernel(9, x64, reps)
+    t_one32 = ctx.time_kernel(10, x32, reps)
     log(f"[bench] apply64 {t_apply64*1e3:.2f} us apply32 {t_apply32*1e3:.2f} us "
         f"cg_apply {t_cg_apply*1e3:.2f} us cg_update {t_cg_update*1e3:.2f} us "
         f"cg_iter {t_cg_iter*1e3:.2f} us cg_iter32 {t_cg_iter32*1e3:.2f} us")
-    # per free DOF and CG iteration (8 B each): the fused apply reads z, p_old
-    # and writes p, qa, qb; the update reads z, qa, qb, D^-1, x, p and writes
-    # z, x.  The roofline is reported for the longer of the two kernels.
+    # per free DOF and CG iteration (8 B each).  Two-kernel form: the fused
+    # apply reads z, p_old and writes p, qa, qb; the update reads z, qa, qb,
+    # D^-1, x, p and writes z, x.  One-kernel form: reads z, p, s, qa, qb,
+    # D^-1, x and writes z, p, s, x, qa, qb (104 B).  The roofline is reported
+    # for the dominant kernel of the CG form the solve uses.
     cg_apply_bytes = 40 * nf
     cg_update_bytes = 64 * nf
+    one_bytes = 104 * nf
     apply_name = f"elem_apply_kernel<double, {prob.p + 1}, {tile['elems_per_unit']}, 1>"
-    if t_cg_apply >= t_cg_update:
+    one_name = f"elem_apply_kernel<double, {prob.p + 1}, {tile['elems_per_unit']}, 2>"
+    if tile["cg_variant"] == 0:
+        kname, kbytes, kt, kdesc = one_name, one_bytes, t_one, "one-kernel CG iteration"
+    elif t_cg_apply >= t_cg_update:
         kname, kbytes, kt, kdesc = apply_name, cg_apply_bytes, t_cg_apply, "fused CG apply"
     else:
         kname, kbytes, kt, kdesc = "cg_update_kernel<double>", cg_update_bytes, t_cg_update, "CG update"
@@ -306,11 +372,8 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(kname),
                 "bytes_per_launch": kbytes, "avg_launch_us": round(kt * 1e3, 3),
-                "other_kernel": {
-                    "kernel": "cg_update_kernel<double>" if kname == apply_name else apply_name,
-                    "achieved_GBs": round((cg_update_bytes / (t_cg_update * 1e-3) if kname == apply_name
-                                           else cg_apply_bytes / (t_cg_apply * 1e-3)) / 1e9, 1),
-                    "avg_launch_us": round((t_cg_update if kname == apply_name else t_cg_apply) * 1e3, 3)}}
+                "cg_form": "one kernel per iteration" if tile["cg_variant"] == 0
+                           else "element + update kernel per iteration"}
     apply_bytes = 16 * nf
     apply_only = {"trace_dof_per_s_fp64": nf / (t_apply64 * 1e-3),
                   "trace_dof_per_s_fp32": nf / (t_apply32 * 1e-3),
@@ -319,30 +382,7 @@ def main():
                   "algorithmic_GBs_fp64": round(apply_bytes / (t_apply64 * 1e-3) / 1e9, 1),
                   "algorithmic_GBs_fp32": round(apply_bytes / 2 / (t_apply32 * 1e-3) / 1e9, 1)}
 
-    # ---- time-to-1e-10: FP64 vs mixed precision ------------------------------
-    mixed = None
-    if not args.no_mixed:
-        def solve_time(o, reps=3):
-            ts, last = [], None
-            for _ in range(reps):
-                trace.zero_()
-                torch.cuda.synchronize()
-                t = time.perf_counter()
-                _, _, inf = ctx.solve_forcing(f, trace, want_volume=False, opts=o)
-                torch.cuda.synchronize()
-                ts.append(1e3 * (time.perf_counter() - t))
-                last = inf
-            return statistics.median(ts), last, trace.clone()
-        t64, i64, u64 = solve_time(pkg.default_opts(rtol=1e-10))
-        tmx, imx, umx = solve_time(pkg.default_opts(rtol=1e-10, mixed=1))
-        diff = float(torch.linalg.norm(umx - u64) / torch.linalg.norm(u64))
-        mixed = {"fp64_ms": round(t64, 3), "mixed_ms": round(tmx, 3),
-                 "speedup": round(t64 / tmx, 3), "fp64_iters": i64["iters"],
-                 "mixed_inner_iters": imx["iters"], "mixed_outer": imx["outer_iters"],
-                 "fp64_rel_res": i64["rel_res"], "mixed_rel_res": imx["rel_res"],
-                 "mixed_vs_fp64_rel_diff": diff}
-        log(f"[bench] time-to-1e-10 fp64 {t64:.2f} ms ({i64['iters']} it), mixed {tmx:.2f} ms "
-            f"({imx['iters']} inner, {imx['outer_iters']} outer), diff {diff:.1e}")
+    mixed = None if args.no_mixed else bench_mixed(pkg, W, torch, dev)
 
     batched = None if args.no_batch else bench_batched(pkg, W, torch, dev)
     adjoint = None if args.no_adjoint else bench_adjoint(pkg, W, torch, dev)
@@ -366,12 +406,15 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "apply_only": apply_only,
-        "cg_iteration_us": {"fp64": round(t_cg_iter * 1e3, 3), "fp32": round(t_cg_iter32 * 1e3, 3),
+        "cg_iteration_us": {"two_kernel_fp64": round(t_cg_iter * 1e3, 3),
+                            "two_kernel_fp32": round(t_cg_iter32 * 1e3, 3),
                             "fused_apply_fp64": round(t_cg_apply * 1e3, 3),
-                            "update_fp64": round(t_cg_update * 1e3, 3)},
+                            "update_fp64": round(t_cg_update * 1e3, 3),
+                            "one_kernel_fp64": round(t_one * 1e3, 3),
+                            "one_kernel_fp32": round(t_one32 * 1e3, 3)},
         "mixed_precision": mixed,
         "tile": {"variant": variant, "elems_per_unit": tile["elems_per_unit"],
-                 "threads_per_unit": tile["threads_per_unit"],
+                 "threads_per_unit": tile["threads_per_unit"], "cg_variant": tile["cg_variant"],
                  "autotune_cg_iter_us": [round(t * 1e3, 3) for t in tile_times]},
         "batched": batched,
         "adjoint": adjoint,

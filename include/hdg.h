@@ -101,6 +101,11 @@ typedef struct {
   double inner_rtol;  /* mixed: relative reduction asked of each inner solve */
   int max_outer;      /* mixed: cap on defect-correction steps              */
   int check_every;    /* iterations per host convergence poll (>= 1)        */
+  int variant;        /* CG form: 0 one kernel per iteration (Chronopoulos-
+                         Gear form of the same PCG: one reduction point per
+                         iteration); 1 textbook PCG, an element kernel and a
+                         vector update kernel per iteration; -1 the
+                         context's choice (hdg_autotune, or by mesh size)  */
 } hdg_solve_opts;
 
 typedef struct {
@@ -112,7 +117,7 @@ typedef struct {
 } hdg_solve_info;
 
 /* Fill *opts with defaults: rtol 1e-10, maxit 20000, Jacobi, FP64,
- * inner_rtol 1e-4, max_outer 12, check_every 25. */
+ * inner_rtol 1e-4, max_outer 12, check_every 25, variant -1. */
 void hdg_default_opts(hdg_solve_opts* opts);
 
 /* Create a context for one mesh (paper section "LDG operator structure in
@@ -235,17 +240,20 @@ hdg_status hdg_adjoint(hdg_ctx* ctx, const double* f, const double* trace,
  * (0, 1 or 2).  Synchronises the stream; invalidates captured CG graphs. */
 hdg_status hdg_set_tile(hdg_ctx* ctx, int variant);
 
-/* Autotuner: times one fused FP64 CG iteration (apply + update) for every
- * tile variant on this context's mesh (`reps` launches each, HIP events on
- * the context stream), selects the fastest and returns it in *chosen
- * (times_ms: host double[3] or NULL).  Synchronises the stream. */
+/* Autotuner: times one FP64 CG iteration in both CG forms (see
+ * hdg_solve_opts.variant) for every tile variant on this context's mesh
+ * (`reps` launches each, HIP events on the context stream), keeps the
+ * fastest pair as the context's tile shape and CG form, returns the tile
+ * variant in *chosen and, in times_ms (host double[3] or NULL), the best time
+ * of each tile variant.  Synchronises the stream. */
 hdg_status hdg_autotune(hdg_ctx* ctx, int reps, int* chosen, double* times_ms);
 
 /* Current tile shape: *variant (0..2), *elems_per_unit (elements of one
- * work unit) and *threads_per_unit (threads of one FP64 work unit, a
- * multiple of 64); any pointer may be NULL.  Host-only, no GPU work. */
+ * work unit), *threads_per_unit (threads of one FP64 work unit, a multiple
+ * of 64), and the context's CG form *cg_variant (0 or 1); any pointer may
+ * be NULL.  Host-only, no GPU work. */
 hdg_status hdg_tile_shape(const hdg_ctx* ctx, int* variant, int* elems_per_unit,
-                          int* threads_per_unit);
+                          int* threads_per_unit, int* cg_variant);
 
 /* Diagonal of K^_ff (eigen basis), device double[n_free] output. */
 hdg_status hdg_diagonal(hdg_ctx* ctx, double* diag_free);
@@ -256,7 +264,8 @@ hdg_status hdg_diagonal(hdg_ctx* ctx, double* diag_free);
  * (x -> y), 1 = FP32 eigen-basis element apply, 2 = FP64 CG iteration
  * (fused apply + update), 3 = FP32 CG iteration, 4 / 5 = FP64 fused CG
  * apply / update alone, 6 / 7 = the same in FP32, 8 = plain FP64 copy
- * x -> y (reference traffic).  x, y device buffers of n_free values of the
+ * x -> y (reference traffic), 9 / 10 = one-kernel CG iteration (solver
+ * variant 0) in FP64 / FP32.  x, y device buffers of n_free values of the
  * matching type (x read; y written only by 8).  Synchronises. */
 hdg_status hdg_time_kernel(hdg_ctx* ctx, int which, const void* x, void* y,
                            int reps, double* ms);

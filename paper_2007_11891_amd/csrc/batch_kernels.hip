@@ -137,9 +137,9 @@ __device__ inline double run_units(const UnitIO<double>& io, const double* tabs,
   cdouble* ct = (cdouble*)tp;
   const ConstTab tab{ct + o, ct + o + NP, ct + o + 2 * NP, ct[o + 3 * NP]};
   auto& sm = *reinterpret_cast<UnitSmem<double, NP, EPB>*>(smem);
-  double dot = 0.0;
-  for (int u = u0; u < u1; ++u) dot += apply_unit<double, NP, EPB, 1>(io, tab, sm, u);
-  return dot;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int u = u0; u < u1; ++u) apply_unit<double, NP, EPB, 1>(io, tab, sm, u, acc);
+  return acc[0];
 }
 
 __device__ inline double dispatch_units(int np, int variant, const UnitIO<double>& io,

@@ -27,6 +27,16 @@ struct ApplyIO {
   int pmax;
   int n_upd;         // number of update-kernel partials
   CgScalars* sc;
+  // one-kernel CG (MODE 2): ping-pong buffers, selected by rd = launch parity
+  T* zb[2];
+  T* pb[2];
+  T* sb[2];
+  T* qab[2];
+  T* qbb[2];
+  T* x;
+  const T* dinv;
+  int rd;            // this launch reads state slot rd and writes slot rd ^ 1
+  int n_parts;       // partials per slot written by the previous launch
 };
 
 // CG prologue: read slot A, sum the update partials (r.z and r.r), decide
@@ -69,7 +79,87 @@ __device__ inline void cg_prologue(const ApplyIO<T>& io, double* s_red, int* ite
   }
 }
 
-template <typename T, int NP, int EPB, int MODE>   // MODE 0: plain apply, 1: fused CG apply
+// Prologue of the one-kernel CG iteration (Chronopoulos-Gear form of the
+// preconditioned CG, one global reduction per iteration).  Launch k reads
+// slot rd = k & 1 and writes slot rd ^ 1 (block 0).  For k >= 1 it sums the
+// previous launch's partials of delta = z.Az, gamma = r.z and r.r (all of
+// iterate k - 1), tests convergence of x_{k-1}, and forms
+//   beta_{k-1} = gamma_{k-1} / gamma_{k-2}            (0 for k = 1)
+//   alpha_{k-1} = gamma_{k-1} / (delta_{k-1} - beta_{k-1} gamma_{k-1} / alpha_{k-2})
+// (alpha_0 = gamma_0 / delta_0).  Slot fields: rho = gamma of the previous
+// iterate, alpha = its alpha, iter = k.  A finished solve skips the launch.
+template <typename T, int NT>
+__device__ inline void cgcg_prologue(const ApplyIO<T>& io, double* s_red, bool* first, T* alpha,
+                                     T* beta, bool* skip) {
+  CgState* R = io.rd ? &io.sc->B : &io.sc->A;
+  CgState* W = io.rd ? &io.sc->A : &io.sc->B;
+  const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+  const int rdone = R->done;
+  if (rdone) {                              // uniform over the grid
+    if (leader) {
+      W->done = rdone;
+      W->iter = R->iter;
+      W->rr = R->rr;
+      W->rr_stop = R->rr_stop;
+    }
+    *skip = true;
+    return;
+  }
+  const int k = R->iter;
+  const double rtol2 = R->rtol2;
+  const int maxit = R->maxit;
+  if (k == 0) {
+    *first = true;
+    *skip = false;
+    *alpha = 0;
+    *beta = 0;
+    if (leader) {
+      W->iter = 1;
+      W->rtol2 = rtol2;
+      W->maxit = maxit;
+      W->done = 0;
+    }
+    return;
+  }
+  *first = false;
+  const int ks = io.rd ^ 1;
+  double gam, rr;
+  sum_partials2<NT>(io.partials + (size_t)(2 + ks) * io.pmax,
+                    io.partials + (size_t)(4 + ks) * io.pmax, io.n_parts, s_red, &gam, &rr);
+  const double del = sum_partials<NT>(io.partials + (size_t)ks * io.pmax, io.n_parts, 1, 0, s_red);
+  const double rr_stop = (k == 1) ? rtol2 * rr : R->rr_stop;
+  int done = 0;
+  double a = 0.0, b = 0.0;
+  if (!isfinite(rr) || !isfinite(gam)) done = 3;
+  else if (rr <= rr_stop) done = 1;
+  else if (k - 1 >= maxit) done = 2;
+  else {
+    b = (k == 1) ? 0.0 : gam / R->rho;
+    a = (k == 1) ? gam / del : gam / (del - b * gam / R->alpha);
+    if (!(a > 0.0) || !isfinite(a) || !isfinite(b)) done = 3;
+  }
+  if (leader) {
+    W->rr = rr;
+    W->rr_stop = rr_stop;
+    W->rtol2 = rtol2;
+    W->maxit = maxit;
+    W->pq = del;
+    W->done = done;
+    if (done) {
+      W->iter = k - 1;                      // iterations completed: x_{k-1} is the result
+    } else {
+      W->rho = gam;
+      W->alpha = a;
+      W->iter = k + 1;
+    }
+  }
+  *skip = done != 0;
+  *alpha = (T)a;
+  *beta = (T)b;
+}
+
+// MODE 0: plain apply, 1: fused CG apply (two-kernel CG), 2: one-kernel CG iteration
+template <typename T, int NP, int EPB, int MODE>
 __global__ void __launch_bounds__((unit_threads<NP, EPB>()))
 elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int units_per_block) {
   constexpr int NT = unit_threads<NP, EPB>();
@@ -87,6 +177,27 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
   if constexpr (MODE == 0) {
     u.x_free = io.x_free;
     u.x_bdry = io.x_bdry;
+  } else if constexpr (MODE == 2) {
+    bool skip, first;
+    T alpha, beta;
+    cgcg_prologue<T, NT>(io, s_red, &first, &alpha, &beta, &skip);
+    if (skip) return;
+    const int rd = io.rd, wr = io.rd ^ 1;
+    u.first = first;
+    u.alpha = alpha;
+    u.beta = beta;
+    u.z_old = first ? io.zb[rd] : io.zb[wr];   // z_k lives in zb[k & 1]
+    u.z_new = io.zb[rd];
+    u.p_in = io.pb[rd];                        // p_{k-2}
+    u.p_out = io.pb[wr];                       // p_{k-1}
+    u.s_old = io.sb[rd];
+    u.s_new = io.sb[wr];
+    u.w_a = io.qab[wr];                        // A z_{k-1}, from the previous launch
+    u.w_b = io.qbb[wr];
+    u.qa = io.qab[rd];
+    u.qb = io.qbb[rd];
+    u.dinv = io.dinv;
+    u.x = io.x;
   } else {
     bool skip;
     T beta;
@@ -98,13 +209,23 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
     u.beta = beta;
   }
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  double dot = 0.0;
+  double acc[3] = {0.0, 0.0, 0.0};
   for (int un = 0; un < units_per_block; ++un)
-    dot += apply_unit<T, NP, EPB, MODE>(u, tab, sm, bid * units_per_block + un);
+    apply_unit<T, NP, EPB, MODE>(u, tab, sm, bid * units_per_block + un, acc);
   if constexpr (MODE == 1) {
     // one partial per block, summed by every block of the update kernel
-    const double bs = block_sum<NT>(dot, s_red);
+    const double bs = block_sum<NT>(acc[0], s_red);
     if (threadIdx.x == 0) io.partials[(size_t)(iter & 1) * io.pmax + blockIdx.x] = bs;
+  } else if constexpr (MODE == 2) {
+    // z.Az, r.z, r.r of this launch's iterate, one partial each per block
+    const double b0 = block_sum<NT>(acc[0], s_red);
+    const double b1 = block_sum<NT>(acc[1], s_red);
+    const double b2 = block_sum<NT>(acc[2], s_red);
+    if (threadIdx.x == 0) {
+      io.partials[(size_t)io.rd * io.pmax + blockIdx.x] = b0;
+      io.partials[(size_t)(2 + io.rd) * io.pmax + blockIdx.x] = b1;
+      io.partials[(size_t)(4 + io.rd) * io.pmax + blockIdx.x] = b2;
+    }
   }
 }
 
@@ -241,6 +362,28 @@ hipError_t launch_cg_apply(const hdg_ctx* c, CgWork<T>& w, hipStream_t s) {
   return launch_apply_dispatch<T, 1>(c, tab_of<T>(c), io, s);
 }
 
+template <typename T>
+hipError_t launch_cgcg_iter(const hdg_ctx* c, CgWork<T>& w, int rd, hipStream_t s) {
+  ApplyIO<T> io{};
+  for (int i = 0; i < 2; ++i) {
+    io.zb[i] = w.zz[i];
+    io.pb[i] = w.p[i];
+    io.sb[i] = w.s[i];
+    io.qab[i] = w.qq[i][0];
+    io.qbb[i] = w.qq[i][1];
+  }
+  io.x = w.x;
+  io.dinv = w.dinv;
+  io.partials = w.partials;
+  io.pmax = w.pmax;
+  io.sc = w.sc;
+  io.rd = rd;
+  io.n_parts = w.apply_blocks;
+  return launch_apply_dispatch<T, 2>(c, tab_of<T>(c), io, s);
+}
+
+template hipError_t launch_cgcg_iter<double>(const hdg_ctx*, CgWork<double>&, int, hipStream_t);
+template hipError_t launch_cgcg_iter<float>(const hdg_ctx*, CgWork<float>&, int, hipStream_t);
 template hipError_t launch_elem_apply<double>(const hdg_ctx*, const double*, const double*,
                                               double*, double*, hipStream_t);
 template hipError_t launch_elem_apply<float>(const hdg_ctx*, const float*, const float*, float*,

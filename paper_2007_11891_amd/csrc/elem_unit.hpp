@@ -64,11 +64,24 @@ struct UnitIO {
   const T* x_bdry;         // may be null
   T* qa;
   T* qb;
-  // fused CG apply: p = z + beta p_old
+  // fused CG apply (MODE 1): p = z + beta p_old
   const T* z;              // z = D^-1 r
   const T* p_in;
   T* p_out;
   T beta;
+  // one-kernel CG iteration (MODE 2): w = qa_old + qb_old = A z_old,
+  //   s = D^-1 w + beta s_old, p = z_old + beta p_old, x += alpha p,
+  //   z = z_old - alpha s, then the operator applied to z
+  const T* z_old;
+  T* z_new;
+  const T* s_old;
+  T* s_new;
+  const T* w_a;
+  const T* w_b;
+  const T* dinv;
+  T* x;
+  T alpha;
+  bool first;              // first launch: the operator applied to z_old as is
 };
 
 // 1D data of one degree seen through pointers (the batched solver keeps the
@@ -89,11 +102,12 @@ struct UnitSmem {
 };
 
 // Processes elements [unit EPB, unit EPB + EPB).  Every thread of the block
-// calls it; threads beyond EPB * tpe idle.  Returns the thread's share of the
-// element-local quadratic forms p_e^T K_e p_e (MODE 1).
+// calls it; threads beyond EPB * tpe idle.  Adds to acc the thread's share of
+// the element-local quadratic forms v_e^T K_e v_e of the input v (MODES 1, 2)
+// and, in MODE 2, of r.z and r.r over the faces the unit owns (acc[1], acc[2]).
 template <typename T, int NP, int EPB, int MODE, typename Tab>
-__device__ inline double apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
-                                    int unit) {
+__device__ inline void apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
+                                  int unit, double* acc) {
   constexpr int NF = NP * NP;
   constexpr int TPE = tpe<NP>();
   constexpr int P = upitch<NP>();
@@ -130,9 +144,30 @@ __device__ inline double apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSme
           const int64_t g = (int64_t)fid[f] * NF + col;
           if constexpr (MODE == 0) {
             v = io.x_free[g];
-          } else {
+          } else if constexpr (MODE == 1) {
             v = io.z[g] + io.beta * io.p_in[g];
             if (f & 1) io.p_out[g] = v;             // the element below owns the face
+          } else {
+            const T d = io.dinv[g];
+            if (io.first) {
+              v = io.z_old[g];
+            } else {
+              const T zo = io.z_old[g];
+              const T sn = d * (io.w_a[g] + io.w_b[g]) + io.beta * io.s_old[g];
+              v = zo - io.alpha * sn;
+              if (f & 1) {                          // the element below owns the face
+                const T pn = zo + io.beta * io.p_in[g];
+                io.s_new[g] = sn;
+                io.p_out[g] = pn;
+                io.z_new[g] = v;
+                io.x[g] += io.alpha * pn;
+              }
+            }
+            if (f & 1) {
+              const double r = (double)div_fast(v, d);
+              acc[1] += (double)v * r;
+              acc[2] += r * r;
+            }
           }
         } else if (MODE == 0 && io.x_bdry != nullptr) {
           v = io.x_bdry[(int64_t)(fid[f] - io.nff) * NF + col];
@@ -206,11 +241,11 @@ __device__ inline double apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSme
       const int64_t g = (int64_t)fid[f] * NF + col;
       if (f & 1) io.qa[g] = out[f];
       else io.qb[g] = out[f];
-      if constexpr (MODE == 1) dot += (double)(xf[f] * out[f]);
+      if constexpr (MODE != 0) dot += (double)(xf[f] * out[f]);
     }
   }
   __syncthreads();                          // LDS is reused by the next unit
-  return dot;
+  acc[0] += dot;
 }
 
 }  // namespace hdg

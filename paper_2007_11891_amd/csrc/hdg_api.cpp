@@ -62,14 +62,22 @@ hdg_status alloc_work(hdg_ctx* c, CgWork<T>& w) {
   ST_TRY(dalloc(&w.p[1], n));
   ST_TRY(dalloc(&w.qa, n));
   ST_TRY(dalloc(&w.qb, n));
+  ST_TRY(dalloc(&w.zz[1], n));
+  ST_TRY(dalloc(&w.s[0], n));
+  ST_TRY(dalloc(&w.s[1], n));
+  ST_TRY(dalloc(&w.qq[1][0], n));
+  ST_TRY(dalloc(&w.qq[1][1], n));
+  w.zz[0] = w.z;
+  w.qq[0][0] = w.qa;
+  w.qq[0][1] = w.qb;
   w.pmax = std::max(max_apply, w.update_blocks);
   ST_TRY(dalloc(&w.partials, 6 * (int64_t)w.pmax));
   ST_TRY(dalloc(&w.sc, 1));
   HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(CgScalars), c->stream));
   HIP_TRY(hipMemsetAsync(w.partials, 0, sizeof(double) * 6 * (size_t)w.pmax, c->stream));
   if (n > 0) {
-    HIP_TRY(hipMemsetAsync(w.qa, 0, sizeof(T) * n, c->stream));
-    HIP_TRY(hipMemsetAsync(w.qb, 0, sizeof(T) * n, c->stream));
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) HIP_TRY(hipMemsetAsync(w.qq[i][j], 0, sizeof(T) * n, c->stream));
   }
   return HDG_OK;
 }
@@ -84,6 +92,12 @@ void free_work(CgWork<T>& w) {
   dfree(w.p[1]);
   dfree(w.qa);
   dfree(w.qb);
+  dfree(w.zz[1]);
+  dfree(w.s[0]);
+  dfree(w.s[1]);
+  dfree(w.qq[1][0]);
+  dfree(w.qq[1][1]);
+  w.zz[0] = w.qq[0][0] = w.qq[0][1] = nullptr;
   dfree(w.partials);
   dfree(w.sc);
 }
@@ -95,10 +109,12 @@ double* dinv_of<double>(hdg_ctx* c) { return c->d_tmp[3]; }
 template <>
 float* dinv_of<float>(hdg_ctx* c) { return c->d_dinv32; }
 
-// Capture `iters` CG iterations (fused apply + update) into a graph.
+// Capture `iters` CG iterations into a graph: variant 0 one launch per
+// iteration (state slot parity alternating, iters even), variant 1 the fused
+// apply + update pair.
 template <typename T>
-hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters) {
-  if (w.graph && w.graph_iters == iters) return HDG_OK;
+hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters, int variant) {
+  if (w.graph && w.graph_iters == iters && w.graph_variant == variant) return HDG_OK;
   if (w.graph) {
     (void)hipGraphExecDestroy(w.graph);
     w.graph = nullptr;
@@ -107,8 +123,12 @@ hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters) {
   HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
   hipError_t err = hipSuccess;
   for (int it = 0; it < iters && err == hipSuccess; ++it) {
-    err = launch_cg_apply<T>(c, w, c->cap_stream);
-    if (err == hipSuccess) err = launch_cg_update<T>(c, w, c->cap_stream);
+    if (variant == 0) {
+      err = launch_cgcg_iter<T>(c, w, it & 1, c->cap_stream);
+    } else {
+      err = launch_cg_apply<T>(c, w, c->cap_stream);
+      if (err == hipSuccess) err = launch_cg_update<T>(c, w, c->cap_stream);
+    }
   }
   hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (err != hipSuccess) {
@@ -120,16 +140,19 @@ hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters) {
   (void)hipGraphDestroy(g);
   HIP_TRY(e3);
   w.graph_iters = iters;
+  w.graph_variant = variant;
   return HDG_OK;
 }
 
 // Preconditioned CG on K^_ff w.x = b (eigen basis, precision T).  The
 // iterations run as captured graphs of `check_every` iterations; the host
 // keeps one graph in flight ahead of the convergence check, so a converged
-// solve costs at most one extra graph of no-op kernels.
+// solve costs at most one extra graph of no-op kernels.  variant 0: one
+// kernel per iteration (Chronopoulos-Gear recurrences); 1: textbook PCG
+// with an element kernel and an update kernel per iteration.
 template <typename T>
 hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
-                  int check_every, int* iters_out, int* done_out) {
+                  int check_every, int variant, int* iters_out, int* done_out) {
   *iters_out = 0;
   *done_out = 1;
   if (w.n == 0) return HDG_OK;
@@ -141,9 +164,14 @@ hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
   hs[2].A.maxit = std::max(1, maxit);
   hs[2].A.rho = 1.0;
   HIP_TRY(hipMemcpyAsync(w.sc, &hs[2], sizeof(CgScalars), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(launch_cg_init<T>(c, w, b, c->stream));
   check_every = std::max(1, check_every);
-  ST_TRY(build_graph<T>(c, w, check_every));
+  if (variant == 0) {
+    HIP_TRY(launch_cgcg_init<T>(c, w, b, c->stream));
+    check_every += check_every & 1;           // launches alternate the state slot
+  } else {
+    HIP_TRY(launch_cg_init<T>(c, w, b, c->stream));
+  }
+  ST_TRY(build_graph<T>(c, w, check_every, variant));
   hipEvent_t ev[2] = {nullptr, nullptr};
   for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   struct EvGuard {
@@ -153,8 +181,8 @@ hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
         if (e[i]) (void)hipEventDestroy(e[i]);
     }
   } guard{ev};
-  // the apply that detects convergence also applies the last x update, so
-  // one more graph may be needed after the cap; +2 chunks of slack
+  // the launch that detects the stop comes after the last iteration's
+  // launch(es); +2 chunks of slack
   const int max_chunks = (std::max(1, maxit) + check_every - 1) / check_every + 2;
   bool seen_done = false;
   for (int k = 0; k < max_chunks; ++k) {
@@ -180,8 +208,15 @@ hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
   return HDG_OK;
 }
 
+// CG form of a solve: the option if given, else the context's (autotuned)
+// choice.
+int cg_variant_of(const hdg_ctx* c, const hdg_solve_opts* o) {
+  return o->variant >= 0 ? o->variant : c->cg_variant;
+}
+
 hdg_status validate_opts(const hdg_solve_opts* o) {
   if (!(o->rtol > 0.0) || o->maxit < 1 || (o->precond != 0 && o->precond != 1) ||
+      (o->variant < -1 || o->variant > 1) ||
       (o->mixed != 0 && o->mixed != 1) || o->check_every < 1 ||
       (o->mixed && (!(o->inner_rtol > 0.0) || o->inner_rtol >= 1.0 || o->max_outer < 1)))
     return fail(HDG_EINVAL, "invalid solver options");
@@ -226,7 +261,8 @@ hdg_status solve_eigen(hdg_ctx* c, const double* b, double* x_out, const hdg_sol
     inf.rel_res = 0.0;
   } else if (!o->mixed) {
     int it = 0, done = 0;
-    ST_TRY(run_cg<double>(c, c->w64, b, o->rtol, o->maxit, o->check_every, &it, &done));
+    ST_TRY(run_cg<double>(c, c->w64, b, o->rtol, o->maxit, o->check_every, cg_variant_of(c, o),
+                          &it, &done));
     inf.iters = it;
     HIP_TRY(hipMemcpyAsync(x_out, c->w64.x, sizeof(double) * c->n_free,
                            hipMemcpyDeviceToDevice, c->stream));
@@ -246,7 +282,8 @@ hdg_status solve_eigen(hdg_ctx* c, const double* b, double* x_out, const hdg_sol
       const double rn = std::sqrt(rr);
       HIP_TRY(launch_cast_scale_64_32(c->d_tmp[2], b32, 1.0 / rn, c->n_free, c->stream));
       int it = 0, done = 0;
-      ST_TRY(run_cg<float>(c, c->w32, b32, o->inner_rtol, o->maxit, o->check_every, &it, &done));
+      ST_TRY(run_cg<float>(c, c->w32, b32, o->inner_rtol, o->maxit, o->check_every,
+                         cg_variant_of(c, o), &it, &done));
       inner_total += it;
       HIP_TRY(launch_axpy_32_64(c->w32.x, xacc, rn, c->n_free, c->stream));
       ST_TRY(residual64(c, b, xacc, &rr));
@@ -323,6 +360,7 @@ void hdg_default_opts(hdg_solve_opts* o) {
   o->inner_rtol = 1e-4;
   o->max_outer = 12;
   o->check_every = 25;
+  o->variant = -1;
 }
 
 const char* hdg_last_error(void) { return g_err.c_str(); }
@@ -383,6 +421,9 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
   c->np = p + 1;
   c->tau = tau_hat;
   c->n_elem = ne;
+  // CG form before any autotuning: one kernel per iteration for meshes small
+  // enough that launch latency dominates, else the two-kernel form
+  c->cg_variant = ne * (int64_t)(p + 1) * (p + 1) <= ((int64_t)1 << 18) ? 0 : 1;
   const int n1 = n_elem[0], n2 = n_elem[1], n3 = n_elem[2];
   const int64_t nf0 = (int64_t)(n1 - 1) * n2 * n3, nf1 = (int64_t)n1 * (n2 - 1) * n3,
                 nf2 = (int64_t)n1 * n2 * (n3 - 1);
@@ -854,30 +895,38 @@ hdg_status hdg_autotune(hdg_ctx* c, int reps, int* chosen, double* times_ms) {
     if (chosen) *chosen = c->tile_variant;
     return HDG_OK;
   }
-  // time the fused FP64 CG iteration (apply + update) of every tile variant
-  // on this context's mesh, keep the fastest
+  // time one FP64 CG iteration in both forms (one kernel: id 9; element +
+  // update kernel: id 2) for every tile variant on this context's mesh and
+  // keep the fastest pair
   double best = 1e300;
-  int best_v = 0;
+  int best_v = 0, best_cg = 0;
   double* x = c->d_tmp[1];
   HIP_TRY(launch_fill64(x, 1.0, c->n_free, c->stream));
   for (int v = 0; v < kNumTileVariants; ++v) {
     ST_TRY(hdg_set_tile(c, v));
-    double ms = 0.0;
-    ST_TRY(hdg_time_kernel(c, 2, x, nullptr, reps, &ms));
-    if (times_ms) times_ms[v] = ms;
-    if (ms < best) {
-      best = ms;
-      best_v = v;
+    double tv = 1e300;
+    for (int cg = 0; cg < 2; ++cg) {
+      double ms = 0.0;
+      ST_TRY(hdg_time_kernel(c, cg == 0 ? 9 : 2, x, nullptr, reps, &ms));
+      tv = std::min(tv, ms);
+      if (ms < best) {
+        best = ms;
+        best_v = v;
+        best_cg = cg;
+      }
     }
+    if (times_ms) times_ms[v] = tv;
   }
   ST_TRY(hdg_set_tile(c, best_v));
+  c->cg_variant = best_cg;
   if (chosen) *chosen = best_v;
   return HDG_OK;
 }
 
 hdg_status hdg_tile_shape(const hdg_ctx* c, int* variant, int* elems_per_unit,
-                          int* threads_per_unit) {
+                          int* threads_per_unit, int* cg_variant) {
   if (!c) return fail(HDG_EINVAL, "ctx is NULL");
+  if (cg_variant) *cg_variant = c->cg_variant;
   if (variant) *variant = c->tile_variant;
   if (elems_per_unit) *elems_per_unit = tile_epb(c->np, c->tile_variant);
   if (threads_per_unit) *threads_per_unit = tile_threads(c->np, c->tile_variant);
@@ -894,13 +943,14 @@ hdg_status hdg_diagonal(hdg_ctx* c, double* diag_free) {
 
 hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int reps, double* ms) {
   if (!c || !x || !ms || reps < 1) return fail(HDG_EINVAL, "invalid argument");
-  if (which < 0 || which > 8) return fail(HDG_EINVAL, "unknown kernel id %d", which);
+  if (which < 0 || which > 10) return fail(HDG_EINVAL, "unknown kernel id %d", which);
   if (which == 8 && (!y || y == x)) return fail(HDG_EINVAL, "copy needs a distinct y");
   if (c->n_free == 0) {
     *ms = 0.0;
     return HDG_OK;
   }
-  const bool f32 = (which == 1 || which == 3 || which == 6 || which == 7);
+  const bool f32 = (which == 1 || which == 3 || which == 6 || which == 7 || which == 10);
+  const bool one_kernel = (which == 9 || which == 10);
   if (f32) ST_TRY(alloc_work(c, c->w32));
   // CG-state kernels need an initialised run that never finishes
   if (which >= 2) {
@@ -913,16 +963,29 @@ hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int re
     if (f32) {
       c->w32.dinv = c->d_dinv32;
       HIP_TRY(hipMemcpyAsync(c->w32.sc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(launch_cg_init<float>(c, c->w32, static_cast<const float*>(x), c->stream));
+      if (one_kernel)
+        HIP_TRY(launch_cgcg_init<float>(c, c->w32, static_cast<const float*>(x), c->stream));
+      else
+        HIP_TRY(launch_cg_init<float>(c, c->w32, static_cast<const float*>(x), c->stream));
     } else {
       c->w64.dinv = c->d_tmp[3];
       HIP_TRY(hipMemcpyAsync(c->w64.sc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(launch_cg_init<double>(c, c->w64, static_cast<const double*>(x), c->stream));
+      if (one_kernel)
+        HIP_TRY(launch_cgcg_init<double>(c, c->w64, static_cast<const double*>(x), c->stream));
+      else
+        HIP_TRY(launch_cg_init<double>(c, c->w64, static_cast<const double*>(x), c->stream));
     }
-    // prime the state with one apply so that an update has a p.q to consume
-    if (f32) HIP_TRY(launch_cg_apply<float>(c, c->w32, c->stream));
-    else HIP_TRY(launch_cg_apply<double>(c, c->w64, c->stream));
+    // prime the state: the first launch (one-kernel CG), or one apply so that
+    // an update has a p.q to consume
+    if (one_kernel) {
+      if (f32) HIP_TRY(launch_cgcg_iter<float>(c, c->w32, 0, c->stream));
+      else HIP_TRY(launch_cgcg_iter<double>(c, c->w64, 0, c->stream));
+    } else {
+      if (f32) HIP_TRY(launch_cg_apply<float>(c, c->w32, c->stream));
+      else HIP_TRY(launch_cg_apply<double>(c, c->w64, c->stream));
+    }
   }
+  int parity = 1;   // one-kernel CG: state slot of the next launch
   auto launch = [&]() -> hipError_t {
     switch (which) {
       case 0: return launch_elem_apply<double>(c, static_cast<const double*>(x), nullptr,
@@ -941,6 +1004,16 @@ hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int re
       case 5: return launch_cg_update<double>(c, c->w64, c->stream);
       case 6: return launch_cg_apply<float>(c, c->w32, c->stream);
       case 7: return launch_cg_update<float>(c, c->w32, c->stream);
+      case 9: {
+        const int rd = parity;
+        parity ^= 1;
+        return launch_cgcg_iter<double>(c, c->w64, rd, c->stream);
+      }
+      case 10: {
+        const int rd = parity;
+        parity ^= 1;
+        return launch_cgcg_iter<float>(c, c->w32, rd, c->stream);
+      }
       default: return launch_copy64(static_cast<const double*>(x), static_cast<double*>(y),
                                     c->n_free, c->stream);
     }

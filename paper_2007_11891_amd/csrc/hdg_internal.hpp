@@ -80,6 +80,10 @@ struct CgWork {
   T* p[2] = {nullptr, nullptr};
   T* qa = nullptr;       // contribution of the element below each face
   T* qb = nullptr;       // contribution of the element above each face
+  // one-kernel CG: second z, s = D^-1 A p (ping-pong), second qa/qb set
+  T* zz[2] = {nullptr, nullptr};   // zz[0] aliases z
+  T* s[2] = {nullptr, nullptr};
+  T* qq[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // qq[i] = {qa_i, qb_i}; qq[0] aliases qa, qb
   T* dinv = nullptr;
   double* partials = nullptr;  // pq[2][pmax] | rz[2][pmax] | rr[2][pmax]
   int pmax = 0;                // partial slots per buffer
@@ -89,6 +93,7 @@ struct CgWork {
   int update_blocks = 0;
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
+  int graph_variant = -1;
 };
 
 struct KernelConfig {
@@ -101,6 +106,7 @@ struct hdg_ctx {
   int n[3] = {0, 0, 0};
   int p = 0, np = 0;
   int tile_variant = 0;           // elements per work unit: epb_max >> variant
+  int cg_variant = 1;             // CG form when the options leave it open
   double tau = 0.0;
   int64_t n_elem = 0, n_free = 0, n_all = 0, n_vol = 0;
   int64_t n_free_faces = 0, n_faces = 0;
@@ -146,6 +152,11 @@ template <typename T>
 hipError_t launch_cg_apply(const hdg_ctx* c, CgWork<T>& w, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_update(const hdg_ctx* c, CgWork<T>& w, hipStream_t s);
+// one-kernel CG iteration (reads state slot rd, writes rd ^ 1) and its init
+template <typename T>
+hipError_t launch_cgcg_iter(const hdg_ctx* c, CgWork<T>& w, int rd, hipStream_t s);
+template <typename T>
+hipError_t launch_cgcg_init(const hdg_ctx* c, CgWork<T>& w, const T* b, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_init(const hdg_ctx* c, CgWork<T>& w, const T* b, hipStream_t s);
 

@@ -138,6 +138,32 @@ cg_init_kernel(int64_t n, const T* __restrict__ b, T* __restrict__ z, T* __restr
   }
 }
 
+// One-kernel CG: z_0 = D^-1 b (r_0 = b), x = 0, p_{-1} = s_{-1} = 0.  The
+// first iteration launch applies the operator to z_0 and reduces r.z, r.r.
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+cgcg_init_kernel(int64_t n, const T* __restrict__ b, T* __restrict__ z0, T* __restrict__ x,
+                 T* __restrict__ p1, T* __restrict__ s1, const T* __restrict__ dinv) {
+  for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * kVecThreads) {
+    z0[g] = dinv[g] * b[g];
+    x[g] = 0;
+    p1[g] = 0;
+    s1[g] = 0;
+  }
+}
+
+template <typename T>
+hipError_t launch_cgcg_init(const hdg_ctx*, CgWork<T>& w, const T* b, hipStream_t s) {
+  hipLaunchKernelGGL((cgcg_init_kernel<T>), dim3(w.update_blocks), dim3(kVecThreads), 0, s, w.n, b,
+                     w.zz[0], w.x, w.p[1], w.s[1], w.dinv);
+  return hipGetLastError();
+}
+template hipError_t launch_cgcg_init<double>(const hdg_ctx*, CgWork<double>&, const double*,
+                                             hipStream_t);
+template hipError_t launch_cgcg_init<float>(const hdg_ctx*, CgWork<float>&, const float*,
+                                            hipStream_t);
+
 template <typename T>
 hipError_t launch_cg_update(const hdg_ctx* c, CgWork<T>& w, hipStream_t s) {
   hipLaunchKernelGGL((cg_update_kernel<T>), dim3(w.update_blocks), dim3(kVecThreads), 0, s, w.n,

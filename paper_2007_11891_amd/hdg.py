@@ -44,7 +44,8 @@ class HdgError(RuntimeError):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("maxit", ctypes.c_int), ("precond", ctypes.c_int),
                 ("mixed", ctypes.c_int), ("inner_rtol", ctypes.c_double),
-                ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("variant", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -102,7 +103,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hdg_time_kernel": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int, dp]),
         "hdg_set_tile": (ctypes.c_int, [vp, ctypes.c_int]),
         "hdg_autotune": (ctypes.c_int, [vp, ctypes.c_int, ip, dp]),
-        "hdg_tile_shape": (ctypes.c_int, [vp, ip, ip, ip]),
+        "hdg_tile_shape": (ctypes.c_int, [vp, ip, ip, ip, ip]),
         "hdg_batch_create": (ctypes.c_int, [ctypes.c_int, ip, ip, dp, ctypes.c_double, vp,
                                             ctypes.POINTER(vp)]),
         "hdg_batch_destroy": (ctypes.c_int, [vp]),
@@ -357,9 +358,11 @@ class HdgContext:
         return ch.value, list(t)
 
     def tile_shape(self) -> dict:
-        v, e, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(self._lib.hdg_tile_shape(self._h, ctypes.byref(v), ctypes.byref(e), ctypes.byref(t)))
-        return {"variant": v.value, "elems_per_unit": e.value, "threads_per_unit": t.value}
+        v, e, t, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.hdg_tile_shape(self._h, ctypes.byref(v), ctypes.byref(e), ctypes.byref(t),
+                                        ctypes.byref(g)))
+        return {"variant": v.value, "elems_per_unit": e.value, "threads_per_unit": t.value,
+                "cg_variant": g.value}
 
     def time_kernel(self, which: int, x, reps: int = 100, y=None) -> float:
         """Mean launch time (ms) of an internal kernel, HIP events on the context stream."""
