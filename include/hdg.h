@@ -117,7 +117,7 @@ typedef struct {
 } hdg_solve_info;
 
 /* Fill *opts with defaults: rtol 1e-10, maxit 20000, Jacobi, FP64,
- * inner_rtol 1e-4, max_outer 12, check_every 25, variant -1. */
+ * inner_rtol 1e-2, max_outer 12, check_every 25, variant -1. */
 void hdg_default_opts(hdg_solve_opts* opts);
 
 /* Create a context for one mesh (paper section "LDG operator structure in

@@ -357,7 +357,7 @@ void hdg_default_opts(hdg_solve_opts* o) {
   o->maxit = 20000;
   o->precond = 1;
   o->mixed = 0;
-  o->inner_rtol = 1e-4;
+  o->inner_rtol = 1e-2;
   o->max_outer = 12;
   o->check_every = 25;
   o->variant = -1;
