@@ -415,7 +415,7 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
     return cleanup(fail(HDG_EHIP, "occupancy query of the persistent kernel failed"));
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
     return cleanup(fail(HDG_EHIP, "device attribute query failed"));
-  b->nblocks = std::min(per_cu, 2) * n_cu;
+  b->nblocks = std::min(per_cu, 4) * n_cu;
   // each block range splits into at most one more segment than problems it touches
   b->max_segs = count + b->nblocks + 1;
   const int ms = b->max_segs;

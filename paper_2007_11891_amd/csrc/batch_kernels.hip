@@ -137,8 +137,13 @@ __device__ inline double run_units(const UnitIO<double>& io, const double* tabs,
   cdouble* ct = (cdouble*)tp;
   const ConstTab tab{ct + o, ct + o + NP, ct + o + 2 * NP, ct[o + 3 * NP]};
   auto& sm = *reinterpret_cast<UnitSmem<double, NP, EPB>*>(smem);
+  // the thread index through an empty asm: otherwise the compiler hoists every
+  // degree's per-lane index arithmetic (loop-invariant) to the kernel entry
+  // and keeps all of it live, which more than doubles the vector registers
+  int tid = (int)threadIdx.x;
+  asm volatile("" : "+v"(tid));
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int u = u0; u < u1; ++u) apply_unit<double, NP, EPB, 1>(io, tab, sm, u, acc);
+  for (int u = u0; u < u1; ++u) apply_unit<double, NP, EPB, 1>(io, tab, sm, u, acc, tid);
   return acc[0];
 }
 
@@ -156,7 +161,7 @@ __device__ inline double dispatch_units(int np, int variant, const UnitIO<double
   }
 }
 
-__global__ void __launch_bounds__(kBT, 2) batch_cg_kernel(BatchArgs a) {
+__global__ void __launch_bounds__(kBT, 4) batch_cg_kernel(BatchArgs a) {
   __shared__ double smem[kBatchLdsWords];
   __shared__ double s_red[kBT / 64];
   const int bid = blockIdx.x;

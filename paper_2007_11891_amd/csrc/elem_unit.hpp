@@ -102,22 +102,22 @@ struct UnitSmem {
 };
 
 // Processes elements [unit EPB, unit EPB + EPB).  Every thread of the block
-// calls it; threads beyond EPB * tpe idle.  Adds to acc the thread's share of
+// calls it (tid = its index in the block); threads beyond EPB * tpe idle.  Adds to acc the thread's share of
 // the element-local quadratic forms v_e^T K_e v_e of the input v (MODES 1, 2)
 // and, in MODE 2, of r.z and r.r over the faces the unit owns (acc[1], acc[2]).
 template <typename T, int NP, int EPB, int MODE, typename Tab>
 __device__ inline void apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
-                                  int unit, double* acc) {
+                                  int unit, double* acc, int tid = (int)threadIdx.x) {
   constexpr int NF = NP * NP;
   constexpr int TPE = tpe<NP>();
   constexpr int P = upitch<NP>();
   int slot, col;
   if constexpr (is_group<NP>()) {
-    slot = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / TPE));   // wave-uniform
-    col = (int)(threadIdx.x % TPE);
+    slot = __builtin_amdgcn_readfirstlane(tid / TPE);   // wave-uniform
+    col = tid % TPE;
   } else {
-    slot = (int)(threadIdx.x / NF);
-    col = (int)(threadIdx.x % NF);
+    slot = tid / NF;
+    col = tid % NF;
   }
   const bool colok = col < NF;
   const int q1 = col % NP, q2 = col / NP;
