@@ -30,6 +30,7 @@ namespace hdg {
 
 constexpr int kBT = 256;                 // threads per block
 constexpr unsigned kSpinLimit = 1u << 22;
+constexpr int kMaxBlocksPerThread = 8;   // grid of at most kBT * 8 blocks
 
 template <int NP>
 __host__ __device__ constexpr int unit_lds_words() { return epb_max<NP>() * lds_elem_words<NP>(); }
@@ -57,16 +58,27 @@ __device__ inline bool grid_sync(const BatchArgs& a, unsigned epoch) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (blockIdx.x == 0) {
+    // each thread watches blocks tid + 1 + j kBT (j < kMaxBlocksPerThread),
+    // all its loads in flight together
     bool ok = true;
-    for (unsigned i = threadIdx.x + 1; i < gridDim.x && ok; i += kBT) {
-      unsigned spins = 0;
-      while (__hip_atomic_load(arrive + (size_t)i * kFlagStride, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) {
-          ok = false;
-          break;
-        }
+    unsigned spins = 0;
+    for (;;) {
+      unsigned v[kMaxBlocksPerThread];
+#pragma unroll
+      for (int j = 0; j < kMaxBlocksPerThread; ++j) {
+        const unsigned i = threadIdx.x + 1 + j * kBT;
+        v[j] = i < gridDim.x ? __hip_atomic_load(arrive + (size_t)i * kFlagStride, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
+                             : epoch;
+      }
+      bool all = true;
+#pragma unroll
+      for (int j = 0; j < kMaxBlocksPerThread; ++j) all = all && v[j] >= epoch;
+      if (all) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        ok = false;
+        break;
       }
     }
     if (!ok) __hip_atomic_store(&gb->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -143,7 +155,7 @@ __device__ inline double run_units(const UnitIO<double>& io, const double* tabs,
   int tid = (int)threadIdx.x;
   asm volatile("" : "+v"(tid));
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int u = u0; u < u1; ++u) apply_unit<double, NP, EPB, 1>(io, tab, sm, u, acc, tid);
+  run_units_pipelined<double, NP, EPB, 1>(io, tab, sm, u0, u1, acc, tid);
   return acc[0];
 }
 
@@ -161,7 +173,7 @@ __device__ inline double dispatch_units(int np, int variant, const UnitIO<double
   }
 }
 
-__global__ void __launch_bounds__(kBT, 4) batch_cg_kernel(BatchArgs a) {
+__global__ void __launch_bounds__(kBT, 3) batch_cg_kernel(BatchArgs a) {
   __shared__ double smem[kBatchLdsWords];
   __shared__ double s_red[kBT / 64];
   const int bid = blockIdx.x;
@@ -354,6 +366,7 @@ hipError_t launch_batch_reset(BatchState* A, BatchState* B, GridBar* bar, unsign
 }
 
 hipError_t launch_batch_cg(const BatchArgs& args, int nblocks, hipStream_t s) {
+  if (nblocks < 1 || nblocks > kBT * kMaxBlocksPerThread) return hipErrorInvalidValue;
   BatchArgs a = args;
   void* params[] = {&a};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(batch_cg_kernel), dim3(nblocks),

@@ -158,8 +158,10 @@ __device__ inline void cgcg_prologue(const ApplyIO<T>& io, double* s_red, bool* 
   *beta = (T)b;
 }
 
-// MODE 0: plain apply, 1: fused CG apply (two-kernel CG), 2: one-kernel CG iteration
-template <typename T, int NP, int EPB, int MODE>
+// MODE 0: plain apply, 1: fused CG apply (two-kernel CG), 2: one-kernel CG iteration.
+// PIPE: the block's units run software-pipelined (chosen when a block has
+// more than one unit; it costs registers).
+template <typename T, int NP, int EPB, int MODE, int PIPE>
 __global__ void __launch_bounds__((unit_threads<NP, EPB>()))
 elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int units_per_block) {
   constexpr int NT = unit_threads<NP, EPB>();
@@ -210,8 +212,13 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
   }
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int un = 0; un < units_per_block; ++un)
-    apply_unit<T, NP, EPB, MODE>(u, tab, sm, bid * units_per_block + un, acc);
+  if constexpr (MODE == 2 || PIPE == 0) {
+    for (int un = 0; un < units_per_block; ++un)
+      apply_unit<T, NP, EPB, MODE>(u, tab, sm, bid * units_per_block + un, acc);
+  } else {
+    run_units_pipelined<T, NP, EPB, MODE>(u, tab, sm, bid * units_per_block,
+                                          (bid + 1) * units_per_block, acc);
+  }
   if constexpr (MODE == 1) {
     // one partial per block, summed by every block of the update kernel
     const double bs = block_sum<NT>(acc[0], s_red);
@@ -261,8 +268,12 @@ static hipError_t launch_variant(const hdg_ctx* c, const ElemTab<T>& tab, const 
   int nb, upb;
   grid_for(c->n_elem, EPB, &nb, &upb);
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL((elem_apply_kernel<T, NP, EPB, MODE>), dim3(nb),
-                     dim3(unit_threads<NP, EPB>()), 0, s, c->mesh, tab, io, upb);
+  if (MODE != 2 && upb > 1)
+    hipLaunchKernelGGL((elem_apply_kernel<T, NP, EPB, MODE, (MODE != 2 ? 1 : 0)>), dim3(nb),
+                       dim3(unit_threads<NP, EPB>()), 0, s, c->mesh, tab, io, upb);
+  else
+    hipLaunchKernelGGL((elem_apply_kernel<T, NP, EPB, MODE, 0>), dim3(nb),
+                       dim3(unit_threads<NP, EPB>()), 0, s, c->mesh, tab, io, upb);
   return hipGetLastError();
 }
 

@@ -101,87 +101,99 @@ struct UnitSmem {
   T u[EPB][upitch<NP>() * NP * NP + 1];
 };
 
-// Processes elements [unit EPB, unit EPB + EPB).  Every thread of the block
-// calls it (tid = its index in the block); threads beyond EPB * tpe idle.  Adds to acc the thread's share of
-// the element-local quadratic forms v_e^T K_e v_e of the input v (MODES 1, 2)
-// and, in MODE 2, of r.z and r.r over the faces the unit owns (acc[1], acc[2]).
-template <typename T, int NP, int EPB, int MODE, typename Tab>
-__device__ inline void apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
-                                  int unit, double* acc, int tid = (int)threadIdx.x) {
+// Lane geometry of a work unit: element slot within the unit and face-node
+// column (q1, q2) of the thread with block index tid.
+struct UnitLane {
+  int slot, col, q1, q2, sl;
+  bool colok;
+};
+template <int NP, int EPB>
+__device__ inline UnitLane unit_lane(int tid) {
   constexpr int NF = NP * NP;
   constexpr int TPE = tpe<NP>();
-  constexpr int P = upitch<NP>();
-  int slot, col;
+  UnitLane L;
   if constexpr (is_group<NP>()) {
-    slot = __builtin_amdgcn_readfirstlane(tid / TPE);   // wave-uniform
-    col = tid % TPE;
+    L.slot = __builtin_amdgcn_readfirstlane(tid / TPE);   // wave-uniform
+    L.col = tid % TPE;
   } else {
-    slot = tid / NF;
-    col = tid % NF;
+    L.slot = tid / NF;
+    L.col = tid % NF;
   }
-  const bool colok = col < NF;
-  const int q1 = col % NP, q2 = col / NP;
-  const int e = unit * EPB + slot;
-  const bool active = slot < EPB && e < io.n_elem;
-  const int sl = slot < EPB ? slot : 0;
-  double dot = 0.0;
+  L.colok = L.col < NF;
+  L.q1 = L.col % NP;
+  L.q2 = L.col / NP;
+  L.sl = L.slot < EPB ? L.slot : 0;
+  return L;
+}
 
-  T d[4] = {0, 0, 0, 0};
+// Registers of one unit between its loads and its arithmetic: the element
+// record and the raw face values (MODE 0: the input x; MODE 1: z and p_old).
+template <typename T>
+struct UnitRegs {
+  bool active;
   int fid[6];
-  T xf[6];
-  if (active) {
+  T d[4];
+  T a[6];
+  T b[6];
+};
+
+// Element record of the lane's element in unit `unit`.
+template <typename T, int NP, int EPB>
+__device__ inline void unit_info(const UnitIO<T>& io, const UnitLane& L, int unit, UnitRegs<T>& R) {
+  const int e = unit * EPB + L.slot;
+  R.active = L.slot < EPB && e < io.n_elem;
+  if (R.active) {
     const ElemInfo* ei = io.info + e;
-    d[0] = (T)(ei->d[0] * io.lam[e]);
-    d[1] = (T)ei->d[1];
-    d[2] = (T)ei->d[2];
-    d[3] = (T)ei->d[3];
+    R.d[0] = (T)(ei->d[0] * io.lam[e]);
+    R.d[1] = (T)ei->d[1];
+    R.d[2] = (T)ei->d[2];
+    R.d[3] = (T)ei->d[3];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      fid[f] = ei->fid[f];
-      T v = 0;
-      if (colok) {
-        if (fid[f] < io.nff) {
-          const int64_t g = (int64_t)fid[f] * NF + col;
-          if constexpr (MODE == 0) {
-            v = io.x_free[g];
-          } else if constexpr (MODE == 1) {
-            v = io.z[g] + io.beta * io.p_in[g];
-            if (f & 1) io.p_out[g] = v;             // the element below owns the face
-          } else {
-            const T d = io.dinv[g];
-            if (io.first) {
-              v = io.z_old[g];
-            } else {
-              const T zo = io.z_old[g];
-              const T sn = d * (io.w_a[g] + io.w_b[g]) + io.beta * io.s_old[g];
-              v = zo - io.alpha * sn;
-              if (f & 1) {                          // the element below owns the face
-                const T pn = zo + io.beta * io.p_in[g];
-                io.s_new[g] = sn;
-                io.p_out[g] = pn;
-                io.z_new[g] = v;
-                io.x[g] += io.alpha * pn;
-              }
-            }
-            if (f & 1) {
-              const double r = (double)div_fast(v, d);
-              acc[1] += (double)v * r;
-              acc[2] += r * r;
-            }
-          }
-        } else if (MODE == 0 && io.x_bdry != nullptr) {
-          v = io.x_bdry[(int64_t)(fid[f] - io.nff) * NF + col];
+    for (int f = 0; f < 6; ++f) R.fid[f] = ei->fid[f];
+  }
+}
+
+// Issues the face loads of a unit (MODES 0 and 1); no arithmetic on them, so
+// that they can stay in flight while another unit computes.
+template <typename T, int NP, int MODE>
+__device__ inline void unit_data(const UnitIO<T>& io, const UnitLane& L, UnitRegs<T>& R) {
+  constexpr int NF = NP * NP;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    R.a[f] = 0;
+    R.b[f] = 0;
+    if (R.active && L.colok) {
+      if (R.fid[f] < io.nff) {
+        const int64_t g = (int64_t)R.fid[f] * NF + L.col;
+        if constexpr (MODE == 0) {
+          R.a[f] = io.x_free[g];
+        } else {
+          R.a[f] = io.z[g];
+          R.b[f] = io.p_in[g];
         }
-        if (f < 4) sm.face[sl][f][col] = v;
+      } else if (MODE == 0 && io.x_bdry != nullptr) {
+        R.a[f] = io.x_bdry[(int64_t)(R.fid[f] - io.nff) * NF + L.col];
       }
-      xf[f] = v;
     }
   }
+}
+
+// Element arithmetic of one unit given its input face values xf (already in
+// registers, faces 0..3 also staged in LDS by the caller before the first
+// barrier): expansion into the element eigenspace, reductions back to the
+// faces, stores of qa / qb, and the quadratic form xf.out into *dot.
+template <typename T, int NP, int EPB, int MODE, typename Tab>
+__device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
+                                 const UnitLane& L, bool active, const int* fid, const T* d,
+                                 const T* xf, double* dot) {
+  constexpr int NF = NP * NP;
+  constexpr int P = upitch<NP>();
+  const int sl = L.sl, q1 = L.q1, q2 = L.q2, col = L.col;
   __syncthreads();
 
   // expansion into the element eigenspace, division, axis-2 reduction
   T r2lo = 0, r2hi = 0;
-  if (active && colok) {
+  if (active && L.colok) {
     const T* f0lo = sm.face[sl][0];
     const T* f0hi = sm.face[sl][1];
     const T* f1lo = sm.face[sl][2];
@@ -207,7 +219,7 @@ __device__ inline void apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSmem<
   __syncthreads();
 
   // reductions back to the faces and the face-diagonal term
-  if (active && colok) {
+  if (active && L.colok) {
     T out[6];
     {
       // axis 0: face node (q2,q3) = col
@@ -241,11 +253,111 @@ __device__ inline void apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSmem<
       const int64_t g = (int64_t)fid[f] * NF + col;
       if (f & 1) io.qa[g] = out[f];
       else io.qb[g] = out[f];
-      if constexpr (MODE != 0) dot += (double)(xf[f] * out[f]);
+      if constexpr (MODE != 0) *dot += (double)(xf[f] * out[f]);
     }
   }
   __syncthreads();                          // LDS is reused by the next unit
+}
+
+// MODES 0 and 1 from loaded registers: forms the input (MODE 1:
+// p = z + beta p_old, written by the element below each face), stages it and
+// runs the element arithmetic.
+template <typename T, int NP, int EPB, int MODE, typename Tab>
+__device__ inline void unit_compute(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
+                                    const UnitLane& L, const UnitRegs<T>& R, double* acc) {
+  constexpr int NF = NP * NP;
+  T xf[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    T v = R.a[f];
+    if constexpr (MODE == 1) {
+      v = R.a[f] + io.beta * R.b[f];
+      if ((f & 1) && R.active && L.colok && R.fid[f] < io.nff)
+        io.p_out[(int64_t)R.fid[f] * NF + L.col] = v;   // the element below owns the face
+    }
+    xf[f] = v;
+    if (f < 4 && R.active && L.colok) sm.face[L.sl][f][L.col] = v;
+  }
+  double dot = 0.0;
+  unit_core<T, NP, EPB, MODE>(io, tab, sm, L, R.active, R.fid, R.d, xf, &dot);
   acc[0] += dot;
+}
+
+// Processes elements [unit EPB, unit EPB + EPB).  Every thread of the block
+// calls it (tid = its index in the block); threads beyond EPB * tpe idle.
+// Adds to acc the thread's share of the element-local quadratic forms
+// v_e^T K_e v_e of the input v (MODES 1, 2) and, in MODE 2, of r.z and r.r
+// over the faces the unit owns (acc[1], acc[2]).
+template <typename T, int NP, int EPB, int MODE, typename Tab>
+__device__ inline void apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
+                                  int unit, double* acc, int tid = (int)threadIdx.x) {
+  constexpr int NF = NP * NP;
+  const UnitLane L = unit_lane<NP, EPB>(tid);
+  UnitRegs<T> R;
+  unit_info<T, NP, EPB>(io, L, unit, R);
+  if constexpr (MODE != 2) {
+    unit_data<T, NP, MODE>(io, L, R);
+    unit_compute<T, NP, EPB, MODE>(io, tab, sm, L, R, acc);
+  } else {
+    T xf[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      T v = 0;
+      if (R.active && L.colok && R.fid[f] < io.nff) {
+        const int64_t g = (int64_t)R.fid[f] * NF + L.col;
+        const T d = io.dinv[g];
+        if (io.first) {
+          v = io.z_old[g];
+        } else {
+          const T zo = io.z_old[g];
+          const T sn = d * (io.w_a[g] + io.w_b[g]) + io.beta * io.s_old[g];
+          v = zo - io.alpha * sn;
+          if (f & 1) {                          // the element below owns the face
+            const T pn = zo + io.beta * io.p_in[g];
+            io.s_new[g] = sn;
+            io.p_out[g] = pn;
+            io.z_new[g] = v;
+            io.x[g] += io.alpha * pn;
+          }
+        }
+        if (f & 1) {
+          const double r = (double)div_fast(v, d);
+          acc[1] += (double)v * r;
+          acc[2] += r * r;
+        }
+      }
+      xf[f] = v;
+      if (f < 4 && R.active && L.colok) sm.face[L.sl][f][L.col] = v;
+    }
+    double dot = 0.0;
+    unit_core<T, NP, EPB, MODE>(io, tab, sm, L, R.active, R.fid, R.d, xf, &dot);
+    acc[0] += dot;
+  }
+}
+
+// Units [u0, u1) with the loads of unit u + 1 (and the element records of
+// unit u + 2) issued before the arithmetic of unit u, so that a block always
+// has memory traffic in flight (MODES 0 and 1).
+template <typename T, int NP, int EPB, int MODE, typename Tab>
+__device__ inline void run_units_pipelined(const UnitIO<T>& io, const Tab& tab,
+                                           UnitSmem<T, NP, EPB>& sm, int u0, int u1, double* acc,
+                                           int tid = (int)threadIdx.x) {
+  static_assert(MODE != 2, "the one-kernel CG iteration is not pipelined");
+  if (u0 >= u1) return;
+  const UnitLane L = unit_lane<NP, EPB>(tid);
+  UnitRegs<T> cur, nxt;
+  unit_info<T, NP, EPB>(io, L, u0, cur);
+  unit_data<T, NP, MODE>(io, L, cur);
+  if (u0 + 1 < u1) unit_info<T, NP, EPB>(io, L, u0 + 1, nxt);
+  for (int u = u0; u < u1; ++u) {
+    const UnitRegs<T> c = cur;
+    if (u + 1 < u1) {
+      unit_data<T, NP, MODE>(io, L, nxt);
+      cur = nxt;
+      if (u + 2 < u1) unit_info<T, NP, EPB>(io, L, u + 2, nxt);
+    }
+    unit_compute<T, NP, EPB, MODE>(io, tab, sm, L, c, acc);
+  }
 }
 
 }  // namespace hdg
