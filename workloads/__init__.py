@@ -69,6 +69,53 @@ def u_paper(x, y, z, k=5.0):
             * np.sin(k * (3 * x - 2 * y + 2 * z)))
 
 
+# u_paper as a product of five factors g_m(k (a_m . x + c_m)), g_m = cos for
+# the first factor, sin for the others: (a_m, c_m, is_cos)
+_PAPER_FACTORS = (((1.0, -3.0, 2.0), 0.0, True), ((1.0, 0.0, 0.0), 1.0, False),
+                  ((0.0, -1.0, 0.0), 1.0, False), ((2.0, 1.0, 0.0), 0.0, False),
+                  ((3.0, -2.0, 2.0), 0.0, False))
+
+
+def f_paper(x, y, z, lam, k=5.0):
+    """lambda u - laplace u for u_paper, evaluated analytically.
+
+    For u = prod_m g_m(k (a_m . x + c_m)) with g'' = -g:
+      laplace u = -k^2 sum_m |a_m|^2 u
+                  + k^2 sum_{m != n} (a_m . a_n) g_m' g_n' prod_{l != m, n} g_l.
+    """
+    X = (np.asarray(x, dtype=np.float64), np.asarray(y, dtype=np.float64),
+         np.asarray(z, dtype=np.float64))
+    g, dg, a = [], [], []
+    for am, cm, is_cos in _PAPER_FACTORS:
+        t = k * (am[0] * X[0] + am[1] * X[1] + am[2] * X[2] + cm)
+        g.append(np.cos(t) if is_cos else np.sin(t))
+        dg.append(-np.sin(t) if is_cos else np.cos(t))
+        a.append(np.asarray(am))
+    m5 = len(g)
+    u = np.prod(g, axis=0)
+    lap = -k * k * sum(float(a[m] @ a[m]) for m in range(m5)) * u
+    for m in range(m5):
+        for n in range(m5):
+            if m == n:
+                continue
+            rest = np.ones_like(u)
+            for l in range(m5):
+                if l != m and l != n:
+                    rest = rest * g[l]
+            lap = lap + k * k * float(a[m] @ a[n]) * dg[m] * dg[n] * rest
+    return lam * u - lap
+
+
+def paper_case(p: int, n: int = 8, tau_e: float = 25.0, lam: float = 0.0) -> Problem:
+    """The paper's solver test: (0, 2 pi)^3, n^3 uniform elements, degree p,
+    penalty tau_e = 2 tau_hat / h (so tau_hat = tau_e h / 2), Poisson
+    (lambda = 0) by default, Dirichlet data and forcing from u_paper."""
+    h = 2.0 * math.pi / n
+    return Problem(f"paper_p{p}", (n, n, n), [np.full(n, h)] * 3, p=p, tau=tau_e * h / 2.0,
+                   lam=np.full(n ** 3, float(lam)), u_exact=u_paper,
+                   f_func=f_paper, dirichlet_zero=False)
+
+
 def poly_tensor(coeffs: np.ndarray) -> Callable:
     """Tensor polynomial sum_{abc} c[a,b,c] x^a y^b z^c (degree <= p per axis).
 
