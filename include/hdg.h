@@ -97,8 +97,12 @@ typedef struct {
   double rtol;        /* stop when ||r||_2 <= rtol ||F^||_2 (eigen basis)   */
   int maxit;          /* iteration cap (FP64 CG, or per inner FP32 solve)   */
   int precond;        /* 0: none, 1: Jacobi                                  */
-  int mixed;          /* 0: FP64 CG; 1: FP32 inner CG + FP64 defect correction */
-  double inner_rtol;  /* mixed: relative reduction asked of each inner solve */
+  int mixed;          /* 0: FP64 CG; 1: FP32 CG with FP64 residual replacement
+                         (reliable updates: the FP32 CG keeps its search
+                         direction across replacements)                      */
+  double inner_rtol;  /* mixed: residual reduction of each FP32 segment between
+                         two FP64 residual replacements (values below 1e-4
+                         are raised to 1e-4)                                 */
   int max_outer;      /* mixed: cap on defect-correction steps              */
   int check_every;    /* iterations per host convergence poll (>= 1)        */
   int variant;        /* CG form: 0 one kernel per iteration (Chronopoulos-

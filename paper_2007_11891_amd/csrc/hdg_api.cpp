@@ -151,6 +151,10 @@ hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters, int variant) {
 // kernel per iteration (Chronopoulos-Gear recurrences); 1: textbook PCG
 // with an element kernel and an update kernel per iteration.
 template <typename T>
+hdg_status cg_drive(hdg_ctx* c, CgWork<T>& w, int budget, int check_every, int variant,
+                    int* iters_out, int* done_out);
+
+template <typename T>
 hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
                   int check_every, int variant, int* iters_out, int* done_out) {
   *iters_out = 0;
@@ -164,13 +168,20 @@ hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
   hs[2].A.maxit = std::max(1, maxit);
   hs[2].A.rho = 1.0;
   HIP_TRY(hipMemcpyAsync(w.sc, &hs[2], sizeof(CgScalars), hipMemcpyHostToDevice, c->stream));
+  if (variant == 0) HIP_TRY(launch_cgcg_init<T>(c, w, b, c->stream));
+  else HIP_TRY(launch_cg_init<T>(c, w, b, c->stream));
+  return cg_drive<T>(c, w, std::max(1, maxit), check_every, variant, iters_out, done_out);
+}
+
+// Replays the captured iterations until the device reports a stop (at most
+// `budget` more iterations plus slack); the state afterwards is in
+// c->h_scal[0].
+template <typename T>
+hdg_status cg_drive(hdg_ctx* c, CgWork<T>& w, int budget, int check_every, int variant,
+                    int* iters_out, int* done_out) {
+  CgScalars* hs = c->h_scal;
   check_every = std::max(1, check_every);
-  if (variant == 0) {
-    HIP_TRY(launch_cgcg_init<T>(c, w, b, c->stream));
-    check_every += check_every & 1;           // launches alternate the state slot
-  } else {
-    HIP_TRY(launch_cg_init<T>(c, w, b, c->stream));
-  }
+  if (variant == 0) check_every += check_every & 1;   // launches alternate the state slot
   ST_TRY(build_graph<T>(c, w, check_every, variant));
   hipEvent_t ev[2] = {nullptr, nullptr};
   for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -183,7 +194,7 @@ hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
   } guard{ev};
   // the launch that detects the stop comes after the last iteration's
   // launch(es); +2 chunks of slack
-  const int max_chunks = (std::max(1, maxit) + check_every - 1) / check_every + 2;
+  const int max_chunks = (std::max(1, budget) + check_every - 1) / check_every + 2;
   bool seen_done = false;
   for (int k = 0; k < max_chunks; ++k) {
     HIP_TRY(hipGraphLaunch(w.graph, c->stream));
@@ -269,25 +280,54 @@ hdg_status solve_eigen(hdg_ctx* c, const double* b, double* x_out, const hdg_sol
     if (done == 2) result = HDG_ENOCONV;
   } else {
     ST_TRY(alloc_work(c, c->w32));
-    // FP32 right-hand side buffer: reuse p-ping-pong of nothing; keep a
-    // dedicated FP32 vector in d_vol_tmp-independent storage
+    // FP32 inner CG with reliable updates: after each segment that lowers the
+    // (normalised) FP32 residual by inner_rtol, the FP64 solution takes the
+    // FP32 correction, the FP64 residual is recomputed and replaces the FP32
+    // one (normalised again), and the FP32 CG continues with its search
+    // direction and previous r.z rescaled to the new normalisation instead of
+    // restarting.  The inner CG uses the two-kernel form.
     float* b32 = reinterpret_cast<float*>(c->d_tmp[1]);   // n_free floats fit in n_free doubles
     double* xacc = x_out;
+    CgWork<float>& w = c->w32;
+    // an FP32 CG segment cannot reliably lower its residual by much more
+    // than four orders: smaller requests stagnate until the iteration cap
+    const double inner = std::max(o->inner_rtol, 1e-4);
     HIP_TRY(launch_fill64(xacc, 0.0, c->n_free, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->d_tmp[2], b, sizeof(double) * c->n_free, hipMemcpyDeviceToDevice,
-                           c->stream));
     double rr = bb;
-    int outer = 0, inner_total = 0;
-    while (std::sqrt(rr) > o->rtol * inf.rhs_norm && outer < o->max_outer) {
-      const double rn = std::sqrt(rr);
-      HIP_TRY(launch_cast_scale_64_32(c->d_tmp[2], b32, 1.0 / rn, c->n_free, c->stream));
-      int it = 0, done = 0;
-      ST_TRY(run_cg<float>(c, c->w32, b32, o->inner_rtol, o->maxit, o->check_every,
-                         cg_variant_of(c, o), &it, &done));
-      inner_total += it;
-      HIP_TRY(launch_axpy_32_64(c->w32.x, xacc, rn, c->n_free, c->stream));
+    double sigma = std::sqrt(rr);
+    HIP_TRY(launch_cast_scale_64_32(b, b32, 1.0 / sigma, c->n_free, c->stream));
+    // it: the device's iteration counter of the current FP32 run (buffer and
+    // state-slot parities follow it); base: iterations of earlier runs
+    int outer = 0, inner_total = 0, it = 0, done = 0, base = 0;
+    ST_TRY(run_cg<float>(c, w, b32, inner, o->maxit, o->check_every, 1, &it, &done));
+    for (;;) {
+      inner_total = base + it;
+      HIP_TRY(launch_axpy_32_64(w.x, xacc, sigma, c->n_free, c->stream));
       ST_TRY(residual64(c, b, xacc, &rr));
       ++outer;
+      if (std::sqrt(rr) <= o->rtol * inf.rhs_norm || outer >= o->max_outer || rr == 0.0) break;
+      const double sig_new = std::sqrt(rr);
+      HIP_TRY(launch_cast_scale_64_32(c->d_tmp[2], b32, 1.0 / sig_new, c->n_free, c->stream));
+      if (done == 1) {
+        // continue at iteration `it` with the replaced residual
+        const double q = sigma / sig_new;
+        HIP_TRY(launch_cg_continue<float>(c, w, b32, it, q, c->stream));
+        CgScalars* hs = c->h_scal;
+        hs[2] = hs[0];
+        hs[2].A.rho *= q * q;
+        hs[2].A.rr_stop = inner * inner;   // |b32| = 1
+        hs[2].A.rtol2 = inner * inner;
+        hs[2].A.maxit = it + std::max(1, o->maxit);
+        hs[2].A.done = 0;
+        HIP_TRY(hipMemcpyAsync(w.sc, &hs[2], sizeof(CgScalars), hipMemcpyHostToDevice,
+                               c->stream));
+        ST_TRY(cg_drive<float>(c, w, std::max(1, o->maxit), o->check_every, 1, &it, &done));
+      } else {
+        // the segment hit its cap: restart from the replaced residual
+        base += it;
+        ST_TRY(run_cg<float>(c, w, b32, inner, o->maxit, o->check_every, 1, &it, &done));
+      }
+      sigma = sig_new;
     }
     inf.iters = inner_total;
     inf.outer_iters = outer;

@@ -152,6 +152,10 @@ template <typename T>
 hipError_t launch_cg_apply(const hdg_ctx* c, CgWork<T>& w, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_update(const hdg_ctx* c, CgWork<T>& w, hipStream_t s);
+// two-kernel CG continued on a replaced residual b at iteration `iter`
+template <typename T>
+hipError_t launch_cg_continue(const hdg_ctx* c, CgWork<T>& w, const T* b, int iter, double pscale,
+                              hipStream_t s);
 // one-kernel CG iteration (reads state slot rd, writes rd ^ 1) and its init
 template <typename T>
 hipError_t launch_cgcg_iter(const hdg_ctx* c, CgWork<T>& w, int rd, hipStream_t s);

@@ -138,6 +138,47 @@ cg_init_kernel(int64_t n, const T* __restrict__ b, T* __restrict__ z, T* __restr
   }
 }
 
+// Continuation of a CG on a replaced residual (reliable update of the mixed-
+// precision solver): z = D^-1 b, x = 0, the previous direction rescaled,
+// and the r.z / r.r partials the next apply sums (state slot `slot`).
+template <typename T>
+__global__ void __launch_bounds__(kVecThreads)
+cg_continue_kernel(int64_t n, const T* __restrict__ b, T* __restrict__ z, T* __restrict__ x,
+                   T* __restrict__ p_prev, T pscale, const T* __restrict__ dinv,
+                   double* __restrict__ partials, int pmax, int slot) {
+  __shared__ double s_red[kVecThreads / 64];
+  T rz_t = 0, rr_t = 0;
+  for (int64_t g = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * kVecThreads) {
+    const T v = b[g];
+    const T zv = dinv[g] * v;
+    z[g] = zv;
+    x[g] = 0;
+    p_prev[g] *= pscale;
+    rz_t += v * zv;
+    rr_t += v * v;
+  }
+  const double brz = block_sum<kVecThreads>((double)rz_t, s_red);
+  const double brr = block_sum<kVecThreads>((double)rr_t, s_red);
+  if (threadIdx.x == 0) {
+    partials[(size_t)(2 + slot) * pmax + blockIdx.x] = brz;
+    partials[(size_t)(4 + slot) * pmax + blockIdx.x] = brr;
+  }
+}
+
+template <typename T>
+hipError_t launch_cg_continue(const hdg_ctx*, CgWork<T>& w, const T* b, int iter, double pscale,
+                              hipStream_t s) {
+  T* p_prev = (iter & 1) ? w.p[0] : w.p[1];   // p_{k-1}: the input direction of iteration k
+  hipLaunchKernelGGL((cg_continue_kernel<T>), dim3(w.update_blocks), dim3(kVecThreads), 0, s, w.n,
+                     b, w.z, w.x, p_prev, (T)pscale, w.dinv, w.partials, w.pmax, iter & 1);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_continue<double>(const hdg_ctx*, CgWork<double>&, const double*, int,
+                                               double, hipStream_t);
+template hipError_t launch_cg_continue<float>(const hdg_ctx*, CgWork<float>&, const float*, int,
+                                              double, hipStream_t);
+
 // One-kernel CG: z_0 = D^-1 b (r_0 = b), x = 0, p_{-1} = s_{-1} = 0.  The
 // first iteration launch applies the operator to z_0 and reduces r.z, r.r.
 template <typename T>
