@@ -299,25 +299,49 @@ __device__ inline void apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSmem<
     unit_data<T, NP, MODE>(io, L, R);
     unit_compute<T, NP, EPB, MODE>(io, tab, sm, L, R, acc);
   } else {
+    // every load of the unit is issued before its first store, so that all of
+    // them are in flight together (a store in between would order them)
+    bool on[6];
+    T dv[6], zo[6], wa[6], wb[6], so[6], pi[3], xo[3];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      on[f] = R.active && L.colok && R.fid[f] < io.nff;
+      dv[f] = 1;
+      zo[f] = wa[f] = wb[f] = so[f] = 0;
+      if (f & 1) pi[f >> 1] = xo[f >> 1] = 0;
+      if (on[f]) {
+        const int64_t g = (int64_t)R.fid[f] * NF + L.col;
+        dv[f] = io.dinv[g];
+        zo[f] = io.z_old[g];
+        if (!io.first) {
+          wa[f] = io.w_a[g];
+          wb[f] = io.w_b[g];
+          so[f] = io.s_old[g];
+          if (f & 1) {
+            pi[f >> 1] = io.p_in[g];
+            xo[f >> 1] = io.x[g];
+          }
+        }
+      }
+    }
     T xf[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       T v = 0;
-      if (R.active && L.colok && R.fid[f] < io.nff) {
+      if (on[f]) {
         const int64_t g = (int64_t)R.fid[f] * NF + L.col;
-        const T d = io.dinv[g];
+        const T d = dv[f];
         if (io.first) {
-          v = io.z_old[g];
+          v = zo[f];
         } else {
-          const T zo = io.z_old[g];
-          const T sn = d * (io.w_a[g] + io.w_b[g]) + io.beta * io.s_old[g];
-          v = zo - io.alpha * sn;
+          const T sn = d * (wa[f] + wb[f]) + io.beta * so[f];
+          v = zo[f] - io.alpha * sn;
           if (f & 1) {                          // the element below owns the face
-            const T pn = zo + io.beta * io.p_in[g];
+            const T pn = zo[f] + io.beta * pi[f >> 1];
             io.s_new[g] = sn;
             io.p_out[g] = pn;
             io.z_new[g] = v;
-            io.x[g] += io.alpha * pn;
+            io.x[g] = xo[f >> 1] + io.alpha * pn;
           }
         }
         if (f & 1) {
