@@ -27,12 +27,18 @@ struct ApplyIO {
   int pmax;
   int n_upd;         // number of update-kernel partials
   CgScalars* sc;
-  // one-kernel CG (MODE 2): ping-pong buffers, selected by rd = launch parity
-  T* zb[2];
-  T* pb[2];
-  T* sb[2];
-  T* qab[2];
-  T* qbb[2];
+  // one-kernel CG (MODE 2): the ping-pong buffers of slot rd (read) and
+  // slot rd ^ 1 (written), resolved by the host for this launch's parity
+  T* z_rd;
+  T* z_wr;
+  T* p_rd;
+  T* p_wr;
+  T* s_rd;
+  T* s_wr;
+  T* qa_rd;
+  T* qb_rd;
+  T* qa_wr;
+  T* qb_wr;
   T* x;
   const T* dinv;
   int rd;            // this launch reads state slot rd and writes slot rd ^ 1
@@ -80,36 +86,46 @@ __device__ inline void cg_prologue(const ApplyIO<T>& io, double* s_red, int* ite
 }
 
 // Prologue of the one-kernel CG iteration (Chronopoulos-Gear form of the
-// preconditioned CG, one global reduction per iteration).  Launch k reads
-// slot rd = k & 1 and writes slot rd ^ 1 (block 0).  For k >= 1 it sums the
-// previous launch's partials of delta = z.Az, gamma = r.z and r.r (all of
-// iterate k - 1), tests convergence of x_{k-1}, and forms
-//   beta_{k-1} = gamma_{k-1} / gamma_{k-2}            (0 for k = 1)
-//   alpha_{k-1} = gamma_{k-1} / (delta_{k-1} - beta_{k-1} gamma_{k-1} / alpha_{k-2})
-// (alpha_0 = gamma_0 / delta_0).  Slot fields: rho = gamma of the previous
-// iterate, alpha = its alpha, iter = k.  A finished solve skips the launch.
-template <typename T, int NT>
-__device__ inline void cgcg_prologue(const ApplyIO<T>& io, double* s_red, bool* first, T* alpha,
-                                     T* beta, bool* skip) {
+// preconditioned CG, one global reduction per iteration), in two parts so
+// that the first unit's face loads can be issued in between.  Launch k reads
+// slot rd = k & 1 and writes slot rd ^ 1 (block 0).
+//
+// cgcg_head: a finished solve skips the launch (block 0 carries the final
+// state over to the other slot); otherwise returns k.
+template <typename T>
+__device__ inline bool cgcg_head(const ApplyIO<T>& io, int* k) {
   CgState* R = io.rd ? &io.sc->B : &io.sc->A;
   CgState* W = io.rd ? &io.sc->A : &io.sc->B;
-  const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
   const int rdone = R->done;
+  *k = R->iter;
   if (rdone) {                              // uniform over the grid
-    if (leader) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
       W->done = rdone;
       W->iter = R->iter;
       W->rr = R->rr;
       W->rr_stop = R->rr_stop;
     }
-    *skip = true;
-    return;
+    return true;
   }
-  const int k = R->iter;
+  return false;
+}
+
+// cgcg_scalars: for k >= 1, sums the previous launch's partials of
+// delta = z.Az, gamma = r.z and r.r (all of iterate k - 1), tests
+// convergence of x_{k-1}, and forms
+//   beta_{k-1} = gamma_{k-1} / gamma_{k-2}            (0 for k = 1)
+//   alpha_{k-1} = gamma_{k-1} / (delta_{k-1} - beta_{k-1} gamma_{k-1} / alpha_{k-2})
+// (alpha_0 = gamma_0 / delta_0).  Slot fields: rho = gamma of the previous
+// iterate, alpha = its alpha, iter = k.  *skip when the solve ends here.
+template <typename T, int NT>
+__device__ inline void cgcg_scalars(const ApplyIO<T>& io, int k, double* s_red, T* alpha, T* beta,
+                                    bool* skip) {
+  CgState* R = io.rd ? &io.sc->B : &io.sc->A;
+  CgState* W = io.rd ? &io.sc->A : &io.sc->B;
+  const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
   const double rtol2 = R->rtol2;
   const int maxit = R->maxit;
   if (k == 0) {
-    *first = true;
     *skip = false;
     *alpha = 0;
     *beta = 0;
@@ -121,7 +137,6 @@ __device__ inline void cgcg_prologue(const ApplyIO<T>& io, double* s_red, bool* 
     }
     return;
   }
-  *first = false;
   const int ks = io.rd ^ 1;
   double gam, rr;
   sum_partials2<NT>(io.partials + (size_t)(2 + ks) * io.pmax,
@@ -180,26 +195,49 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
     u.x_free = io.x_free;
     u.x_bdry = io.x_bdry;
   } else if constexpr (MODE == 2) {
-    bool skip, first;
-    T alpha, beta;
-    cgcg_prologue<T, NT>(io, s_red, &first, &alpha, &beta, &skip);
-    if (skip) return;
-    const int rd = io.rd, wr = io.rd ^ 1;
+    int k;
+    if (cgcg_head(io, &k)) return;
+    const bool first = k == 0;
     u.first = first;
-    u.alpha = alpha;
-    u.beta = beta;
-    u.z_old = first ? io.zb[rd] : io.zb[wr];   // z_k lives in zb[k & 1]
-    u.z_new = io.zb[rd];
-    u.p_in = io.pb[rd];                        // p_{k-2}
-    u.p_out = io.pb[wr];                       // p_{k-1}
-    u.s_old = io.sb[rd];
-    u.s_new = io.sb[wr];
-    u.w_a = io.qab[wr];                        // A z_{k-1}, from the previous launch
-    u.w_b = io.qbb[wr];
-    u.qa = io.qab[rd];
-    u.qb = io.qbb[rd];
+    u.z_old = first ? io.z_rd : io.z_wr;       // z_k lives in slot k & 1
+    u.z_new = io.z_rd;
+    u.p_in = io.p_rd;                          // p_{k-2}
+    u.p_out = io.p_wr;                         // p_{k-1}
+    u.s_old = io.s_rd;
+    u.s_new = io.s_wr;
+    u.w_a = io.qa_wr;                          // A z_{k-1}, from the previous launch
+    u.w_b = io.qb_wr;
+    u.qa = io.qa_rd;
+    u.qb = io.qb_rd;
     u.dinv = io.dinv;
     u.x = io.x;
+    // the first unit's loads go out before the scalar prologue's
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const UnitLane L = unit_lane<NP, EPB>((int)threadIdx.x);
+    UnitRegs<T> R0;
+    CgLoads<T> C0;
+    unit_info<T, NP, EPB>(u, L, bid * units_per_block, R0);
+    cg2_loads<T, NP>(u, L, R0, C0);
+    bool skip;
+    T alpha, beta;
+    cgcg_scalars<T, NT>(io, k, s_red, &alpha, &beta, &skip);
+    if (skip) return;
+    u.alpha = alpha;
+    u.beta = beta;
+    double acc[3] = {0.0, 0.0, 0.0};
+    cg2_compute<T, NP, EPB>(u, tab, sm, L, R0, C0, acc);
+    for (int un = 1; un < units_per_block; ++un)
+      apply_unit<T, NP, EPB, MODE>(u, tab, sm, bid * units_per_block + un, acc);
+    // z.Az, r.z, r.r of this launch's iterate, one partial each per block
+    const double b0 = block_sum<NT>(acc[0], s_red);
+    const double b1 = block_sum<NT>(acc[1], s_red);
+    const double b2 = block_sum<NT>(acc[2], s_red);
+    if (threadIdx.x == 0) {
+      io.partials[(size_t)io.rd * io.pmax + blockIdx.x] = b0;
+      io.partials[(size_t)(2 + io.rd) * io.pmax + blockIdx.x] = b1;
+      io.partials[(size_t)(4 + io.rd) * io.pmax + blockIdx.x] = b2;
+    }
+    return;
   } else {
     bool skip;
     T beta;
@@ -212,7 +250,7 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
   }
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   double acc[3] = {0.0, 0.0, 0.0};
-  if constexpr (MODE == 2 || PIPE == 0) {
+  if constexpr (PIPE == 0) {
     for (int un = 0; un < units_per_block; ++un)
       apply_unit<T, NP, EPB, MODE>(u, tab, sm, bid * units_per_block + un, acc);
   } else {
@@ -223,16 +261,6 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
     // one partial per block, summed by every block of the update kernel
     const double bs = block_sum<NT>(acc[0], s_red);
     if (threadIdx.x == 0) io.partials[(size_t)(iter & 1) * io.pmax + blockIdx.x] = bs;
-  } else if constexpr (MODE == 2) {
-    // z.Az, r.z, r.r of this launch's iterate, one partial each per block
-    const double b0 = block_sum<NT>(acc[0], s_red);
-    const double b1 = block_sum<NT>(acc[1], s_red);
-    const double b2 = block_sum<NT>(acc[2], s_red);
-    if (threadIdx.x == 0) {
-      io.partials[(size_t)io.rd * io.pmax + blockIdx.x] = b0;
-      io.partials[(size_t)(2 + io.rd) * io.pmax + blockIdx.x] = b1;
-      io.partials[(size_t)(4 + io.rd) * io.pmax + blockIdx.x] = b2;
-    }
   }
 }
 
@@ -376,13 +404,17 @@ hipError_t launch_cg_apply(const hdg_ctx* c, CgWork<T>& w, hipStream_t s) {
 template <typename T>
 hipError_t launch_cgcg_iter(const hdg_ctx* c, CgWork<T>& w, int rd, hipStream_t s) {
   ApplyIO<T> io{};
-  for (int i = 0; i < 2; ++i) {
-    io.zb[i] = w.zz[i];
-    io.pb[i] = w.p[i];
-    io.sb[i] = w.s[i];
-    io.qab[i] = w.qq[i][0];
-    io.qbb[i] = w.qq[i][1];
-  }
+  const int wr = rd ^ 1;
+  io.z_rd = w.zz[rd];
+  io.z_wr = w.zz[wr];
+  io.p_rd = w.p[rd];
+  io.p_wr = w.p[wr];
+  io.s_rd = w.s[rd];
+  io.s_wr = w.s[wr];
+  io.qa_rd = w.qq[rd][0];
+  io.qb_rd = w.qq[rd][1];
+  io.qa_wr = w.qq[wr][0];
+  io.qb_wr = w.qq[wr][1];
   io.x = w.x;
   io.dinv = w.dinv;
   io.partials = w.partials;

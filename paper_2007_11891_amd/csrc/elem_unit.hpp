@@ -283,6 +283,86 @@ __device__ inline void unit_compute(const UnitIO<T>& io, const Tab& tab, UnitSme
   acc[0] += dot;
 }
 
+// One-kernel CG iteration (MODE 2), split into its loads and its arithmetic
+// so that the loads of a unit can be issued before the launch's scalar
+// prologue.  Every load of the unit is issued before its first store, so
+// that all of them are in flight together (a store in between would order
+// them).  In the first launch only D^-1 and z are read.
+template <typename T>
+struct CgLoads {
+  bool on[6];
+  T dv[6], zo[6], wa[6], wb[6], so[6], pi[3], xo[3];
+};
+
+template <typename T, int NP>
+__device__ inline void cg2_loads(const UnitIO<T>& io, const UnitLane& L, const UnitRegs<T>& R,
+                                 CgLoads<T>& C) {
+  constexpr int NF = NP * NP;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    C.on[f] = R.active && L.colok && R.fid[f] < io.nff;
+    C.dv[f] = 1;
+    C.zo[f] = C.wa[f] = C.wb[f] = C.so[f] = 0;
+    if (f & 1) C.pi[f >> 1] = C.xo[f >> 1] = 0;
+    if (C.on[f]) {
+      const int64_t g = (int64_t)R.fid[f] * NF + L.col;
+      C.dv[f] = io.dinv[g];
+      C.zo[f] = io.z_old[g];
+      if (!io.first) {
+        C.wa[f] = io.w_a[g];
+        C.wb[f] = io.w_b[g];
+        C.so[f] = io.s_old[g];
+        if (f & 1) {
+          C.pi[f >> 1] = io.p_in[g];
+          C.xo[f >> 1] = io.x[g];
+        }
+      }
+    }
+  }
+}
+
+// Per face: s = D^-1 w + beta s_old, z = z_old - alpha s, and on the faces
+// the unit owns p = z_old + beta p_old, x += alpha p and the r.z, r.r
+// shares; then the operator applied to z.
+template <typename T, int NP, int EPB, typename Tab>
+__device__ inline void cg2_compute(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
+                                   const UnitLane& L, const UnitRegs<T>& R, const CgLoads<T>& C,
+                                   double* acc) {
+  constexpr int NF = NP * NP;
+  T xf[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    T v = 0;
+    if (C.on[f]) {
+      const int64_t g = (int64_t)R.fid[f] * NF + L.col;
+      const T d = C.dv[f];
+      if (io.first) {
+        v = C.zo[f];
+      } else {
+        const T sn = d * (C.wa[f] + C.wb[f]) + io.beta * C.so[f];
+        v = C.zo[f] - io.alpha * sn;
+        if (f & 1) {                          // the element below owns the face
+          const T pn = C.zo[f] + io.beta * C.pi[f >> 1];
+          io.s_new[g] = sn;
+          io.p_out[g] = pn;
+          io.z_new[g] = v;
+          io.x[g] = C.xo[f >> 1] + io.alpha * pn;
+        }
+      }
+      if (f & 1) {
+        const double r = (double)div_fast(v, d);
+        acc[1] += (double)v * r;
+        acc[2] += r * r;
+      }
+    }
+    xf[f] = v;
+    if (f < 4 && R.active && L.colok) sm.face[L.sl][f][L.col] = v;
+  }
+  double dot = 0.0;
+  unit_core<T, NP, EPB, 2>(io, tab, sm, L, R.active, R.fid, R.d, xf, &dot);
+  acc[0] += dot;
+}
+
 // Processes elements [unit EPB, unit EPB + EPB).  Every thread of the block
 // calls it (tid = its index in the block); threads beyond EPB * tpe idle.
 // Adds to acc the thread's share of the element-local quadratic forms
@@ -299,63 +379,9 @@ __device__ inline void apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSmem<
     unit_data<T, NP, MODE>(io, L, R);
     unit_compute<T, NP, EPB, MODE>(io, tab, sm, L, R, acc);
   } else {
-    // every load of the unit is issued before its first store, so that all of
-    // them are in flight together (a store in between would order them)
-    bool on[6];
-    T dv[6], zo[6], wa[6], wb[6], so[6], pi[3], xo[3];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      on[f] = R.active && L.colok && R.fid[f] < io.nff;
-      dv[f] = 1;
-      zo[f] = wa[f] = wb[f] = so[f] = 0;
-      if (f & 1) pi[f >> 1] = xo[f >> 1] = 0;
-      if (on[f]) {
-        const int64_t g = (int64_t)R.fid[f] * NF + L.col;
-        dv[f] = io.dinv[g];
-        zo[f] = io.z_old[g];
-        if (!io.first) {
-          wa[f] = io.w_a[g];
-          wb[f] = io.w_b[g];
-          so[f] = io.s_old[g];
-          if (f & 1) {
-            pi[f >> 1] = io.p_in[g];
-            xo[f >> 1] = io.x[g];
-          }
-        }
-      }
-    }
-    T xf[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      T v = 0;
-      if (on[f]) {
-        const int64_t g = (int64_t)R.fid[f] * NF + L.col;
-        const T d = dv[f];
-        if (io.first) {
-          v = zo[f];
-        } else {
-          const T sn = d * (wa[f] + wb[f]) + io.beta * so[f];
-          v = zo[f] - io.alpha * sn;
-          if (f & 1) {                          // the element below owns the face
-            const T pn = zo[f] + io.beta * pi[f >> 1];
-            io.s_new[g] = sn;
-            io.p_out[g] = pn;
-            io.z_new[g] = v;
-            io.x[g] = xo[f >> 1] + io.alpha * pn;
-          }
-        }
-        if (f & 1) {
-          const double r = (double)div_fast(v, d);
-          acc[1] += (double)v * r;
-          acc[2] += r * r;
-        }
-      }
-      xf[f] = v;
-      if (f < 4 && R.active && L.colok) sm.face[L.sl][f][L.col] = v;
-    }
-    double dot = 0.0;
-    unit_core<T, NP, EPB, MODE>(io, tab, sm, L, R.active, R.fid, R.d, xf, &dot);
-    acc[0] += dot;
+    CgLoads<T> C;
+    cg2_loads<T, NP>(io, L, R, C);
+    cg2_compute<T, NP, EPB>(io, tab, sm, L, R, C, acc);
   }
 }
 
