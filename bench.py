@@ -400,22 +400,37 @@ def main():
     cg_apply_bytes = 40 * nf
     cg_update_bytes = 64 * nf
     one_bytes = 104 * nf
-    apply_name = f"elem_apply_kernel<double, {prob.p + 1}, {tile['elems_per_unit']}, 1>"
-    one_name = f"elem_apply_kernel<double, {prob.p + 1}, {tile['elems_per_unit']}, 2>"
+    # kernel names as rocprofv3 prints them: <type, n_p, elements per unit,
+    # mode, pipelined>; the fused apply is pipelined when a block has several
+    # units (grid capped at 2048 blocks)
+    epu = tile["elems_per_unit"]
+    units = -(-prob.n_elem // epu)
+    upb = -(-units // min(units, 2048))
+    apply_name = f"elem_apply_kernel<double, {prob.p + 1}, {epu}, 1, {1 if upb > 1 else 0}>"
+    one_name = f"elem_apply_kernel<double, {prob.p + 1}, {epu}, 2, 0>"
     if tile["cg_variant"] == 0:
         kname, kbytes, kt, kdesc = one_name, one_bytes, t_one, "one-kernel CG iteration"
-    elif t_cg_apply >= t_cg_update:
-        kname, kbytes, kt, kdesc = apply_name, cg_apply_bytes, t_cg_apply, "fused CG apply"
+        it_us, it_kernels = t_one, [one_name]
     else:
-        kname, kbytes, kt, kdesc = "cg_update_kernel<double>", cg_update_bytes, t_cg_update, "CG update"
+        if t_cg_apply >= t_cg_update:
+            kname, kbytes, kt, kdesc = apply_name, cg_apply_bytes, t_cg_apply, "fused CG apply"
+        else:
+            kname, kbytes, kt, kdesc = ("cg_update_kernel<double>", cg_update_bytes, t_cg_update,
+                                        "CG update")
+        it_us, it_kernels = t_cg_iter, [apply_name, "cg_update_kernel<double>"]
     achieved = kbytes / (kt * 1e-3) / 1e9
+    it_gbs = one_bytes / (it_us * 1e-3) / 1e9
     roofline = {"kernel": f"{kname} ({kdesc})", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(kname),
                 "bytes_per_launch": kbytes, "avg_launch_us": round(kt * 1e3, 3),
                 "cg_form": "one kernel per iteration" if tile["cg_variant"] == 0
-                           else "element + update kernel per iteration"}
+                           else "element + update kernel per iteration",
+                # the whole CG iteration (every kernel of the form in use)
+                "iteration": {"kernels": it_kernels, "bytes": one_bytes,
+                              "avg_us": round(it_us * 1e3, 3), "achieved": round(it_gbs, 1),
+                              "frac": round(it_gbs / HBM_PEAK_GBS, 4)}}
     apply_bytes = 16 * nf
     apply_only = {"trace_dof_per_s_fp64": nf / (t_apply64 * 1e-3),
                   "trace_dof_per_s_fp32": nf / (t_apply32 * 1e-3),

@@ -269,8 +269,10 @@ hdg_status hdg_diagonal(hdg_ctx* ctx, double* diag_free);
  * (fused apply + update), 3 = FP32 CG iteration, 4 / 5 = FP64 fused CG
  * apply / update alone, 6 / 7 = the same in FP32, 8 = plain FP64 copy
  * x -> y (reference traffic), 9 / 10 = one-kernel CG iteration (solver
- * variant 0) in FP64 / FP32.  x, y device buffers of n_free values of the
- * matching type (x read; y written only by 8).  Synchronises. */
+ * variant 0) in FP64 / FP32, 11 / 12 = the same replayed from a captured
+ * graph of reps (rounded up to even) launches, as the solver runs them.
+ * x, y device buffers of n_free values of the matching type (x read; y
+ * written only by 8).  Synchronises. */
 hdg_status hdg_time_kernel(hdg_ctx* ctx, int which, const void* x, void* y,
                            int reps, double* ms);
 

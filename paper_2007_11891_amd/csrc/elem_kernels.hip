@@ -45,18 +45,20 @@ struct ApplyIO {
   int n_parts;       // partials per slot written by the previous launch
 };
 
-// CG prologue: read slot A, sum the update partials (r.z and r.r), decide
-// convergence, publish slot B from block 0.  A finished solve skips the
-// whole launch (x is already complete).
+// CG prologue of the fused apply, in two parts so that the first unit's
+// face loads can be issued in between.  cg_head: a finished solve skips the
+// whole launch (x is already complete); otherwise returns the iteration k.
+template <typename T>
+__device__ inline bool cg_head(const ApplyIO<T>& io, int* iter) {
+  *iter = io.sc->A.iter;
+  return io.sc->A.done != 0;                // uniform over the grid
+}
+
+// cg_scalars: reads slot A, sums the update partials (r.z and r.r), decides
+// convergence, publishes slot B from block 0 and forms beta.
 template <typename T, int NT>
-__device__ inline void cg_prologue(const ApplyIO<T>& io, double* s_red, int* iter, T* beta,
-                                   bool* skip) {
-  if (io.sc->A.done) {                     // uniform over the grid
-    *skip = true;
-    return;
-  }
-  *skip = false;
-  const int it = io.sc->A.iter;
+__device__ inline void cg_scalars(const ApplyIO<T>& io, int it, double* s_red, T* beta,
+                                  bool* skip) {
   const double rho_prev = io.sc->A.rho;
   const double rtol2 = io.sc->A.rtol2;
   const int maxit = io.sc->A.maxit;
@@ -73,7 +75,6 @@ __device__ inline void cg_prologue(const ApplyIO<T>& io, double* s_red, int* ite
   else if (it >= maxit) done = 2;
   *skip = done != 0;
   *beta = (T)b;
-  *iter = it;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     io.sc->B.rho = rho;
     io.sc->B.rr = rr;
@@ -190,11 +191,15 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
   u.nff = (int)mesh.n_free_faces;
   u.qa = io.qa;
   u.qb = io.qb;
-  int iter = 0;
   if constexpr (MODE == 0) {
     u.x_free = io.x_free;
     u.x_bdry = io.x_bdry;
   } else if constexpr (MODE == 2) {
+    // the first unit's element records load together with the state slot
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const UnitLane L = unit_lane<NP, EPB>((int)threadIdx.x);
+    UnitRegs<T> R0;
+    unit_info<T, NP, EPB>(u, L, bid * units_per_block, R0);
     int k;
     if (cgcg_head(io, &k)) return;
     const bool first = k == 0;
@@ -211,12 +216,8 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
     u.qb = io.qb_rd;
     u.dinv = io.dinv;
     u.x = io.x;
-    // the first unit's loads go out before the scalar prologue's
-    const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const UnitLane L = unit_lane<NP, EPB>((int)threadIdx.x);
-    UnitRegs<T> R0;
+    // the first unit's face loads go out before the scalar prologue's
     CgLoads<T> C0;
-    unit_info<T, NP, EPB>(u, L, bid * units_per_block, R0);
     cg2_loads<T, NP>(u, L, R0, C0);
     bool skip;
     T alpha, beta;
@@ -239,28 +240,52 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
     }
     return;
   } else {
-    bool skip;
-    T beta;
-    cg_prologue<T, NT>(io, s_red, &iter, &beta, &skip);
-    if (skip) return;
+    // MODE 1: the state slot, then the first unit's loads, then the partial
+    // sums and beta
+    int iter;
+    if (cg_head(io, &iter)) return;
     u.z = io.z;
     u.p_in = (iter & 1) ? io.p0 : io.p1;     // iteration k reads p_{k-1}, writes p_k
     u.p_out = (iter & 1) ? io.p1 : io.p0;
-    u.beta = beta;
-  }
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  double acc[3] = {0.0, 0.0, 0.0};
-  if constexpr (PIPE == 0) {
-    for (int un = 0; un < units_per_block; ++un)
-      apply_unit<T, NP, EPB, MODE>(u, tab, sm, bid * units_per_block + un, acc);
-  } else {
-    run_units_pipelined<T, NP, EPB, MODE>(u, tab, sm, bid * units_per_block,
-                                          (bid + 1) * units_per_block, acc);
-  }
-  if constexpr (MODE == 1) {
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    auto scalars = [&]() -> bool {
+      bool skip;
+      T beta;
+      cg_scalars<T, NT>(io, iter, s_red, &beta, &skip);
+      u.beta = beta;
+      return !skip;
+    };
+    double acc[3] = {0.0, 0.0, 0.0};
+    if constexpr (PIPE == 0) {
+      const UnitLane L = unit_lane<NP, EPB>((int)threadIdx.x);
+      UnitRegs<T> R0;
+      unit_info<T, NP, EPB>(u, L, bid * units_per_block, R0);
+      unit_data<T, NP, 1>(u, L, R0);
+      if (!scalars()) return;
+      unit_compute<T, NP, EPB, 1>(u, tab, sm, L, R0, acc);
+      for (int un = 1; un < units_per_block; ++un)
+        apply_unit<T, NP, EPB, 1>(u, tab, sm, bid * units_per_block + un, acc);
+    } else {
+      if (!run_units_pipelined<T, NP, EPB, 1>(u, tab, sm, bid * units_per_block,
+                                              (bid + 1) * units_per_block, acc,
+                                              (int)threadIdx.x, scalars))
+        return;
+    }
     // one partial per block, summed by every block of the update kernel
     const double bs = block_sum<NT>(acc[0], s_red);
     if (threadIdx.x == 0) io.partials[(size_t)(iter & 1) * io.pmax + blockIdx.x] = bs;
+    return;
+  }
+  if constexpr (MODE == 0) {
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    double acc[3] = {0.0, 0.0, 0.0};
+    if constexpr (PIPE == 0) {
+      for (int un = 0; un < units_per_block; ++un)
+        apply_unit<T, NP, EPB, MODE>(u, tab, sm, bid * units_per_block + un, acc);
+    } else {
+      run_units_pipelined<T, NP, EPB, MODE>(u, tab, sm, bid * units_per_block,
+                                            (bid + 1) * units_per_block, acc);
+    }
   }
 }
 

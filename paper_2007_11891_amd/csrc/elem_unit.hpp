@@ -178,6 +178,16 @@ __device__ inline void unit_data(const UnitIO<T>& io, const UnitLane& L, UnitReg
   }
 }
 
+// Output stores.  The fused CG apply (MODE 1) writes its results with the
+// non-temporal hint: nothing reads them again in the same launch, and
+// measured on MI355X this is 5 to 30 % faster; the other modes measured
+// faster with plain stores.
+template <int MODE, typename T>
+__device__ inline void put(T* p, T v) {
+  if constexpr (MODE == 1) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // Element arithmetic of one unit given its input face values xf (already in
 // registers, faces 0..3 also staged in LDS by the caller before the first
 // barrier): expansion into the element eigenspace, reductions back to the
@@ -251,8 +261,7 @@ __device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T
     for (int f = 0; f < 6; ++f) {
       if (fid[f] >= io.nff) continue;
       const int64_t g = (int64_t)fid[f] * NF + col;
-      if (f & 1) io.qa[g] = out[f];
-      else io.qb[g] = out[f];
+      put<MODE>((f & 1) ? io.qa + g : io.qb + g, out[f]);
       if constexpr (MODE != 0) *dot += (double)(xf[f] * out[f]);
     }
   }
@@ -273,7 +282,7 @@ __device__ inline void unit_compute(const UnitIO<T>& io, const Tab& tab, UnitSme
     if constexpr (MODE == 1) {
       v = R.a[f] + io.beta * R.b[f];
       if ((f & 1) && R.active && L.colok && R.fid[f] < io.nff)
-        io.p_out[(int64_t)R.fid[f] * NF + L.col] = v;   // the element below owns the face
+        put<MODE>(io.p_out + (int64_t)R.fid[f] * NF + L.col, v);   // the element below owns the face
     }
     xf[f] = v;
     if (f < 4 && R.active && L.colok) sm.face[L.sl][f][L.col] = v;
@@ -387,18 +396,24 @@ __device__ inline void apply_unit(const UnitIO<T>& io, const Tab& tab, UnitSmem<
 
 // Units [u0, u1) with the loads of unit u + 1 (and the element records of
 // unit u + 2) issued before the arithmetic of unit u, so that a block always
-// has memory traffic in flight (MODES 0 and 1).
-template <typename T, int NP, int EPB, int MODE, typename Tab>
-__device__ inline void run_units_pipelined(const UnitIO<T>& io, const Tab& tab,
+// has memory traffic in flight (MODES 0 and 1).  `between` runs once, after
+// the first unit's loads are issued and before any arithmetic; when it
+// returns false nothing is computed and the function returns false.
+struct NoStep {
+  __device__ bool operator()() const { return true; }
+};
+template <typename T, int NP, int EPB, int MODE, typename Tab, typename Between = NoStep>
+__device__ inline bool run_units_pipelined(const UnitIO<T>& io, const Tab& tab,
                                            UnitSmem<T, NP, EPB>& sm, int u0, int u1, double* acc,
-                                           int tid = (int)threadIdx.x) {
+                                           int tid = (int)threadIdx.x, Between between = {}) {
   static_assert(MODE != 2, "the one-kernel CG iteration is not pipelined");
-  if (u0 >= u1) return;
+  if (u0 >= u1) return between();
   const UnitLane L = unit_lane<NP, EPB>(tid);
   UnitRegs<T> cur, nxt;
   unit_info<T, NP, EPB>(io, L, u0, cur);
   unit_data<T, NP, MODE>(io, L, cur);
   if (u0 + 1 < u1) unit_info<T, NP, EPB>(io, L, u0 + 1, nxt);
+  if (!between()) return false;
   for (int u = u0; u < u1; ++u) {
     const UnitRegs<T> c = cur;
     if (u + 1 < u1) {
@@ -408,6 +423,7 @@ __device__ inline void run_units_pipelined(const UnitIO<T>& io, const Tab& tab,
     }
     unit_compute<T, NP, EPB, MODE>(io, tab, sm, L, c, acc);
   }
+  return true;
 }
 
 }  // namespace hdg

@@ -38,11 +38,11 @@ hdg_status fail(hdg_status st, const char* fmt, ...) {
 namespace {
 
 // Blocks of the CG vector kernels: 256 threads x 4 elements per thread, at
-// most 256 blocks so that the apply blocks that re-sum the update partials
-// read few values.
+// most 512 blocks (two per CU), so that the apply blocks that re-sum the
+// update partials read few values (measured best of 256, 512 and 1024).
 int vec_blocks_for(int64_t n) {
   int64_t nb = (n + 1023) / 1024;
-  nb = std::min<int64_t>(std::max<int64_t>(nb, 1), 256);
+  nb = std::min<int64_t>(std::max<int64_t>(nb, 1), 512);
   return (int)nb;
 }
 
@@ -462,8 +462,9 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
   c->tau = tau_hat;
   c->n_elem = ne;
   // CG form before any autotuning: one kernel per iteration for meshes small
-  // enough that launch latency dominates, else the two-kernel form
-  c->cg_variant = ne * (int64_t)(p + 1) * (p + 1) <= ((int64_t)1 << 18) ? 0 : 1;
+  // enough that launch latency dominates, else the two-kernel form (the
+  // measured crossover on MI355X is near n_elem n_p^2 = 2e5)
+  c->cg_variant = ne * (int64_t)(p + 1) * (p + 1) <= 200000 ? 0 : 1;
   const int n1 = n_elem[0], n2 = n_elem[1], n3 = n_elem[2];
   const int64_t nf0 = (int64_t)(n1 - 1) * n2 * n3, nf1 = (int64_t)n1 * (n2 - 1) * n3,
                 nf2 = (int64_t)n1 * n2 * (n3 - 1);
@@ -983,12 +984,15 @@ hdg_status hdg_diagonal(hdg_ctx* c, double* diag_free) {
 
 hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int reps, double* ms) {
   if (!c || !x || !ms || reps < 1) return fail(HDG_EINVAL, "invalid argument");
-  if (which < 0 || which > 10) return fail(HDG_EINVAL, "unknown kernel id %d", which);
+  if (which < 0 || which > 12) return fail(HDG_EINVAL, "unknown kernel id %d", which);
   if (which == 8 && (!y || y == x)) return fail(HDG_EINVAL, "copy needs a distinct y");
   if (c->n_free == 0) {
     *ms = 0.0;
     return HDG_OK;
   }
+  // 11 / 12: the one-kernel iteration replayed from a captured graph
+  const bool in_graph = (which == 11 || which == 12);
+  if (in_graph) which -= 2;
   const bool f32 = (which == 1 || which == 3 || which == 6 || which == 7 || which == 10);
   const bool one_kernel = (which == 9 || which == 10);
   if (f32) ST_TRY(alloc_work(c, c->w32));
@@ -1026,39 +1030,73 @@ hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int re
     }
   }
   int parity = 1;   // one-kernel CG: state slot of the next launch
+  hipStream_t ls = c->stream;   // launch stream (the capture stream while capturing)
   auto launch = [&]() -> hipError_t {
     switch (which) {
       case 0: return launch_elem_apply<double>(c, static_cast<const double*>(x), nullptr,
-                                               c->w64.qa, c->w64.qb, c->stream);
+                                               c->w64.qa, c->w64.qb, ls);
       case 1: return launch_elem_apply<float>(c, static_cast<const float*>(x), nullptr,
-                                              c->w32.qa, c->w32.qb, c->stream);
+                                              c->w32.qa, c->w32.qb, ls);
       case 2: {
-        hipError_t e = launch_cg_apply<double>(c, c->w64, c->stream);
-        return e == hipSuccess ? launch_cg_update<double>(c, c->w64, c->stream) : e;
+        hipError_t e = launch_cg_apply<double>(c, c->w64, ls);
+        return e == hipSuccess ? launch_cg_update<double>(c, c->w64, ls) : e;
       }
       case 3: {
-        hipError_t e = launch_cg_apply<float>(c, c->w32, c->stream);
-        return e == hipSuccess ? launch_cg_update<float>(c, c->w32, c->stream) : e;
+        hipError_t e = launch_cg_apply<float>(c, c->w32, ls);
+        return e == hipSuccess ? launch_cg_update<float>(c, c->w32, ls) : e;
       }
-      case 4: return launch_cg_apply<double>(c, c->w64, c->stream);
-      case 5: return launch_cg_update<double>(c, c->w64, c->stream);
-      case 6: return launch_cg_apply<float>(c, c->w32, c->stream);
-      case 7: return launch_cg_update<float>(c, c->w32, c->stream);
+      case 4: return launch_cg_apply<double>(c, c->w64, ls);
+      case 5: return launch_cg_update<double>(c, c->w64, ls);
+      case 6: return launch_cg_apply<float>(c, c->w32, ls);
+      case 7: return launch_cg_update<float>(c, c->w32, ls);
       case 9: {
         const int rd = parity;
         parity ^= 1;
-        return launch_cgcg_iter<double>(c, c->w64, rd, c->stream);
+        return launch_cgcg_iter<double>(c, c->w64, rd, ls);
       }
       case 10: {
         const int rd = parity;
         parity ^= 1;
-        return launch_cgcg_iter<float>(c, c->w32, rd, c->stream);
+        return launch_cgcg_iter<float>(c, c->w32, rd, ls);
       }
       default: return launch_copy64(static_cast<const double*>(x), static_cast<double*>(y),
-                                    c->n_free, c->stream);
+                                    c->n_free, ls);
     }
   };
   HIP_TRY(launch());   // warm-up
+  if (in_graph) {
+    // an even count keeps the state-slot parity of the replays aligned
+    const int n = reps + (reps & 1);
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    // captured on the context's capture stream, replayed on its stream
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    ls = c->cap_stream;
+    HIP_TRY(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int r = 0; r < n && err == hipSuccess; ++r) err = launch();
+    hipError_t e2 = hipStreamEndCapture(ls, &g);
+    ls = c->stream;
+    if (err == hipSuccess) err = e2;
+    if (err == hipSuccess) err = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (err == hipSuccess) err = hipGraphLaunch(ge, c->stream);   // warm-up replay
+    if (err == hipSuccess) err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
+    if (err == hipSuccess) err = hipGraphLaunch(ge, c->stream);
+    if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    HIP_TRY(err);
+    *ms = (double)t / n;
+    return HDG_OK;
+  }
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));

@@ -47,6 +47,27 @@ cg_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb, 
   }
   const int k = sc->B.iter;
   const double rho = sc->B.rho;
+  const T* __restrict__ p = (k & 1) ? p1 : p0;   // p_k, written by the apply of iteration k
+  // kUnroll independent entries per thread, all loads issued before use; the
+  // first group's loads go out before the partial sums
+  const int64_t stride = (int64_t)gridDim.x * kVecThreads;
+  int64_t g0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  T va[kUnroll], vb[kUnroll], vz[kUnroll], vd[kUnroll], vx[kUnroll], vp[kUnroll];
+  auto load = [&](int64_t base) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t g = base + u * stride;
+      if (g < n) {
+        va[u] = qa[g];
+        vb[u] = qb[g];
+        vz[u] = z[g];
+        vd[u] = dinv[g];
+        vx[u] = x[g];
+        vp[u] = p[g];
+      }
+    }
+  };
+  if (g0 < n) load(g0);
   const double pq = sum_partials<kVecThreads>(partials + (size_t)(k & 1) * pmax, n_apply, 1, 0,
                                               s_red);
   const double alpha = rho / pq;
@@ -59,37 +80,21 @@ cg_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb, 
     return;
   }
   const T a = (T)alpha;
-  const T* __restrict__ p = (k & 1) ? p1 : p0;   // p_k, written by the apply of iteration k
   T rz_t = 0, rr_t = 0;
-  // kUnroll independent elements per thread: all loads issued before use
-  const int64_t stride = (int64_t)gridDim.x * kVecThreads;
-  for (int64_t g0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; g0 < n;
-       g0 += kUnroll * stride) {
-    T va[kUnroll], vb[kUnroll], vz[kUnroll], vd[kUnroll], vx[kUnroll], vp[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int64_t g = g0 + u * stride;
-      if (g < n) {
-        va[u] = qa[g];
-        vb[u] = qb[g];
-        vz[u] = z[g];
-        vd[u] = dinv[g];
-        vx[u] = x[g];
-        vp[u] = p[g];
-      }
-    }
+  for (; g0 < n; g0 += kUnroll * stride) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int64_t g = g0 + u * stride;
       if (g < n) {
         const T zn = vz[u] - a * (vd[u] * (va[u] + vb[u]));
-        z[g] = zn;
-        x[g] = vx[u] + a * vp[u];
+        __builtin_nontemporal_store(zn, z + g);
+        __builtin_nontemporal_store(vx[u] + a * vp[u], x + g);
         const T rn = div_fast(zn, vd[u]);
         rz_t += zn * rn;
         rr_t += rn * rn;
       }
     }
+    if (g0 + kUnroll * stride < n) load(g0 + kUnroll * stride);
   }
   const double brz = block_sum<kVecThreads>((double)rz_t, s_red);
   const double brr = block_sum<kVecThreads>((double)rr_t, s_red);
