@@ -67,6 +67,33 @@ __device__ inline double block_sum(double v, double* sbuf) {
   }
 }
 
+// K block sums at once (one LDS exchange): the same tree as block_sum for
+// each; the results are valid in thread 0.
+template <int NT, int K>
+__device__ inline void block_sums(double (&v)[K]) {
+  constexpr int NW = NT / 64;
+  __shared__ double s_w[K][NW];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if constexpr (NW > 1) {
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) s_w[k][threadIdx.x >> 6] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) t += s_w[k][i];
+        v[k] = t;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Deterministic sum of nparts partials written by an earlier launch, with
 // stride `stride` and offset `off`, by a whole block of NT threads.  Every
 // block that calls it gets the same value (same order, same tree); the result
@@ -119,6 +146,57 @@ __device__ inline void sum_partials2(const double* __restrict__ pa, const double
   *rb = s_bc2[1];
   __syncthreads();
 }
+
+// K partial arrays of nparts values each, summed by a whole block of NT
+// threads in a fixed order (every block gets the same bits): thread t adds
+// entries t + u NT + c 4 NT into accumulator u (chunks c in order), the four
+// accumulators combine as (v0 + v1) + (v2 + v3), then a wavefront butterfly,
+// then the wavefront sums in order.  The loads of the first chunk are issued
+// by `issue`, so that a kernel can put them in flight early and do other
+// work before `reduce` (which loads any further chunks and returns the sums
+// in every thread).
+template <int NT, int K>
+struct PartialSums {
+  double v[K][4];
+  __device__ inline void issue(const double* const* p, int nparts) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = (int)threadIdx.x + u * NT;
+        v[k][u] = i < nparts ? p[k][i] : 0.0;
+      }
+  }
+  __device__ inline void reduce(const double* const* p, int nparts, double* out) {
+    for (int i0 = (int)threadIdx.x + 4 * NT; i0 < nparts; i0 += 4 * NT) {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + u * NT;
+          if (i < nparts) v[k][u] += p[k][i];
+        }
+    }
+    constexpr int NW = NT / 64;
+    __shared__ double s_w[K][NW];
+    double w[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) w[k] = wave_sum((v[k][0] + v[k][1]) + (v[k][2] + v[k][3]));
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) s_w[k][threadIdx.x >> 6] = w[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < NW; ++i) t += s_w[k][i];
+      out[k] = t;
+    }
+    __syncthreads();                         // s_w is reused by the next call
+  }
+};
 
 // Face id of the face of element (i,j,k) normal to axis a on side s (0 low,
 // 1 high).  Sets *is_free.

@@ -46,27 +46,28 @@ struct ApplyIO {
 };
 
 // CG prologue of the fused apply, in two parts so that the first unit's
-// face loads can be issued in between.  cg_head: a finished solve skips the
-// whole launch (x is already complete); otherwise returns the iteration k.
+// face loads and the partials' loads can be issued in between.  cg_head: a
+// finished solve skips the whole launch (x is already complete); otherwise
+// returns the iteration k.
 template <typename T>
 __device__ inline bool cg_head(const ApplyIO<T>& io, int* iter) {
   *iter = io.sc->A.iter;
   return io.sc->A.done != 0;                // uniform over the grid
 }
 
-// cg_scalars: reads slot A, sums the update partials (r.z and r.r), decides
-// convergence, publishes slot B from block 0 and forms beta.
+// cg_scalars: reads slot A, sums the update partials (r.z and r.r, loads
+// already issued into ps), decides convergence, publishes slot B from block 0
+// and forms beta.
 template <typename T, int NT>
-__device__ inline void cg_scalars(const ApplyIO<T>& io, int it, double* s_red, T* beta,
-                                  bool* skip) {
+__device__ inline void cg_scalars(const ApplyIO<T>& io, int it, PartialSums<NT, 2>& ps,
+                                  const double* const* pp, T* beta, bool* skip) {
   const double rho_prev = io.sc->A.rho;
   const double rtol2 = io.sc->A.rtol2;
   const int maxit = io.sc->A.maxit;
   double rr_stop = io.sc->A.rr_stop;
-  const int k2 = it & 1;
-  double rho, rr;
-  sum_partials2<NT>(io.partials + (size_t)(2 + k2) * io.pmax,
-                    io.partials + (size_t)(4 + k2) * io.pmax, io.n_upd, s_red, &rho, &rr);
+  double sums[2];
+  ps.reduce(pp, io.n_upd, sums);
+  const double rho = sums[0], rr = sums[1];
   if (it == 0) rr_stop = rtol2 * rr;
   const double b = (it == 0) ? 0.0 : rho / rho_prev;
   int done = 0;
@@ -112,15 +113,16 @@ __device__ inline bool cgcg_head(const ApplyIO<T>& io, int* k) {
 }
 
 // cgcg_scalars: for k >= 1, sums the previous launch's partials of
-// delta = z.Az, gamma = r.z and r.r (all of iterate k - 1), tests
+// delta = z.Az, gamma = r.z and r.r (all of iterate k - 1; their loads were
+// issued into ps at the start of the launch), tests
 // convergence of x_{k-1}, and forms
 //   beta_{k-1} = gamma_{k-1} / gamma_{k-2}            (0 for k = 1)
 //   alpha_{k-1} = gamma_{k-1} / (delta_{k-1} - beta_{k-1} gamma_{k-1} / alpha_{k-2})
 // (alpha_0 = gamma_0 / delta_0).  Slot fields: rho = gamma of the previous
 // iterate, alpha = its alpha, iter = k.  *skip when the solve ends here.
 template <typename T, int NT>
-__device__ inline void cgcg_scalars(const ApplyIO<T>& io, int k, double* s_red, T* alpha, T* beta,
-                                    bool* skip) {
+__device__ inline void cgcg_scalars(const ApplyIO<T>& io, int k, PartialSums<NT, 3>& ps,
+                                    const double* const* pp, T* alpha, T* beta, bool* skip) {
   CgState* R = io.rd ? &io.sc->B : &io.sc->A;
   CgState* W = io.rd ? &io.sc->A : &io.sc->B;
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
@@ -138,11 +140,9 @@ __device__ inline void cgcg_scalars(const ApplyIO<T>& io, int k, double* s_red, 
     }
     return;
   }
-  const int ks = io.rd ^ 1;
-  double gam, rr;
-  sum_partials2<NT>(io.partials + (size_t)(2 + ks) * io.pmax,
-                    io.partials + (size_t)(4 + ks) * io.pmax, io.n_parts, s_red, &gam, &rr);
-  const double del = sum_partials<NT>(io.partials + (size_t)ks * io.pmax, io.n_parts, 1, 0, s_red);
+  double sums[3];
+  ps.reduce(pp, io.n_parts, sums);
+  const double del = sums[0], gam = sums[1], rr = sums[2];
   const double rr_stop = (k == 1) ? rtol2 * rr : R->rr_stop;
   int done = 0;
   double a = 0.0, b = 0.0;
@@ -200,6 +200,13 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
     const UnitLane L = unit_lane<NP, EPB>((int)threadIdx.x);
     UnitRegs<T> R0;
     unit_info<T, NP, EPB>(u, L, bid * units_per_block, R0);
+    // the previous launch's partials (slot rd ^ 1): delta, gamma, r.r
+    const int ks = io.rd ^ 1;
+    const double* pp[3] = {io.partials + (size_t)ks * io.pmax,
+                           io.partials + (size_t)(2 + ks) * io.pmax,
+                           io.partials + (size_t)(4 + ks) * io.pmax};
+    PartialSums<NT, 3> ps;
+    ps.issue(pp, io.n_parts);
     int k;
     if (cgcg_head(io, &k)) return;
     const bool first = k == 0;
@@ -221,7 +228,7 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
     cg2_loads<T, NP>(u, L, R0, C0);
     bool skip;
     T alpha, beta;
-    cgcg_scalars<T, NT>(io, k, s_red, &alpha, &beta, &skip);
+    cgcg_scalars<T, NT>(io, k, ps, pp, &alpha, &beta, &skip);
     if (skip) return;
     u.alpha = alpha;
     u.beta = beta;
@@ -230,13 +237,11 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
     for (int un = 1; un < units_per_block; ++un)
       apply_unit<T, NP, EPB, MODE>(u, tab, sm, bid * units_per_block + un, acc);
     // z.Az, r.z, r.r of this launch's iterate, one partial each per block
-    const double b0 = block_sum<NT>(acc[0], s_red);
-    const double b1 = block_sum<NT>(acc[1], s_red);
-    const double b2 = block_sum<NT>(acc[2], s_red);
+    block_sums<NT, 3>(acc);
     if (threadIdx.x == 0) {
-      io.partials[(size_t)io.rd * io.pmax + blockIdx.x] = b0;
-      io.partials[(size_t)(2 + io.rd) * io.pmax + blockIdx.x] = b1;
-      io.partials[(size_t)(4 + io.rd) * io.pmax + blockIdx.x] = b2;
+      io.partials[(size_t)io.rd * io.pmax + blockIdx.x] = acc[0];
+      io.partials[(size_t)(2 + io.rd) * io.pmax + blockIdx.x] = acc[1];
+      io.partials[(size_t)(4 + io.rd) * io.pmax + blockIdx.x] = acc[2];
     }
     return;
   } else {
@@ -248,10 +253,15 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
     u.p_in = (iter & 1) ? io.p0 : io.p1;     // iteration k reads p_{k-1}, writes p_k
     u.p_out = (iter & 1) ? io.p1 : io.p0;
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int k2 = iter & 1;
+    const double* pp[2] = {io.partials + (size_t)(2 + k2) * io.pmax,
+                           io.partials + (size_t)(4 + k2) * io.pmax};
+    PartialSums<NT, 2> ps;
+    ps.issue(pp, io.n_upd);
     auto scalars = [&]() -> bool {
       bool skip;
       T beta;
-      cg_scalars<T, NT>(io, iter, s_red, &beta, &skip);
+      cg_scalars<T, NT>(io, iter, ps, pp, &beta, &skip);
       u.beta = beta;
       return !skip;
     };

@@ -180,8 +180,8 @@ __device__ inline void unit_data(const UnitIO<T>& io, const UnitLane& L, UnitReg
 
 // Output stores.  The fused CG apply (MODE 1) writes its results with the
 // non-temporal hint: nothing reads them again in the same launch, and
-// measured on MI355X this is 5 to 30 % faster; the other modes measured
-// faster with plain stores.
+// measured on MI355X its CG iteration is 2 to 10 % faster for it; the other
+// kernels measured as fast or faster with plain stores.
 template <int MODE, typename T>
 __device__ inline void put(T* p, T v) {
   if constexpr (MODE == 1) __builtin_nontemporal_store(v, p);

@@ -463,8 +463,8 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
   c->n_elem = ne;
   // CG form before any autotuning: one kernel per iteration for meshes small
   // enough that launch latency dominates, else the two-kernel form (the
-  // measured crossover on MI355X is near n_elem n_p^2 = 2e5)
-  c->cg_variant = ne * (int64_t)(p + 1) * (p + 1) <= 200000 ? 0 : 1;
+  // measured crossover on MI355X lies between n_elem n_p^2 = 2.6e5 and 6.8e5)
+  c->cg_variant = ne * (int64_t)(p + 1) * (p + 1) <= 400000 ? 0 : 1;
   const int n1 = n_elem[0], n2 = n_elem[1], n3 = n_elem[2];
   const int64_t nf0 = (int64_t)(n1 - 1) * n2 * n3, nf1 = (int64_t)n1 * (n2 - 1) * n3,
                 nf2 = (int64_t)n1 * n2 * (n3 - 1);

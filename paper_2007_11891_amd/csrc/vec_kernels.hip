@@ -49,7 +49,7 @@ cg_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb, 
   const double rho = sc->B.rho;
   const T* __restrict__ p = (k & 1) ? p1 : p0;   // p_k, written by the apply of iteration k
   // kUnroll independent entries per thread, all loads issued before use; the
-  // first group's loads go out before the partial sums
+  // partials' loads and the first group's go out before the partial sums
   const int64_t stride = (int64_t)gridDim.x * kVecThreads;
   int64_t g0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
   T va[kUnroll], vb[kUnroll], vz[kUnroll], vd[kUnroll], vx[kUnroll], vp[kUnroll];
@@ -67,9 +67,12 @@ cg_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb, 
       }
     }
   };
+  const double* pp[1] = {partials + (size_t)(k & 1) * pmax};
+  PartialSums<kVecThreads, 1> ps;
+  ps.issue(pp, n_apply);
   if (g0 < n) load(g0);
-  const double pq = sum_partials<kVecThreads>(partials + (size_t)(k & 1) * pmax, n_apply, 1, 0,
-                                              s_red);
+  double pq;
+  ps.reduce(pp, n_apply, &pq);
   const double alpha = rho / pq;
   if (!(pq > 0.0) || !isfinite(alpha)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -87,8 +90,8 @@ cg_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb, 
       const int64_t g = g0 + u * stride;
       if (g < n) {
         const T zn = vz[u] - a * (vd[u] * (va[u] + vb[u]));
-        __builtin_nontemporal_store(zn, z + g);
-        __builtin_nontemporal_store(vx[u] + a * vp[u], x + g);
+        z[g] = zn;
+        x[g] = vx[u] + a * vp[u];
         const T rn = div_fast(zn, vd[u]);
         rz_t += zn * rn;
         rr_t += rn * rn;
@@ -96,12 +99,12 @@ cg_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb, 
     }
     if (g0 + kUnroll * stride < n) load(g0 + kUnroll * stride);
   }
-  const double brz = block_sum<kVecThreads>((double)rz_t, s_red);
-  const double brr = block_sum<kVecThreads>((double)rr_t, s_red);
+  double sums[2] = {(double)rz_t, (double)rr_t};
+  block_sums<kVecThreads, 2>(sums);
   const int k1 = (k + 1) & 1;
   if (threadIdx.x == 0) {
-    partials[(size_t)(2 + k1) * pmax + blockIdx.x] = brz;
-    partials[(size_t)(4 + k1) * pmax + blockIdx.x] = brr;
+    partials[(size_t)(2 + k1) * pmax + blockIdx.x] = sums[0];
+    partials[(size_t)(4 + k1) * pmax + blockIdx.x] = sums[1];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     // rho_k becomes the previous rho of iteration k+1
