@@ -103,6 +103,23 @@ def measured_traffic(kernel: str):
     return None if entry is None else entry.get("traffic_bytes")
 
 
+def cg_iteration_roofline(c, W, torch, dev, fp32: bool, reps: int = 50):
+    """Mean time of one CG iteration (HIP events, back-to-back launches) in
+    the CG form and tile shape the context uses, as an HBM roofline entry:
+    104 B per free DOF in FP64, 52 B in FP32."""
+    nf = c.sizes.n_free
+    one = c.tile_shape()["cg_variant"] == 0
+    which = (10 if fp32 else 9) if one else (3 if fp32 else 2)
+    x = torch.as_tensor(W.random_trace(nf, 7), device=dev)
+    if fp32:
+        x = x.float()
+    t = c.time_kernel(which, x, reps)
+    nbytes = (52 if fp32 else 104) * nf
+    gbs = nbytes / (t * 1e-3) / 1e9
+    return {"form": "one kernel" if one else "two kernels", "avg_us": round(t * 1e3, 3),
+            "bytes": nbytes, "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def bench_mixed(pkg, W, torch, dev, reps: int = 3):
     """FP32-inner / FP64-outer vs plain FP64, time to relative residual 1e-10
     on the 32^3 unit-cube mesh, p in {4, 8, 12}, lambda in {1e-2, 1, 1e2},
@@ -146,7 +163,9 @@ def bench_mixed(pkg, W, torch, dev, reps: int = 3):
                    "mixed_vs_fp64_trace_rel_diff":
                        float(torch.linalg.norm(trmx - tr64) / torch.linalg.norm(tr64)),
                    "fp64_nodal_error": float(torch.linalg.norm(uv64 - u_ex)) / nrm,
-                   "mixed_nodal_error": float(torch.linalg.norm(uvmx - u_ex)) / nrm}
+                   "mixed_nodal_error": float(torch.linalg.norm(uvmx - u_ex)) / nrm,
+                   "fp64_iteration": cg_iteration_roofline(c, W, torch, dev, False),
+                   "fp32_iteration": cg_iteration_roofline(c, W, torch, dev, True)}
             log(f"[bench] mixed 32^3 p={p} lam={lam:g}: fp64 {t64:.2f} ms ({i64['iters']} it), "
                 f"mixed {tmx:.2f} ms ({imx['iters']} inner, {imx['outer_iters']} outer), "
                 f"x{t64 / tmx:.2f}")
@@ -292,7 +311,8 @@ def bench_adjoint(pkg, W, torch, dev, reps: int = 3):
            "forward_ms": round(fw_ms, 3), "adjoint_ms": round(ad_ms, 3),
            "forward_iters": info["iters"], "adjoint_iters": ainfo["iters"],
            "gradients_per_s": 1e3 / ad_ms,
-           "adjoint_trace_dof_per_s": nf * ainfo["iters"] / (ad_ms * 1e-3)}
+           "adjoint_trace_dof_per_s": nf * ainfo["iters"] / (ad_ms * 1e-3),
+           "cg_iteration": cg_iteration_roofline(c, W, torch, dev, False)}
     c.close()
     return out
 

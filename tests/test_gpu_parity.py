@@ -309,3 +309,26 @@ def test_solver_variants_agree_at_full_size():
         out.append((to_host(tr), info["iters"]))
     assert abs(out[0][1] - out[1][1]) <= 2
     assert rel_err(out[0][0], out[1][0]) < 1e-8
+
+
+def test_many_block_partials_at_full_size():
+    """Perturbed 16^3, p = 7 with one element per work unit: 2048 blocks per
+    element kernel, so every CG kernel re-sums more partials than its block
+    has threads times four (the multi-chunk path of the fixed-order sums).
+    Both CG forms reach the true residual 1e-10 and agree with the default
+    tile shape's solution."""
+    import paper_2007_11891_amd as pkg
+    prob = W.perturbed(n=16, p=7, lam=10.0, seed=2)
+    c = gpu_ctx(prob.n, prob.widths, prob.p, prob.tau, prob.lam)
+    f = to_dev(prob.f_values)
+    ref, _, info0 = c.solve_forcing(f, c.zeros_trace(), want_volume=False,
+                                    opts=pkg.default_opts(rtol=1e-10, variant=0))
+    ref = to_host(ref)
+    c.set_tile(2)
+    for variant in (0, 1):
+        tr, _, info = c.solve_forcing(f, c.zeros_trace(), want_volume=False,
+                                      opts=pkg.default_opts(rtol=1e-10, variant=variant))
+        print(f"[many partials] variant {variant}: {info}", flush=True)
+        assert info["rel_res"] < 1.5e-10
+        assert abs(info["iters"] - info0["iters"]) <= 2
+        assert rel_err(to_host(tr), ref) < 1e-8
