@@ -15,6 +15,8 @@ Modules:
   element   - dense element system, K_e, F_e, recovery
   system    - global assembly, Dirichlet elimination, solve, adjoint
   fastdiag  - the paper's factorised operator, used only to pin its claims
+  pcg       - the paper's nodal-basis CG solvers (no, diagonal, block
+              preconditioner) by definition, for the solver comparison
 
 Every function is pinned by tests in ``tests/test_oracle_*.py`` against closed
 forms, invariants and exactness properties of the discretisation.
