@@ -90,16 +90,27 @@ typedef enum {
   HDG_TO_NODAL_RESIDUAL = 3
 } hdg_transform;
 
-/* Solver options.  The CG runs on K^_ff in the eigen-face basis with the
- * diagonal (Jacobi) preconditioner of K^ (the paper's HDG-trans solver,
- * section "Summary of solution method"); x0 = 0. */
+/* Solver options.  By default the CG runs on K^_ff in the eigen-face basis
+ * with the diagonal (Jacobi) preconditioner of K^ (the paper's HDG-trans
+ * solver, section "Summary of solution method"); x0 = 0.  precond 0, 2 and 3
+ * select the paper's other solvers of that section, which run the CG in the
+ * nodal trace basis with the operator applied through the face transforms
+ * (FP64 only, textbook form; `variant` and `mixed` do not apply):
+ *   0  HDG-unprec: no preconditioner;
+ *   2  HDG-diag: the main diagonal of the inverse face blocks of K_ff
+ *      (section "Preconditioners");
+ *   3  HDG-block: the inverse face blocks of K_ff (algorithm
+ *      "Block_Preconditioner"), applied as (S x S) diag(1/y) (S^T x S^T).
+ * For them rtol and rel_res refer to the nodal basis (||F||_2). */
 typedef struct {
   double rtol;        /* stop when ||r||_2 <= rtol ||F^||_2 (eigen basis)   */
   int maxit;          /* iteration cap (FP64 CG, or per inner FP32 solve)   */
-  int precond;        /* 0: none, 1: Jacobi                                  */
+  int precond;        /* 0: none, 1: Jacobi in the eigen basis (default),
+                         2: nodal diagonal, 3: nodal face blocks (above)   */
   int mixed;          /* 0: FP64 CG; 1: FP32 CG with FP64 residual replacement
                          (reliable updates: the FP32 CG keeps its search
-                         direction across replacements)                      */
+                         direction across replacements); precond 1 only,
+                         else HDG_EUNSUPPORTED                               */
   double inner_rtol;  /* mixed: residual reduction of each FP32 segment between
                          two FP64 residual replacements (values below 1e-4
                          are raised to 1e-4)                                 */

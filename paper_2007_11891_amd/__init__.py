@@ -10,4 +10,5 @@ from .hdg import (  # noqa: F401
     HdgBatch, HdgContext, HdgError, SolveOpts, default_opts, load_library, tables, LIB_PATH,
     EXPORTS,
     TO_EIGEN_UNKNOWN, TO_EIGEN_RESIDUAL, TO_NODAL_UNKNOWN, TO_NODAL_RESIDUAL,
+    PRECOND_NONE, PRECOND_EIGEN_JACOBI, PRECOND_NODAL_DIAG, PRECOND_NODAL_BLOCK,
 )

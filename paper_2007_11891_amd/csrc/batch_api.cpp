@@ -577,9 +577,10 @@ hdg_status hdg_batch_solve_forcing(hdg_batch* b, const double* f, double* trace_
   hdg_solve_opts o;
   hdg_default_opts(&o);
   if (opts) o = *opts;
-  if (!(o.rtol > 0.0) || o.maxit < 1 || o.check_every < 1 || (o.precond != 0 && o.precond != 1))
+  if (!(o.rtol > 0.0) || o.maxit < 1 || o.check_every < 1 || o.precond < 0 || o.precond > 3)
     return fail(HDG_EINVAL, "invalid solver options");
-  if (o.precond == 0) return fail(HDG_EUNSUPPORTED, "only the Jacobi preconditioner is built");
+  if (o.precond != 1)
+    return fail(HDG_EUNSUPPORTED, "the batched solver runs the transformed (precond 1) CG only");
   if (o.mixed) return fail(HDG_EUNSUPPORTED, "the batched solver runs in FP64 only");
   ST_TRY(upload_probs(b, o.rtol * o.rtol, o.maxit));
   // the apply that detects the stop also applies the last x update: one more pass

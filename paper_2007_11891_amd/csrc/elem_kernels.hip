@@ -192,6 +192,7 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
   u.qa = io.qa;
   u.qb = io.qb;
   if constexpr (MODE == 0) {
+    if (io.sc && io.sc->B.done) return;      // inside a finished nodal-basis CG
     u.x_free = io.x_free;
     u.x_bdry = io.x_bdry;
   } else if constexpr (MODE == 2) {
@@ -412,12 +413,13 @@ const ElemTab<float>& tab_of<float>(const hdg_ctx* c) { return c->et32; }
 
 template <typename T>
 hipError_t launch_elem_apply(const hdg_ctx* c, const T* x_free, const T* x_bdry, T* qa, T* qb,
-                             hipStream_t s) {
+                             hipStream_t s, CgScalars* skip_if_done) {
   ApplyIO<T> io{};
   io.x_free = x_free;
   io.x_bdry = x_bdry;
   io.qa = qa;
   io.qb = qb;
+  io.sc = skip_if_done;
   return launch_apply_dispatch<T, 0>(c, tab_of<T>(c), io, s);
 }
 
@@ -463,9 +465,9 @@ hipError_t launch_cgcg_iter(const hdg_ctx* c, CgWork<T>& w, int rd, hipStream_t 
 template hipError_t launch_cgcg_iter<double>(const hdg_ctx*, CgWork<double>&, int, hipStream_t);
 template hipError_t launch_cgcg_iter<float>(const hdg_ctx*, CgWork<float>&, int, hipStream_t);
 template hipError_t launch_elem_apply<double>(const hdg_ctx*, const double*, const double*,
-                                              double*, double*, hipStream_t);
+                                              double*, double*, hipStream_t, CgScalars*);
 template hipError_t launch_elem_apply<float>(const hdg_ctx*, const float*, const float*, float*,
-                                             float*, hipStream_t);
+                                             float*, hipStream_t, CgScalars*);
 template hipError_t launch_cg_apply<double>(const hdg_ctx*, CgWork<double>&, hipStream_t);
 template hipError_t launch_cg_apply<float>(const hdg_ctx*, CgWork<float>&, hipStream_t);
 

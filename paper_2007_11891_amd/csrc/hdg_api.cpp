@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -70,7 +71,7 @@ hdg_status alloc_work(hdg_ctx* c, CgWork<T>& w) {
   w.zz[0] = w.z;
   w.qq[0][0] = w.qa;
   w.qq[0][1] = w.qb;
-  w.pmax = std::max(max_apply, w.update_blocks);
+  w.pmax = std::max({max_apply, w.update_blocks, ncg_face_blocks(c->np, c->n_free_faces)});
   ST_TRY(dalloc(&w.partials, 6 * (int64_t)w.pmax));
   ST_TRY(dalloc(&w.sc, 1));
   HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(CgScalars), c->stream));
@@ -111,7 +112,8 @@ float* dinv_of<float>(hdg_ctx* c) { return c->d_dinv32; }
 
 // Capture `iters` CG iterations into a graph: variant 0 one launch per
 // iteration (state slot parity alternating, iters even), variant 1 the fused
-// apply + update pair.
+// apply + update pair, variant 10 + pc the nodal-basis CG with
+// preconditioner pc (FP64).
 template <typename T>
 hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters, int variant) {
   if (w.graph && w.graph_iters == iters && w.graph_variant == variant) return HDG_OK;
@@ -123,7 +125,12 @@ hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters, int variant) {
   HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
   hipError_t err = hipSuccess;
   for (int it = 0; it < iters && err == hipSuccess; ++it) {
-    if (variant == 0) {
+    if (variant >= 10) {
+      if constexpr (std::is_same<T, double>::value)
+        err = launch_ncg_iter(c, w, variant - 10, c->cap_stream);
+      else
+        err = hipErrorInvalidValue;
+    } else if (variant == 0) {
       err = launch_cgcg_iter<T>(c, w, it & 1, c->cap_stream);
     } else {
       err = launch_cg_apply<T>(c, w, c->cap_stream);
@@ -226,12 +233,13 @@ int cg_variant_of(const hdg_ctx* c, const hdg_solve_opts* o) {
 }
 
 hdg_status validate_opts(const hdg_solve_opts* o) {
-  if (!(o->rtol > 0.0) || o->maxit < 1 || (o->precond != 0 && o->precond != 1) ||
+  if (!(o->rtol > 0.0) || o->maxit < 1 || o->precond < 0 || o->precond > 3 ||
       (o->variant < -1 || o->variant > 1) ||
       (o->mixed != 0 && o->mixed != 1) || o->check_every < 1 ||
       (o->mixed && (!(o->inner_rtol > 0.0) || o->inner_rtol >= 1.0 || o->max_outer < 1)))
     return fail(HDG_EINVAL, "invalid solver options");
-  if (o->precond == 0) return fail(HDG_EUNSUPPORTED, "only the Jacobi preconditioner is built");
+  if (o->mixed && o->precond != 1)
+    return fail(HDG_EUNSUPPORTED, "mixed precision runs the transformed (precond 1) solver only");
   return HDG_OK;
 }
 
@@ -362,7 +370,8 @@ hdg_status eigen_boundary(hdg_ctx* c, const double* trace, const double** out) {
 }
 
 const double* mat64(const hdg_ctx* c, int kind) {
-  // storage order: St, StM, S, MS
+  // storage order: St, StM, S, MS, then S o S (entrywise square, used for the
+  // diagonal of the nodal block preconditioner)
   const int npf = c->np * c->np;
   switch (kind) {
     case HDG_TO_EIGEN_UNKNOWN: return c->d_mats64 + npf;      // S^T M
@@ -379,6 +388,88 @@ const float* mat32(const hdg_ctx* c, int kind) {
     case HDG_TO_NODAL_UNKNOWN: return c->d_mats32 + 2 * npf;
     default: return c->d_mats32 + 3 * npf;
   }
+}
+
+// Nodal-basis CG of the paper's solver comparison (HDG-unprec, HDG-diag,
+// HDG-block): solves K_ff x = F in the nodal trace basis with the
+// preconditioner pc (0 none, 2 diagonal of the inverse face blocks, 3 the
+// inverse face blocks); F and x_out are nodal, FP64, free length.  The
+// reported residual is ||F - K x|| / ||F|| recomputed in FP64.
+hdg_status solve_nodal(hdg_ctx* c, const double* F, double* x_out, const hdg_solve_opts* o,
+                       hdg_solve_info* info) {
+  hdg_solve_info inf{};
+  auto t0 = std::chrono::steady_clock::now();
+  ST_TRY(alloc_work(c, c->w64));
+  CgWork<double>& w = c->w64;
+  w.dinv = dinv_of<double>(c);
+  const int pc = o->precond;
+  double bb = 0.0;
+  ST_TRY(norm2_64(c, F, &bb));
+  inf.rhs_norm = std::sqrt(bb);
+  hdg_status result = HDG_OK;
+  const int npf = c->np * c->np;
+  if (bb == 0.0) {
+    HIP_TRY(launch_fill64(x_out, 0.0, c->n_free, c->stream));
+  } else {
+    if (pc == 2)   // d = ((S o S) x (S o S)) (1 / y) per face
+      HIP_TRY(launch_face_transform<double>(c->np, c->d_mats64 + 4 * npf, w.dinv, nullptr,
+                                            w.zz[1], c->n_free_faces, c->stream));
+    CgScalars* hs = c->h_scal;
+    HIP_TRY(hipStreamSynchronize(c->stream));   // the upload slot is reused below
+    hs[2] = CgScalars{};
+    hs[2].A.rtol2 = o->rtol * o->rtol;
+    hs[2].A.maxit = std::max(1, o->maxit);
+    hs[2].A.rho = 1.0;
+    HIP_TRY(hipMemcpyAsync(w.sc, &hs[2], sizeof(CgScalars), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(launch_ncg_init(c, w, pc, F, c->stream));
+    int it = 0, done = 0;
+    ST_TRY(cg_drive<double>(c, w, std::max(1, o->maxit), o->check_every, 10 + pc, &it, &done));
+    inf.iters = it;
+    HIP_TRY(hipMemcpyAsync(x_out, w.x, sizeof(double) * c->n_free, hipMemcpyDeviceToDevice,
+                           c->stream));
+    if (done == 2) result = HDG_ENOCONV;
+    // FP64 residual in the nodal basis: F - (M S x M S)(qa + qb) of K^ (S^T M x S^T M) x
+    double* xe = w.p[1];
+    HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_EIGEN_UNKNOWN), x_out, nullptr,
+                                          xe, c->n_free_faces, c->stream));
+    HIP_TRY(launch_elem_apply<double>(c, xe, nullptr, w.qa, w.qb, c->stream));
+    HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_NODAL_RESIDUAL), w.qa, nullptr,
+                                          w.s[0], c->n_free_faces, c->stream));
+    HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_NODAL_RESIDUAL), w.qb, nullptr,
+                                          w.s[1], c->n_free_faces, c->stream));
+    HIP_TRY(launch_residual64(F, w.s[0], w.s[1], w.qq[1][0], c->n_free, w.partials, c->d_red,
+                              w.update_blocks, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->h_red, c->d_red, sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    inf.rel_res = std::sqrt(*c->h_red) / inf.rhs_norm;
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  inf.t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  if (result == HDG_ENOCONV)
+    return fail(HDG_ENOCONV, "solver stopped after %d iterations at relative residual %.3e",
+                inf.iters, inf.rel_res);
+  return result;
+}
+
+// K^_ff x^ = b^ (eigen basis in and out) with the solver the options name:
+// the transformed CG (precond 1), or a nodal-basis CG on F = (M S x M S) b^
+// whose nodal solution is mapped back, x^ = (S^T M x S^T M) x.  b^ and x^
+// must not alias the FP64 CG workspace, d_tmp[2] or d_tmp[3].
+hdg_status solve_any(hdg_ctx* c, const double* bhat, double* xhat, const hdg_solve_opts* o,
+                     hdg_solve_info* info) {
+  if (o->precond == 1) return solve_eigen(c, bhat, xhat, o, info);
+  double* F = c->d_tmp[2];
+  HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_NODAL_RESIDUAL), bhat, nullptr, F,
+                                        c->n_free_faces, c->stream));
+  ST_TRY(alloc_work(c, c->w64));
+  double* xn = c->w64.qq[1][1];   // not used by the nodal CG or its residual
+  hdg_status st = solve_nodal(c, F, xn, o, info);
+  if (st != HDG_OK && st != HDG_ENOCONV) return st;
+  HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_EIGEN_UNKNOWN), xn, nullptr, xhat,
+                                        c->n_free_faces, c->stream));
+  return st;
 }
 
 hdg_status upload_lambda_and_diag(hdg_ctx* c) {
@@ -501,8 +592,8 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
   }
   if ((st = dalloc(&c->d_lam, ne)) != HDG_OK) return cleanup(st);
   if ((st = dalloc(&c->d_info, ne)) != HDG_OK) return cleanup(st);
-  if ((st = dalloc(&c->d_mats64, 4 * npf)) != HDG_OK) return cleanup(st);
-  if ((st = dalloc(&c->d_mats32, 4 * npf)) != HDG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_mats64, 5 * npf)) != HDG_OK) return cleanup(st);
+  if ((st = dalloc(&c->d_mats32, 5 * npf)) != HDG_OK) return cleanup(st);
   if ((st = dalloc(&c->d_diag, c->n_free)) != HDG_OK) return cleanup(st);
   if ((st = dalloc(&c->d_dinv32, c->n_free)) != HDG_OK) return cleanup(st);
   for (int t = 0; t < 4; ++t)
@@ -517,11 +608,12 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
                     hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(HDG_ENOMEM, "pinned host allocation failed"));
 
-  std::vector<double> mats(4 * npf);
+  std::vector<double> mats(5 * npf);
   std::copy(c->tab.St.begin(), c->tab.St.end(), mats.begin());
   std::copy(c->tab.StM.begin(), c->tab.StM.end(), mats.begin() + npf);
   std::copy(c->tab.S.begin(), c->tab.S.end(), mats.begin() + 2 * npf);
   std::copy(c->tab.MS.begin(), c->tab.MS.end(), mats.begin() + 3 * npf);
+  for (int i = 0; i < npf; ++i) mats[4 * npf + i] = c->tab.S[i] * c->tab.S[i];   // S o S
   std::vector<float> mats32(mats.begin(), mats.end());
 
   auto h2d = [&](void* dst, const void* src, size_t bytes) -> hdg_status {
@@ -803,7 +895,7 @@ hdg_status hdg_solve(hdg_ctx* c, const double* F_free, double* u_free, const hdg
                                         bhat, c->n_free_faces, c->stream));
   double* xhat = c->d_tmp[1];
   if (o.mixed) xhat = u_free;   // d_tmp[1] holds the FP32 right-hand side in mixed mode
-  hdg_status st = solve_eigen(c, bhat, xhat, &o, info);
+  hdg_status st = solve_any(c, bhat, xhat, &o, info);
   if (st != HDG_OK && st != HDG_ENOCONV) return st;
   HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_NODAL_UNKNOWN), xhat, nullptr,
                                         u_free, c->n_free_faces, c->stream));
@@ -828,7 +920,7 @@ hdg_status hdg_solve_forcing(hdg_ctx* c, const double* f, double* trace, double*
     HIP_TRY(launch_volume(c, VOL_RHS, 1, f, nullptr, xb, nullptr, nullptr, w.qa, w.qb, nullptr,
                           nullptr, c->stream));
     HIP_TRY(launch_combine<double>(w.qa, w.qb, bhat, c->n_free, c->stream));
-    st = solve_eigen(c, bhat, xhat, &o, info);
+    st = solve_any(c, bhat, xhat, &o, info);
     if (st != HDG_OK && st != HDG_ENOCONV) return st;
   } else if (info) {
     *info = hdg_solve_info{};
@@ -893,7 +985,7 @@ hdg_status hdg_adjoint(hdg_ctx* c, const double* f, const double* trace, const d
       dfree(muhat);
       return fail(HDG_EHIP, "adjoint rhs failed: %s", hipGetErrorString(e));
     }
-    st = solve_eigen(c, jhat, muhat, &o, info);
+    st = solve_any(c, jhat, muhat, &o, info);
     if (st != HDG_OK && st != HDG_ENOCONV) {
       dfree(jhat);
       dfree(muhat);

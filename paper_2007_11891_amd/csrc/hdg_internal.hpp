@@ -143,10 +143,11 @@ struct hdg_ctx {
 namespace hdg {
 
 // ---- kernel launchers (defined in the .hip translation units) -------------
-// element apply in the eigen basis, output split into qa/qb.
+// element apply in the eigen basis, output split into qa/qb; with a CG
+// state, nothing is done once its slot B reports a finished solve.
 template <typename T>
 hipError_t launch_elem_apply(const hdg_ctx* c, const T* x_free, const T* x_bdry,
-                             T* qa, T* qb, hipStream_t s);
+                             T* qa, T* qb, hipStream_t s, CgScalars* skip_if_done = nullptr);
 // fused CG apply (see kernels_cg.hip)
 template <typename T>
 hipError_t launch_cg_apply(const hdg_ctx* c, CgWork<T>& w, hipStream_t s);
@@ -163,6 +164,12 @@ template <typename T>
 hipError_t launch_cgcg_init(const hdg_ctx* c, CgWork<T>& w, const T* b, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_init(const hdg_ctx* c, CgWork<T>& w, const T* b, hipStream_t s);
+// nodal-basis CG (precond 0 none, 2 diagonal, 3 block; see nodal_cg.hip):
+// its start from the right-hand side b and one iteration
+hipError_t launch_ncg_init(const hdg_ctx* c, CgWork<double>& w, int precond, const double* b,
+                           hipStream_t s);
+hipError_t launch_ncg_iter(const hdg_ctx* c, CgWork<double>& w, int precond, hipStream_t s);
+int ncg_face_blocks(int np, int64_t n_faces);
 
 // y = qa + qb (optionally scaled); or y = b - (qa + qb) with the squared norm
 // reduced into red[0] (FP64)

@@ -130,6 +130,13 @@ def _check(status: int, allow_noconv: bool = False):
     raise HdgError(status, msg.decode() if msg else "")
 
 
+# SolveOpts.precond: the paper's solvers (section "Summary of solution method")
+PRECOND_NONE = 0          # HDG-unprec, nodal basis
+PRECOND_EIGEN_JACOBI = 1  # HDG-trans, eigen-face basis (default)
+PRECOND_NODAL_DIAG = 2    # HDG-diag, nodal basis
+PRECOND_NODAL_BLOCK = 3   # HDG-block, nodal basis
+
+
 def default_opts(**kw) -> SolveOpts:
     o = SolveOpts()
     load_library().hdg_default_opts(ctypes.byref(o))
@@ -290,7 +297,8 @@ class HdgContext:
                                  EIGEN if basis == "eigen" else NODAL))
         return out
 
-    def solve(self, F_free, opts: Optional[SolveOpts] = None, u_free=None):
+    def solve(self, F_free, opts: Optional[SolveOpts] = None, u_free=None,
+              allow_noconv: bool = False):
         torch = _torch()
         if u_free is None:
             u_free = self._empty(self.sizes.n_free)
@@ -299,7 +307,7 @@ class HdgContext:
         st = self._lib.hdg_solve(self._h, _dptr(F_free, self.sizes.n_free, torch.float64, "F"),
                                  _dptr(u_free, self.sizes.n_free, torch.float64, "u"),
                                  ctypes.byref(o), ctypes.byref(info))
-        _check(st)
+        _check(st, allow_noconv=allow_noconv)
         return u_free, info.as_dict()
 
     def solve_forcing(self, f, trace, u_vol=None, want_volume: bool = True,
