@@ -179,11 +179,22 @@ def bench_mixed(pkg, W, torch, dev, reps: int = 3):
             "geomean_speedup": round(float(np.exp(np.mean(np.log(sp)))), 3), "cases": rows}
 
 
+# The paper's four HDG solvers (section "Summary of solution method"):
+# precond code of hdg_solve_opts, timing id of one iteration, algorithmic
+# bytes per free DOF and iteration.  HDG-trans: the CG form in use (one-kernel
+# 104 B, two-kernel 104 B).  Nodal solvers: p and z in, p and p^ out (32 B),
+# element apply (24 B), q = (M S x M S)(qa + qb) with p.q (32 B), update
+# (unprec 56, diag 64, block 48 B) and for HDG-block z = P^-1 r (24 B).
+PAPER_SOLVERS = (("trans", 1, None, 104), ("unprec", 0, 13, 144), ("diag", 2, 14, 152),
+                 ("block", 3, 15, 160))
+
+
 def bench_paper_case(pkg, W, torch, dev, reps: int = 3):
     """The paper's solver test: (0, 2 pi)^3, 8^3 elements, Poisson, tau_e = 25,
-    five-factor k = 5 manufactured solution, stop at 1e-10: iterations, time
-    per solve (RHS + CG + recovery) and time per degree of freedom
-    n_e (p + 1)^3, the paper's unit."""
+    five-factor k = 5 manufactured solution, stop at 1e-10, for the paper's
+    four HDG solvers: iterations, time per solve (RHS + CG + recovery), time
+    per degree of freedom n_e (p + 1)^3 (the paper's unit) and the time and
+    roofline fraction of one iteration."""
     rows = []
     for p in (2, 4, 6, 8, 10, 12, 14, 16):
         pr = W.paper_case(p)
@@ -195,28 +206,43 @@ def bench_paper_case(pkg, W, torch, dev, reps: int = 3):
         g = torch.as_tensor(W.u_paper(*tx.T), device=dev)
         u_ex = torch.as_tensor(W.u_paper(*vx.T), device=dev)
         nf = c.sizes.n_free
-        o = pkg.default_opts(rtol=1e-10)
-        ts = []
-        for _ in range(reps + 1):
-            tr = g.clone()
-            tr[:nf] = 0
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            _, uv, info = c.solve_forcing(f, tr, opts=o)
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t)
-        t = statistics.median(ts[1:])
         ndof = pr.n_elem * (p + 1) ** 3
-        rows.append({"p": p, "iters": info["iters"], "solve_ms": round(1e3 * t, 3),
-                     "us_per_dof": 1e6 * t / ndof, "ns_per_dof_per_iter": 1e9 * t / ndof / info["iters"],
-                     "max_error": float(torch.max(torch.abs(uv - u_ex))), "n_trace_free": nf})
-        log(f"[bench] paper case p={p}: {info['iters']} it, {1e3 * t:.2f} ms, "
-            f"{1e6 * t / ndof:.4f} us/DOF, max error {rows[-1]['max_error']:.2e}")
+        row = {"p": p, "n_trace_free": nf}
+        xr = torch.as_tensor(W.random_trace(nf, 3), device=dev)
+        for name, pc, tid, bpd in PAPER_SOLVERS:
+            o = pkg.default_opts(rtol=1e-10, precond=pc)
+            ts = []
+            for _ in range(reps + 1):
+                tr = g.clone()
+                tr[:nf] = 0
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, uv, info = c.solve_forcing(f, tr, opts=o)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            t = statistics.median(ts[1:])
+            if tid is None:
+                tid = 9 if c.tile_shape()["cg_variant"] == 0 else 2
+            t_it = c.time_kernel(tid, xr, 50)
+            gbs = bpd * nf / (t_it * 1e-3) / 1e9
+            row[name] = {"iters": info["iters"], "solve_ms": round(1e3 * t, 3),
+                         "us_per_dof": 1e6 * t / ndof,
+                         "ns_per_dof_per_iter": 1e9 * t / ndof / max(info["iters"], 1),
+                         "iteration_us": round(t_it * 1e3, 3), "iteration_bytes": bpd * nf,
+                         "iteration_frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "max_error": float(torch.max(torch.abs(uv - u_ex)))}
+        rows.append(row)
+        log(f"[bench] paper case p={p}: " + ", ".join(
+            f"{nm} {row[nm]['iters']} it {row[nm]['solve_ms']:.2f} ms" for nm, *_ in PAPER_SOLVERS)
+            + f"; trans {row['trans']['us_per_dof']:.4f} us/DOF, max error "
+            f"{row['trans']['max_error']:.2e}")
         c.close()
     return {"workload": "(0, 2 pi)^3, 8^3 uniform elements, lambda = 0, tau_e = 25, u = five-factor k = 5 "
-                        "solution (paper's test case), rel. residual 1e-10",
-            "paper_reference": "about 1 us per degree of freedom for the transformed HDG solver on one "
-                               "Xeon E5-2680 v3 core (p >= 8), about 100 iterations",
+                        "solution (paper's test case), rel. residual 1e-10; solvers HDG-trans "
+                        "(eigen basis, Jacobi), HDG-unprec, HDG-diag, HDG-block (nodal basis)",
+            "paper_reference": "about 1 us per degree of freedom for the transformed HDG solver and "
+                               "about 2.5 us for HDG-block on one Xeon E5-2680 v3 core (p >= 8); "
+                               "about 100 iterations for HDG-block and HDG-trans",
             "cases": rows}
 
 
@@ -363,7 +389,8 @@ def main():
         x64 = torch.as_tensor(W.random_trace(nf, 1), device=dev)
         y64 = torch.empty_like(x64)
         for which, name in ((0, "apply64"), (1, "apply32"), (4, "cg_apply64"),
-                            (5, "cg_update64"), (9, "cg_onekernel64"), (8, "copy64")):
+                            (5, "cg_update64"), (9, "cg_onekernel64"), (8, "copy64"),
+                            (13, "nodal_unprec64"), (14, "nodal_diag64"), (15, "nodal_block64")):
             xin = x64.float() if which == 1 else x64
             ms = ctx.time_kernel(which, xin, args.reps, y=y64 if which == 8 else None)
             log(f"[bench] {name} {ms * 1e3:.3f} us")
@@ -451,6 +478,16 @@ def main():
                 "iteration": {"kernels": it_kernels, "bytes": one_bytes,
                               "avg_us": round(it_us * 1e3, 3), "achieved": round(it_gbs, 1),
                               "frac": round(it_gbs / HBM_PEAK_GBS, 4)}}
+    # the paper's nodal-basis solvers at the same size: one CG iteration each
+    nodal_iteration = {}
+    for name, pc, tid, bpd in PAPER_SOLVERS[1:]:
+        t_it = ctx.time_kernel(tid, x64, reps)
+        gbs = bpd * nf / (t_it * 1e-3) / 1e9
+        nodal_iteration[name] = {"avg_us": round(t_it * 1e3, 3), "bytes": bpd * nf,
+                                 "achieved_GBs": round(gbs, 1),
+                                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    log("[bench] nodal-basis CG iteration: " + ", ".join(
+        f"{k} {v['avg_us']:.2f} us ({v['frac']:.3f})" for k, v in nodal_iteration.items()))
     apply_bytes = 16 * nf
     apply_only = {"trace_dof_per_s_fp64": nf / (t_apply64 * 1e-3),
                   "trace_dof_per_s_fp32": nf / (t_apply32 * 1e-3),
@@ -484,6 +521,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "apply_only": apply_only,
+        "nodal_solver_iteration": nodal_iteration,
         "cg_iteration_us": {"two_kernel_fp64": round(t_cg_iter * 1e3, 3),
                             "two_kernel_fp32": round(t_cg_iter32 * 1e3, 3),
                             "fused_apply_fp64": round(t_cg_apply * 1e3, 3),

@@ -281,7 +281,9 @@ hdg_status hdg_diagonal(hdg_ctx* ctx, double* diag_free);
  * apply / update alone, 6 / 7 = the same in FP32, 8 = plain FP64 copy
  * x -> y (reference traffic), 9 / 10 = one-kernel CG iteration (solver
  * variant 0) in FP64 / FP32, 11 / 12 = the same replayed from a captured
- * graph of reps (rounded up to even) launches, as the solver runs them.
+ * graph of reps (rounded up to even) launches, as the solver runs them,
+ * 13 / 14 / 15 = one iteration of the nodal-basis CG with precond 0 / 2 / 3
+ * (HDG-unprec / HDG-diag / HDG-block, FP64, x as the right-hand side).
  * x, y device buffers of n_free values of the matching type (x read; y
  * written only by 8).  Synchronises. */
 hdg_status hdg_time_kernel(hdg_ctx* ctx, int which, const void* x, void* y,

@@ -1076,7 +1076,7 @@ hdg_status hdg_diagonal(hdg_ctx* c, double* diag_free) {
 
 hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int reps, double* ms) {
   if (!c || !x || !ms || reps < 1) return fail(HDG_EINVAL, "invalid argument");
-  if (which < 0 || which > 12) return fail(HDG_EINVAL, "unknown kernel id %d", which);
+  if (which < 0 || which > 15) return fail(HDG_EINVAL, "unknown kernel id %d", which);
   if (which == 8 && (!y || y == x)) return fail(HDG_EINVAL, "copy needs a distinct y");
   if (c->n_free == 0) {
     *ms = 0.0;
@@ -1087,6 +1087,9 @@ hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int re
   if (in_graph) which -= 2;
   const bool f32 = (which == 1 || which == 3 || which == 6 || which == 7 || which == 10);
   const bool one_kernel = (which == 9 || which == 10);
+  // 13 / 14 / 15: one iteration of the nodal-basis CG with preconditioner 0 / 2 / 3
+  const bool nodal = (which >= 13 && which <= 15);
+  const int npc = which == 13 ? 0 : (which == 14 ? 2 : 3);
   if (f32) ST_TRY(alloc_work(c, c->w32));
   // CG-state kernels need an initialised run that never finishes
   if (which >= 2) {
@@ -1106,14 +1109,22 @@ hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int re
     } else {
       c->w64.dinv = c->d_tmp[3];
       HIP_TRY(hipMemcpyAsync(c->w64.sc, &init, sizeof(init), hipMemcpyHostToDevice, c->stream));
-      if (one_kernel)
+      if (nodal) {
+        if (npc == 2)
+          HIP_TRY(launch_face_transform<double>(c->np, c->d_mats64 + 4 * c->np * c->np,
+                                                c->w64.dinv, nullptr, c->w64.zz[1],
+                                                c->n_free_faces, c->stream));
+        HIP_TRY(launch_ncg_init(c, c->w64, npc, static_cast<const double*>(x), c->stream));
+      } else if (one_kernel)
         HIP_TRY(launch_cgcg_init<double>(c, c->w64, static_cast<const double*>(x), c->stream));
       else
         HIP_TRY(launch_cg_init<double>(c, c->w64, static_cast<const double*>(x), c->stream));
     }
     // prime the state: the first launch (one-kernel CG), or one apply so that
     // an update has a p.q to consume
-    if (one_kernel) {
+    if (nodal) {
+      // the nodal iteration needs no priming
+    } else if (one_kernel) {
       if (f32) HIP_TRY(launch_cgcg_iter<float>(c, c->w32, 0, c->stream));
       else HIP_TRY(launch_cgcg_iter<double>(c, c->w64, 0, c->stream));
     } else {
@@ -1151,6 +1162,9 @@ hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int re
         parity ^= 1;
         return launch_cgcg_iter<float>(c, c->w32, rd, ls);
       }
+      case 13:
+      case 14:
+      case 15: return launch_ncg_iter(c, c->w64, npc, ls);
       default: return launch_copy64(static_cast<const double*>(x), static_cast<double*>(y),
                                     c->n_free, ls);
     }

@@ -104,3 +104,18 @@ def test_nodal_solvers_on_the_paper_case():
         its[pc] = info["iters"]
     assert abs(its[3] - its[1]) <= 0.1 * its[1]
     assert its[3] < its[2] <= its[0] + 2
+
+
+def test_nodal_iteration_timing_ids():
+    """hdg_time_kernel 13 / 14 / 15 run one nodal-basis CG iteration each
+    (the bench's per-iteration figures) and leave the context usable."""
+    import paper_2007_11891_amd as pkg
+    o, c = _pair((3, 3, 3), 4)
+    nf = c.sizes.n_free
+    x = to_dev(W.random_trace(nf, 5))
+    for which in (13, 14, 15):
+        assert c.time_kernel(which, x, 5) > 0.0
+    F = W.random_trace(nf, 6)
+    K = o.assemble_K()[:nf, :nf].toarray()
+    u, info = c.solve(to_dev(F), opts=pkg.default_opts(precond=3, rtol=1e-12))
+    assert rel_err(to_host(u), np.linalg.solve(K, F)) < 1e-9
