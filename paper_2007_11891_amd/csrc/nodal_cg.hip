@@ -62,24 +62,39 @@ struct NcgArgs {
   CgScalars* sc;
 };
 
+// The two rows of a 1D matrix A (n_p x n_p, row-major) a thread needs for
+// (A x A) on its face node (qa, qb) = (lt % n_p, lt / n_p).
+template <int NP>
+struct Rows {
+  double a[NP], b[NP];
+  __device__ inline void load(const double* __restrict__ A, int lt, bool active) {
+    const int qa = active ? lt % NP : 0, qb = active ? lt / NP : 0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      a[k] = A[qa * NP + k];
+      b[k] = A[qb * NP + k];
+    }
+  }
+};
+
 // (A x A) applied to the face held in s_in (n_p x n_p, lower index fastest):
 // t[a, c] = sum_b A[a, b] in[b, c], then out[a, c] = sum_d A[c, d] t[a, d].
 // Every thread of the block calls it (two barriers).
 template <int NP>
-__device__ inline double face_tt(const double* __restrict__ A, const double* s_in, double* s_t,
-                                 int lt, bool active) {
+__device__ inline double face_tt(const Rows<NP>& A, const double* s_in, double* s_t, int lt,
+                                 bool active) {
   const int qa = lt % NP, qb = lt / NP;
   if (active) {
     double acc = 0.0;
 #pragma unroll
-    for (int b = 0; b < NP; ++b) acc += A[qa * NP + b] * s_in[b + NP * qb];
+    for (int b = 0; b < NP; ++b) acc += A.a[b] * s_in[b + NP * qb];
     s_t[lt] = acc;
   }
   __syncthreads();
   double out = 0.0;
   if (active) {
 #pragma unroll
-    for (int d = 0; d < NP; ++d) out += A[qb * NP + d] * s_t[qa + NP * d];
+    for (int d = 0; d < NP; ++d) out += A.b[d] * s_t[qa + NP * d];
   }
   __syncthreads();
   return out;
@@ -97,12 +112,28 @@ __global__ void __launch_bounds__(NcgFace<NP>::NT) ncg_in_kernel(NcgArgs a) {
   if (a.sc->A.done) return;                  // uniform over the grid
   const int it = a.sc->A.iter;
   const int k2 = it & 1;
+  // issued together: the partials, the first face group's z and p, A's rows
   const int n_rz = a.precond == 3 ? a.n_face_blocks : a.n_vec_blocks;
   const double* prz[1] = {a.partials + (size_t)(2 + k2) * a.pmax};
   const double* prr[1] = {a.partials + (size_t)(4 + k2) * a.pmax};
   PartialSums<NT, 1> srz, srr;
   srz.issue(prz, n_rz);
   srr.issue(prr, a.n_vec_blocks);
+  const int slot = threadIdx.x / NF;
+  const int lt = threadIdx.x - slot * NF;
+  const int sl = slot < FPB ? slot : 0;
+  const int64_t groups = (a.n_faces + FPB - 1) / FPB;
+  int64_t g = blockIdx.x;
+  double zv = 0.0, pv = 0.0;
+  {
+    const int64_t f = g * FPB + slot;
+    if (g < groups && slot < FPB && f < a.n_faces) {
+      zv = a.z[f * NF + lt];
+      pv = a.p[f * NF + lt];
+    }
+  }
+  Rows<NP> A;
+  A.load(a.m_in, lt, slot < FPB);
   const double rho_prev = a.sc->A.rho;
   const double rtol2 = a.sc->A.rtol2;
   const int maxit = a.sc->A.maxit;
@@ -126,21 +157,21 @@ __global__ void __launch_bounds__(NcgFace<NP>::NT) ncg_in_kernel(NcgArgs a) {
     a.sc->B.done = done;
   }
   if (done) return;
-  const int slot = threadIdx.x / NF;
-  const int lt = threadIdx.x - slot * NF;
-  const int64_t groups = (a.n_faces + FPB - 1) / FPB;
-  for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+  for (; g < groups; g += gridDim.x) {
     const int64_t f = g * FPB + slot;
     const bool active = slot < FPB && f < a.n_faces;
     const int64_t i = f * NF + lt;
+    if (g != (int64_t)blockIdx.x && active) {   // later groups: load here
+      zv = a.z[i];
+      pv = a.p[i];
+    }
     if (active) {
-      const double v = a.z[i] + beta * a.p[i];
+      const double v = zv + beta * pv;
       a.p[i] = v;
       s_in[slot][lt] = v;
     }
     __syncthreads();
-    const double o = face_tt<NP>(a.m_in, s_in[slot < FPB ? slot : 0],
-                                 s_t[slot < FPB ? slot : 0], lt, active);
+    const double o = face_tt<NP>(A, s_in[sl], s_t[sl], lt, active);
     if (active) a.phat[i] = o;
   }
 }
@@ -157,6 +188,8 @@ __global__ void __launch_bounds__(NcgFace<NP>::NT) ncg_out_kernel(NcgArgs a) {
   const int slot = threadIdx.x / NF;
   const int lt = threadIdx.x - slot * NF;
   const int64_t groups = (a.n_faces + FPB - 1) / FPB;
+  Rows<NP> A;
+  A.load(a.m_out, lt, slot < FPB);
   double pq[1] = {0.0};
   for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
     const int64_t f = g * FPB + slot;
@@ -168,8 +201,8 @@ __global__ void __launch_bounds__(NcgFace<NP>::NT) ncg_out_kernel(NcgArgs a) {
       pv = a.p[i];
     }
     __syncthreads();
-    const double o = face_tt<NP>(a.m_out, s_in[slot < FPB ? slot : 0],
-                                 s_t[slot < FPB ? slot : 0], lt, active);
+    const double o = face_tt<NP>(A, s_in[slot < FPB ? slot : 0], s_t[slot < FPB ? slot : 0], lt,
+                                 active);
     if (active) {
       a.q[i] = o;
       pq[0] += pv * o;
@@ -196,6 +229,9 @@ __global__ void __launch_bounds__(NcgFace<NP>::NT) ncg_block_kernel(NcgArgs a, i
   const int slot = threadIdx.x / NF;
   const int lt = threadIdx.x - slot * NF;
   const int64_t groups = (a.n_faces + FPB - 1) / FPB;
+  Rows<NP> At, As;
+  At.load(a.m_st, lt, slot < FPB);
+  As.load(a.m_s, lt, slot < FPB);
   double rz[1] = {0.0};
   for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
     const int64_t f = g * FPB + slot;
@@ -209,10 +245,10 @@ __global__ void __launch_bounds__(NcgFace<NP>::NT) ncg_block_kernel(NcgArgs a, i
     }
     __syncthreads();
     const int sl = slot < FPB ? slot : 0;
-    const double e = face_tt<NP>(a.m_st, s_in[sl], s_t[sl], lt, active);
+    const double e = face_tt<NP>(At, s_in[sl], s_t[sl], lt, active);
     if (active) s_in[slot][lt] = dv * e;
     __syncthreads();
-    const double zv = face_tt<NP>(a.m_s, s_in[sl], s_t[sl], lt, active);
+    const double zv = face_tt<NP>(As, s_in[sl], s_t[sl], lt, active);
     if (active) {
       a.z[i] = zv;
       rz[0] += rv * zv;
