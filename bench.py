@@ -183,10 +183,11 @@ def bench_mixed(pkg, W, torch, dev, reps: int = 3):
 # precond code of hdg_solve_opts, timing id of one iteration, algorithmic
 # bytes per free DOF and iteration.  HDG-trans: the CG form in use (one-kernel
 # 104 B, two-kernel 104 B).  Nodal solvers: p and z in, p and p^ out (32 B),
-# element apply (24 B), q = (M S x M S)(qa + qb) with p.q (32 B), update
-# (unprec 56, diag 64, block 48 B) and for HDG-block z = P^-1 r (24 B).
+# element apply (24 B), q = (M S x M S)(qa + qb) with p.q (32 B) and the
+# update with z = P^-1 r (unprec 56, diag 64, block 64 B: x, p, r, q, 1/y in,
+# x, r, z out).
 PAPER_SOLVERS = (("trans", 1, None, 104), ("unprec", 0, 13, 144), ("diag", 2, 14, 152),
-                 ("block", 3, 15, 160))
+                 ("block", 3, 15, 152))
 
 
 def bench_paper_case(pkg, W, torch, dev, reps: int = 3):

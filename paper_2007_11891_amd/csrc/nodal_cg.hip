@@ -14,12 +14,13 @@
 // per face (o: entrywise square), computed once per solve.  1 / y is the
 // eigen-basis Jacobi diagonal of HDG-trans.
 //
-// One iteration is four or five launches: ncg_in (state slot A -> B, beta,
+// One iteration is four launches: ncg_in (state slot A -> B, beta,
 // p = z + beta p, p^ = (S^T M x S^T M) p), the element apply of p^, ncg_out
-// (q = (M S x M S)(qa + qb), p.q partials), ncg_update (alpha, x += alpha p,
-// r -= alpha q, z = r or d r; slot B -> A) and, for HDG-block, ncg_block
-// (z = P^-1 r).  Reductions are fixed-order sums of block partials, as in the
-// transformed CG; partial slot k & 1 holds iteration k's r.z, r.r and p.q.
+// (q = (M S x M S)(qa + qb), p.q partials) and the update (alpha,
+// x += alpha p, r -= alpha q, z = P^-1 r; slot B -> A), a vector kernel for
+// HDG-unprec / HDG-diag and a face kernel for HDG-block.  Reductions are
+// fixed-order sums of block partials, as in the transformed CG; partial slot
+// k & 1 holds iteration k's r.z, r.r and p.q.
 #include "device_common.hpp"
 
 namespace hdg {
@@ -113,12 +114,12 @@ __global__ void __launch_bounds__(NcgFace<NP>::NT) ncg_in_kernel(NcgArgs a) {
   const int it = a.sc->A.iter;
   const int k2 = it & 1;
   // issued together: the partials, the first face group's z and p, A's rows
-  const int n_rz = a.precond == 3 ? a.n_face_blocks : a.n_vec_blocks;
-  const double* prz[1] = {a.partials + (size_t)(2 + k2) * a.pmax};
-  const double* prr[1] = {a.partials + (size_t)(4 + k2) * a.pmax};
-  PartialSums<NT, 1> srz, srr;
-  srz.issue(prz, n_rz);
-  srr.issue(prr, a.n_vec_blocks);
+  // partials of HDG-block come from the face-structured update
+  const int nparts = a.precond == 3 ? a.n_face_blocks : a.n_vec_blocks;
+  const double* pp[2] = {a.partials + (size_t)(2 + k2) * a.pmax,
+                         a.partials + (size_t)(4 + k2) * a.pmax};
+  PartialSums<NT, 2> sums;
+  sums.issue(pp, nparts);
   const int slot = threadIdx.x / NF;
   const int lt = threadIdx.x - slot * NF;
   const int sl = slot < FPB ? slot : 0;
@@ -138,9 +139,9 @@ __global__ void __launch_bounds__(NcgFace<NP>::NT) ncg_in_kernel(NcgArgs a) {
   const double rtol2 = a.sc->A.rtol2;
   const int maxit = a.sc->A.maxit;
   double rr_stop = a.sc->A.rr_stop;
-  double rho, rr;
-  srz.reduce(prz, n_rz, &rho);
-  srr.reduce(prr, a.n_vec_blocks, &rr);
+  double red[2];
+  sums.reduce(pp, nparts, red);
+  const double rho = red[0], rr = red[1];
   if (it == 0) rr_stop = rtol2 * rr;
   const double beta = (it == 0) ? 0.0 : rho / rho_prev;
   int done = 0;
@@ -212,27 +213,23 @@ __global__ void __launch_bounds__(NcgFace<NP>::NT) ncg_out_kernel(NcgArgs a) {
   if (threadIdx.x == 0) a.partials[(size_t)k2 * a.pmax + blockIdx.x] = pq[0];
 }
 
-// z = P^-1 r for the block preconditioner, (S x S) diag(1 / y) (S^T x S^T) r
-// per free face, and the r.z partials of slot `slot` (the iteration that
-// this residual starts).  init: the right-hand side's (no state check).
+// HDG-block at the start of the solve: z = P^-1 r with
+// P^-1 = (S x S) diag(1 / y) (S^T x S^T) per free face, and the partials of
+// r.z and r.r of iteration 0.
 template <int NP>
-__global__ void __launch_bounds__(NcgFace<NP>::NT) ncg_block_kernel(NcgArgs a, int init) {
+__global__ void __launch_bounds__(NcgFace<NP>::NT) ncg_block_init_kernel(NcgArgs a) {
   using F = NcgFace<NP>;
   constexpr int NF = F::NF, FPB = F::FPB, NT = F::NT;
   __shared__ double s_in[FPB][NF];
   __shared__ double s_t[FPB][NF];
-  int pslot = 0;
-  if (!init) {
-    if (a.sc->B.done || a.sc->A.done) return;   // uniform over the grid
-    pslot = (a.sc->B.iter + 1) & 1;
-  }
   const int slot = threadIdx.x / NF;
   const int lt = threadIdx.x - slot * NF;
+  const int sl = slot < FPB ? slot : 0;
   const int64_t groups = (a.n_faces + FPB - 1) / FPB;
   Rows<NP> At, As;
   At.load(a.m_st, lt, slot < FPB);
   As.load(a.m_s, lt, slot < FPB);
-  double rz[1] = {0.0};
+  double sums[2] = {0.0, 0.0};
   for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
     const int64_t f = g * FPB + slot;
     const bool active = slot < FPB && f < a.n_faces;
@@ -244,24 +241,130 @@ __global__ void __launch_bounds__(NcgFace<NP>::NT) ncg_block_kernel(NcgArgs a, i
       s_in[slot][lt] = rv;
     }
     __syncthreads();
-    const int sl = slot < FPB ? slot : 0;
     const double e = face_tt<NP>(At, s_in[sl], s_t[sl], lt, active);
     if (active) s_in[slot][lt] = dv * e;
     __syncthreads();
     const double zv = face_tt<NP>(As, s_in[sl], s_t[sl], lt, active);
     if (active) {
       a.z[i] = zv;
-      rz[0] += rv * zv;
+      sums[0] += rv * zv;
+      sums[1] += rv * rv;
     }
   }
-  block_sums<NT, 1>(rz);
-  if (threadIdx.x == 0) a.partials[(size_t)(2 + pslot) * a.pmax + blockIdx.x] = rz[0];
+  block_sums<NT, 2>(sums);
+  if (threadIdx.x == 0) {
+    a.partials[(size_t)2 * a.pmax + blockIdx.x] = sums[0];
+    a.partials[(size_t)4 * a.pmax + blockIdx.x] = sums[1];
+  }
 }
 
-// Update of iteration k (reads slot B, writes slot A from block 0):
-// alpha = rho / p.q, x += alpha p, r -= alpha q, z = r (HDG-unprec) or d r
-// (HDG-diag; HDG-block forms z in ncg_block_kernel), partials of r.z and r.r
-// for iteration k + 1.
+// HDG-block's update of iteration k, one face group at a time (reads slot B,
+// writes slot A from block 0): alpha = rho / p.q, x += alpha p,
+// r -= alpha q, z = (S x S) diag(1 / y) (S^T x S^T) r, partials of r.z and
+// r.r for iteration k + 1.
+template <int NP>
+__global__ void __launch_bounds__(NcgFace<NP>::NT) ncg_update_block_kernel(NcgArgs a) {
+  using F = NcgFace<NP>;
+  constexpr int NF = F::NF, FPB = F::FPB, NT = F::NT;
+  __shared__ double s_in[FPB][NF];
+  __shared__ double s_t[FPB][NF];
+  if (a.sc->A.done) return;                  // broke down in an earlier update
+  const int done = a.sc->B.done;
+  if (done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.sc->A.done = done;
+      a.sc->A.rr = a.sc->B.rr;
+      a.sc->A.iter = a.sc->B.iter;
+    }
+    return;
+  }
+  const int k = a.sc->B.iter;
+  const double rho = a.sc->B.rho;
+  // issued together: the p.q partials, the first face group's vectors, the rows
+  const double* ppq[1] = {a.partials + (size_t)(k & 1) * a.pmax};
+  PartialSums<NT, 1> spq;
+  spq.issue(ppq, a.n_face_blocks);
+  const int slot = threadIdx.x / NF;
+  const int lt = threadIdx.x - slot * NF;
+  const int sl = slot < FPB ? slot : 0;
+  const int64_t groups = (a.n_faces + FPB - 1) / FPB;
+  int64_t g = blockIdx.x;
+  double xv = 0.0, pv = 0.0, rv = 0.0, qv = 0.0, dv = 0.0;
+  {
+    const int64_t f = g * FPB + slot;
+    if (g < groups && slot < FPB && f < a.n_faces) {
+      const int64_t i = f * NF + lt;
+      xv = a.x[i];
+      pv = a.p[i];
+      rv = a.r[i];
+      qv = a.q[i];
+      dv = a.dinv[i];
+    }
+  }
+  Rows<NP> At, As;
+  At.load(a.m_st, lt, slot < FPB);
+  As.load(a.m_s, lt, slot < FPB);
+  double pq;
+  spq.reduce(ppq, a.n_face_blocks, &pq);
+  const double alpha = rho / pq;
+  if (!(pq > 0.0) || !isfinite(alpha)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.sc->A.done = 3;
+      a.sc->A.iter = k;
+      a.sc->A.pq = pq;
+    }
+    return;
+  }
+  double sums[2] = {0.0, 0.0};
+  for (; g < groups; g += gridDim.x) {
+    const int64_t f = g * FPB + slot;
+    const bool active = slot < FPB && f < a.n_faces;
+    const int64_t i = f * NF + lt;
+    if (g != (int64_t)blockIdx.x && active) {   // later groups: load here
+      xv = a.x[i];
+      pv = a.p[i];
+      rv = a.r[i];
+      qv = a.q[i];
+      dv = a.dinv[i];
+    }
+    double rn = 0.0;
+    if (active) {
+      rn = rv - alpha * qv;
+      a.x[i] = xv + alpha * pv;
+      a.r[i] = rn;
+      s_in[slot][lt] = rn;
+    }
+    __syncthreads();
+    const double e = face_tt<NP>(At, s_in[sl], s_t[sl], lt, active);
+    if (active) s_in[slot][lt] = dv * e;
+    __syncthreads();
+    const double zv = face_tt<NP>(As, s_in[sl], s_t[sl], lt, active);
+    if (active) {
+      a.z[i] = zv;
+      sums[0] += rn * zv;
+      sums[1] += rn * rn;
+    }
+  }
+  block_sums<NT, 2>(sums);
+  const int k1 = (k + 1) & 1;
+  if (threadIdx.x == 0) {
+    a.partials[(size_t)(2 + k1) * a.pmax + blockIdx.x] = sums[0];
+    a.partials[(size_t)(4 + k1) * a.pmax + blockIdx.x] = sums[1];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.sc->A.rho = rho;
+    a.sc->A.alpha = alpha;
+    a.sc->A.pq = pq;
+    a.sc->A.rr_stop = a.sc->B.rr_stop;
+    a.sc->A.rr = a.sc->B.rr;
+    a.sc->A.iter = k + 1;
+    a.sc->A.done = 0;
+  }
+}
+
+// Update of iteration k for HDG-unprec and HDG-diag (reads slot B, writes
+// slot A from block 0): alpha = rho / p.q, x += alpha p, r -= alpha q,
+// z = r or d r, partials of r.z and r.r for iteration k + 1.
 __global__ void __launch_bounds__(kNcgVecThreads) ncg_update_kernel(NcgArgs a) {
   if (a.sc->A.done) return;                  // broke down in an earlier update
   const int done = a.sc->B.done;
@@ -313,11 +416,9 @@ __global__ void __launch_bounds__(kNcgVecThreads) ncg_update_kernel(NcgArgs a) {
         const double rn = rv[u] - alpha * qv[u];
         a.x[g] = xv[u] + alpha * pv[u];
         a.r[g] = rn;
-        if (pc != 3) {
-          const double zn = dv[u] * rn;
-          a.z[g] = zn;
-          sums[0] += rn * zn;
-        }
+        const double zn = dv[u] * rn;
+        a.z[g] = zn;
+        sums[0] += rn * zn;
         sums[1] += rn * rn;
       }
     }
@@ -325,7 +426,7 @@ __global__ void __launch_bounds__(kNcgVecThreads) ncg_update_kernel(NcgArgs a) {
   block_sums<kNcgVecThreads, 2>(sums);
   const int k1 = (k + 1) & 1;
   if (threadIdx.x == 0) {
-    if (pc != 3) a.partials[(size_t)(2 + k1) * a.pmax + blockIdx.x] = sums[0];
+    a.partials[(size_t)(2 + k1) * a.pmax + blockIdx.x] = sums[0];
     a.partials[(size_t)(4 + k1) * a.pmax + blockIdx.x] = sums[1];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -339,8 +440,9 @@ __global__ void __launch_bounds__(kNcgVecThreads) ncg_update_kernel(NcgArgs a) {
   }
 }
 
-// Start of the solve: x = 0, r = b, p = 0, z = b or d b, partials of r.z
-// (unless HDG-block) and r.r for iteration 0.
+// Start of the solve: x = 0, r = b, p = 0, and for HDG-unprec / HDG-diag
+// z = b or d b with the partials of r.z and r.r of iteration 0 (HDG-block's
+// come from ncg_block_init_kernel).
 __global__ void __launch_bounds__(kNcgVecThreads) ncg_init_kernel(NcgArgs a) {
   const int pc = a.precond;
   double sums[2] = {0.0, 0.0};
@@ -358,8 +460,8 @@ __global__ void __launch_bounds__(kNcgVecThreads) ncg_init_kernel(NcgArgs a) {
     sums[1] += bv * bv;
   }
   block_sums<kNcgVecThreads, 2>(sums);
-  if (threadIdx.x == 0) {
-    if (pc != 3) a.partials[(size_t)2 * a.pmax + blockIdx.x] = sums[0];
+  if (threadIdx.x == 0 && pc != 3) {
+    a.partials[(size_t)2 * a.pmax + blockIdx.x] = sums[0];
     a.partials[(size_t)4 * a.pmax + blockIdx.x] = sums[1];
   }
 }
@@ -423,11 +525,12 @@ static hipError_t ncg_face_launch(int which, const NcgArgs& a, int nb, hipStream
   constexpr int NT = NcgFace<NP>::NT;
   if (which == 0) hipLaunchKernelGGL(ncg_in_kernel<NP>, dim3(nb), dim3(NT), 0, s, a);
   else if (which == 1) hipLaunchKernelGGL(ncg_out_kernel<NP>, dim3(nb), dim3(NT), 0, s, a);
-  else hipLaunchKernelGGL(ncg_block_kernel<NP>, dim3(nb), dim3(NT), 0, s, a, which == 3 ? 1 : 0);
+  else if (which == 2) hipLaunchKernelGGL(ncg_update_block_kernel<NP>, dim3(nb), dim3(NT), 0, s, a);
+  else hipLaunchKernelGGL(ncg_block_init_kernel<NP>, dim3(nb), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
-// which: 0 in, 1 out, 2 block (iteration), 3 block (initial residual)
+// which: 0 in, 1 out, 2 HDG-block update, 3 HDG-block start
 static hipError_t ncg_face(const hdg_ctx* c, int which, const NcgArgs& a, hipStream_t s) {
   const int nb = a.n_face_blocks;
   switch (c->np) {
@@ -455,12 +558,10 @@ hipError_t launch_ncg_iter(const hdg_ctx* c, CgWork<double>& w, int precond, hip
   hipError_t e = ncg_face(c, 0, a, s);
   if (e == hipSuccess) e = launch_elem_apply<double>(c, a.phat, nullptr, w.qa, w.qb, s, w.sc);
   if (e == hipSuccess) e = ncg_face(c, 1, a, s);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(ncg_update_kernel, dim3(a.n_vec_blocks), dim3(kNcgVecThreads), 0, s, a);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess && precond == 3) e = ncg_face(c, 2, a, s);
-  return e;
+  if (e != hipSuccess) return e;
+  if (precond == 3) return ncg_face(c, 2, a, s);
+  hipLaunchKernelGGL(ncg_update_kernel, dim3(a.n_vec_blocks), dim3(kNcgVecThreads), 0, s, a);
+  return hipGetLastError();
 }
 
 }  // namespace hdg
