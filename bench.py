@@ -247,6 +247,34 @@ def bench_paper_case(pkg, W, torch, dev, reps: int = 3):
             "cases": rows}
 
 
+def bench_tau_sweep(pkg, W, torch, dev):
+    """The paper's penalty study: its solver test case with tau_e in
+    {1, 25, 625} (section "Robustness against increases in the penalty
+    parameter"): iterations of HDG-trans to 1e-10 and maximum nodal error."""
+    rows = []
+    for tau_e in (1.0, 25.0, 625.0):
+        for p in (2, 4, 8, 12, 16):
+            pr = W.paper_case(p, tau_e=tau_e)
+            c = pkg.HdgContext(pr.n, pr.widths, pr.p, pr.tau, pr.lam)
+            vx, tx = c.coords()
+            vx, tx = vx.cpu().numpy(), tx.cpu().numpy()
+            f = torch.as_tensor(W.f_paper(*vx.T, 0.0), device=dev)
+            g = torch.as_tensor(W.u_paper(*tx.T), device=dev)
+            u_ex = torch.as_tensor(W.u_paper(*vx.T), device=dev)
+            nf = c.sizes.n_free
+            tr = g.clone()
+            tr[:nf] = 0
+            _, uv, info = c.solve_forcing(f, tr, opts=pkg.default_opts(rtol=1e-10))
+            rows.append({"tau_e": tau_e, "p": p, "iters": info["iters"],
+                         "max_error": float(torch.max(torch.abs(uv - u_ex)))})
+            c.close()
+        log("[bench] tau_e " + f"{tau_e:g}: " + ", ".join(
+            f"p={r['p']} {r['iters']} it err {r['max_error']:.2e}" for r in rows if r["tau_e"] == tau_e))
+    return {"workload": "paper's test case (8^3 elements, lambda = 0, k = 5) with tau_e in {1, 25, 625}, "
+                        "HDG-trans to 1e-10",
+            "cases": rows}
+
+
 def bench_batched(pkg, W, torch, dev, reps: int = 3):
     """256 independent unit-cube problems (n_a ~ U{4..12}, p ~ U{2..10},
     lambda log-uniform in [1e-2, 1e2], f ~ N(0,1), seed 4) in one persistent
@@ -502,6 +530,7 @@ def main():
     batched = None if args.no_batch else bench_batched(pkg, W, torch, dev)
     adjoint = None if args.no_adjoint else bench_adjoint(pkg, W, torch, dev)
     paper_case = None if args.no_paper_case else bench_paper_case(pkg, W, torch, dev)
+    tau_sweep = None if args.no_paper_case else bench_tau_sweep(pkg, W, torch, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -536,6 +565,7 @@ def main():
         "batched": batched,
         "adjoint": adjoint,
         "paper_case": paper_case,
+        "tau_sweep": tau_sweep,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

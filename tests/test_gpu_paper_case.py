@@ -72,3 +72,35 @@ def test_paper_case_convergence_and_iterations():
     assert errs[16] < 0.2 * errs[8]
     for p in (8, 12, 16):
         assert 50 <= its[p] <= 250, its          # the paper: about 100 over a wide range of p
+
+
+def test_penalty_study_trends():
+    """The paper's penalty study (tau_e in {1, 25, 625} on its test case):
+    a larger penalty lowers the solution error and costs iterations, by
+    about a factor 1.5 from 25 to 625 at p = 2 and much less at high p."""
+    import paper_2007_11891_amd as pkg
+    res = {}
+    for tau_e in (1.0, 25.0, 625.0):
+        for p in (2, 12):
+            pr = W.paper_case(p, tau_e=tau_e)
+            c = pkg.HdgContext(pr.n, pr.widths, pr.p, pr.tau, pr.lam)
+            vx, tx = c.coords()
+            vx, tx = vx.cpu().numpy(), tx.cpu().numpy()
+            f = torch.as_tensor(W.f_paper(*vx.T, 0.0), device="cuda")
+            g = torch.as_tensor(W.u_paper(*tx.T), device="cuda")
+            u_ex = torch.as_tensor(W.u_paper(*vx.T), device="cuda")
+            nf = c.sizes.n_free
+            tr = g.clone()
+            tr[:nf] = 0
+            _, uv, info = c.solve_forcing(f, tr, opts=pkg.default_opts(rtol=1e-10))
+            err = float(torch.max(torch.abs(uv - u_ex)))
+            print(f"[penalty] tau_e={tau_e:g} p={p}: {info['iters']} it, error {err:.3e}", flush=True)
+            assert info["rel_res"] < 1.5e-10
+            res[tau_e, p] = (info["iters"], err)
+            c.close()
+    for p in (2, 12):
+        assert res[625.0, p][1] < res[25.0, p][1] < res[1.0, p][1]
+        assert res[1.0, p][0] <= res[25.0, p][0] <= res[625.0, p][0]
+    grow2 = res[625.0, 2][0] / res[25.0, 2][0]
+    grow12 = res[625.0, 12][0] / res[25.0, 12][0]
+    assert 1.2 < grow2 < 2.5 and grow12 < grow2
