@@ -10,19 +10,30 @@ starts at the origin.  Element e = i + n1 (j + n2 k).  Element nodes: GLL index
 q1 + n_p (q2 + n_p q3), q1 fastest; the volume vector is element-major.
 
 Faces: the faces normal to axis a sit on planes m = 0..n_a.  Interior planes
-m = 1..n_a-1 carry the free unknowns, boundary planes m = 0 and m = n_a carry
-Dirichlet data.  The trace vector is
+m = 1..n_a-1 always carry free unknowns.  Each of the six sides of the box
+(axis a, side s: 0 the plane m = 0, 1 the plane m = n_a) is either a
+Dirichlet side (u = g_D, the default) or a Neumann side (n . grad u = g_N,
+equation (neumann_flux)); the set is a bit mask with bit 2a + s for a
+Neumann side.  The trace of a Neumann side is unknown too.  The trace
+vector is
 
-    [free faces normal to x1][... x2][... x3][boundary faces]
+    [interior faces normal to x1][... x2][... x3][Neumann faces]   (free part)
+    [Dirichlet faces]                                              (g_D)
+    [Neumann data]                                                 (g_N)
 
-Free faces of axis a are ordered lexicographically with x1 fastest over their
-position (m along a, element indices along the two other axes):
+Interior faces of axis a are ordered lexicographically with x1 fastest over
+their position (m along a, element indices along the two other axes):
     a=0: id = (m-1) + (n1-1) (j + n2 k)
     a=1: id = i + n1 ((m-1) + (n2-1) k)
     a=2: id = i + n1 (j + n2 (m-1))
-The boundary tail holds, for a = 0, 1, 2, the low plane then the high plane,
-each ordered t_b + n_b t_c over the tangential element indices (b < c).
+Boundary faces come side by side in the order (a, s) = (0,0), (0,1), (1,0),
+(1,1), (2,0), (2,1), each side ordered t_b + n_b t_c over the tangential
+element indices (b < c); the Neumann sides in the free part, the Dirichlet
+sides in the g_D block.  The g_N block repeats the Neumann faces' order: the
+data of the i-th Neumann face follows the g_D block at offset i n_p^2.
 Within a face: n_p x n_p GLL nodes, id = q_b + n_p q_c (lower axis fastest).
+With no Neumann side this is the plain Dirichlet layout (free part = interior
+faces, tail = all boundary faces).
 
 Element-local face vectors follow the paper's Table 1 shapes (first index
 fastest): u1 is 2 x n_p x n_p (side, q2, q3), u2 is n_p x 2 x n_p (q1, side,
@@ -34,10 +45,13 @@ import numpy as np
 
 
 class Layout:
-    def __init__(self, n, p):
+    def __init__(self, n, p, neumann: int = 0):
         self.n = tuple(int(v) for v in n)
         self.p = int(p)
         self.np_ = self.p + 1
+        self.neumann = int(neumann)
+        if not 0 <= self.neumann < 64:
+            raise ValueError("neumann mask must be in [0, 63]")
         n1, n2, n3 = self.n
         npf = self.np_ ** 2
         self.face_counts_free = [(n1 - 1) * n2 * n3, n1 * (n2 - 1) * n3, n1 * n2 * (n3 - 1)]
@@ -46,18 +60,41 @@ class Layout:
         for a in range(3):
             self.free_offset[a] = off
             off += self.face_counts_free[a]
-        self.n_free_faces = off
+        self.n_int_faces = off
         tang = [(n2, n3), (n1, n3), (n1, n2)]
+        self.side_faces = {(a, s): tang[a][0] * tang[a][1] for a in range(3) for s in (0, 1)}
         self.bdry_offset = {}
-        for a in range(3):
-            for side in (0, 1):
-                self.bdry_offset[(a, side)] = off
-                off += tang[a][0] * tang[a][1]
+        for want_neumann in (True, False):
+            for a in range(3):
+                for side in (0, 1):
+                    if self.is_neumann_side(a, side) == want_neumann:
+                        self.bdry_offset[(a, side)] = off
+                        off += self.side_faces[(a, side)]
+            if want_neumann:
+                self.n_free_faces = off
         self.n_faces = off
+        self.n_neu_faces = self.n_free_faces - self.n_int_faces
+        self.n_dir_faces = self.n_faces - self.n_free_faces
         self.n_free = self.n_free_faces * npf
-        self.n_all = self.n_faces * npf
+        self.n_all = (self.n_faces + self.n_neu_faces) * npf
         self.n_elem = n1 * n2 * n3
         self.n_vol = self.n_elem * self.np_ ** 3
+
+    def is_neumann_side(self, a, side):
+        return bool((self.neumann >> (2 * a + side)) & 1)
+
+    def neumann_data_index(self, fid):
+        """First trace-vector index of the g_N data of Neumann face fid."""
+        if not self.n_int_faces <= fid < self.n_free_faces:
+            raise IndexError("not a Neumann face")
+        return (self.n_faces + fid - self.n_int_faces) * self.np_ ** 2
+
+    def face_side(self, fid):
+        """(a, s) of a boundary face, None for an interior face."""
+        for key, off in self.bdry_offset.items():
+            if off <= fid < off + self.side_faces[key]:
+                return key
+        return None
 
     def face_id(self, a, m, t):
         """Global face index of the face normal to axis a on plane m; t = the
@@ -149,7 +186,8 @@ def volume_coords(layout: Layout, widths, gll_x):
 
 
 def trace_coords(layout: Layout, widths, gll_x):
-    """Physical coordinates of every trace node, shape (n_all, 3)."""
+    """Physical coordinates of every trace node, shape (n_all, 3); the g_N
+    block repeats the coordinates of its Neumann faces."""
     npn = layout.np_
     X = [axis_breaks(w) for w in widths]
     ref = (np.asarray(gll_x) + 1.0) / 2.0
@@ -169,4 +207,22 @@ def trace_coords(layout: Layout, widths, gll_x):
                 out[rows, a] = X[a][m]
                 out[rows, b] = cb.ravel()
                 out[rows, c] = cc.ravel()
+    npf = npn * npn
+    for f in range(layout.n_int_faces, layout.n_free_faces):
+        d = layout.neumann_data_index(f)
+        out[d:d + npf] = out[f * npf:(f + 1) * npf]
+    return out
+
+
+def trace_normals(layout: Layout):
+    """Outward unit normal of the boundary at every trace node (rows of the
+    Neumann faces, the g_D block and the g_N block), zero elsewhere."""
+    npf = layout.np_ ** 2
+    out = np.zeros((layout.n_all, 3))
+    for (a, s), off in layout.bdry_offset.items():
+        nf = layout.side_faces[(a, s)]
+        out[off * npf:(off + nf) * npf, a] = 2.0 * s - 1.0
+        if layout.is_neumann_side(a, s):
+            d = layout.neumann_data_index(off)
+            out[d:d + nf * npf, a] = 2.0 * s - 1.0
     return out

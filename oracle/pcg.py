@@ -55,16 +55,18 @@ def diagonal_preconditioner(K_ff, npf: int):
     return apply, d
 
 
-def pcg(K, F, apply_pinv=None, rtol: float = 1e-10, maxit: int = 100000):
+def pcg(K, F, apply_pinv=None, rtol: float = 1e-10, maxit: int = 100000, x0=None):
     """Textbook preconditioned CG for the SPD matrix K (dense or sparse),
-    x_0 = 0; stops when ||r||_2 <= rtol ||F||_2.  Returns (x, iterations,
-    history of ||r||_2 / ||F||_2)."""
+    from x0 (default 0); stops when ||r||_2 <= rtol ||F||_2.  Returns (x,
+    iterations, history of ||r||_2 / ||F||_2)."""
     F = np.asarray(F, dtype=np.float64)
-    x = np.zeros_like(F)
-    r = F.copy()
+    x = np.zeros_like(F) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    r = F - K @ x if x0 is not None else F.copy()
     nF = np.linalg.norm(F)
-    hist = [1.0 if nF > 0 else 0.0]
+    hist = [np.linalg.norm(r) / nF if nF > 0 else 0.0]
     if nF == 0.0:
+        return x, 0, hist
+    if hist[0] <= rtol:
         return x, 0, hist
     z = r.copy() if apply_pinv is None else apply_pinv(r)
     p = z.copy()

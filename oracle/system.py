@@ -5,10 +5,29 @@ TEST INFRASTRUCTURE ONLY: nothing in the product path may import this module.
 Follows equation (hdg_system): K u~ = F with K = sum_e Q_e^T K_e Q_e and
 F = sum_e Q_e^T F_e, where Q_e scatters global trace unknowns to the element
 faces (the element-local ordering of Table 1).  Dirichlet data is imposed
-strongly: all trace nodes on boundary faces are fixed to g_D (the values of
+strongly: all trace nodes on Dirichlet faces are fixed to g_D (the values of
 the Dirichlet function at the face nodes) and eliminated,
 
     K_ff u~_f = F_f - K_fD g_D.
+
+On a Neumann side (equation (neumann_flux), n . grad u = g_N) the trace is
+unknown and the flux row of the element system (the last row of equation
+(ldg_element_operator)) carries the boundary data: there the numerical flux
+equals g_N, which adds the face integral of mu g_N to F_e,
+
+    g_N,e = (h_b h_c / 4) (M x M) g_N      (face normal to axis a, b, c the others)
+
+with g_N sampled at the face nodes.
+
+The initial guess of the solution process (section "Summary of solution
+method") hybridizes a volume field u: q = grad u by differentiation, then
+the flux of equation (fluxu) on every face,
+
+    u~ = (tau+ u+ + tau- u-) / (tau+ + tau-) - (q+.n+ + q-.n-) / (tau+ + tau-),
+
+tau = 2 tau_hat / h_a of the element on either side.  On a Neumann face
+there is one element; the outside is read as tau- = 0 with the flux
+q-.n- = -g_N it would bring, so u~ = u+ - (q+.n+ - g_N) / tau+.
 
 Recovery of u per element uses the element system (see ``element``).  The
 adjoint of u(lambda, f) is the dense transpose of the same steps:
@@ -26,14 +45,18 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .basis import standard_matrices
+from .basis import lagrange_deriv_eval, standard_matrices
 from .element import ElementSystem
-from .layout import Layout, trace_coords, volume_coords
+from .layout import Layout, trace_coords, trace_normals, volume_coords
+
+
+def npf_of(layout):
+    return layout.np_ ** 2
 
 
 class HdgOracle:
-    def __init__(self, n, widths, p, tau, lam, exact_mass=False, cache_limit=64):
-        self.layout = Layout(n, p)
+    def __init__(self, n, widths, p, tau, lam, exact_mass=False, cache_limit=64, neumann=0):
+        self.layout = Layout(n, p, neumann)
         self.widths = [np.asarray(w, dtype=np.float64) for w in widths]
         self.p = int(p)
         self.tau = float(tau)
@@ -89,6 +112,9 @@ class HdgOracle:
 
     def trace_coords(self):
         return trace_coords(self.layout, self.widths, self.std["x"])
+
+    def trace_normals(self):
+        return trace_normals(self.layout)
 
     def mass_diag(self):
         """Diagonal of the lumped global mass matrix (volume ordering)."""
@@ -163,13 +189,75 @@ class HdgOracle:
             F[m] += self.rhs_element(e, f_vol[self.vol_slice(e)])
         return F
 
+    def neumann_load(self, g_all):
+        """Sum of the g_N,e over the Neumann faces, as a free-trace vector
+        (g_all: full trace vector whose g_N block holds n . grad u)."""
+        L = self.layout
+        npn = L.np_
+        npf = npn * npn
+        out = np.zeros(L.n_free)
+        M = self.std["M"]
+        Mf = np.kron(M, M)
+        for e in range(L.n_elem):
+            i, j, k = L.elem_ijk(e)
+            h = self.elem_h(e)
+            idx = (i, j, k)
+            for a in range(3):
+                b, c = [ax for ax in range(3) if ax != a]
+                for s in (0, 1):
+                    fid = L.face_id(a, idx[a] + s, idx)
+                    if not L.n_int_faces <= fid < L.n_free_faces:
+                        continue
+                    d = L.neumann_data_index(fid)
+                    out[fid * npf:(fid + 1) * npf] += h[b] * h[c] / 4.0 * (Mf @ g_all[d:d + npf])
+        return out
+
     def lifted_rhs(self, f_vol, g_all):
-        """F_f - K_fD g_D (g_all: Dirichlet values in the boundary tail)."""
-        nf = self.layout.n_free
+        """F_f - K_fD g_D + g_N,f (g_all: Dirichlet values in the g_D block,
+        Neumann data in the g_N block)."""
+        L = self.layout
+        nf = L.n_free
         F = self.assemble_F(f_vol)
-        xD = np.zeros(self.layout.n_all)
-        xD[nf:] = g_all[nf:]
-        return F[:nf] - self.apply(xD)[:nf]
+        xD = np.zeros(L.n_all)
+        end = L.n_faces * npf_of(L)
+        xD[nf:end] = g_all[nf:end]
+        rhs = F[:nf] - self.apply(xD)[:nf]
+        if L.n_neu_faces:
+            rhs = rhs + self.neumann_load(g_all)
+        return rhs
+
+    # -- initial guess -------------------------------------------------------------
+    def hybridize(self, u_vol, g_all=None):
+        """Free trace u~ of a volume field by the flux of equation (fluxu)
+        with q = grad u (see the module docstring)."""
+        L = self.layout
+        npn = L.np_
+        npf = npn * npn
+        dphi = lagrange_deriv_eval(self.std["x"], np.array([-1.0, 1.0]))   # [end, k]
+        num = np.zeros(L.n_free)
+        den = np.zeros(L.n_free_faces)
+        for e in range(L.n_elem):
+            i, j, k = L.elem_ijk(e)
+            idx = (i, j, k)
+            h = self.elem_h(e)
+            cube = u_vol[self.vol_slice(e)].reshape(npn, npn, npn)   # [q3][q2][q1]
+            for a in range(3):
+                ax = 2 - a                       # cube axis of x_{a+1}
+                for s in (0, 1):
+                    fid = L.face_id(a, idx[a] + s, idx)
+                    if fid >= L.n_free_faces:
+                        continue
+                    end = s * (npn - 1)
+                    uf = np.take(cube, end, axis=ax).ravel()
+                    dn = (2.0 * s - 1.0) * (2.0 / h[a]) * np.tensordot(cube, dphi[s], axes=([ax], [0])).ravel()
+                    tau_e = 2.0 * self.tau / h[a]
+                    sl = slice(fid * npf, (fid + 1) * npf)
+                    num[sl] += tau_e * uf - dn
+                    den[fid] += tau_e
+                    if fid >= L.n_int_faces and g_all is not None:
+                        d = L.neumann_data_index(fid)
+                        num[sl] += g_all[d:d + npf]
+        return num / np.repeat(den, npf)
 
     # -- solve & recovery ------------------------------------------------------------
     def solve(self, f_vol, g_all):

@@ -62,3 +62,11 @@ def face_T(S, layout, n_faces):
         sl = slice(f * npn * npn, (f + 1) * npn * npn)
         T[sl, sl] = blk
     return T
+
+
+def bc_vector(layout, u, grad, T, normals):
+    """Full trace vector of boundary data for the layout: u at every node
+    (g_D on the Dirichlet block) and n . grad u in the g_N block."""
+    nrm = np.array(normals, copy=True)
+    nrm[: layout.n_faces * layout.np_ ** 2] = 0.0
+    return W.boundary_data(u, grad, T, nrm)

@@ -155,6 +155,58 @@ def poly_tensor(coeffs: np.ndarray) -> Callable:
     return u, f
 
 
+def poly_tensor_grad(coeffs: np.ndarray) -> Callable:
+    """Gradient of the tensor polynomial of ``poly_tensor``: returns g with
+    g(x, y, z) of shape (..., 3)."""
+    c = np.asarray(coeffs, dtype=np.float64)
+    P = c.shape[0]
+
+    def _d1(axis):
+        d = np.zeros_like(c)
+        for m in range(1, P):
+            src = [slice(None)] * 3
+            dst = [slice(None)] * 3
+            src[axis] = m
+            dst[axis] = m - 1
+            d[tuple(dst)] += m * c[tuple(src)]
+        return d
+
+    parts = [_d1(0), _d1(1), _d1(2)]
+
+    def g(x, y, z):
+        out = []
+        for cc in parts:
+            v = np.zeros(np.broadcast(x, y, z).shape)
+            for a in range(cc.shape[0]):
+                for b in range(cc.shape[1]):
+                    for e in range(cc.shape[2]):
+                        if cc[a, b, e] != 0.0:
+                            v = v + cc[a, b, e] * x ** a * y ** b * z ** e
+            out.append(v)
+        return np.stack(out, axis=-1)
+
+    return g
+
+
+def grad_sin3(x, y, z):
+    """Gradient of u_sin3."""
+    return np.stack([np.pi * np.cos(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z),
+                     np.pi * np.sin(np.pi * x) * np.cos(np.pi * y) * np.sin(np.pi * z),
+                     np.pi * np.sin(np.pi * x) * np.sin(np.pi * y) * np.cos(np.pi * z)], axis=-1)
+
+
+def boundary_data(u, grad, coords: np.ndarray, normals: np.ndarray) -> np.ndarray:
+    """Full trace vector of boundary data: u at every node, replaced by the
+    normal derivative n . grad u wherever ``normals`` marks a g_N slot
+    (rows with a nonzero normal that the caller passes for the g_N block
+    only).  coords / normals: (n_all, 3)."""
+    out = u(*coords.T)
+    rows = np.nonzero(np.any(normals != 0.0, axis=1))[0]
+    if rows.size:
+        out[rows] = np.einsum("ij,ij->i", normals[rows], grad(*coords[rows].T))
+    return out
+
+
 # ----------------------------------------------------------------------------
 # Problem descriptions
 # ----------------------------------------------------------------------------
