@@ -6,7 +6,8 @@
  *
  * Problem (paper, equation (helmholtz_equation)):
  *     lambda u - laplace u = f  in the box [0, sum h_1] x [0, sum h_2] x [0, sum h_3],
- *     u = g_D on the whole boundary,
+ *     u = g_D on the Dirichlet sides (all six unless hdg_create_bc names
+ *     Neumann sides), n . grad u = g_N on the Neumann sides (outward n),
  * discretised on a Cartesian mesh of n1 x n2 x n3 cuboids with per-axis
  * widths, Lagrange polynomials of degree p on Gauss-Lobatto-Legendre (GLL)
  * points (lumped GLL mass matrix), penalty tau_{i,e} = 2 tau_hat / h_{i,e}
@@ -36,16 +37,22 @@
  *   Volume vectors (length n_vol = n1 n2 n3 n_p^3): element
  *     e = i + n1 (j + n2 k), then node q1 + n_p (q2 + n_p q3), q1 fastest
  *     (the paper's Kronecker ordering, equation (tp_definition)).
- *   Trace vectors: faces normal to x1, then x2, then x3, interior faces only
- *     ("free" part, length n_free), followed by the boundary faces ("tail",
- *     length n_all - n_free).  Interior faces of axis a sit on planes
+ *   Trace vectors: the unknowns ("free" part, length n_free) are the
+ *     interior faces normal to x1, then x2, then x3, followed by the faces
+ *     of the Neumann sides; then the "tail" (length n_all - n_free): the
+ *     faces of the Dirichlet sides (g_D), then the g_N block, which holds
+ *     n . grad u at the nodes of each Neumann face in the order of those
+ *     faces in the free part.  Interior faces of axis a sit on planes
  *     m = 1..n_a-1 and are ordered with x1 fastest over (plane, element
  *     indices of the two other axes):
  *         a=0: (m-1) + (n1-1)(j + n2 k)
  *         a=1: i + n1((m-1) + (n2-1) k)
  *         a=2: i + n1(j + n2 (m-1))
- *     The tail holds, for a = 0, 1, 2, the plane m = 0 then m = n_a, each
- *     ordered t_b + n_b t_c over the two tangential element indices (b < c).
+ *     Sides are numbered k = 2a + s (s = 0 the plane m = 0, s = 1 the plane
+ *     m = n_a) and come in increasing k, each ordered t_b + n_b t_c over the
+ *     two tangential element indices (b < c): the Neumann sides in the free
+ *     part, the Dirichlet sides in the tail.  With no Neumann side the free
+ *     part is the interior faces and the tail every boundary face.
  *     Within a face: n_p x n_p nodes, q_b + n_p q_c (lower axis fastest).
  *   Bases of trace vectors: HDG_BASIS_NODAL holds nodal values (u~) or
  *     nodal residuals; HDG_BASIS_EIGEN holds the transformed unknowns of the
@@ -121,6 +128,15 @@ typedef struct {
                          iteration); 1 textbook PCG, an element kernel and a
                          vector update kernel per iteration; -1 the
                          context's choice (hdg_autotune, or by mesh size)  */
+  int guess;          /* 0: CG from x0 = 0; 1: the unknowns passed in (u_free
+                         of hdg_solve, the free part of trace in
+                         hdg_solve_forcing) are the initial guess, e.g. from
+                         hdg_hybridize (section "Summary of solution method").
+                         The CG then solves for the correction from the
+                         residual F - K x0 with the stopping test unchanged
+                         (||r|| <= rtol ||F||, in the solver's basis); iters
+                         counts the correction's iterations, 0 when x0 already
+                         passes.  hdg_adjoint ignores it.                   */
 } hdg_solve_opts;
 
 typedef struct {
@@ -152,6 +168,18 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2,
                       const double* h3, int p, double tau_hat,
                       const double* lambda_host, double lambda_const,
                       void* stream, hdg_ctx** out);
+
+/* hdg_create with Neumann sides (equation (neumann_flux)): bit 2a + s of
+ * neumann_sides (0..63) makes side s of axis a (s = 0: x_{a+1} = 0, s = 1:
+ * x_{a+1} = sum h_{a+1}) a Neumann side, n . grad u = g_N, whose trace is
+ * unknown; the others stay Dirichlet.  hdg_create is this call with 0.  The
+ * layout of trace vectors follows (see "Layouts" above).  All six sides
+ * Neumann with lambda = 0 everywhere is rejected (HDG_EINVAL): the
+ * condensed operator is then singular.  Batched solves stay Dirichlet. */
+hdg_status hdg_create_bc(const int n_elem[3], const double* h1, const double* h2,
+                         const double* h3, int p, double tau_hat,
+                         const double* lambda_host, double lambda_const,
+                         int neumann_sides, void* stream, hdg_ctx** out);
 
 /* Release the context and its device memory (synchronises its stream). */
 hdg_status hdg_destroy(hdg_ctx* ctx);
@@ -197,13 +225,15 @@ hdg_status hdg_face_transform(hdg_ctx* ctx, hdg_transform kind,
                               const double* in, double* out, int64_t n_faces);
 
 /* Right-hand side of the condensed system with the Dirichlet lift,
- *     F_f = F(f)_f - K_fD g_D,   F(f)_e = -R_e^T A_e^-1 [M_e f_e; 0]
+ *     F_f = F(f)_f - K_fD g_D + g_N,f,   F(f)_e = -R_e^T A_e^-1 [M_e f_e; 0]
  * (derived from eliminating u, q in the element system; the printed solver
  * listing has the opposite sign), evaluated by fast diagonalisation:
- * F^_e = -B^_e^T D_Z^-1 (S_e^T M_e f_e - B^_e u^_D,e).
+ * F^_e = -B^_e^T D_Z^-1 (S_e^T M_e f_e - B^_e u^_D,e).  g_N,f is the face
+ * integral of mu g_N on the Neumann faces (the flux row of the element
+ * system, equation (ldg_element_operator)): (h_b h_c / 4) (M x M) g_N.
  *   f        device double[n_vol] nodal forcing
- *   trace    device double[n_all] nodal trace; only the tail (g_D) is read;
- *            NULL means g_D = 0
+ *   trace    device double[n_all] nodal trace; only the tail (g_D and g_N)
+ *            is read; NULL means g_D = 0 and g_N = 0
  *   F_free   device double[n_free] output in the requested basis */
 hdg_status hdg_rhs(hdg_ctx* ctx, const double* f, const double* trace,
                    double* F_free, hdg_basis basis);
@@ -211,16 +241,18 @@ hdg_status hdg_rhs(hdg_ctx* ctx, const double* f, const double* trace,
 /* Solve K_ff u_f = F_f by preconditioned CG in the eigen-face basis
  * (transformed solver listing: transform, pCG on K^, transform back).
  *   F_free   device double[n_free], nodal residual basis
- *   u_free   device double[n_free], output nodal trace unknowns
+ *   u_free   device double[n_free], output nodal trace unknowns (input: the
+ *            initial guess when opts->guess = 1)
  * Returns HDG_ENOCONV (info filled, u_free = last iterate) when the cap is
  * reached.  Synchronises the stream.  opts NULL = defaults. */
 hdg_status hdg_solve(hdg_ctx* ctx, const double* F_free, double* u_free,
                      const hdg_solve_opts* opts, hdg_solve_info* info);
 
-/* Whole solution process for forcing f and Dirichlet data: RHS, CG in the
+/* Whole solution process for forcing f and boundary data: RHS, CG in the
  * eigen basis, back transform, recovery of u per element.
  *   f        device double[n_vol]
- *   trace    device double[n_all] in: tail = g_D (nodal); out: free part =
+ *   trace    device double[n_all] in: tail = g_D and g_N (nodal), and with
+ *            opts->guess = 1 the free part = initial guess; out: free part =
  *            nodal solution trace (tail unchanged)
  *   u_vol    device double[n_vol] output, or NULL to skip the recovery */
 hdg_status hdg_solve_forcing(hdg_ctx* ctx, const double* f, double* trace,
@@ -234,6 +266,22 @@ hdg_status hdg_solve_forcing(hdg_ctx* ctx, const double* f, double* trace,
  *   part and g_D tail);  u_vol device double[n_vol] output. */
 hdg_status hdg_reconstruct(hdg_ctx* ctx, const double* f, const double* trace,
                            double* u_vol);
+
+/* Initial guess of the trace from a volume field (paper, section "Summary
+ * of solution method": q = grad u by differentiation, then the flux of
+ * equation (fluxu) on every face):
+ *     u~ = (tau+ u+ + tau- u-) / (tau+ + tau-) - (q+.n+ + q-.n-) / (tau+ + tau-)
+ * with tau = 2 tau_hat / h_a of the element on either side and q.n the
+ * derivative of the element polynomial along the outward normal at the face
+ * node.  On a Neumann face the outside brings tau- = 0 and q-.n- = -g_N:
+ * u~ = u+ - (q+.n+ - g_N) / tau+.
+ *   u_vol       device double[n_vol] volume field (e.g. the last time step)
+ *   trace       device double[n_all]; only the g_N block is read; NULL
+ *               means g_N = 0
+ *   trace_free  device double[n_free] output, nodal (may be the free part of
+ *               trace) */
+hdg_status hdg_hybridize(hdg_ctx* ctx, const double* u_vol, const double* trace,
+                         double* trace_free);
 
 /* Adjoint of u(lambda, f) for a scalar loss J(u) (not in the paper; derived
  * from equation (hdg_operator_factorized) and the recovery formula).  Given

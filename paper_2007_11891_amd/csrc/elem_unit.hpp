@@ -132,6 +132,7 @@ template <typename T>
 struct UnitRegs {
   bool active;
   int fid[6];
+  int nm;          // faces that are unknowns with this element alone (bit f)
   T d[4];
   T a[6];
   T b[6];
@@ -142,6 +143,7 @@ template <typename T, int NP, int EPB>
 __device__ inline void unit_info(const UnitIO<T>& io, const UnitLane& L, int unit, UnitRegs<T>& R) {
   const int e = unit * EPB + L.slot;
   R.active = L.slot < EPB && e < io.n_elem;
+  R.nm = 0;
   if (R.active) {
     const ElemInfo* ei = io.info + e;
     R.d[0] = (T)(ei->d[0] * io.lam[e]);
@@ -150,6 +152,7 @@ __device__ inline void unit_info(const UnitIO<T>& io, const UnitLane& L, int uni
     R.d[3] = (T)ei->d[3];
 #pragma unroll
     for (int f = 0; f < 6; ++f) R.fid[f] = ei->fid[f];
+    R.nm = ei->nmask;
   }
 }
 
@@ -191,11 +194,13 @@ __device__ inline void put(T* p, T v) {
 // Element arithmetic of one unit given its input face values xf (already in
 // registers, faces 0..3 also staged in LDS by the caller before the first
 // barrier): expansion into the element eigenspace, reductions back to the
-// faces, stores of qa / qb, and the quadratic form xf.out into *dot.
+// faces, stores of qa / qb, and the quadratic form xf.out into *dot.  A face
+// in nm (on a Neumann side of the box) has no second element: its other
+// slot is written with zero, so that qa + qb is the face's sum.
 template <typename T, int NP, int EPB, int MODE, typename Tab>
 __device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
-                                 const UnitLane& L, bool active, const int* fid, const T* d,
-                                 const T* xf, double* dot) {
+                                 const UnitLane& L, bool active, const int* fid, int nm,
+                                 const T* d, const T* xf, double* dot) {
   constexpr int NF = NP * NP;
   constexpr int P = upitch<NP>();
   const int sl = L.sl, q1 = L.q1, q2 = L.q2, col = L.col;
@@ -262,6 +267,7 @@ __device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T
       if (fid[f] >= io.nff) continue;
       const int64_t g = (int64_t)fid[f] * NF + col;
       put<MODE>((f & 1) ? io.qa + g : io.qb + g, out[f]);
+      if ((nm >> f) & 1) put<MODE>((f & 1) ? io.qb + g : io.qa + g, (T)0);
       if constexpr (MODE != 0) *dot += (double)(xf[f] * out[f]);
     }
   }
@@ -281,14 +287,15 @@ __device__ inline void unit_compute(const UnitIO<T>& io, const Tab& tab, UnitSme
     T v = R.a[f];
     if constexpr (MODE == 1) {
       v = R.a[f] + io.beta * R.b[f];
-      if ((f & 1) && R.active && L.colok && R.fid[f] < io.nff)
-        put<MODE>(io.p_out + (int64_t)R.fid[f] * NF + L.col, v);   // the element below owns the face
+      // the element below owns the face; on a Neumann side the only element
+      if (((f & 1) || ((R.nm >> f) & 1)) && R.active && L.colok && R.fid[f] < io.nff)
+        put<MODE>(io.p_out + (int64_t)R.fid[f] * NF + L.col, v);
     }
     xf[f] = v;
     if (f < 4 && R.active && L.colok) sm.face[L.sl][f][L.col] = v;
   }
   double dot = 0.0;
-  unit_core<T, NP, EPB, MODE>(io, tab, sm, L, R.active, R.fid, R.d, xf, &dot);
+  unit_core<T, NP, EPB, MODE>(io, tab, sm, L, R.active, R.fid, R.nm, R.d, xf, &dot);
   acc[0] += dot;
 }
 
@@ -332,7 +339,9 @@ __device__ inline void cg2_loads(const UnitIO<T>& io, const UnitLane& L, const U
 
 // Per face: s = D^-1 w + beta s_old, z = z_old - alpha s, and on the faces
 // the unit owns p = z_old + beta p_old, x += alpha p and the r.z, r.r
-// shares; then the operator applied to z.
+// shares; then the operator applied to z.  A unit owns the high face of each
+// axis and, on a Neumann side at the low end of the box, the low face too;
+// the loads of the latter are issued here (rare: boundary elements only).
 template <typename T, int NP, int EPB, typename Tab>
 __device__ inline void cg2_compute(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
                                    const UnitLane& L, const UnitRegs<T>& R, const CgLoads<T>& C,
@@ -345,6 +354,7 @@ __device__ inline void cg2_compute(const UnitIO<T>& io, const Tab& tab, UnitSmem
     if (C.on[f]) {
       const int64_t g = (int64_t)R.fid[f] * NF + L.col;
       const T d = C.dv[f];
+      const bool own_lo = !(f & 1) && ((R.nm >> f) & 1);
       if (io.first) {
         v = C.zo[f];
       } else {
@@ -356,9 +366,16 @@ __device__ inline void cg2_compute(const UnitIO<T>& io, const Tab& tab, UnitSmem
           io.p_out[g] = pn;
           io.z_new[g] = v;
           io.x[g] = C.xo[f >> 1] + io.alpha * pn;
+        } else if (own_lo) {
+          const T pn = C.zo[f] + io.beta * io.p_in[g];
+          const T xo = io.x[g];
+          io.s_new[g] = sn;
+          io.p_out[g] = pn;
+          io.z_new[g] = v;
+          io.x[g] = xo + io.alpha * pn;
         }
       }
-      if (f & 1) {
+      if ((f & 1) || own_lo) {
         const double r = (double)div_fast(v, d);
         acc[1] += (double)v * r;
         acc[2] += r * r;
@@ -368,7 +385,7 @@ __device__ inline void cg2_compute(const UnitIO<T>& io, const Tab& tab, UnitSmem
     if (f < 4 && R.active && L.colok) sm.face[L.sl][f][L.col] = v;
   }
   double dot = 0.0;
-  unit_core<T, NP, EPB, 2>(io, tab, sm, L, R.active, R.fid, R.d, xf, &dot);
+  unit_core<T, NP, EPB, 2>(io, tab, sm, L, R.active, R.fid, R.nm, R.d, xf, &dot);
   acc[0] += dot;
 }
 

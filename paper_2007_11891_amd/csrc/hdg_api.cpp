@@ -234,6 +234,7 @@ int cg_variant_of(const hdg_ctx* c, const hdg_solve_opts* o) {
 
 hdg_status validate_opts(const hdg_solve_opts* o) {
   if (!(o->rtol > 0.0) || o->maxit < 1 || o->precond < 0 || o->precond > 3 ||
+      (o->guess != 0 && o->guess != 1) ||
       (o->variant < -1 || o->variant > 1) ||
       (o->mixed != 0 && o->mixed != 1) || o->check_every < 1 ||
       (o->mixed && (!(o->inner_rtol > 0.0) || o->inner_rtol >= 1.0 || o->max_outer < 1)))
@@ -355,7 +356,8 @@ hdg_status solve_eigen(hdg_ctx* c, const double* b, double* x_out, const hdg_sol
   return result;
 }
 
-int64_t n_bdry_faces(const hdg_ctx* c) { return c->n_faces - c->n_free_faces; }
+// faces of the boundary tail: the Dirichlet faces, then the g_N block
+int64_t n_bdry_faces(const hdg_ctx* c) { return (c->n_all - c->n_free) / ((int64_t)c->np * c->np); }
 
 // Eigen-basis Dirichlet data of a nodal trace (tail) into c->d_tmp[0]'s
 // boundary scratch; returns the pointer (or null for a null trace).
@@ -472,6 +474,55 @@ hdg_status solve_any(hdg_ctx* c, const double* bhat, double* xhat, const hdg_sol
   return st;
 }
 
+// solve_any from the initial guess x^0 held in xhat (eigen basis): the
+// correction d solves K^ d = b^ - K^ x^0 with the tolerance scaled so that
+// the test ||r|| <= rtol ||F|| keeps its meaning (norms in the basis the
+// chosen solver measures: eigen for precond 1, nodal otherwise); then
+// x^ = x^0 + d.  info reports the correction's iterations and the residual
+// relative to ||F||.
+hdg_status solve_from_guess(hdg_ctx* c, const double* bhat, double* xhat, const hdg_solve_opts* o,
+                            hdg_solve_info* info) {
+  if (!o->guess) return solve_any(c, bhat, xhat, o, info);
+  auto t0 = std::chrono::steady_clock::now();
+  ST_TRY(alloc_work(c, c->w64));
+  if (!c->d_guess) ST_TRY(dalloc(&c->d_guess, 2 * c->n_free));
+  double* r0 = c->d_guess;
+  double* dx = c->d_guess + c->n_free;
+  double rr0 = 0.0;
+  ST_TRY(residual64(c, bhat, xhat, &rr0));   // r^0 = b^ - K^ x^0 into d_tmp[2]
+  HIP_TRY(launch_copy64(c->d_tmp[2], r0, c->n_free, c->stream));
+  double nb2 = 0.0, nr2 = rr0;
+  if (o->precond == 1) {
+    ST_TRY(norm2_64(c, bhat, &nb2));
+  } else {
+    HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_NODAL_RESIDUAL), bhat, nullptr,
+                                          c->d_tmp[2], c->n_free_faces, c->stream));
+    ST_TRY(norm2_64(c, c->d_tmp[2], &nb2));
+    HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_NODAL_RESIDUAL), r0, nullptr,
+                                          c->d_tmp[2], c->n_free_faces, c->stream));
+    ST_TRY(norm2_64(c, c->d_tmp[2], &nr2));
+  }
+  const double nb = std::sqrt(nb2), nr = std::sqrt(nr2);
+  hdg_solve_info inf{};
+  hdg_status st = HDG_OK;
+  if (nr <= o->rtol * nb || nr == 0.0) {
+    inf.rel_res = nb > 0.0 ? nr / nb : 0.0;
+  } else {
+    hdg_solve_opts o2 = *o;
+    o2.guess = 0;
+    o2.rtol = o->rtol * nb / nr;
+    st = solve_any(c, r0, dx, &o2, &inf);
+    if (st != HDG_OK && st != HDG_ENOCONV) return st;
+    HIP_TRY(launch_add64(dx, xhat, c->n_free, c->stream));
+    inf.rel_res *= nr / nb;
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  inf.rhs_norm = nb;
+  inf.t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  return st;
+}
+
 hdg_status upload_lambda_and_diag(hdg_ctx* c) {
   HIP_TRY(launch_diag(c, c->d_diag, c->stream));
   HIP_TRY(launch_recip_64_32(c->d_diag, c->d_dinv32, c->d_tmp[3], c->n_free, c->stream));
@@ -492,6 +543,7 @@ void hdg_default_opts(hdg_solve_opts* o) {
   o->max_outer = 12;
   o->check_every = 25;
   o->variant = -1;
+  o->guess = 0;
 }
 
 const char* hdg_last_error(void) { return g_err.c_str(); }
@@ -515,6 +567,12 @@ hdg_status hdg_tables(int p, double tau_hat, double* x, double* w, double* D, do
 hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, const double* h3,
                       int p, double tau_hat, const double* lambda_host, double lambda_const,
                       void* stream, hdg_ctx** out) {
+  return hdg_create_bc(n_elem, h1, h2, h3, p, tau_hat, lambda_host, lambda_const, 0, stream, out);
+}
+
+hdg_status hdg_create_bc(const int n_elem[3], const double* h1, const double* h2,
+                         const double* h3, int p, double tau_hat, const double* lambda_host,
+                         double lambda_const, int neumann_sides, void* stream, hdg_ctx** out) {
   if (!out) return fail(HDG_EINVAL, "out is NULL");
   *out = nullptr;
   if (!n_elem) return fail(HDG_EINVAL, "n_elem is NULL");
@@ -538,6 +596,19 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
   } else if (!(lambda_const >= 0.0) || !std::isfinite(lambda_const)) {
     return fail(HDG_EINVAL, "lambda_const must be finite and >= 0");
   }
+  if (neumann_sides < 0 || neumann_sides > 63)
+    return fail(HDG_EINVAL, "neumann_sides must be a mask of bits 0..5, got %d", neumann_sides);
+  if (neumann_sides == 63) {
+    bool any = false;
+    if (lambda_host) {
+      for (int64_t e = 0; e < ne && !any; ++e) any = lambda_host[e] > 0.0;
+    } else {
+      any = lambda_const > 0.0;
+    }
+    if (!any)
+      return fail(HDG_EINVAL, "every side Neumann with lambda = 0: the condensed operator is "
+                              "singular (constants are in its kernel)");
+  }
 
   hdg_ctx* c = new (std::nothrow) hdg_ctx();
   if (!c) return fail(HDG_ENOMEM, "host allocation failed");
@@ -551,6 +622,7 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
   c->p = p;
   c->np = p + 1;
   c->tau = tau_hat;
+  c->neumann = neumann_sides;
   c->n_elem = ne;
   // CG form before any autotuning: one kernel per iteration for meshes small
   // enough that launch latency dominates, else the two-kernel form (the
@@ -559,12 +631,27 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
   const int n1 = n_elem[0], n2 = n_elem[1], n3 = n_elem[2];
   const int64_t nf0 = (int64_t)(n1 - 1) * n2 * n3, nf1 = (int64_t)n1 * (n2 - 1) * n3,
                 nf2 = (int64_t)n1 * n2 * (n3 - 1);
-  c->n_free_faces = nf0 + nf1 + nf2;
   const int64_t tb[3] = {(int64_t)n2 * n3, (int64_t)n1 * n3, (int64_t)n1 * n2};
-  c->n_faces = c->n_free_faces + 2 * (tb[0] + tb[1] + tb[2]);
+  // face ids: interior faces, then the Neumann sides (free), then the
+  // Dirichlet sides, each side in the order (0,0), (0,1), (1,0), ... (2,1)
+  int64_t side_off[6];
+  c->n_int_faces = nf0 + nf1 + nf2;
+  {
+    int64_t off = c->n_int_faces;
+    for (int pass = 1; pass >= 0; --pass) {
+      for (int k = 0; k < 6; ++k)
+        if (((neumann_sides >> k) & 1) == pass) {
+          side_off[k] = off;
+          off += tb[k >> 1];
+        }
+      if (pass == 1) c->n_free_faces = off;
+    }
+    c->n_faces = off;
+  }
+  c->n_neu_faces = c->n_free_faces - c->n_int_faces;
   const int64_t npf = (int64_t)c->np * c->np;
   c->n_free = c->n_free_faces * npf;
-  c->n_all = c->n_faces * npf;
+  c->n_all = (c->n_faces + c->n_neu_faces) * npf;
   c->n_vol = ne * npf * c->np;
   c->tab = make_tables(p, tau_hat);
   for (int a = 0; a < 3; ++a) c->h_host[a].assign(hs[a], hs[a] + n_elem[a]);
@@ -643,13 +730,11 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
   m.foff[0] = 0;
   m.foff[1] = nf0;
   m.foff[2] = nf0 + nf1;
-  int64_t off = c->n_free_faces;
-  for (int a = 0; a < 3; ++a)
-    for (int s = 0; s < 2; ++s) {
-      m.boff[2 * a + s] = off;
-      off += tb[a];
-    }
+  for (int k = 0; k < 6; ++k) m.boff[k] = side_off[k];
+  m.neumann = neumann_sides;
+  m.n_int_faces = c->n_int_faces;
   m.n_free_faces = c->n_free_faces;
+  m.n_dir_faces = c->n_faces - c->n_free_faces;
   {
     // per-element face ids and metric factors
     std::vector<ElemInfo> info((size_t)ne);
@@ -669,7 +754,14 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, c
                                       ? m.foff[2] + i + (int64_t)n1 * (j + (int64_t)n2 * (pl2 - 1))
                                       : m.boff[4 + (pl2 == 0 ? 0 : 1)] + i + (int64_t)n1 * j);
           }
-          ei.pad[0] = ei.pad[1] = 0;
+          ei.nmask = 0;
+          ei.pad = 0;
+          const int pls[3] = {i, j, k}, nls[3] = {n1, n2, n3};
+          for (int f = 0; f < 6; ++f) {
+            const int a = f >> 1, s = f & 1;
+            const bool bnd = (pls[a] + s == 0) || (pls[a] + s == nls[a]);
+            if (bnd && ((neumann_sides >> (2 * a + (s ? 1 : 0))) & 1)) ei.nmask |= 1 << f;
+          }
           const double d0 = hs[0][i] * hs[1][j] * hs[2][k] * 0.125;
           ei.d[0] = d0;
           ei.d[1] = d0 * (2.0 / hs[0][i]) * (2.0 / hs[0][i]);
@@ -711,6 +803,7 @@ hdg_status hdg_destroy(hdg_ctx* c) {
   dfree(c->d_dinv32);
   for (auto& t : c->d_tmp) dfree(t);
   dfree(c->d_vol_tmp);
+  dfree(c->d_guess);
   dfree(c->d_red);
   dfree(c->d_cnt);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -801,6 +894,11 @@ hdg_status hdg_coords(hdg_ctx* c, double* vol_xyz, double* trace_xyz) {
                             : m.boff[4 + (pl == 0 ? 0 : 1)] + i + (int64_t)n1 * j;
           put(fid, 2, pl, i, j);
         }
+    // the g_N block repeats the nodes of the Neumann faces
+    const size_t fw = (size_t)np * np * 3;
+    for (int64_t f = c->n_int_faces; f < c->n_free_faces; ++f)
+      std::copy(t.begin() + f * fw, t.begin() + (f + 1) * fw,
+                t.begin() + (c->n_faces + f - c->n_int_faces) * fw);
     HIP_TRY(hipMemcpyAsync(trace_xyz, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice,
                            c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -812,7 +910,8 @@ hdg_status hdg_face_transform(hdg_ctx* c, hdg_transform kind, const double* in, 
                               int64_t n_faces) {
   if (!c || !in || !out) return fail(HDG_EINVAL, "NULL argument");
   if (kind < 0 || kind > 3) return fail(HDG_EINVAL, "unknown transform %d", (int)kind);
-  if (n_faces < 0 || n_faces > c->n_faces) return fail(HDG_EINVAL, "n_faces out of range");
+  if (n_faces < 0 || n_faces > c->n_all / ((int64_t)c->np * c->np))
+    return fail(HDG_EINVAL, "n_faces out of range");
   HIP_TRY(launch_face_transform<double>(c->np, mat64(c, kind), in, nullptr, out, n_faces,
                                         c->stream));
   return HDG_OK;
@@ -895,7 +994,10 @@ hdg_status hdg_solve(hdg_ctx* c, const double* F_free, double* u_free, const hdg
                                         bhat, c->n_free_faces, c->stream));
   double* xhat = c->d_tmp[1];
   if (o.mixed) xhat = u_free;   // d_tmp[1] holds the FP32 right-hand side in mixed mode
-  hdg_status st = solve_any(c, bhat, xhat, &o, info);
+  if (o.guess)
+    HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_EIGEN_UNKNOWN), u_free, nullptr,
+                                          xhat, c->n_free_faces, c->stream));
+  hdg_status st = solve_from_guess(c, bhat, xhat, &o, info);
   if (st != HDG_OK && st != HDG_ENOCONV) return st;
   HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_NODAL_UNKNOWN), xhat, nullptr,
                                         u_free, c->n_free_faces, c->stream));
@@ -920,7 +1022,10 @@ hdg_status hdg_solve_forcing(hdg_ctx* c, const double* f, double* trace, double*
     HIP_TRY(launch_volume(c, VOL_RHS, 1, f, nullptr, xb, nullptr, nullptr, w.qa, w.qb, nullptr,
                           nullptr, c->stream));
     HIP_TRY(launch_combine<double>(w.qa, w.qb, bhat, c->n_free, c->stream));
-    st = solve_any(c, bhat, xhat, &o, info);
+    if (o.guess)   // in place: the guess in the free part of trace
+      HIP_TRY(launch_face_transform<double>(c->np, mat64(c, HDG_TO_EIGEN_UNKNOWN), trace, nullptr,
+                                            xhat, c->n_free_faces, c->stream));
+    st = solve_from_guess(c, bhat, xhat, &o, info);
     if (st != HDG_OK && st != HDG_ENOCONV) return st;
   } else if (info) {
     *info = hdg_solve_info{};
@@ -948,6 +1053,17 @@ hdg_status hdg_reconstruct(hdg_ctx* c, const double* f, const double* trace, dou
   return HDG_OK;
 }
 
+hdg_status hdg_hybridize(hdg_ctx* c, const double* u_vol, const double* trace,
+                         double* trace_free) {
+  if (!c || !u_vol || !trace_free) return fail(HDG_EINVAL, "NULL argument");
+  if (c->n_free == 0) return HDG_OK;
+  CgWork<double>& w = c->w64;
+  HIP_TRY(launch_volume(c, VOL_HYB, 0, u_vol, nullptr, trace ? trace + c->n_free : nullptr,
+                        nullptr, nullptr, w.qa, w.qb, nullptr, nullptr, c->stream));
+  HIP_TRY(launch_combine<double>(w.qa, w.qb, trace_free, c->n_free, c->stream));
+  return HDG_OK;
+}
+
 hdg_status hdg_adjoint(hdg_ctx* c, const double* f, const double* trace, const double* dJdu,
                        double* dJdlambda, double* dJdf, const hdg_solve_opts* opts,
                        hdg_solve_info* info) {
@@ -956,6 +1072,7 @@ hdg_status hdg_adjoint(hdg_ctx* c, const double* f, const double* trace, const d
   hdg_default_opts(&o);
   if (opts) o = *opts;
   ST_TRY(validate_opts(&o));
+  o.guess = 0;
   const double* xb = nullptr;
   ST_TRY(eigen_boundary(c, trace, &xb));
   CgWork<double>& w = c->w64;

@@ -22,23 +22,29 @@ struct ElemTab {
 };
 
 // Per-element data precomputed at set-up: the six face ids (axis a, side s
-// at index 2a+s; ids >= n_free_faces are boundary faces) and the metric
-// factors d0..d3 (paper, section "LDG operator structure in three
-// dimensions").  64 bytes, read with scalar loads.
+// at index 2a+s; ids >= n_free_faces are Dirichlet faces), the faces that
+// are unknowns with this element alone (bit 2a+s: a face on a Neumann side
+// of the box) and the metric factors d0..d3 (paper, section "LDG operator
+// structure in three dimensions").  64 bytes, read with scalar loads.
 struct ElemInfo {
   int fid[6];
-  int pad[2];
+  int nmask;
+  int pad;
   double d[4];
 };
 
 // Mesh description on the device.  Face ids follow the canonical layout:
-// free faces of axis 0, 1, 2 then the boundary tail (see include/hdg.h).
+// interior faces of axis 0, 1, 2, the faces of the Neumann sides (free), then
+// the faces of the Dirichlet sides (see include/hdg.h).
 struct MeshDev {
   int n1, n2, n3;
+  int neumann;         // bit 2a+s: side s of axis a is a Neumann side
   int64_t n_elem;
-  int64_t foff[3];     // first free face id of each axis
-  int64_t boff[6];     // first boundary face id of (axis, side)
-  int64_t n_free_faces;
+  int64_t foff[3];     // first interior face id of each axis
+  int64_t boff[6];     // first face id of (axis, side), free or Dirichlet
+  int64_t n_int_faces;   // interior faces
+  int64_t n_free_faces;  // interior + Neumann faces
+  int64_t n_dir_faces;   // faces of the Dirichlet sides
   const double* h1;
   const double* h2;
   const double* h3;
@@ -108,8 +114,10 @@ struct hdg_ctx {
   int tile_variant = 0;           // elements per work unit: epb_max >> variant
   int cg_variant = 1;             // CG form when the options leave it open
   double tau = 0.0;
+  int neumann = 0;                // bit 2a+s: side s of axis a is a Neumann side
   int64_t n_elem = 0, n_free = 0, n_all = 0, n_vol = 0;
   int64_t n_free_faces = 0, n_faces = 0;
+  int64_t n_int_faces = 0, n_neu_faces = 0;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;   // private stream for graph capture
   int device = 0;
@@ -134,6 +142,7 @@ struct hdg_ctx {
   // inner rhs (mixed), [2] FP64 residual, [3] inverse diagonal (FP64)
   double* d_tmp[4] = {nullptr, nullptr, nullptr, nullptr};
   double* d_vol_tmp = nullptr;
+  double* d_guess = nullptr;    // free-length scratch of solves from an initial guess (lazy)
   double* d_red = nullptr;      // small reduction scratch
   unsigned* d_cnt = nullptr;
   hdg::CgScalars* h_scal = nullptr;   // pinned host slots: [0..1] polling, [2] upload
@@ -188,7 +197,9 @@ hipError_t launch_face_transform(int np, const T* A, const T* in, const T* in2, 
 hipError_t launch_diag(const hdg_ctx* c, double* diag, hipStream_t s);
 
 // volume-source element kernel (RHS / recovery / adjoint)
-enum VolMode { VOL_RHS = 0, VOL_RECON = 1, VOL_ADJ = 2 };
+// (VOL_HYB: the initial-guess flux of a volume field, f = the field,
+// x_bdry = the nodal boundary tail for g_N, output into qa / qb)
+enum VolMode { VOL_RHS = 0, VOL_RECON = 1, VOL_ADJ = 2, VOL_HYB = 3 };
 hipError_t launch_volume(const hdg_ctx* c, int mode, int src_is_forcing,
                          const double* f, const double* x_free, const double* x_bdry,
                          const double* r2, const double* mu_free,
@@ -202,6 +213,7 @@ hipError_t launch_axpy_32_64(const float* in, double* out, double scale, int64_t
                              hipStream_t s);
 hipError_t launch_fill64(double* out, double v, int64_t n, hipStream_t s);
 hipError_t launch_copy64(const double* in, double* out, int64_t n, hipStream_t s);
+hipError_t launch_add64(const double* in, double* out, int64_t n, hipStream_t s);   // out += in
 hipError_t launch_fill32(float* out, float v, int64_t n, hipStream_t s);
 hipError_t launch_recip_64_32(const double* diag, float* dinv32, double* dinv64, int64_t n,
                               hipStream_t s);

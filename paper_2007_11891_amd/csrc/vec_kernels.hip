@@ -316,6 +316,18 @@ __global__ void copy64_kernel(int64_t n, const double* __restrict__ in, double* 
        g += (int64_t)gridDim.x * blockDim.x)
     out[g] = in[g];
 }
+__global__ void add64_kernel(int64_t n, const double* __restrict__ in, double* __restrict__ out) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x)
+    out[g] += in[g];
+}
+hipError_t launch_add64(const double* in, double* out, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(add64_kernel, dim3(vec_blocks(n, 8192)), dim3(kVecThreads), 0, s, n, in,
+                     out);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy64(const double* in, double* out, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(copy64_kernel, dim3(vec_blocks(n, 8192)), dim3(kVecThreads), 0, s, n, in,
@@ -457,63 +469,90 @@ template hipError_t launch_face_transform<float>(int, const float*, const float*
                                                  float*, int64_t, hipStream_t);
 
 // ------------------------------------------------------------ diagonal ----
-// diag(K^) at a free face node: sum over the two adjacent elements of
+// diag(K^) at a free face node: sum over the adjacent elements of
 //   d_a H - d_a^2 sum_q BS[q,s]^2 / (lambda d0 + d_a Lam[q] + d_b Lam[qb] + d_c Lam[qc])
 // with s = 1 for the element below the face and s = 0 for the one above
 // (paper: equation (hdg_op_east_east_transformed) and the diagonal
-// preconditioner that follows it).
+// preconditioner that follows it).  An interior face has two elements, a
+// face of a Neumann side one.
+__device__ inline double diag_share(const MeshDev& m, const ElemTab<double>& tab, int np, int a,
+                                    int ei, int ej, int ek, int s, int qb, int qc) {
+  const int64_t e = ei + (int64_t)m.n1 * (ej + (int64_t)m.n2 * ek);
+  const double h1 = m.h1[ei], h2 = m.h2[ej], h3 = m.h3[ek];
+  const double d0 = h1 * h2 * h3 * 0.125;
+  const double dd[3] = {d0 * 4.0 / (h1 * h1), d0 * 4.0 / (h2 * h2), d0 * 4.0 / (h3 * h3)};
+  const int b = (a == 0) ? 1 : 0;
+  const int c = (a == 2) ? 1 : 2;
+  const double base = d0 * m.lam[e] + dd[b] * tab.lam[qb] + dd[c] * tab.lam[qc];
+  const double* bs = s ? tab.bs1 : tab.bs0;
+  double sum = 0.0;
+  for (int q = 0; q < np; ++q) sum += bs[q] * bs[q] / (base + dd[a] * tab.lam[q]);
+  return dd[a] * tab.H - dd[a] * dd[a] * sum;
+}
+
 __global__ void __launch_bounds__(256)
 diag_kernel(const MeshDev m, const ElemTab<double> tab, int np, double* __restrict__ diag) {
   const int nf = np * np;
   const int64_t n = m.n_free_faces * nf;
+  const int nel[3] = {m.n1, m.n2, m.n3};
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
        g += (int64_t)gridDim.x * blockDim.x) {
     const int64_t fid = g / nf;
     const int lt = (int)(g - fid * nf);
     const int qb = lt % np, qc = lt / np;
-    int a, pl, ti, tj, tk;   // axis, plane, element indices (one replaced by plane)
-    if (fid < m.foff[1]) {
-      a = 0;
-      int64_t loc = fid - m.foff[0];
-      pl = (int)(loc % (m.n1 - 1)) + 1;
-      loc /= (m.n1 - 1);
-      tj = (int)(loc % m.n2);
-      tk = (int)(loc / m.n2);
-      ti = 0;
-    } else if (fid < m.foff[2]) {
-      a = 1;
-      int64_t loc = fid - m.foff[1];
-      ti = (int)(loc % m.n1);
-      loc /= m.n1;
-      pl = (int)(loc % (m.n2 - 1)) + 1;
-      tk = (int)(loc / (m.n2 - 1));
-      tj = 0;
-    } else {
-      a = 2;
-      int64_t loc = fid - m.foff[2];
-      ti = (int)(loc % m.n1);
-      loc /= m.n1;
-      tj = (int)(loc % m.n2);
-      pl = (int)(loc / m.n2) + 1;
-      tk = 0;
-    }
     double acc = 0.0;
-    for (int side = 0; side < 2; ++side) {
-      // side 0: element below (its high face, s = 1); side 1: element above (s = 0)
-      const int ei = (a == 0) ? pl - 1 + side : ti;
-      const int ej = (a == 1) ? pl - 1 + side : tj;
-      const int ek = (a == 2) ? pl - 1 + side : tk;
-      const int64_t e = ei + (int64_t)m.n1 * (ej + (int64_t)m.n2 * ek);
-      const double h1 = m.h1[ei], h2 = m.h2[ej], h3 = m.h3[ek];
-      const double d0 = h1 * h2 * h3 * 0.125;
-      const double dd[3] = {d0 * 4.0 / (h1 * h1), d0 * 4.0 / (h2 * h2), d0 * 4.0 / (h3 * h3)};
-      const int b = (a == 0) ? 1 : 0;
-      const int c = (a == 2) ? 1 : 2;
-      const double base = d0 * m.lam[e] + dd[b] * tab.lam[qb] + dd[c] * tab.lam[qc];
-      const double* bs = (side == 0) ? tab.bs1 : tab.bs0;
-      double sum = 0.0;
-      for (int q = 0; q < np; ++q) sum += bs[q] * bs[q] / (base + dd[a] * tab.lam[q]);
-      acc += dd[a] * tab.H - dd[a] * dd[a] * sum;
+    if (fid < m.n_int_faces) {
+      int a, pl, ti, tj, tk;   // axis, plane, element indices (one replaced by plane)
+      if (fid < m.foff[1]) {
+        a = 0;
+        int64_t loc = fid - m.foff[0];
+        pl = (int)(loc % (m.n1 - 1)) + 1;
+        loc /= (m.n1 - 1);
+        tj = (int)(loc % m.n2);
+        tk = (int)(loc / m.n2);
+        ti = 0;
+      } else if (fid < m.foff[2]) {
+        a = 1;
+        int64_t loc = fid - m.foff[1];
+        ti = (int)(loc % m.n1);
+        loc /= m.n1;
+        pl = (int)(loc % (m.n2 - 1)) + 1;
+        tk = (int)(loc / (m.n2 - 1));
+        tj = 0;
+      } else {
+        a = 2;
+        int64_t loc = fid - m.foff[2];
+        ti = (int)(loc % m.n1);
+        loc /= m.n1;
+        tj = (int)(loc % m.n2);
+        pl = (int)(loc / m.n2) + 1;
+        tk = 0;
+      }
+      for (int side = 0; side < 2; ++side) {
+        // side 0: element below (its high face, s = 1); side 1: element above (s = 0)
+        const int ei = (a == 0) ? pl - 1 + side : ti;
+        const int ej = (a == 1) ? pl - 1 + side : tj;
+        const int ek = (a == 2) ? pl - 1 + side : tk;
+        acc += diag_share(m, tab, np, a, ei, ej, ek, 1 - side, qb, qc);
+      }
+    } else {
+      // a face of a Neumann side: find the side, then its one element
+      int k = 0;
+      for (; k < 5; ++k) {
+        if (!((m.neumann >> k) & 1)) continue;
+        const int a = k >> 1;
+        const int64_t cnt = (int64_t)nel[a == 0 ? 1 : 0] * nel[a == 2 ? 1 : 2];
+        if (fid >= m.boff[k] && fid < m.boff[k] + cnt) break;
+      }
+      const int a = k >> 1, s = k & 1;
+      const int64_t loc = fid - m.boff[k];
+      const int nb = nel[a == 0 ? 1 : 0];
+      const int tb = (int)(loc % nb), tc = (int)(loc / nb);
+      const int pos = s ? nel[a] - 1 : 0;
+      const int ei = (a == 0) ? pos : tb;
+      const int ej = (a == 1) ? pos : (a == 0 ? tb : tc);
+      const int ek = (a == 2) ? pos : tc;
+      acc = diag_share(m, tab, np, a, ei, ej, ek, s, qb, qc);
     }
     diag[g] = acc;
   }

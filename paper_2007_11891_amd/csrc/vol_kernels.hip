@@ -11,6 +11,18 @@
 //   adjoint:  a = D_Z^-1 (S_e^T r - B^_e mu),  u_E = D_Z^-1 (S_e^T M_e f - B^_e x)
 //             dJ/dlambda_e = -d0 sum a u_E,  dJ/df_e = d0 (M S x M S x M S) a
 //
+// On a face of a Neumann side the right-hand side also carries the face
+// integral of mu g_N (the flux row of the element system); in the eigen
+// basis that is (h_b h_c / 4) (S^T M x S^T M) g_N, the tail transform of the
+// g_N block scaled by the face measure.
+//
+// The initial-guess flux (section "Summary of solution method", equation
+// (fluxu)) of a volume field u with q = grad u: each element adds
+//   (tau_e u - q.n + [g_N on a Neumann face]) / (tau_e + tau_neighbour)
+// to each of its free faces, tau = 2 tau_hat / h_a, tau_neighbour = 0 on a
+// Neumann face; q.n at a face node is (2s - 1) (2 / h_a) sum_k phi_k'(+-1)
+// u_k along the normal line.
+//
 // These run once per solve and cost O(n_p^4) per element (three 1D
 // contractions of the n_p^3 cube held in LDS).  One element per block.
 #include "device_common.hpp"
@@ -29,6 +41,8 @@ struct VolArgs {
   double* out_elem;
   const double* mats;     // St, StM, S, MS (row-major n_p x n_p each)
   int src_is_forcing;     // 1: g = d0 (S^T M)^3 f, 0: g = (S^T)^3 f
+  double tau_hat;         // VOL_HYB: penalty scale
+  double dend[2][kMaxNP]; // VOL_HYB: phi_k'(-1), phi_k'(+1) on the reference interval
 };
 
 // cube <- scale * (A x A x A) cube, cube [q3][q2][q1]; NF threads, thread lt
@@ -64,27 +78,27 @@ __device__ inline void cube_transform(double* cube, const double* __restrict__ A
 }
 
 template <int NP>
-__device__ inline void load_faces(const MeshDev& m, int i, int j, int k, const double* x_free,
+__device__ inline void load_faces(const MeshDev& m, int64_t e, const double* x_free,
                                   const double* x_bdry, int lt, double* s_face, double* xf,
-                                  int64_t* fid, bool* ffree) {
+                                  int64_t* fid, bool* ffree, int* nm) {
   constexpr int NF = NP * NP;
+  const ElemInfo* ei = m.info + e;
+  *nm = ei->nmask;
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      bool fr;
-      const int64_t f = face_of(m, a, s, i, j, k, &fr);
-      fid[2 * a + s] = f;
-      ffree[2 * a + s] = fr;
-      double v = 0.0;
-      if (fr) {
-        if (x_free) v = x_free[f * NF + lt];
-      } else if (x_bdry) {
-        v = x_bdry[(f - m.n_free_faces) * NF + lt];
-      }
-      xf[2 * a + s] = v;
-      s_face[(2 * a + s) * NF + lt] = v;
+  for (int f = 0; f < 6; ++f) {
+    const int64_t id = ei->fid[f];
+    const bool fr = id < m.n_free_faces;
+    fid[f] = id;
+    ffree[f] = fr;
+    double v = 0.0;
+    if (fr) {
+      if (x_free) v = x_free[id * NF + lt];
+    } else if (x_bdry) {
+      v = x_bdry[(id - m.n_free_faces) * NF + lt];
     }
+    xf[f] = v;
+    s_face[f * NF + lt] = v;
+  }
 }
 
 // w = (cube - B^ x) / D_Z in place; returns the axis-2 reductions.
@@ -110,6 +124,61 @@ __device__ inline void eig_solve(double* cube, const double* s_face, const doubl
   }
   *r2lo = lo;
   *r2hi = hi;
+}
+
+// VOL_HYB: the initial-guess flux contributions of element e (cube = u_e in
+// LDS, loaded and synchronised by the caller).  Thread lt holds face node lt
+// of every face: (q2,q3), (q1,q3), (q1,q2) for the faces normal to x1, x2, x3.
+template <int NP>
+__device__ inline void hyb_faces(const MeshDev& m, const VolArgs& va, int64_t e, int i, int j,
+                                 int k, const double* cube, int lt, bool active) {
+  constexpr int NF = NP * NP;
+  if (!active) return;
+  const ElemInfo* ei = m.info + e;
+  const int nm = ei->nmask;
+  const int idx[3] = {i, j, k};
+  const int nel[3] = {m.n1, m.n2, m.n3};
+  const double* hs[3] = {m.h1, m.h2, m.h3};
+  const int r = lt % NP, t = lt / NP;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int base, stride;
+    if (a == 0) { base = NP * lt; stride = 1; }
+    else if (a == 1) { base = r + NF * t; stride = NP; }
+    else { base = lt; stride = NF; }
+    double line[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) line[q] = cube[base + stride * q];
+    const double h = hs[a][idx[a]];
+    const double tau_e = 2.0 * va.tau_hat / h;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int f = 2 * a + s;
+      const int64_t id = ei->fid[f];
+      if (id >= m.n_free_faces) continue;
+      double der = 0.0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) der += va.dend[s][q] * line[q];
+      const double qn = (s ? 1.0 : -1.0) * (2.0 / h) * der;
+      double num = tau_e * line[s ? NP - 1 : 0] - qn;
+      double den = tau_e;
+      const bool neu = (nm >> f) & 1;
+      if (neu) {
+        if (va.x_bdry) num += va.x_bdry[(m.n_dir_faces + id - m.n_int_faces) * NF + lt];
+      } else {
+        const int nb = idx[a] + (s ? 1 : -1);
+        if (nb >= 0 && nb < nel[a]) den += 2.0 * va.tau_hat / hs[a][nb];
+      }
+      const int64_t g = id * NF + lt;
+      const double v = num / den;
+      if (s) va.qa[g] = v;
+      else va.qb[g] = v;
+      if (neu) {
+        if (s) va.qb[g] = 0.0;
+        else va.qa[g] = 0.0;
+      }
+    }
+  }
 }
 
 template <int NP, int MODE>
@@ -150,6 +219,10 @@ volume_kernel(const MeshDev mesh, const ElemTab<double> tab, VolArgs va) {
     }
   }
   __syncthreads();
+  if constexpr (MODE == VOL_HYB) {
+    hyb_faces<NP>(mesh, va, e, i, j, k, s_cube, lt, active);
+    return;
+  }
   if (MODE == VOL_ADJ || va.src_is_forcing) cube_transform<NP>(s_cube, StM, d0, lt, active);
   else cube_transform<NP>(s_cube, St, 1.0, lt, active);
   if constexpr (MODE == VOL_ADJ) cube_transform<NP>(s_cube2, St, 1.0, lt, active);
@@ -157,8 +230,9 @@ volume_kernel(const MeshDev mesh, const ElemTab<double> tab, VolArgs va) {
   double xf[6];
   int64_t fid[6];
   bool ffree[6];
+  int nm = 0;
   double r2lo = 0.0, r2hi = 0.0;
-  if (active) load_faces<NP>(mesh, i, j, k, va.x_free, va.x_bdry, lt, s_face, xf, fid, ffree);
+  if (active) load_faces<NP>(mesh, e, va.x_free, va.x_bdry, lt, s_face, xf, fid, ffree, &nm);
   __syncthreads();
   if (active) eig_solve<NP>(s_cube, s_face, d, tab, lt, &r2lo, &r2hi);
   __syncthreads();
@@ -186,12 +260,24 @@ volume_kernel(const MeshDev mesh, const ElemTab<double> tab, VolArgs va) {
       }
       out[4] = -d[3] * r2lo;
       out[5] = -d[3] * r2hi;
+      const double hh[3] = {h1, h2, h3};
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
         if (!ffree[f]) continue;
         const int64_t g = fid[f] * NF + lt;
-        if (f & 1) va.qa[g] = out[f];
-        else va.qb[g] = out[f];
+        double v = out[f];
+        const bool neu = (nm >> f) & 1;
+        if (neu && va.x_bdry) {   // face integral of mu g_N, eigen basis
+          const int a = f >> 1;
+          const double area = 0.25 * hh[a == 0 ? 1 : 0] * hh[a == 2 ? 1 : 2];
+          v += area * va.x_bdry[(mesh.n_dir_faces + fid[f] - mesh.n_int_faces) * NF + lt];
+        }
+        if (f & 1) va.qa[g] = v;
+        else va.qb[g] = v;
+        if (neu) {
+          if (f & 1) va.qb[g] = 0.0;
+          else va.qa[g] = 0.0;
+        }
       }
     }
   } else if constexpr (MODE == VOL_RECON) {
@@ -201,7 +287,7 @@ volume_kernel(const MeshDev mesh, const ElemTab<double> tab, VolArgs va) {
       for (int q3 = 0; q3 < NP; ++q3) va.out_vol[e * NV + lt + NF * q3] = s_cube[lt + NF * q3];
     }
   } else {  // VOL_ADJ: adjoint cube a from (r2, mu); u_E already in s_cube
-    if (active) load_faces<NP>(mesh, i, j, k, va.mu_free, nullptr, lt, s_face, xf, fid, ffree);
+    if (active) load_faces<NP>(mesh, e, va.mu_free, nullptr, lt, s_face, xf, fid, ffree, &nm);
     __syncthreads();
     double t0, t1;
     if (active) eig_solve<NP>(s_cube2, s_face, d, tab, lt, &t0, &t1);
@@ -242,6 +328,7 @@ static hipError_t launch_vol_np(const hdg_ctx* c, int mode, const VolArgs& va, h
   if (c->n_elem == 0) return hipSuccess;
   if (mode == VOL_RHS) return launch_vol_mode<NP, VOL_RHS>(c, va, s);
   if (mode == VOL_RECON) return launch_vol_mode<NP, VOL_RECON>(c, va, s);
+  if (mode == VOL_HYB) return launch_vol_mode<NP, VOL_HYB>(c, va, s);
   return launch_vol_mode<NP, VOL_ADJ>(c, va, s);
 }
 
@@ -261,6 +348,11 @@ hipError_t launch_volume(const hdg_ctx* c, int mode, int src_is_forcing, const d
   va.out_elem = out_elem;
   va.mats = c->d_mats64;
   va.src_is_forcing = src_is_forcing ? 1 : 0;
+  va.tau_hat = c->tau;
+  for (int q = 0; q < c->np; ++q) {   // phi_q'(x_i) = D_iq / w_i at the end nodes
+    va.dend[0][q] = c->tab.D[q] / c->tab.w[0];
+    va.dend[1][q] = c->tab.D[(c->np - 1) * c->np + q] / c->tab.w[c->np - 1];
+  }
   switch (c->np) {
 #define HDG_CASE(N) \
   case N: return launch_vol_np<N>(c, mode, va, s);

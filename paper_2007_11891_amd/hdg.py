@@ -26,9 +26,10 @@ TO_EIGEN_UNKNOWN, TO_EIGEN_RESIDUAL, TO_NODAL_UNKNOWN, TO_NODAL_RESIDUAL = 0, 1,
 
 # every symbol include/hdg.h declares
 EXPORTS = (
-    "hdg_default_opts", "hdg_create", "hdg_destroy", "hdg_last_error", "hdg_sizes",
-    "hdg_set_lambda", "hdg_tables", "hdg_coords", "hdg_apply", "hdg_face_transform",
-    "hdg_rhs", "hdg_solve", "hdg_solve_forcing", "hdg_reconstruct", "hdg_adjoint",
+    "hdg_default_opts", "hdg_create", "hdg_create_bc", "hdg_destroy", "hdg_last_error",
+    "hdg_sizes", "hdg_set_lambda", "hdg_tables", "hdg_coords", "hdg_apply", "hdg_face_transform",
+    "hdg_rhs", "hdg_solve", "hdg_solve_forcing", "hdg_reconstruct", "hdg_hybridize",
+    "hdg_adjoint",
     "hdg_diagonal", "hdg_time_kernel", "hdg_set_tile", "hdg_autotune", "hdg_tile_shape",
     "hdg_batch_create", "hdg_batch_destroy", "hdg_batch_sizes", "hdg_batch_set_tile",
     "hdg_batch_tiles", "hdg_batch_autotune", "hdg_batch_time_cg", "hdg_batch_solve_forcing",
@@ -45,7 +46,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("maxit", ctypes.c_int), ("precond", ctypes.c_int),
                 ("mixed", ctypes.c_int), ("inner_rtol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("variant", ctypes.c_int)]
+                ("variant", ctypes.c_int), ("guess", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -83,6 +84,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hdg_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
         "hdg_create": (ctypes.c_int, [ip, dp, dp, dp, ctypes.c_int, ctypes.c_double, dp,
                                       ctypes.c_double, vp, ctypes.POINTER(vp)]),
+        "hdg_create_bc": (ctypes.c_int, [ip, dp, dp, dp, ctypes.c_int, ctypes.c_double, dp,
+                                         ctypes.c_double, ctypes.c_int, vp, ctypes.POINTER(vp)]),
         "hdg_destroy": (ctypes.c_int, [vp]),
         "hdg_last_error": (ctypes.c_char_p, []),
         "hdg_sizes": (ctypes.c_int, [vp, i64p, i64p, i64p]),
@@ -97,6 +100,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hdg_solve_forcing": (ctypes.c_int, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
                                              ctypes.POINTER(SolveInfo)]),
         "hdg_reconstruct": (ctypes.c_int, [vp, vp, vp, vp]),
+        "hdg_hybridize": (ctypes.c_int, [vp, vp, vp, vp]),
         "hdg_adjoint": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
                                        ctypes.POINTER(SolveInfo)]),
         "hdg_diagonal": (ctypes.c_int, [vp, vp]),
@@ -191,10 +195,11 @@ class Sizes:
 
 
 class HdgContext:
-    """One Cartesian mesh / degree / lambda field on the current GPU."""
+    """One Cartesian mesh / degree / lambda field on the current GPU;
+    ``neumann`` is the mask of Neumann sides (bit 2a + s), 0 = all Dirichlet."""
 
     def __init__(self, n: Sequence[int], widths: Sequence[np.ndarray], p: int, tau: float,
-                 lam, device=None):
+                 lam, device=None, neumann: int = 0):
         torch = _torch()
         lib = load_library()
         if not torch.cuda.is_available():
@@ -204,6 +209,7 @@ class HdgContext:
         self.n = tuple(int(v) for v in n)
         self.p = int(p)
         self.n_elem = self.n[0] * self.n[1] * self.n[2]
+        self.neumann = int(neumann)
         self._widths = [np.ascontiguousarray(w, dtype=np.float64) for w in widths]
         nn = (ctypes.c_int * 3)(*self.n)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -220,9 +226,9 @@ class HdgContext:
             stream = torch.cuda.current_stream(self.device)
             self._stream = stream
             h = ctypes.c_void_p()
-            _check(lib.hdg_create(nn, *(w.ctypes.data_as(dp) for w in self._widths), self.p,
-                                  float(tau), lam_ptr, lam_const,
-                                  ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+            _check(lib.hdg_create_bc(nn, *(w.ctypes.data_as(dp) for w in self._widths), self.p,
+                                     float(tau), lam_ptr, lam_const, self.neumann,
+                                     ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
         self._h = h
         nf, na, nv = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib.hdg_sizes(self._h, ctypes.byref(nf), ctypes.byref(na), ctypes.byref(nv)))
@@ -312,7 +318,9 @@ class HdgContext:
 
     def solve_forcing(self, f, trace, u_vol=None, want_volume: bool = True,
                       opts: Optional[SolveOpts] = None, allow_noconv: bool = False):
-        """Solve with forcing f; trace: in = Dirichlet tail, out = nodal solution."""
+        """Solve with forcing f; trace: in = boundary tail (g_D, g_N) and, with
+        opts.guess = 1, the initial guess in the free part; out = nodal
+        solution in the free part."""
         torch = _torch()
         if want_volume and u_vol is None:
             u_vol = self._empty(self.sizes.n_vol)
@@ -334,6 +342,17 @@ class HdgContext:
                                          _dptr(trace, self.sizes.n_all, torch.float64, "trace"),
                                          _dptr(u_vol, self.sizes.n_vol, torch.float64, "u_vol")))
         return u_vol
+
+    def hybridize(self, u_vol, trace=None, out=None):
+        """Initial-guess trace (free part, nodal) from a volume field; the
+        g_N block of ``trace`` is read on Neumann faces."""
+        torch = _torch()
+        if out is None:
+            out = self._empty(self.sizes.n_free)
+        tp = None if trace is None else _dptr(trace, self.sizes.n_all, torch.float64, "trace")
+        _check(self._lib.hdg_hybridize(self._h, _dptr(u_vol, self.sizes.n_vol, torch.float64, "u"),
+                                       tp, _dptr(out, self.sizes.n_free, torch.float64, "out")))
+        return out
 
     def adjoint(self, f, trace, dJdu, opts: Optional[SolveOpts] = None):
         torch = _torch()

@@ -124,3 +124,25 @@ def test_batch_create_rejects_invalid_arguments_without_gpu_work():
     assert lib.hdg_batch_create(1, None, None, None, 1.0, None, ctypes.byref(out)) == -1
     assert lib.hdg_batch_destroy(None) == 0
 
+
+
+def test_neumann_mask_validation_without_gpu():
+    """hdg_create_bc rejects a mask outside 0..63 and the singular pure
+    Neumann problem with lambda = 0 before touching a device."""
+    import ctypes
+    import numpy as np
+    import paper_2007_11891_amd as pkg
+    lib = pkg.load_library()
+    n = (ctypes.c_int * 3)(2, 2, 2)
+    h = np.array([0.5, 0.5])
+    dp = ctypes.POINTER(ctypes.c_double)
+    out = ctypes.c_void_p()
+    args = [n, h.ctypes.data_as(dp), h.ctypes.data_as(dp), h.ctypes.data_as(dp), 3, 1.0]
+    assert lib.hdg_create_bc(*args, None, 1.0, 64, None, ctypes.byref(out)) == -1
+    assert b"neumann" in lib.hdg_last_error()
+    assert lib.hdg_create_bc(*args, None, 0.0, 63, None, ctypes.byref(out)) == -1
+    assert b"singular" in lib.hdg_last_error()
+    lam = np.zeros(8)
+    assert lib.hdg_create_bc(*args, lam.ctypes.data_as(dp), 0.0, 63, None,
+                             ctypes.byref(out)) == -1
+    assert not out.value
