@@ -275,6 +275,84 @@ def bench_tau_sweep(pkg, W, torch, dev):
             "cases": rows}
 
 
+def bench_neumann(pkg, W, torch, dev, reps: int = 3):
+    """Neumann sides and initial-guess solves on the headline mesh (16^3
+    perturbed, p = 7, f ~ U[-1, 1], seed 2): the sides normal to x1 and x3
+    Neumann (g_N = 0.5), the others Dirichlet (g_D = 0).  One-kernel CG
+    iteration and whole solve against the all-Dirichlet mesh; then the
+    solve at lambda = 11 from zero and from the hybridized volume solution
+    at lambda = 10 (a time step's worth of change)."""
+    mask = 0b110011
+    prob = W.perturbed(n=16, p=7, lam=10.0, seed=2)
+    f = torch.as_tensor(prob.f_values, device=dev)
+    rows = {}
+    for name, m in (("dirichlet", 0), ("neumann", mask)):
+        c = pkg.HdgContext(prob.n, prob.widths, prob.p, prob.tau, prob.lam, neumann=m)
+        c.autotune(reps=20)
+        nf = c.sizes.n_free
+        x = torch.as_tensor(W.random_trace(nf, 1), device=dev)
+        t_it = c.time_kernel(9, x, 200)
+        bc = c.zeros_trace()
+        bc[nf:] = 0.5 if m else 0.0
+        o = pkg.default_opts(rtol=1e-10)
+        c.solve_forcing(f, bc.clone(), opts=o)
+        walls = []
+        for _ in range(reps):
+            tr = bc.clone()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, uv, info = c.solve_forcing(f, tr, opts=o)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t)
+        rows[name] = {"n_free": nf, "one_kernel_iteration_us": round(t_it * 1e3, 3),
+                      "iters": info["iters"], "solve_ms": round(statistics.median(walls) * 1e3, 3)}
+        if m:
+            ctx_n, bc_n, u_prev = c, bc, uv
+        else:
+            c.close()
+    # initial guess: lambda 10 -> 11
+    lam2 = prob.lam * 1.1
+    c2 = pkg.HdgContext(prob.n, prob.widths, prob.p, prob.tau, lam2, neumann=mask)
+    c2.autotune(reps=20)
+    nf = c2.sizes.n_free
+    nv = c2.sizes.n_vol
+    res = {}
+    for name, guess in (("zero", 0), ("hybridized", 1)):
+        o = pkg.default_opts(rtol=1e-10, guess=guess)
+        walls = []
+        for _ in range(reps + 1):
+            tr = bc_n.clone()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            if guess:
+                c2.hybridize(u_prev, bc_n, out=tr[:nf])
+            _, _, info = c2.solve_forcing(f, tr, want_volume=False, opts=o)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t)
+        res[name] = {"iters": info["iters"], "rel_res": info["rel_res"],
+                     "ms": round(statistics.median(walls[1:]) * 1e3, 3)}
+    out_free = torch.empty(nf, dtype=torch.float64, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c2.hybridize(u_prev, bc_n, out=out_free)
+    e0.record()
+    for _ in range(50):
+        c2.hybridize(u_prev, bc_n, out=out_free)
+    e1.record()
+    torch.cuda.synchronize()
+    t_h = e0.elapsed_time(e1) / 50
+    hyb_bytes = 8 * nv + 16 * nf + 24 * nf     # volume read, two face slots, their sum
+    res["hybridize_us"] = round(t_h * 1e3, 3)
+    res["hybridize_GBs"] = round(hyb_bytes / (t_h * 1e-3) / 1e9, 1)
+    log(f"[bench] neumann: {rows}; guess {res}")
+    ctx_n.close()
+    c2.close()
+    return {"workload": "16^3 perturbed, p = 7, f~U[-1,1]; sides x1 and x3 Neumann (g_N = 0.5), "
+                        "x2 Dirichlet (g_D = 0); CG to 1e-10",
+            "boundary": rows,
+            "initial_guess": {"case": "lambda 10 -> 11 everywhere; guess = hybridized volume "
+                                      "solution at lambda 10", **res}}
+
+
 def bench_batched(pkg, W, torch, dev, reps: int = 3):
     """256 independent unit-cube problems (n_a ~ U{4..12}, p ~ U{2..10},
     lambda log-uniform in [1e-2, 1e2], f ~ N(0,1), seed 4) in one persistent
@@ -388,6 +466,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-paper-case", action="store_true")
+    ap.add_argument("--no-neumann", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -531,6 +610,7 @@ def main():
     adjoint = None if args.no_adjoint else bench_adjoint(pkg, W, torch, dev)
     paper_case = None if args.no_paper_case else bench_paper_case(pkg, W, torch, dev)
     tau_sweep = None if args.no_paper_case else bench_tau_sweep(pkg, W, torch, dev)
+    neumann = None if args.no_neumann else bench_neumann(pkg, W, torch, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -566,6 +646,7 @@ def main():
         "adjoint": adjoint,
         "paper_case": paper_case,
         "tau_sweep": tau_sweep,
+        "neumann": neumann,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
