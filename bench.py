@@ -276,18 +276,21 @@ def bench_tau_sweep(pkg, W, torch, dev):
 
 
 def bench_neumann(pkg, W, torch, dev, reps: int = 3):
-    """Neumann sides and initial-guess solves on the headline mesh (16^3
-    perturbed, p = 7, f ~ U[-1, 1], seed 2): the sides normal to x1 and x3
-    Neumann (g_N = 0.5), the others Dirichlet (g_D = 0).  One-kernel CG
-    iteration and whole solve against the all-Dirichlet mesh; then the
-    solve at lambda = 11 from zero and from the hybridized volume solution
-    at lambda = 10 (a time step's worth of change)."""
+    """Neumann sides, the exact mass matrix and initial-guess solves on the
+    headline mesh (16^3 perturbed, p = 7, f ~ U[-1, 1], seed 2): the sides
+    normal to x1 and x3 Neumann (g_N = 0.5), the others Dirichlet (g_D = 0);
+    and all sides Dirichlet with the exact mass.  One-kernel CG iteration and
+    whole solve against the lumped all-Dirichlet mesh; then the solve at
+    lambda = 11 from zero and from the hybridized volume solution at
+    lambda = 10 (a time step's worth of change)."""
     mask = 0b110011
     prob = W.perturbed(n=16, p=7, lam=10.0, seed=2)
     f = torch.as_tensor(prob.f_values, device=dev)
     rows = {}
-    for name, m in (("dirichlet", 0), ("neumann", mask)):
-        c = pkg.HdgContext(prob.n, prob.widths, prob.p, prob.tau, prob.lam, neumann=m)
+    for name, m, em in (("dirichlet", 0, False), ("neumann", mask, False),
+                        ("exact_mass", 0, True)):
+        c = pkg.HdgContext(prob.n, prob.widths, prob.p, prob.tau, prob.lam, neumann=m,
+                           exact_mass=em)
         c.autotune(reps=20)
         nf = c.sizes.n_free
         x = torch.as_tensor(W.random_trace(nf, 1), device=dev)
@@ -306,7 +309,7 @@ def bench_neumann(pkg, W, torch, dev, reps: int = 3):
             walls.append(time.perf_counter() - t)
         rows[name] = {"n_free": nf, "one_kernel_iteration_us": round(t_it * 1e3, 3),
                       "iters": info["iters"], "solve_ms": round(statistics.median(walls) * 1e3, 3)}
-        if m:
+        if name == "neumann":
             ctx_n, bc_n, u_prev = c, bc, uv
         else:
             c.close()
@@ -347,7 +350,7 @@ def bench_neumann(pkg, W, torch, dev, reps: int = 3):
     ctx_n.close()
     c2.close()
     return {"workload": "16^3 perturbed, p = 7, f~U[-1,1]; sides x1 and x3 Neumann (g_N = 0.5), "
-                        "x2 Dirichlet (g_D = 0); CG to 1e-10",
+                        "x2 Dirichlet (g_D = 0); all Dirichlet with the exact mass; CG to 1e-10",
             "boundary": rows,
             "initial_guess": {"case": "lambda 10 -> 11 everywhere; guess = hybridized volume "
                                       "solution at lambda 10", **res}}

@@ -6,7 +6,7 @@
  *
  * Problem (paper, equation (helmholtz_equation)):
  *     lambda u - laplace u = f  in the box [0, sum h_1] x [0, sum h_2] x [0, sum h_3],
- *     u = g_D on the Dirichlet sides (all six unless hdg_create_bc names
+ *     u = g_D on the Dirichlet sides (all six unless hdg_create_ex names
  *     Neumann sides), n . grad u = g_N on the Neumann sides (outward n),
  * discretised on a Cartesian mesh of n1 x n2 x n3 cuboids with per-axis
  * widths, Lagrange polynomials of degree p on Gauss-Lobatto-Legendre (GLL)
@@ -169,17 +169,26 @@ hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2,
                       const double* lambda_host, double lambda_const,
                       void* stream, hdg_ctx** out);
 
-/* hdg_create with Neumann sides (equation (neumann_flux)): bit 2a + s of
- * neumann_sides (0..63) makes side s of axis a (s = 0: x_{a+1} = 0, s = 1:
- * x_{a+1} = sum h_{a+1}) a Neumann side, n . grad u = g_N, whose trace is
- * unknown; the others stay Dirichlet.  hdg_create is this call with 0.  The
- * layout of trace vectors follows (see "Layouts" above).  All six sides
- * Neumann with lambda = 0 everywhere is rejected (HDG_EINVAL): the
- * condensed operator is then singular.  Batched solves stay Dirichlet. */
-hdg_status hdg_create_bc(const int n_elem[3], const double* h1, const double* h2,
+/* hdg_create with Neumann sides and the choice of mass matrix.
+ * neumann_sides (0..63): bit 2a + s makes side s of axis a (s = 0:
+ * x_{a+1} = 0, s = 1: x_{a+1} = sum h_{a+1}) a Neumann side (equation
+ * (neumann_flux)), n . grad u = g_N, whose trace is unknown; the others stay
+ * Dirichlet.  The layout of trace vectors follows (see "Layouts" above).
+ * All six sides Neumann with lambda = 0 everywhere is rejected (HDG_EINVAL):
+ * the condensed operator is then singular.
+ * exact_mass (0 or 1): 1 takes the exact mass matrix M_ij = int phi_i phi_j
+ * of the GLL Lagrange basis instead of the lumped diag(w) (the paper's
+ * remark that lumping keeps the face terms diagonal): S, Lambda, B_S follow
+ * from it, and in the eigen basis the face term of each axis is the 2 x 2
+ * matrix G + C^T M^-1 C, which couples the two opposite faces of an element
+ * (at the same tangential index).  The forcing, recovery and transforms use
+ * the same M.
+ * hdg_create is this call with 0, 0.  Batched solves stay Dirichlet with the
+ * lumped mass. */
+hdg_status hdg_create_ex(const int n_elem[3], const double* h1, const double* h2,
                          const double* h3, int p, double tau_hat,
                          const double* lambda_host, double lambda_const,
-                         int neumann_sides, void* stream, hdg_ctx** out);
+                         int neumann_sides, int exact_mass, void* stream, hdg_ctx** out);
 
 /* Release the context and its device memory (synchronises its stream). */
 hdg_status hdg_destroy(hdg_ctx* ctx);

@@ -126,11 +126,13 @@ __device__ inline double uni_f64(double x) {
 __device__ inline int uni_int(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 typedef const __attribute__((address_space(4))) double cdouble;
-struct ConstTab {
+struct ConstTab {   // lumped mass: the face term is H on both faces, no coupling
   cdouble* bs0;
   cdouble* bs1;
   cdouble* lam;
   double H;
+  double H11;
+  static constexpr double H01 = 0.0;
 };
 
 // Units [u0, u1) of one problem at degree NP - 1 and tile EPB.  The
@@ -147,7 +149,7 @@ __device__ inline double run_units(const UnitIO<double>& io, const double* tabs,
   const double* tp = tabs;
   asm volatile("" : "+s"(tp));
   cdouble* ct = (cdouble*)tp;
-  const ConstTab tab{ct + o, ct + o + NP, ct + o + 2 * NP, ct[o + 3 * NP]};
+  const ConstTab tab{ct + o, ct + o + NP, ct + o + 2 * NP, ct[o + 3 * NP], ct[o + 3 * NP]};
   auto& sm = *reinterpret_cast<UnitSmem<double, NP, EPB>*>(smem);
   // the thread index through an empty asm: otherwise the compiler hoists every
   // degree's per-lane index arithmetic (loop-invariant) to the kernel entry

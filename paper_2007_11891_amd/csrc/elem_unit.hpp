@@ -84,17 +84,6 @@ struct UnitIO {
   bool first;              // first launch: the operator applied to z_old as is
 };
 
-// 1D data of one degree seen through pointers (the batched solver keeps the
-// tables of all its degrees in its kernel arguments); apply_unit takes either
-// this or an ElemTab by value.
-template <typename T>
-struct TabRef {
-  const T* bs0;
-  const T* bs1;
-  const T* lam;
-  T H;
-};
-
 template <typename T, int NP, int EPB>
 struct UnitSmem {
   T face[EPB][4][NP * NP];
@@ -245,8 +234,8 @@ __device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T
         lo += tab.bs0[a] * u[a];
         hi += tab.bs1[a] * u[a];
       }
-      out[0] = d[1] * (tab.H * xf[0] - lo);
-      out[1] = d[1] * (tab.H * xf[1] - hi);
+      out[0] = d[1] * (tab.H * xf[0] + tab.H01 * xf[1] - lo);
+      out[1] = d[1] * (tab.H11 * xf[1] + tab.H01 * xf[0] - hi);
     }
     {
       // axis 1: face node (q1,q3) = col
@@ -257,11 +246,11 @@ __device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T
         lo += tab.bs0[b] * u[P * b];
         hi += tab.bs1[b] * u[P * b];
       }
-      out[2] = d[2] * (tab.H * xf[2] - lo);
-      out[3] = d[2] * (tab.H * xf[3] - hi);
+      out[2] = d[2] * (tab.H * xf[2] + tab.H01 * xf[3] - lo);
+      out[3] = d[2] * (tab.H11 * xf[3] + tab.H01 * xf[2] - hi);
     }
-    out[4] = d[3] * (tab.H * xf[4] - r2lo);
-    out[5] = d[3] * (tab.H * xf[5] - r2hi);
+    out[4] = d[3] * (tab.H * xf[4] + tab.H01 * xf[5] - r2lo);
+    out[5] = d[3] * (tab.H11 * xf[5] + tab.H01 * xf[4] - r2hi);
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       if (fid[f] >= io.nff) continue;

@@ -567,12 +567,14 @@ hdg_status hdg_tables(int p, double tau_hat, double* x, double* w, double* D, do
 hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, const double* h3,
                       int p, double tau_hat, const double* lambda_host, double lambda_const,
                       void* stream, hdg_ctx** out) {
-  return hdg_create_bc(n_elem, h1, h2, h3, p, tau_hat, lambda_host, lambda_const, 0, stream, out);
+  return hdg_create_ex(n_elem, h1, h2, h3, p, tau_hat, lambda_host, lambda_const, 0, 0, stream,
+                       out);
 }
 
-hdg_status hdg_create_bc(const int n_elem[3], const double* h1, const double* h2,
+hdg_status hdg_create_ex(const int n_elem[3], const double* h1, const double* h2,
                          const double* h3, int p, double tau_hat, const double* lambda_host,
-                         double lambda_const, int neumann_sides, void* stream, hdg_ctx** out) {
+                         double lambda_const, int neumann_sides, int exact_mass, void* stream,
+                         hdg_ctx** out) {
   if (!out) return fail(HDG_EINVAL, "out is NULL");
   *out = nullptr;
   if (!n_elem) return fail(HDG_EINVAL, "n_elem is NULL");
@@ -596,6 +598,8 @@ hdg_status hdg_create_bc(const int n_elem[3], const double* h1, const double* h2
   } else if (!(lambda_const >= 0.0) || !std::isfinite(lambda_const)) {
     return fail(HDG_EINVAL, "lambda_const must be finite and >= 0");
   }
+  if (exact_mass != 0 && exact_mass != 1)
+    return fail(HDG_EINVAL, "exact_mass must be 0 or 1, got %d", exact_mass);
   if (neumann_sides < 0 || neumann_sides > 63)
     return fail(HDG_EINVAL, "neumann_sides must be a mask of bits 0..5, got %d", neumann_sides);
   if (neumann_sides == 63) {
@@ -653,7 +657,7 @@ hdg_status hdg_create_bc(const int n_elem[3], const double* h1, const double* h2
   c->n_free = c->n_free_faces * npf;
   c->n_all = (c->n_faces + c->n_neu_faces) * npf;
   c->n_vol = ne * npf * c->np;
-  c->tab = make_tables(p, tau_hat);
+  c->tab = make_tables(p, tau_hat, exact_mass != 0);
   for (int a = 0; a < 3; ++a) c->h_host[a].assign(hs[a], hs[a] + n_elem[a]);
   c->lam_host.resize(ne);
   for (int64_t e = 0; e < ne; ++e) c->lam_host[e] = lambda_host ? lambda_host[e] : lambda_const;
@@ -668,7 +672,11 @@ hdg_status hdg_create_bc(const int n_elem[3], const double* h1, const double* h2
     c->et32.lam[k] = (float)c->tab.Lam[k];
   }
   c->et64.H = c->tab.H;
+  c->et64.H11 = c->tab.H11;
+  c->et64.H01 = c->tab.H01;
   c->et32.H = (float)c->tab.H;
+  c->et32.H11 = (float)c->tab.H11;
+  c->et32.H01 = (float)c->tab.H01;
 
   hdg_status st;
   if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)

@@ -18,7 +18,9 @@ struct ElemTab {
   T bs0[kMaxNP];   // B_S[k][0]
   T bs1[kMaxNP];   // B_S[k][1]
   T lam[kMaxNP];   // Lambda_k
-  T H;             // diagonal of G + C^T M^-1 C
+  T H;             // G + C^T M^-1 C = [[H, H01], [H01, H11]] (low, high face of an axis);
+  T H11;           // H01 = 0 and H11 = H for the lumped mass
+  T H01;
 };
 
 // Per-element data precomputed at set-up: the six face ids (axis a, side s

@@ -2,10 +2,13 @@
 // equation (generalized_eigenvalue_decomposition), equation (hdgbs)).
 //
 // GLL points by Newton iteration on P_p', weights 2 / (p (p+1) P_p(x)^2);
-// Lagrange differentiation by barycentric weights; the generalized symmetric
-// eigenproblem L s = Lambda M s with the lumped (diagonal) GLL mass M is
-// reduced to the ordinary one M^-1/2 L M^-1/2 v = Lambda v and solved by the
-// cyclic Jacobi rotation method; S = M^-1/2 V.
+// Lagrange differentiation by barycentric weights.  The mass matrix is the
+// lumped GLL one, diag(w), or the exact one, M_ij = int phi_i phi_j by
+// Gauss-Legendre quadrature with p + 2 points (exact to degree 2p + 3).  The
+// generalized symmetric eigenproblem L s = Lambda M s is reduced to the
+// ordinary one R^-1 L R^-T v = Lambda v with M = R R^T (R = diag(sqrt(w))
+// for the lumped mass, the Cholesky factor otherwise) and solved by the
+// cyclic Jacobi rotation method; S = R^-T V.
 #include "setup1d.hpp"
 
 #include <algorithm>
@@ -64,6 +67,27 @@ static void gll(int p, std::vector<double>& x, std::vector<double>& w) {
   }
 }
 
+// Gauss-Legendre points (roots of P_n by Newton from Chebyshev guesses) and
+// weights 2 / ((1 - x^2) P_n'(x)^2).
+static void gauss(int n, std::vector<long double>& x, std::vector<long double>& w) {
+  x.assign(n, 0.0L);
+  w.assign(n, 0.0L);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < n; ++i) {
+    long double xi = -std::cos(pi * (i + 0.75L) / (n + 0.5L));
+    long double P = 0.0L, dP = 1.0L;
+    for (int it = 0; it < 100; ++it) {
+      legendre(n, xi, &P, &dP);
+      const long double dx = P / dP;
+      xi -= dx;
+      if (std::fabs(dx) < 1e-19L) break;
+    }
+    legendre(n, xi, &P, &dP);
+    x[i] = xi;
+    w[i] = 2.0L / ((1.0L - xi * xi) * dP * dP);
+  }
+}
+
 // Cyclic Jacobi eigenvalue method for a symmetric n x n matrix A (row-major,
 // overwritten).  Returns eigenvectors in the columns of V.
 static void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& V,
@@ -109,11 +133,12 @@ static void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& V,
   for (int i = 0; i < n; ++i) lam[i] = A[i * n + i];
 }
 
-Tables1D make_tables(int p, double tau) {
+Tables1D make_tables(int p, double tau, bool exact_mass) {
   Tables1D t;
   t.p = p;
   t.np = p + 1;
   t.tau = tau;
+  t.exact_mass = exact_mass;
   const int n = t.np;
   gll(p, t.x, t.w);
   // barycentric weights and the nodal derivative matrix Dh_ij = phi_j'(x_i)
@@ -136,20 +161,90 @@ Tables1D make_tables(int p, double tau) {
   t.D.assign(n * n, 0.0);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) t.D[i * n + j] = t.w[i] * Dh[i * n + j];
+  // mass matrix, its inverse and the factor R (M = R R^T, lower triangular)
+  std::vector<long double> Mi(n * n, 0.0L), Rf(n * n, 0.0L);
+  t.M.assign(n * n, 0.0);
+  if (!exact_mass) {
+    for (int i = 0; i < n; ++i) {
+      t.M[i * n + i] = t.w[i];
+      Mi[i * n + i] = 1.0L / t.w[i];
+      Rf[i * n + i] = std::sqrt((long double)t.w[i]);
+    }
+  } else {
+    std::vector<long double> gx, gw;
+    gauss(p + 2, gx, gw);
+    std::vector<long double> Ml(n * n, 0.0L);
+    for (int g = 0; g < p + 2; ++g) {
+      // phi_j(gx) by the barycentric formula (no Gauss point is a GLL point)
+      std::vector<long double> phi(n);
+      long double den = 0.0L;
+      for (int j = 0; j < n; ++j) {
+        phi[j] = bw[j] / (gx[g] - (long double)t.x[j]);
+        den += phi[j];
+      }
+      for (int j = 0; j < n; ++j) phi[j] /= den;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Ml[i * n + j] += gw[g] * phi[i] * phi[j];
+    }
+    for (int i = 0; i < n * n; ++i) t.M[i] = (double)Ml[i];
+    // Cholesky M = R R^T
+    for (int j = 0; j < n; ++j) {
+      long double d = Ml[j * n + j];
+      for (int k = 0; k < j; ++k) d -= Rf[j * n + k] * Rf[j * n + k];
+      Rf[j * n + j] = std::sqrt(d);
+      for (int i = j + 1; i < n; ++i) {
+        long double v = Ml[i * n + j];
+        for (int k = 0; k < j; ++k) v -= Rf[i * n + k] * Rf[j * n + k];
+        Rf[i * n + j] = v / Rf[j * n + j];
+      }
+    }
+    // M^-1 = R^-T R^-1 from the columns of R^-1 (forward substitution)
+    std::vector<long double> Ri(n * n, 0.0L);
+    for (int c = 0; c < n; ++c)
+      for (int i = c; i < n; ++i) {
+        long double v = (i == c) ? 1.0L : 0.0L;
+        for (int k = c; k < i; ++k) v -= Rf[i * n + k] * Ri[k * n + c];
+        Ri[i * n + c] = v / Rf[i * n + i];
+      }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        long double s = 0.0L;
+        for (int k = 0; k < n; ++k) s += Ri[k * n + i] * Ri[k * n + j];
+        Mi[i * n + j] = s;
+      }
+  }
   // L = E + D M^-1 D^T, E = tau (e0 e0^T + ep ep^T)
   std::vector<double> L(n * n, 0.0);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
       long double s = 0.0L;
-      for (int k = 0; k < n; ++k) s += (long double)t.D[i * n + k] * t.D[j * n + k] / t.w[k];
+      for (int k = 0; k < n; ++k)
+        for (int l = 0; l < n; ++l)
+          if (Mi[k * n + l] != 0.0L) s += (long double)t.D[i * n + k] * Mi[k * n + l] * t.D[j * n + l];
       L[i * n + j] = (double)s;
     }
   L[0] += tau;
   L[n * n - 1] += tau;
-  // A = M^-1/2 L M^-1/2, A v = Lambda v, S = M^-1/2 V
+  // A = R^-1 L R^-T (R lower triangular): solve R Y = L, then R A^T = Y^T
+  std::vector<long double> Y(n * n, 0.0L);
+  for (int c = 0; c < n; ++c)
+    for (int i = 0; i < n; ++i) {
+      long double v = L[i * n + c];
+      for (int k = 0; k < i; ++k) v -= Rf[i * n + k] * Y[k * n + c];
+      Y[i * n + c] = v / Rf[i * n + i];
+    }
   std::vector<double> A(n * n);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) A[i * n + j] = L[i * n + j] / std::sqrt(t.w[i] * t.w[j]);
+  {
+    std::vector<long double> Z(n * n, 0.0L);   // Z = R^-1 Y^T = (Y R^-T)^T = A^T = A
+    for (int c = 0; c < n; ++c)
+      for (int i = 0; i < n; ++i) {
+        long double v = Y[c * n + i];
+        for (int k = 0; k < i; ++k) v -= Rf[i * n + k] * Z[k * n + c];
+        Z[i * n + c] = v / Rf[i * n + i];
+      }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) A[i * n + j] = (double)(0.5L * (Z[i * n + j] + Z[j * n + i]));
+  }
   std::vector<double> V, lam;
   jacobi_eigen(n, A, V, lam);
   std::vector<int> order(n);
@@ -160,28 +255,42 @@ Tables1D make_tables(int p, double tau) {
   for (int c = 0; c < n; ++c) {
     const int src = order[c];
     t.Lam[c] = lam[src];
+    // S column = R^-T v by back substitution
+    std::vector<long double> col(n, 0.0L);
+    for (int i = n - 1; i >= 0; --i) {
+      long double v = V[i * n + src];
+      for (int k = i + 1; k < n; ++k) v -= Rf[k * n + i] * col[k];
+      col[i] = v / Rf[i * n + i];
+    }
     // sign: first entry of clearly nonzero magnitude is positive
     double sgn = 1.0;
-    for (int i = 0; i < n; ++i) {
-      const double v = V[i * n + src];
-      if (std::fabs(v) > 1e-8) { sgn = v > 0 ? 1.0 : -1.0; break; }
-    }
-    for (int i = 0; i < n; ++i) t.S[i * n + c] = sgn * V[i * n + src] / std::sqrt(t.w[i]);
+    for (int i = 0; i < n; ++i)
+      if (std::fabs((double)col[i]) > 1e-8) { sgn = col[i] > 0 ? 1.0 : -1.0; break; }
+    for (int i = 0; i < n; ++i) t.S[i * n + c] = sgn * (double)col[i];
   }
-  // B_S = S^T B - S^T D M^-1 C with B = -tau [e0, ep], C = [-e0, ep]
+  // B_S = S^T B - S^T D M^-1 C with B = -tau [e0, ep], C = [-e0, ep]:
+  // (M^-1 C)_{:,0} = -M^-1 e0, (M^-1 C)_{:,1} = M^-1 ep
   t.BS.assign(n * 2, 0.0);
+  std::vector<long double> DMc0(n, 0.0L), DMc1(n, 0.0L);   // (D M^-1 C) columns
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      DMc0[i] -= (long double)t.D[i * n + k] * Mi[k * n + 0];
+      DMc1[i] += (long double)t.D[i * n + k] * Mi[k * n + (n - 1)];
+    }
   for (int k = 0; k < n; ++k) {
     long double s0 = -(long double)tau * t.S[0 * n + k];
     long double s1 = -(long double)tau * t.S[(n - 1) * n + k];
     for (int i = 0; i < n; ++i) {
-      s0 += (long double)t.S[i * n + k] * t.D[i * n + 0] / t.w[0];
-      s1 -= (long double)t.S[i * n + k] * t.D[i * n + (n - 1)] / t.w[n - 1];
+      s0 -= (long double)t.S[i * n + k] * DMc0[i];
+      s1 -= (long double)t.S[i * n + k] * DMc1[i];
     }
     t.BS[k * 2 + 0] = (double)s0;
     t.BS[k * 2 + 1] = (double)s1;
   }
-  // H = G + C^T M^-1 C = (tau + 1/w_0) I_2 for GLL end points
-  t.H = tau + 1.0 / t.w[0];
+  // H = G + C^T M^-1 C: (tau + 1/w_0) I_2 for the lumped mass
+  t.H = (double)((long double)tau + Mi[0]);
+  t.H11 = (double)((long double)tau + Mi[n * n - 1]);
+  t.H01 = (double)(-Mi[n - 1]);
   // derived per-face / per-axis transform matrices (row-major, out = A in)
   t.StM.assign(n * n, 0.0);
   t.St.assign(n * n, 0.0);
@@ -189,8 +298,13 @@ Tables1D make_tables(int p, double tau) {
   for (int a = 0; a < n; ++a)
     for (int i = 0; i < n; ++i) {
       t.St[a * n + i] = t.S[i * n + a];
-      t.StM[a * n + i] = t.S[i * n + a] * t.w[i];
-      t.MS[a * n + i] = t.w[a] * t.S[a * n + i];
+      long double sm = 0.0L, ms = 0.0L;
+      for (int k = 0; k < n; ++k) {
+        sm += (long double)t.S[k * n + a] * t.M[k * n + i];   // (S^T M)_ai
+        ms += (long double)t.M[a * n + k] * t.S[k * n + i];   // (M S)_ai
+      }
+      t.StM[a * n + i] = (double)sm;
+      t.MS[a * n + i] = (double)ms;
     }
   return t;
 }

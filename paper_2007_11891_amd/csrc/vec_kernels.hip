@@ -470,7 +470,7 @@ template hipError_t launch_face_transform<float>(int, const float*, const float*
 
 // ------------------------------------------------------------ diagonal ----
 // diag(K^) at a free face node: sum over the adjacent elements of
-//   d_a H - d_a^2 sum_q BS[q,s]^2 / (lambda d0 + d_a Lam[q] + d_b Lam[qb] + d_c Lam[qc])
+//   d_a H_ss - d_a^2 sum_q BS[q,s]^2 / (lambda d0 + d_a Lam[q] + d_b Lam[qb] + d_c Lam[qc])
 // with s = 1 for the element below the face and s = 0 for the one above
 // (paper: equation (hdg_op_east_east_transformed) and the diagonal
 // preconditioner that follows it).  An interior face has two elements, a
@@ -487,7 +487,7 @@ __device__ inline double diag_share(const MeshDev& m, const ElemTab<double>& tab
   const double* bs = s ? tab.bs1 : tab.bs0;
   double sum = 0.0;
   for (int q = 0; q < np; ++q) sum += bs[q] * bs[q] / (base + dd[a] * tab.lam[q]);
-  return dd[a] * tab.H - dd[a] * dd[a] * sum;
+  return dd[a] * (s ? tab.H11 : tab.H) - dd[a] * dd[a] * sum;
 }
 
 __global__ void __launch_bounds__(256)

@@ -6,7 +6,7 @@
 //   g   = S_e^T M_e f = d0 (S^T M x S^T M x S^T M) f        (forcing source)
 //   g   = S_e^T r     = (S^T x S^T x S^T) r                 (adjoint source)
 //   w   = D_Z^-1 (g - B^_e x)                               (x: eigen-basis trace)
-//   RHS:      out_{a,s} = -d_a sum_q BS[q,s] w[..q..]       (free faces)
+//   RHS:      out_{a,s} = -d_a sum_q BS[q,s] w[..q..] - d_a H01 x_{a,1-s}   (free faces)
 //   recovery: u_e = S_e w
 //   adjoint:  a = D_Z^-1 (S_e^T r - B^_e mu),  u_E = D_Z^-1 (S_e^T M_e f - B^_e x)
 //             dJ/dlambda_e = -d0 sum a u_E,  dJ/df_e = d0 (M S x M S x M S) a
@@ -265,7 +265,10 @@ volume_kernel(const MeshDev mesh, const ElemTab<double> tab, VolArgs va) {
       for (int f = 0; f < 6; ++f) {
         if (!ffree[f]) continue;
         const int64_t g = fid[f] * NF + lt;
-        double v = out[f];
+        // the face term of the lift: with the exact mass H couples the face
+        // with the opposite one, which may hold Dirichlet data (xf of a free
+        // face is zero here)
+        double v = out[f] - d[1 + (f >> 1)] * tab.H01 * xf[f ^ 1];
         const bool neu = (nm >> f) & 1;
         if (neu && va.x_bdry) {   // face integral of mu g_N, eigen basis
           const int a = f >> 1;

@@ -26,7 +26,7 @@ TO_EIGEN_UNKNOWN, TO_EIGEN_RESIDUAL, TO_NODAL_UNKNOWN, TO_NODAL_RESIDUAL = 0, 1,
 
 # every symbol include/hdg.h declares
 EXPORTS = (
-    "hdg_default_opts", "hdg_create", "hdg_create_bc", "hdg_destroy", "hdg_last_error",
+    "hdg_default_opts", "hdg_create", "hdg_create_ex", "hdg_destroy", "hdg_last_error",
     "hdg_sizes", "hdg_set_lambda", "hdg_tables", "hdg_coords", "hdg_apply", "hdg_face_transform",
     "hdg_rhs", "hdg_solve", "hdg_solve_forcing", "hdg_reconstruct", "hdg_hybridize",
     "hdg_adjoint",
@@ -84,8 +84,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hdg_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
         "hdg_create": (ctypes.c_int, [ip, dp, dp, dp, ctypes.c_int, ctypes.c_double, dp,
                                       ctypes.c_double, vp, ctypes.POINTER(vp)]),
-        "hdg_create_bc": (ctypes.c_int, [ip, dp, dp, dp, ctypes.c_int, ctypes.c_double, dp,
-                                         ctypes.c_double, ctypes.c_int, vp, ctypes.POINTER(vp)]),
+        "hdg_create_ex": (ctypes.c_int, [ip, dp, dp, dp, ctypes.c_int, ctypes.c_double, dp,
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, vp,
+                                         ctypes.POINTER(vp)]),
         "hdg_destroy": (ctypes.c_int, [vp]),
         "hdg_last_error": (ctypes.c_char_p, []),
         "hdg_sizes": (ctypes.c_int, [vp, i64p, i64p, i64p]),
@@ -196,10 +197,11 @@ class Sizes:
 
 class HdgContext:
     """One Cartesian mesh / degree / lambda field on the current GPU;
-    ``neumann`` is the mask of Neumann sides (bit 2a + s), 0 = all Dirichlet."""
+    ``neumann`` is the mask of Neumann sides (bit 2a + s), 0 = all Dirichlet;
+    ``exact_mass`` selects the exact GLL mass matrix instead of the lumped one."""
 
     def __init__(self, n: Sequence[int], widths: Sequence[np.ndarray], p: int, tau: float,
-                 lam, device=None, neumann: int = 0):
+                 lam, device=None, neumann: int = 0, exact_mass: bool = False):
         torch = _torch()
         lib = load_library()
         if not torch.cuda.is_available():
@@ -210,6 +212,7 @@ class HdgContext:
         self.p = int(p)
         self.n_elem = self.n[0] * self.n[1] * self.n[2]
         self.neumann = int(neumann)
+        self.exact_mass = bool(exact_mass)
         self._widths = [np.ascontiguousarray(w, dtype=np.float64) for w in widths]
         nn = (ctypes.c_int * 3)(*self.n)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -226,9 +229,10 @@ class HdgContext:
             stream = torch.cuda.current_stream(self.device)
             self._stream = stream
             h = ctypes.c_void_p()
-            _check(lib.hdg_create_bc(nn, *(w.ctypes.data_as(dp) for w in self._widths), self.p,
+            _check(lib.hdg_create_ex(nn, *(w.ctypes.data_as(dp) for w in self._widths), self.p,
                                      float(tau), lam_ptr, lam_const, self.neumann,
-                                     ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+                                     int(self.exact_mass), ctypes.c_void_p(stream.cuda_stream),
+                                     ctypes.byref(h)))
         self._h = h
         nf, na, nv = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib.hdg_sizes(self._h, ctypes.byref(nf), ctypes.byref(na), ctypes.byref(nv)))

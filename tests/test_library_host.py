@@ -127,8 +127,9 @@ def test_batch_create_rejects_invalid_arguments_without_gpu_work():
 
 
 def test_neumann_mask_validation_without_gpu():
-    """hdg_create_bc rejects a mask outside 0..63 and the singular pure
-    Neumann problem with lambda = 0 before touching a device."""
+    """hdg_create_ex rejects a mask outside 0..63, an exact_mass flag other
+    than 0 / 1 and the singular pure Neumann problem with lambda = 0 before
+    touching a device."""
     import ctypes
     import numpy as np
     import paper_2007_11891_amd as pkg
@@ -138,11 +139,13 @@ def test_neumann_mask_validation_without_gpu():
     dp = ctypes.POINTER(ctypes.c_double)
     out = ctypes.c_void_p()
     args = [n, h.ctypes.data_as(dp), h.ctypes.data_as(dp), h.ctypes.data_as(dp), 3, 1.0]
-    assert lib.hdg_create_bc(*args, None, 1.0, 64, None, ctypes.byref(out)) == -1
+    assert lib.hdg_create_ex(*args, None, 1.0, 64, 0, None, ctypes.byref(out)) == -1
     assert b"neumann" in lib.hdg_last_error()
-    assert lib.hdg_create_bc(*args, None, 0.0, 63, None, ctypes.byref(out)) == -1
+    assert lib.hdg_create_ex(*args, None, 1.0, 0, 2, None, ctypes.byref(out)) == -1
+    assert b"exact_mass" in lib.hdg_last_error()
+    assert lib.hdg_create_ex(*args, None, 0.0, 63, 0, None, ctypes.byref(out)) == -1
     assert b"singular" in lib.hdg_last_error()
     lam = np.zeros(8)
-    assert lib.hdg_create_bc(*args, lam.ctypes.data_as(dp), 0.0, 63, None,
+    assert lib.hdg_create_ex(*args, lam.ctypes.data_as(dp), 0.0, 63, 1, None,
                              ctypes.byref(out)) == -1
     assert not out.value
