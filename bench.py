@@ -394,6 +394,7 @@ def bench_batched(pkg, W, torch, dev, reps: int = 3):
            "wall_ms": round(wall * 1e3, 3), "gpu_ms": round(statistics.median(gpus), 3),
            "iters_min": int(iters.min()), "iters_max": int(iters.max()),
            "iters_sum": int(iters.sum()), "tiles_by_p": tiles,
+           "cg_form": "one element pass per iteration" if b.form() == 1 else "two phases per iteration",
            "cg_iteration_us": round(t_it * 1e3, 2),
            "roofline": {"kernel": "batch_cg_kernel (persistent, one CG iteration of every problem)",
                         "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,

@@ -394,11 +394,21 @@ hdg_status hdg_batch_sizes(const hdg_batch* batch, int64_t* n_free, int64_t* n_v
 hdg_status hdg_batch_set_tile(hdg_batch* batch, int p, int variant);
 hdg_status hdg_batch_tiles(const hdg_batch* batch, int* variants);
 
-/* Autotuner: starting from variant 0 everywhere, tries variants 1 and 2 for
- * one degree at a time (degrees by decreasing share of the work) and keeps
- * a change when the persistent CG, timed over `iters` iterations (best of
- * `reps` launches), gets faster.  variants: host int[17] or NULL, as in
- * hdg_batch_tiles.  Synchronises the stream. */
+/* CG form of the persistent kernel: 0 (default) two phases per iteration
+ * (element pass with the fused p update, then a vector update), two grid
+ * barriers; 1 one element pass per iteration with the Chronopoulos-Gear
+ * recurrences of the single-problem one-kernel CG (the same PCG iterates in
+ * exact arithmetic), one barrier.  set_form synchronises the stream and drops
+ * the graph; hdg_batch_form reports the current form. */
+hdg_status hdg_batch_set_form(hdg_batch* batch, int form);
+hdg_status hdg_batch_form(const hdg_batch* batch, int* form);
+
+/* Autotuner: for each CG form, starting from variant 0 everywhere, tries
+ * variants 1 and 2 for one degree at a time (degrees by decreasing share of
+ * the work) and keeps a change when the persistent CG, timed over `iters`
+ * iterations (best of `reps` launches), gets faster; the faster form with
+ * its tiles stays.  variants: host int[17] or NULL, as in hdg_batch_tiles.
+ * Synchronises the stream. */
 hdg_status hdg_batch_autotune(hdg_batch* batch, int iters, int reps, int* variants);
 
 /* Mean time in *ms of one persistent CG launch of exactly `iters`

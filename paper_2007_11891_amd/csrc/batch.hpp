@@ -85,6 +85,18 @@ struct BatchArgs {
   GridBar* bar;
   unsigned* flags;          // [2][nblocks * kFlagStride]: arrival, release lines
   const double* tabs;       // [kBatchTabWords], written by the host before the launch
+  // one-phase form (Chronopoulos-Gear recurrences, one element pass per
+  // iteration): second slots of z and of A z (qa, qb), the two slots of
+  // s = D^-1 A p, and the per-segment partials of z.Az, r.z, r.r of both
+  // parities: pcg[(slot * 3 + j) * max_segs + segment]
+  int form;                 // 0 two phases (apply, update), 1 one phase
+  int max_segs;
+  double* z1;
+  double* s0;
+  double* s1;
+  double* qa1;
+  double* qb1;
+  double* pcg;
 };
 
 hipError_t batch_occupancy(int* blocks_per_cu);

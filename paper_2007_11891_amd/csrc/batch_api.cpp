@@ -41,6 +41,14 @@ struct hdg_batch {
   double* d_qa = nullptr;
   double* d_qb = nullptr;
   double* d_dinv = nullptr;
+  // one-phase form (see BatchArgs): second slots and its partials
+  int form = 0;
+  double* d_z1 = nullptr;
+  double* d_s0 = nullptr;
+  double* d_s1 = nullptr;
+  double* d_qa1 = nullptr;
+  double* d_qb1 = nullptr;
+  double* d_pcg = nullptr;          // [2 * 3 * max_segs]
   // schedule
   int nblocks = 0;
   int max_segs = 0;                 // bound on segments per phase: count + nblocks
@@ -192,11 +200,21 @@ hdg_status upload_probs(hdg_batch* b, double rtol2, int maxit) {
   return HDG_OK;
 }
 
+// max_iters: passes of the two-phase form for the solve asked; the one-phase
+// form decides on iterate k - 1 in pass k and needs one pass more.
 BatchArgs make_args(const hdg_batch* b, int max_iters) {
   BatchArgs a{};
   a.probs = b->d_probs;
   a.n_probs = b->count;
-  a.max_iters = max_iters;
+  a.max_iters = max_iters + (b->form == 1 ? 1 : 0);
+  a.form = b->form;
+  a.max_segs = b->max_segs;
+  a.z1 = b->d_z1;
+  a.s0 = b->d_s0;
+  a.s1 = b->d_s1;
+  a.qa1 = b->d_qa1;
+  a.qb1 = b->d_qb1;
+  a.pcg = b->d_pcg;
   a.useg = b->d_useg;
   a.useg_range = b->d_useg_range;
   a.vseg = b->d_vseg;
@@ -331,7 +349,8 @@ hdg_status hdg_batch_destroy(hdg_batch* b) {
   drop_graphs(b);
   for (hdg_ctx* c : b->sub) hdg_destroy(c);
   for (double** p : {&b->d_b, &b->d_x, &b->d_z, &b->d_p0, &b->d_p1, &b->d_qa, &b->d_qb,
-                     &b->d_dinv, &b->d_ppq, &b->d_prz, &b->d_prr})
+                     &b->d_dinv, &b->d_ppq, &b->d_prz, &b->d_prr, &b->d_z1, &b->d_s0, &b->d_s1,
+                     &b->d_qa1, &b->d_qb1, &b->d_pcg})
     dfree(*p);
   dfree(b->d_probs);
   dfree(b->d_useg);
@@ -400,7 +419,7 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
   }
   if (b->total_free > ((int64_t)1 << 40)) return cleanup(fail(HDG_EINVAL, "batch too large"));
   for (double** ptr : {&b->d_b, &b->d_x, &b->d_z, &b->d_p0, &b->d_p1, &b->d_qa, &b->d_qb,
-                       &b->d_dinv})
+                       &b->d_dinv, &b->d_z1, &b->d_s0, &b->d_s1, &b->d_qa1, &b->d_qb1})
     if ((st = dalloc(ptr, b->total_free)) != HDG_OK) return cleanup(st);
   // Jacobi inverse diagonals of the single-problem contexts
   for (int i = 0; i < count; ++i) {
@@ -424,7 +443,8 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
       (st = dalloc(&b->d_useg_range, b->nblocks + 1)) != HDG_OK ||
       (st = dalloc(&b->d_vseg_range, b->nblocks + 1)) != HDG_OK ||
       (st = dalloc(&b->d_ppq, ms)) != HDG_OK || (st = dalloc(&b->d_prz, ms)) != HDG_OK ||
-      (st = dalloc(&b->d_prr, ms)) != HDG_OK || (st = dalloc(&b->d_A, count)) != HDG_OK ||
+      (st = dalloc(&b->d_prr, ms)) != HDG_OK || (st = dalloc(&b->d_pcg, 6 * ms)) != HDG_OK ||
+      (st = dalloc(&b->d_A, count)) != HDG_OK ||
       (st = dalloc(&b->d_B, count)) != HDG_OK || (st = dalloc(&b->d_bar, 1)) != HDG_OK ||
       (st = dalloc(&b->d_flags, 2 * (int64_t)b->nblocks * kFlagStride)) != HDG_OK)
     return cleanup(st);
@@ -493,6 +513,21 @@ hdg_status hdg_batch_set_tile(hdg_batch* b, int p, int variant) {
   return build_schedule(b);
 }
 
+hdg_status hdg_batch_set_form(hdg_batch* b, int form) {
+  if (!b) return fail(HDG_EINVAL, "batch is NULL");
+  if (form != 0 && form != 1) return fail(HDG_EINVAL, "form must be 0 or 1, got %d", form);
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->form = form;
+  drop_graphs(b);
+  return HDG_OK;
+}
+
+hdg_status hdg_batch_form(const hdg_batch* b, int* form) {
+  if (!b || !form) return fail(HDG_EINVAL, "NULL argument");
+  *form = b->form;
+  return HDG_OK;
+}
+
 hdg_status hdg_batch_tiles(const hdg_batch* b, int* variants) {
   if (!b || !variants) return fail(HDG_EINVAL, "NULL argument");
   for (int q = 0; q <= kMaxNP - 1; ++q) variants[q] = -1;
@@ -550,22 +585,36 @@ hdg_status hdg_batch_autotune(hdg_batch* b, int iters, int reps, int* variants) 
     *best = m;
     return HDG_OK;
   };
-  ST_TRY(hdg_batch_set_tile(b, 0, 0));
-  double best = 0.0;
-  ST_TRY(measure(&best));
-  for (int q : degs) {
-    int keep = b->variant[q];
-    for (int v = 1; v < kNumTileVariants; ++v) {
-      ST_TRY(hdg_batch_set_tile(b, q, v));
-      double t = 0.0;
-      ST_TRY(measure(&t));
-      if (t < best) {
-        best = t;
-        keep = v;
+  // each form with its own tile search; the faster (form, tiles) pair stays
+  double best_all = 1e300;
+  int best_form = 0;
+  int best_var[kMaxNP + 1];
+  for (int form = 0; form <= 1; ++form) {
+    ST_TRY(hdg_batch_set_form(b, form));
+    ST_TRY(hdg_batch_set_tile(b, 0, 0));
+    double best = 0.0;
+    ST_TRY(measure(&best));
+    for (int q : degs) {
+      int keep = b->variant[q];
+      for (int v = 1; v < kNumTileVariants; ++v) {
+        ST_TRY(hdg_batch_set_tile(b, q, v));
+        double t = 0.0;
+        ST_TRY(measure(&t));
+        if (t < best) {
+          best = t;
+          keep = v;
+        }
       }
+      ST_TRY(hdg_batch_set_tile(b, q, keep));
     }
-    ST_TRY(hdg_batch_set_tile(b, q, keep));
+    if (best < best_all) {
+      best_all = best;
+      best_form = form;
+      std::copy(b->variant, b->variant + kMaxNP + 1, best_var);
+    }
   }
+  ST_TRY(hdg_batch_set_form(b, best_form));
+  for (int q : degs) ST_TRY(hdg_batch_set_tile(b, q, best_var[q]));
   if (variants) ST_TRY(hdg_batch_tiles(b, variants));
   return HDG_OK;
 }

@@ -161,6 +161,38 @@ __device__ inline double run_units(const UnitIO<double>& io, const double* tabs,
   return acc[0];
 }
 
+// The one-phase form: units [u0, u1) of one problem through the one-kernel
+// CG iteration of the single-problem kernels (MODE 2); acc gets the unit's
+// shares of z.Az, r.z and r.r.
+template <int NP, int EPB>
+__device__ inline void run_units_cgcg(const UnitIO<double>& io, const double* tabs, double* smem,
+                                      int u0, int u1, double* acc) {
+  constexpr int o = batch_tab_off(NP);
+  const double* tp = tabs;
+  asm volatile("" : "+s"(tp));
+  cdouble* ct = (cdouble*)tp;
+  const ConstTab tab{ct + o, ct + o + NP, ct + o + 2 * NP, ct[o + 3 * NP], ct[o + 3 * NP]};
+  auto& sm = *reinterpret_cast<UnitSmem<double, NP, EPB>*>(smem);
+  int tid = (int)threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  for (int u = u0; u < u1; ++u) apply_unit<double, NP, EPB, 2>(io, tab, sm, u, acc, tid);
+}
+
+__device__ inline void dispatch_units_cgcg(int np, int variant, const UnitIO<double>& io,
+                                           const double* tabs, double* smem, int u0, int u1,
+                                           double* acc) {
+  switch (np * 4 + variant) {
+#define HDG_UCASE(N)                                                                              \
+  case N * 4 + 0: run_units_cgcg<N, epb_var<N, 0>()>(io, tabs, smem, u0, u1, acc); return;      \
+  case N * 4 + 1: run_units_cgcg<N, epb_var<N, 1>()>(io, tabs, smem, u0, u1, acc); return;      \
+  case N * 4 + 2: run_units_cgcg<N, epb_var<N, 2>()>(io, tabs, smem, u0, u1, acc); return;
+    HDG_UCASE(2) HDG_UCASE(3) HDG_UCASE(4) HDG_UCASE(5) HDG_UCASE(6) HDG_UCASE(7)
+    HDG_UCASE(8) HDG_UCASE(9) HDG_UCASE(10) HDG_UCASE(11)
+#undef HDG_UCASE
+    default: return;
+  }
+}
+
 __device__ inline double dispatch_units(int np, int variant, const UnitIO<double>& io,
                                         const double* tabs, double* smem, int u0, int u1) {
   switch (np * 4 + variant) {
@@ -332,6 +364,141 @@ __global__ void __launch_bounds__(kBT, 3) batch_cg_kernel(BatchArgs a) {
   }
 }
 
+// One-phase form: every iteration is one pass over the element segments, as
+// the single-problem one-kernel CG (Chronopoulos-Gear recurrences): per
+// segment the problem's partials of the previous pass (z.Az, r.z, r.r of
+// iterate k - 1, parity slot (k - 1) & 1) are re-summed in a fixed order,
+// convergence is decided and alpha_{k-1}, beta_{k-1} formed; then each unit
+// updates s, z and, on the faces it owns, p and x, and applies the operator
+// to the new z.  One grid barrier per iteration.  Slots alternate with the
+// parity rd = k & 1 exactly as the single-problem launches do; the state
+// slot read is A for even k, B for odd k.
+__global__ void __launch_bounds__(kBT, 3) batch_cgcg_kernel(BatchArgs a) {
+  __shared__ double smem[kBatchLdsWords];
+  __shared__ double s_red[kBT / 64];
+  // consecutive ranges on one XCD: neighbouring elements of a problem,
+  // whose shared faces both read, meet in the same L2
+  const int bid = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  unsigned epoch = 0;
+
+  // ---- init: z_0 = D^-1 b in slot 0, x = 0, p_{-1} = s_{-1} = 0 (slot 1) ---
+  for (int s = a.vseg_range[bid]; s < a.vseg_range[bid + 1]; ++s) {
+    const BatchSeg sg = a.vseg[s];
+    const int64_t off = a.probs[sg.prob].off;
+    for (int64_t g = off + sg.begin + threadIdx.x; g < off + sg.end; g += kBT) {
+      a.z[g] = a.dinv[g] * a.b[g];
+      a.x[g] = 0.0;
+      a.p1[g] = 0.0;
+      a.s1[g] = 0.0;
+    }
+  }
+  if (!grid_sync(a, ++epoch)) return;
+
+  int it = 0;
+  for (; it < a.max_iters; ++it) {
+    const int rd = it & 1;
+    double* const zs[2] = {a.z, a.z1};
+    double* const ps_[2] = {a.p0, a.p1};
+    double* const ss[2] = {a.s0, a.s1};
+    double* const qas[2] = {a.qa, a.qa1};
+    double* const qbs[2] = {a.qb, a.qb1};
+    const double* prev = a.pcg + (size_t)(rd ^ 1) * 3 * a.max_segs;
+    double* cur = a.pcg + (size_t)rd * 3 * a.max_segs;
+    for (int s = a.useg_range[bid]; s < a.useg_range[bid + 1]; ++s) {
+      const BatchSeg sg = a.useg[s];
+      const int pb = uni_int(sg.prob);
+      const BatchProbDev* P = a.probs + pb;
+      BatchState* R = rd ? a.B + pb : a.A + pb;
+      BatchState* W = rd ? a.A + pb : a.B + pb;
+      const bool owner = (s == P->useg_begin) && threadIdx.x == 0;
+      const int rdone = R->done;
+      if (rdone) {                            // finished earlier: keep both slots equal
+        if (owner && W->done == 0) *W = *R;
+        continue;
+      }
+      const int k = R->iter;
+      double alpha = 0.0, beta = 0.0;
+      if (k == 0) {
+        if (owner) {
+          W->iter = 1;
+          W->done = 0;
+        }
+      } else {
+        double del = 0.0, gam = 0.0, rr = 0.0;
+        sum_partials2<kBT>(prev + P->useg_begin, prev + a.max_segs + P->useg_begin, P->n_usegs,
+                           s_red, &del, &gam);
+        rr = sum_partials<kBT>(prev + 2 * a.max_segs + P->useg_begin, P->n_usegs, 1, 0, s_red);
+        const double rr_stop = (k == 1) ? P->rtol2 * rr : R->rr_stop;
+        int done = 0;
+        if (!isfinite(rr) || !isfinite(gam)) done = 3;
+        else if (rr <= rr_stop) done = 1;
+        else if (k - 1 >= P->maxit) done = 2;
+        else {
+          beta = (k == 1) ? 0.0 : gam / R->rho;
+          alpha = (k == 1) ? gam / del : gam / (del - beta * gam / R->alpha);
+          if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta)) done = 3;
+        }
+        if (owner) {
+          W->rr = rr;
+          W->rr_stop = rr_stop;
+          W->done = done;
+          if (done) {
+            W->iter = k - 1;                  // x_{k-1} is the result
+            atomicAdd(&a.bar->done_count, 1u);
+          } else {
+            W->rho = gam;
+            W->alpha = alpha;
+            W->iter = k + 1;
+          }
+        }
+        if (done) continue;
+      }
+      const int64_t off = P->off;
+      UnitIO<double> io{};
+      io.info = uni_ptr(P->info);
+      io.lam = uni_ptr(P->lam);
+      io.n_elem = uni_int(P->n_elem);
+      io.nff = uni_int(P->nff);
+      io.first = k == 0;
+      io.z_old = uni_ptr((k == 0 ? zs[rd] : zs[rd ^ 1]) + off);
+      io.z_new = uni_ptr(zs[rd] + off);
+      io.p_in = uni_ptr(ps_[rd] + off);
+      io.p_out = uni_ptr(ps_[rd ^ 1] + off);
+      io.s_old = uni_ptr(ss[rd] + off);
+      io.s_new = uni_ptr(ss[rd ^ 1] + off);
+      io.w_a = uni_ptr(qas[rd ^ 1] + off);
+      io.w_b = uni_ptr(qbs[rd ^ 1] + off);
+      io.qa = uni_ptr(qas[rd] + off);
+      io.qb = uni_ptr(qbs[rd] + off);
+      io.dinv = uni_ptr(a.dinv + off);
+      io.x = uni_ptr(a.x + off);
+      io.alpha = uni_f64(alpha);
+      io.beta = uni_f64(beta);
+      double acc[3] = {0.0, 0.0, 0.0};
+      dispatch_units_cgcg(uni_int(P->np), uni_int(P->variant), io, a.tabs, smem, sg.begin, sg.end,
+                          acc);
+      block_sums<kBT, 3>(acc);
+      if (threadIdx.x == 0) {
+        cur[s] = acc[0];
+        cur[a.max_segs + s] = acc[1];
+        cur[2 * a.max_segs + s] = acc[2];
+      }
+    }
+    if (!grid_sync(a, ++epoch)) return;
+    if (__hip_atomic_load(&a.bar->done_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+        (unsigned)a.n_probs)
+      break;
+  }
+  // the result slot: a problem decided in an odd pass wrote slot A, in an
+  // even pass slot B; the host reads A
+  for (int s = a.useg_range[bid]; s < a.useg_range[bid + 1]; ++s) {
+    const BatchSeg sg = a.useg[s];
+    const BatchProbDev* P = a.probs + sg.prob;
+    if (s == P->useg_begin && threadIdx.x == 0 && a.A[sg.prob].done == 0 && a.B[sg.prob].done != 0)
+      a.A[sg.prob] = a.B[sg.prob];
+  }
+}
+
 // State reset before every batched solve (a kernel, so that it can sit in the
 // captured graph next to the solver).
 __global__ void batch_reset_kernel(BatchState* A, BatchState* B, GridBar* bar, unsigned* flags,
@@ -355,7 +522,12 @@ __global__ void batch_reset_kernel(BatchState* A, BatchState* B, GridBar* bar, u
 }
 
 hipError_t batch_occupancy(int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_cg_kernel, kBT, 0);
+  // the grid must be co-resident for both forms
+  int a = 0, b = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, batch_cg_kernel, kBT, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, batch_cgcg_kernel, kBT, 0);
+  *blocks_per_cu = a < b ? a : b;
+  return e;
 }
 
 hipError_t launch_batch_reset(BatchState* A, BatchState* B, GridBar* bar, unsigned* flags,
@@ -371,8 +543,9 @@ hipError_t launch_batch_cg(const BatchArgs& args, int nblocks, hipStream_t s) {
   if (nblocks < 1 || nblocks > kBT * kMaxBlocksPerThread) return hipErrorInvalidValue;
   BatchArgs a = args;
   void* params[] = {&a};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(batch_cg_kernel), dim3(nblocks),
-                                    dim3(kBT), params, 0, s);
+  const void* fn = a.form == 1 ? reinterpret_cast<const void*>(batch_cgcg_kernel)
+                               : reinterpret_cast<const void*>(batch_cg_kernel);
+  return hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kBT), params, 0, s);
 }
 
 }  // namespace hdg

@@ -32,7 +32,8 @@ EXPORTS = (
     "hdg_adjoint",
     "hdg_diagonal", "hdg_time_kernel", "hdg_set_tile", "hdg_autotune", "hdg_tile_shape",
     "hdg_batch_create", "hdg_batch_destroy", "hdg_batch_sizes", "hdg_batch_set_tile",
-    "hdg_batch_tiles", "hdg_batch_autotune", "hdg_batch_time_cg", "hdg_batch_solve_forcing",
+    "hdg_batch_tiles", "hdg_batch_set_form", "hdg_batch_form", "hdg_batch_autotune",
+    "hdg_batch_time_cg", "hdg_batch_solve_forcing",
 )
 
 
@@ -115,6 +116,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hdg_batch_sizes": (ctypes.c_int, [vp, i64p, i64p, i64p, i64p]),
         "hdg_batch_set_tile": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
         "hdg_batch_tiles": (ctypes.c_int, [vp, ip]),
+        "hdg_batch_set_form": (ctypes.c_int, [vp, ctypes.c_int]),
+        "hdg_batch_form": (ctypes.c_int, [vp, ip]),
         "hdg_batch_autotune": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ip]),
         "hdg_batch_time_cg": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp]),
         "hdg_batch_solve_forcing": (ctypes.c_int, [vp, vp, vp, vp, ctypes.POINTER(SolveOpts),
@@ -461,6 +464,15 @@ class HdgBatch:
         v = (ctypes.c_int * 17)()
         _check(self._lib.hdg_batch_tiles(self._h, v))
         return {q: v[q] for q in range(17) if v[q] >= 0}
+
+    def set_form(self, form: int):
+        """0: two phases per CG iteration, 1: one element pass (see hdg.h)."""
+        _check(self._lib.hdg_batch_set_form(self._h, int(form)))
+
+    def form(self) -> int:
+        v = ctypes.c_int()
+        _check(self._lib.hdg_batch_form(self._h, ctypes.byref(v)))
+        return v.value
 
     def autotune(self, iters: int = 20, reps: int = 3) -> dict:
         v = (ctypes.c_int * 17)()

@@ -56,11 +56,14 @@ def small():
     return specs, b, f, refs
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("variant", [0, 1, 2])
-def test_batch_matches_oracle_every_degree_and_tile(small, variant):
+def test_batch_matches_oracle_every_degree_and_tile(small, variant, form):
     import paper_2007_11891_amd as pkg
     specs, b, f, refs = small
-    print(f"[batch vs oracle] tile variant {variant}", flush=True)
+    print(f"[batch vs oracle] tile variant {variant} form {form}", flush=True)
+    b.set_form(form)
+    assert b.form() == form
     b.set_tile(0, variant)
     assert set(b.tiles().values()) == {variant}
     opts = pkg.default_opts(rtol=1e-15, maxit=1500)
@@ -74,20 +77,27 @@ def test_batch_matches_oracle_every_degree_and_tile(small, variant):
             assert rel_err(t, ut_ref) < 1e-12, (i, specs[i], res[i])
         assert rel_err(u, uv_ref) < 1e-12, (i, specs[i], res[i])
     b.set_tile(0, 0)
+    b.set_form(0)
 
 
-def test_problem_without_interior_faces_converges_at_once(small):
+@pytest.mark.parametrize("form", [0, 1])
+def test_problem_without_interior_faces_converges_at_once(small, form):
     import paper_2007_11891_amd as pkg
     specs, b, f, refs = small
+    b.set_form(form)
     _, _, res, _ = b.solve_forcing(to_dev(f), opts=pkg.default_opts(rtol=1e-10))
+    b.set_form(0)
     i = len(specs) - 1
     assert b.n_free[i] == 0
     assert res[i]["status"] == 0 and res[i]["iters"] == 0
 
 
-def test_batch_matches_single_problem_solves_and_is_deterministic(small):
+@pytest.mark.parametrize("form", [0, 1])
+def test_batch_matches_single_problem_solves_and_is_deterministic(small, form):
     import paper_2007_11891_amd as pkg
     specs, b, f, _ = small
+    print(f"[batch vs single] form {form}", flush=True)
+    b.set_form(form)
     opts = pkg.default_opts(rtol=1e-10, maxit=5000)
     tr1, uv1, res1, _ = b.solve_forcing(to_dev(f), opts=opts)
     tr2, uv2, res2, _ = b.solve_forcing(to_dev(f), opts=opts)
@@ -103,6 +113,24 @@ def test_batch_matches_single_problem_solves_and_is_deterministic(small):
             assert rel_err(to_host(tr1[b.free_off[i]:b.free_off[i + 1]]), to_host(t)[:nf]) < 1e-8
         assert rel_err(to_host(uv1[b.vol_off[i]:b.vol_off[i + 1]]), to_host(u)) < 1e-8
         assert res1[i]["rel_res"] <= 1e-10
+    b.set_form(0)
+
+
+def test_batch_iteration_cap_reported_in_both_forms(small):
+    """maxit = 3: a problem that needs more stops with ENOCONV after exactly
+    3 iterations, in either form (tiny ones may converge within 3)."""
+    import paper_2007_11891_amd as pkg
+    specs, b, f, _ = small
+    for form in (0, 1):
+        b.set_form(form)
+        _, _, res, _ = b.solve_forcing(to_dev(f), opts=pkg.default_opts(rtol=1e-14, maxit=3),
+                                       allow_noconv=True)
+        for i, r in enumerate(res):
+            if b.n_free[i]:
+                assert (r["status"] == -4 and r["iters"] == 3) or \
+                       (r["status"] == 0 and r["iters"] <= 3), (form, i, r)
+        assert sum(r["status"] == -4 for r in res) >= len(res) // 2
+    b.set_form(0)
 
 
 def test_batch_rejects_mixed_precision(small):
