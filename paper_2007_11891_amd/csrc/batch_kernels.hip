@@ -134,6 +134,12 @@ struct ConstTab {   // lumped mass: the face term is H on both faces, no couplin
   double H11;
   static constexpr double H01 = 0.0;
 };
+// batched problems are all-Dirichlet with the lumped mass
+template <>
+struct TabTraits<ConstTab> {
+  static constexpr bool neumann = false;
+  static constexpr bool exact_mass = false;
+};
 
 // Units [u0, u1) of one problem at degree NP - 1 and tile EPB.  The
 // per-degree tables (a device buffer the kernel never writes) are read as

@@ -84,6 +84,16 @@ struct UnitIO {
   bool first;              // first launch: the operator applied to z_old as is
 };
 
+// What the 1D tables of a caller can carry: faces on Neumann sides (an
+// element alone on a free face) and the exact-mass coupling H01 of opposite
+// faces.  A table type that never does (the batched solver's) specialises
+// this to drop both from its code paths at compile time.
+template <typename Tab>
+struct TabTraits {
+  static constexpr bool neumann = true;
+  static constexpr bool exact_mass = true;
+};
+
 template <typename T, int NP, int EPB>
 struct UnitSmem {
   T face[EPB][4][NP * NP];
@@ -193,6 +203,8 @@ __device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T
   constexpr int NF = NP * NP;
   constexpr int P = upitch<NP>();
   const int sl = L.sl, q1 = L.q1, q2 = L.q2, col = L.col;
+  if constexpr (!TabTraits<Tab>::neumann) nm = 0;
+  const T h01 = TabTraits<Tab>::exact_mass ? (T)tab.H01 : (T)0;
   __syncthreads();
 
   // expansion into the element eigenspace, division, axis-2 reduction
@@ -234,8 +246,12 @@ __device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T
         lo += tab.bs0[a] * u[a];
         hi += tab.bs1[a] * u[a];
       }
-      out[0] = d[1] * (tab.H * xf[0] + tab.H01 * xf[1] - lo);
-      out[1] = d[1] * (tab.H11 * xf[1] + tab.H01 * xf[0] - hi);
+      out[0] = d[1] * (tab.H * xf[0] - lo);
+      out[1] = d[1] * (tab.H11 * xf[1] - hi);
+      if constexpr (TabTraits<Tab>::exact_mass) {
+        out[0] += d[1] * h01 * xf[1];
+        out[1] += d[1] * h01 * xf[0];
+      }
     }
     {
       // axis 1: face node (q1,q3) = col
@@ -246,11 +262,19 @@ __device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T
         lo += tab.bs0[b] * u[P * b];
         hi += tab.bs1[b] * u[P * b];
       }
-      out[2] = d[2] * (tab.H * xf[2] + tab.H01 * xf[3] - lo);
-      out[3] = d[2] * (tab.H11 * xf[3] + tab.H01 * xf[2] - hi);
+      out[2] = d[2] * (tab.H * xf[2] - lo);
+      out[3] = d[2] * (tab.H11 * xf[3] - hi);
+      if constexpr (TabTraits<Tab>::exact_mass) {
+        out[2] += d[2] * h01 * xf[3];
+        out[3] += d[2] * h01 * xf[2];
+      }
     }
-    out[4] = d[3] * (tab.H * xf[4] + tab.H01 * xf[5] - r2lo);
-    out[5] = d[3] * (tab.H11 * xf[5] + tab.H01 * xf[4] - r2hi);
+    out[4] = d[3] * (tab.H * xf[4] - r2lo);
+    out[5] = d[3] * (tab.H11 * xf[5] - r2hi);
+    if constexpr (TabTraits<Tab>::exact_mass) {
+      out[4] += d[3] * h01 * xf[5];
+      out[5] += d[3] * h01 * xf[4];
+    }
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       if (fid[f] >= io.nff) continue;
@@ -277,7 +301,8 @@ __device__ inline void unit_compute(const UnitIO<T>& io, const Tab& tab, UnitSme
     if constexpr (MODE == 1) {
       v = R.a[f] + io.beta * R.b[f];
       // the element below owns the face; on a Neumann side the only element
-      if (((f & 1) || ((R.nm >> f) & 1)) && R.active && L.colok && R.fid[f] < io.nff)
+      const bool own_lo = TabTraits<Tab>::neumann && ((R.nm >> f) & 1);
+      if (((f & 1) || own_lo) && R.active && L.colok && R.fid[f] < io.nff)
         put<MODE>(io.p_out + (int64_t)R.fid[f] * NF + L.col, v);
     }
     xf[f] = v;
@@ -343,7 +368,7 @@ __device__ inline void cg2_compute(const UnitIO<T>& io, const Tab& tab, UnitSmem
     if (C.on[f]) {
       const int64_t g = (int64_t)R.fid[f] * NF + L.col;
       const T d = C.dv[f];
-      const bool own_lo = !(f & 1) && ((R.nm >> f) & 1);
+      const bool own_lo = TabTraits<Tab>::neumann && !(f & 1) && ((R.nm >> f) & 1);
       if (io.first) {
         v = C.zo[f];
       } else {
