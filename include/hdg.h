@@ -196,12 +196,15 @@ hdg_status hdg_destroy(hdg_ctx* ctx);
 /* Thread-local message of the last failed call. */
 const char* hdg_last_error(void);
 
-/* Vector lengths: trace unknowns (free), whole trace, volume nodes. */
+/* Vector lengths: trace unknowns (free), whole trace (free part, g_D block
+ * and g_N block), volume nodes. */
 hdg_status hdg_sizes(const hdg_ctx* ctx, int64_t* n_free, int64_t* n_all,
                      int64_t* n_vol);
 
 /* Replace the per-element lambda field (device double[n_elem], >= 0, not
- * checked on the device) and rebuild the diagonal preconditioner. */
+ * checked on the device) and rebuild the diagonal preconditioner.  With
+ * every side Neumann, lambda must stay > 0 somewhere (not checked here;
+ * lambda = 0 everywhere makes the operator singular). */
 hdg_status hdg_set_lambda(hdg_ctx* ctx, const double* lambda_dev);
 
 /* Host-only: the 1D tables the context uses, for degree p and tau_hat
@@ -215,8 +218,9 @@ hdg_status hdg_tables(int p, double tau_hat, double* x, double* w, double* D,
                       double* S, double* Lam, double* BS, double* H);
 
 /* Physical coordinates of the volume nodes (device double[n_vol*3], xyz
- * interleaved) and of the trace nodes (device double[n_all*3]); either may
- * be NULL.  Synchronous (computed on the host, copied on the stream). */
+ * interleaved) and of the trace nodes (device double[n_all*3]; the g_N block
+ * repeats the nodes of its Neumann faces); either may be NULL.  Synchronous
+ * (computed on the host, copied on the stream). */
 hdg_status hdg_coords(hdg_ctx* ctx, double* vol_xyz, double* trace_xyz);
 
 /* y = K_ff x (paper: Alg. "HDG_Op_3D", nodal basis, or the transformed
@@ -229,7 +233,8 @@ hdg_status hdg_apply(hdg_ctx* ctx, const void* x, void* y, hdg_dtype dtype,
                      hdg_basis basis);
 
 /* Per-face transform (see hdg_transform) of n_faces consecutive faces
- * (n_faces * n_p^2 FP64 values, device); in == out is allowed. */
+ * (n_faces * n_p^2 FP64 values, device; n_faces <= n_all / n_p^2); in == out
+ * is allowed. */
 hdg_status hdg_face_transform(hdg_ctx* ctx, hdg_transform kind,
                               const double* in, double* out, int64_t n_faces);
 
