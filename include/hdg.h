@@ -136,7 +136,11 @@ typedef struct {
                          residual F - K x0 with the stopping test unchanged
                          (||r|| <= rtol ||F||, in the solver's basis); iters
                          counts the correction's iterations, 0 when x0 already
-                         passes.  hdg_adjoint ignores it.                   */
+                         passes.  2: the same start, stopped when
+                         ||r|| <= rtol ||r_0|| (the paper's protocol for its
+                         test case: the initial residual reduced by rtol).
+                         rel_res is relative to ||F|| in every case.
+                         hdg_adjoint ignores it.                            */
 } hdg_solve_opts;
 
 typedef struct {

@@ -55,10 +55,12 @@ def diagonal_preconditioner(K_ff, npf: int):
     return apply, d
 
 
-def pcg(K, F, apply_pinv=None, rtol: float = 1e-10, maxit: int = 100000, x0=None):
+def pcg(K, F, apply_pinv=None, rtol: float = 1e-10, maxit: int = 100000, x0=None,
+        relative_to: str = "rhs"):
     """Textbook preconditioned CG for the SPD matrix K (dense or sparse),
-    from x0 (default 0); stops when ||r||_2 <= rtol ||F||_2.  Returns (x,
-    iterations, history of ||r||_2 / ||F||_2)."""
+    from x0 (default 0); stops when ||r||_2 <= rtol ||F||_2, or with
+    relative_to="initial" when ||r||_2 <= rtol ||r_0||_2 (the paper's test
+    protocol).  Returns (x, iterations, history of ||r||_2 / ||F||_2)."""
     F = np.asarray(F, dtype=np.float64)
     x = np.zeros_like(F) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
     r = F - K @ x if x0 is not None else F.copy()
@@ -66,6 +68,10 @@ def pcg(K, F, apply_pinv=None, rtol: float = 1e-10, maxit: int = 100000, x0=None
     hist = [np.linalg.norm(r) / nF if nF > 0 else 0.0]
     if nF == 0.0:
         return x, 0, hist
+    if relative_to == "initial":
+        rtol = rtol * hist[0]
+    elif relative_to != "rhs":
+        raise ValueError("relative_to must be 'rhs' or 'initial'")
     if hist[0] <= rtol:
         return x, 0, hist
     z = r.copy() if apply_pinv is None else apply_pinv(r)

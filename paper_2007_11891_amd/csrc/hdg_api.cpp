@@ -234,7 +234,7 @@ int cg_variant_of(const hdg_ctx* c, const hdg_solve_opts* o) {
 
 hdg_status validate_opts(const hdg_solve_opts* o) {
   if (!(o->rtol > 0.0) || o->maxit < 1 || o->precond < 0 || o->precond > 3 ||
-      (o->guess != 0 && o->guess != 1) ||
+      o->guess < 0 || o->guess > 2 ||
       (o->variant < -1 || o->variant > 1) ||
       (o->mixed != 0 && o->mixed != 1) || o->check_every < 1 ||
       (o->mixed && (!(o->inner_rtol > 0.0) || o->inner_rtol >= 1.0 || o->max_outer < 1)))
@@ -476,10 +476,11 @@ hdg_status solve_any(hdg_ctx* c, const double* bhat, double* xhat, const hdg_sol
 
 // solve_any from the initial guess x^0 held in xhat (eigen basis): the
 // correction d solves K^ d = b^ - K^ x^0 with the tolerance scaled so that
-// the test ||r|| <= rtol ||F|| keeps its meaning (norms in the basis the
-// chosen solver measures: eigen for precond 1, nodal otherwise); then
-// x^ = x^0 + d.  info reports the correction's iterations and the residual
-// relative to ||F||.
+// the test ||r|| <= rtol ||F|| keeps its meaning (guess 1), or unscaled, so
+// that the test is ||r|| <= rtol ||r_0|| (guess 2, the paper's protocol);
+// norms in the basis the chosen solver measures: eigen for precond 1, nodal
+// otherwise.  Then x^ = x^0 + d.  info reports the correction's iterations
+// and the residual relative to ||F||.
 hdg_status solve_from_guess(hdg_ctx* c, const double* bhat, double* xhat, const hdg_solve_opts* o,
                             hdg_solve_info* info) {
   if (!o->guess) return solve_any(c, bhat, xhat, o, info);
@@ -505,12 +506,13 @@ hdg_status solve_from_guess(hdg_ctx* c, const double* bhat, double* xhat, const 
   const double nb = std::sqrt(nb2), nr = std::sqrt(nr2);
   hdg_solve_info inf{};
   hdg_status st = HDG_OK;
-  if (nr <= o->rtol * nb || nr == 0.0) {
+  const bool rel_initial = o->guess == 2;
+  if (nr == 0.0 || (!rel_initial && nr <= o->rtol * nb)) {
     inf.rel_res = nb > 0.0 ? nr / nb : 0.0;
   } else {
     hdg_solve_opts o2 = *o;
     o2.guess = 0;
-    o2.rtol = o->rtol * nb / nr;
+    o2.rtol = rel_initial ? o->rtol : o->rtol * nb / nr;
     st = solve_any(c, r0, dx, &o2, &inf);
     if (st != HDG_OK && st != HDG_ENOCONV) return st;
     HIP_TRY(launch_add64(dx, xhat, c->n_free, c->stream));

@@ -104,3 +104,43 @@ def test_penalty_study_trends():
     grow2 = res[625.0, 2][0] / res[25.0, 2][0]
     grow12 = res[625.0, 12][0] / res[25.0, 12][0]
     assert 1.2 < grow2 < 2.5 and grow12 < grow2
+
+
+def test_paper_protocol_start_matches_oracle_cg():
+    """The paper's protocol: the initial trace is the flux (equation (fluxu))
+    of a pseudo-random volume field with the exact values on the boundary,
+    and the CG stops when the initial residual has dropped by 1e-10.  On the
+    test case with 4^3 elements at p = 4, HDG-trans (guess = 2) stops within
+    two iterations of the oracle's Jacobi CG on K^ from the oracle's own
+    hybridized start, and reaches the direct solution."""
+    import paper_2007_11891_amd as pkg
+    from helpers import canonical_oracle_S, face_T
+    from oracle.pcg import pcg
+    pr = W.paper_case(4, n=4)
+    o = oracle.HdgOracle(pr.n, pr.widths, pr.p, pr.tau, pr.lam)
+    c = gpu_ctx(pr.n, pr.widths, pr.p, pr.tau, pr.lam)
+    L = o.layout
+    nf = L.n_free
+    X, T = o.volume_coords(), o.trace_coords()
+    f = W.f_paper(*X.T, 0.0)
+    g = W.u_paper(*T.T)
+    u0 = W.paper_initial_volume(X, 11)
+    # oracle: start, CG in the eigen basis with the Jacobi preconditioner
+    x0 = o.hybridize(u0, g)
+    K = o.assemble_K()[:nf, :nf].toarray()
+    F = o.lifted_rhs(f, g)
+    S, _ = canonical_oracle_S(o.std)
+    Tm = face_T(S, L, L.n_free_faces)
+    Kh = Tm.T @ K @ Tm
+    dinv = 1.0 / np.diag(Kh)
+    xh0 = np.linalg.solve(Tm, x0)
+    _, its, _ = pcg(Kh, Tm.T @ F, lambda r: dinv * r, rtol=1e-10, x0=xh0, relative_to="initial")
+    # GPU: the same start from its own hybridization
+    tr = to_dev(g)
+    c.hybridize(to_dev(u0), tr, out=tr[:nf])
+    assert rel_err(to_host(tr)[:nf], x0) < 1e-13
+    tr, uv, info = c.solve_forcing(to_dev(f), tr, opts=pkg.default_opts(rtol=1e-10, guess=2))
+    print(f"[paper protocol] GPU {info}, oracle {its} iterations", flush=True)
+    assert abs(info["iters"] - its) <= 2, (info, its)
+    ref = np.linalg.solve(K, F)
+    assert rel_err(to_host(tr)[:nf], ref) < 1e-8

@@ -86,3 +86,23 @@ def test_preconditioners_reduce_iterations():
     _, it_d, _ = pcg(K, F, diagonal_preconditioner(K, npf)[0], rtol=1e-10)
     _, it_b, _ = pcg(K, F, block_preconditioner(K, npf), rtol=1e-10)
     assert it_b < it_u and it_d <= it_u + 2
+
+
+def test_stopping_relative_to_initial_residual():
+    """relative_to="initial" stops at ||r|| <= rtol ||r_0||: from x_0 = 0 it
+    is the usual test (r_0 = F); from a start with ||r_0|| = 1e-3 ||F|| it
+    stops at the first iterate that passes rtol * 1e-3 relative to ||F||."""
+    o, K, Q, S, npf = _case(n=(3, 3, 2), p=3, lam=0.3)
+    F = W.random_trace(K.shape[0], 9)
+    x_a, it_a, _ = pcg(K, F, None, rtol=1e-8)
+    x_b, it_b, _ = pcg(K, F, None, rtol=1e-8, relative_to="initial")
+    assert it_a == it_b and np.array_equal(x_a, x_b)
+    ref = np.linalg.solve(K, F)
+    d = W.random_trace(K.shape[0], 10)
+    x0 = ref + d * (1e-3 * np.linalg.norm(F) / np.linalg.norm(K @ d))
+    r0 = np.linalg.norm(F - K @ x0) / np.linalg.norm(F)
+    assert abs(r0 - 1e-3) < 1e-9
+    _, it_c, hist = pcg(K, F, None, rtol=1e-6, x0=x0, relative_to="initial")
+    assert hist[-1] <= 1e-6 * r0 and all(h > 1e-6 * r0 for h in hist[:-1])
+    _, it_d, _ = pcg(K, F, None, rtol=1e-6, x0=x0)
+    assert it_d < it_c

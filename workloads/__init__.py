@@ -116,6 +116,17 @@ def paper_case(p: int, n: int = 8, tau_e: float = 25.0, lam: float = 0.0) -> Pro
                    f_func=f_paper, dirichlet_zero=False)
 
 
+def paper_initial_volume(coords: np.ndarray, seed: int, length: float = 2.0 * math.pi) -> np.ndarray:
+    """The paper's initial guess for its test case: pseudo-random numbers
+    U[0, 1) at the volume nodes inside the domain (0, length)^3, the exact
+    solution u_paper at the nodes on its boundary."""
+    out = np.random.default_rng(seed).uniform(0.0, 1.0, size=coords.shape[0])
+    tol = 1e-12 * length
+    bnd = np.any((np.abs(coords) < tol) | (np.abs(coords - length) < tol), axis=1)
+    out[bnd] = u_paper(*coords[bnd].T)
+    return out
+
+
 def poly_tensor(coeffs: np.ndarray) -> Callable:
     """Tensor polynomial sum_{abc} c[a,b,c] x^a y^b z^c (degree <= p per axis).
 
