@@ -202,6 +202,11 @@ const char* hdg_last_error(void);
 
 /* Vector lengths: trace unknowns (free), whole trace (free part, g_D block
  * and g_N block), volume nodes. */
+/* The same lengths for a mesh, degree and set of Neumann sides without a
+ * context (host-only, touches no GPU; arguments as in hdg_create_ex). */
+hdg_status hdg_layout(const int n_elem[3], int p, int neumann_sides, int64_t* n_free,
+                      int64_t* n_all, int64_t* n_vol);
+
 hdg_status hdg_sizes(const hdg_ctx* ctx, int64_t* n_free, int64_t* n_all,
                      int64_t* n_vol);
 

@@ -525,6 +525,32 @@ hdg_status solve_from_guess(hdg_ctx* c, const double* bhat, double* xhat, const 
   return st;
 }
 
+// Face counts of the trace layout: interior faces, then the Neumann sides
+// (free), then the Dirichlet sides, each side in the order (0,0), (0,1),
+// (1,0), ... (2,1).  side_off[k] is the first face id of side k.
+struct FaceCounts {
+  int64_t n_int, n_free_faces, n_faces, n_neu;
+  int64_t side_off[6];
+};
+FaceCounts face_counts(const int n[3], int neumann_sides) {
+  FaceCounts fc{};
+  const int64_t n1 = n[0], n2 = n[1], n3 = n[2];
+  const int64_t tb[3] = {n2 * n3, n1 * n3, n1 * n2};
+  fc.n_int = (n1 - 1) * n2 * n3 + n1 * (n2 - 1) * n3 + n1 * n2 * (n3 - 1);
+  int64_t off = fc.n_int;
+  for (int pass = 1; pass >= 0; --pass) {
+    for (int k = 0; k < 6; ++k)
+      if (((neumann_sides >> k) & 1) == pass) {
+        fc.side_off[k] = off;
+        off += tb[k >> 1];
+      }
+    if (pass == 1) fc.n_free_faces = off;
+  }
+  fc.n_faces = off;
+  fc.n_neu = fc.n_free_faces - fc.n_int;
+  return fc;
+}
+
 hdg_status upload_lambda_and_diag(hdg_ctx* c) {
   HIP_TRY(launch_diag(c, c->d_diag, c->stream));
   HIP_TRY(launch_recip_64_32(c->d_diag, c->d_dinv32, c->d_tmp[3], c->n_free, c->stream));
@@ -637,23 +663,11 @@ hdg_status hdg_create_ex(const int n_elem[3], const double* h1, const double* h2
   const int n1 = n_elem[0], n2 = n_elem[1], n3 = n_elem[2];
   const int64_t nf0 = (int64_t)(n1 - 1) * n2 * n3, nf1 = (int64_t)n1 * (n2 - 1) * n3,
                 nf2 = (int64_t)n1 * n2 * (n3 - 1);
-  const int64_t tb[3] = {(int64_t)n2 * n3, (int64_t)n1 * n3, (int64_t)n1 * n2};
-  // face ids: interior faces, then the Neumann sides (free), then the
-  // Dirichlet sides, each side in the order (0,0), (0,1), (1,0), ... (2,1)
-  int64_t side_off[6];
-  c->n_int_faces = nf0 + nf1 + nf2;
-  {
-    int64_t off = c->n_int_faces;
-    for (int pass = 1; pass >= 0; --pass) {
-      for (int k = 0; k < 6; ++k)
-        if (((neumann_sides >> k) & 1) == pass) {
-          side_off[k] = off;
-          off += tb[k >> 1];
-        }
-      if (pass == 1) c->n_free_faces = off;
-    }
-    c->n_faces = off;
-  }
+  const FaceCounts fc = face_counts(n_elem, neumann_sides);
+  const int64_t* side_off = fc.side_off;
+  c->n_int_faces = fc.n_int;
+  c->n_free_faces = fc.n_free_faces;
+  c->n_faces = fc.n_faces;
   c->n_neu_faces = c->n_free_faces - c->n_int_faces;
   const int64_t npf = (int64_t)c->np * c->np;
   c->n_free = c->n_free_faces * npf;
@@ -820,6 +834,23 @@ hdg_status hdg_destroy(hdg_ctx* c) {
   if (c->h_scal) (void)hipHostFree(c->h_scal);
   if (c->h_red) (void)hipHostFree(c->h_red);
   delete c;
+  return HDG_OK;
+}
+
+hdg_status hdg_layout(const int n_elem[3], int p, int neumann_sides, int64_t* n_free,
+                      int64_t* n_all, int64_t* n_vol) {
+  if (!n_elem) return fail(HDG_EINVAL, "n_elem is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (n_elem[a] < 1 || n_elem[a] > (1 << 20))
+      return fail(HDG_EINVAL, "n_elem[%d] = %d out of range", a, n_elem[a]);
+  if (p < 1 || p > 16) return fail(HDG_EINVAL, "p must be in [1, 16], got %d", p);
+  if (neumann_sides < 0 || neumann_sides > 63)
+    return fail(HDG_EINVAL, "neumann_sides must be a mask of bits 0..5, got %d", neumann_sides);
+  const FaceCounts fc = face_counts(n_elem, neumann_sides);
+  const int64_t npf = (int64_t)(p + 1) * (p + 1);
+  if (n_free) *n_free = fc.n_free_faces * npf;
+  if (n_all) *n_all = (fc.n_faces + fc.n_neu) * npf;
+  if (n_vol) *n_vol = (int64_t)n_elem[0] * n_elem[1] * n_elem[2] * npf * (p + 1);
   return HDG_OK;
 }
 

@@ -27,7 +27,7 @@ TO_EIGEN_UNKNOWN, TO_EIGEN_RESIDUAL, TO_NODAL_UNKNOWN, TO_NODAL_RESIDUAL = 0, 1,
 # every symbol include/hdg.h declares
 EXPORTS = (
     "hdg_default_opts", "hdg_create", "hdg_create_ex", "hdg_destroy", "hdg_last_error",
-    "hdg_sizes", "hdg_set_lambda", "hdg_tables", "hdg_coords", "hdg_apply", "hdg_face_transform",
+    "hdg_sizes", "hdg_layout", "hdg_set_lambda", "hdg_tables", "hdg_coords", "hdg_apply", "hdg_face_transform",
     "hdg_rhs", "hdg_solve", "hdg_solve_forcing", "hdg_reconstruct", "hdg_hybridize",
     "hdg_adjoint",
     "hdg_diagonal", "hdg_time_kernel", "hdg_set_tile", "hdg_autotune", "hdg_tile_shape",
@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hdg_destroy": (ctypes.c_int, [vp]),
         "hdg_last_error": (ctypes.c_char_p, []),
         "hdg_sizes": (ctypes.c_int, [vp, i64p, i64p, i64p]),
+        "hdg_layout": (ctypes.c_int, [ip, ctypes.c_int, ctypes.c_int, i64p, i64p, i64p]),
         "hdg_set_lambda": (ctypes.c_int, [vp, vp]),
         "hdg_tables": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp, dp, dp]),
         "hdg_coords": (ctypes.c_int, [vp, vp, vp]),
@@ -153,6 +154,15 @@ def default_opts(**kw) -> SolveOpts:
             raise KeyError(k)
         setattr(o, k, v)
     return o
+
+
+def layout(n: Sequence[int], p: int, neumann: int = 0) -> Sizes:
+    """Trace and volume lengths of a mesh without a context (host only)."""
+    nn = (ctypes.c_int * 3)(*(int(v) for v in n))
+    nf, na, nv = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().hdg_layout(nn, int(p), int(neumann), ctypes.byref(nf), ctypes.byref(na),
+                                      ctypes.byref(nv)))
+    return Sizes(nf.value, na.value, nv.value)
 
 
 def tables(p: int, tau: float) -> dict:

@@ -149,3 +149,16 @@ def test_neumann_mask_validation_without_gpu():
     assert lib.hdg_create_ex(*args, lam.ctypes.data_as(dp), 0.0, 63, 1, None,
                              ctypes.byref(out)) == -1
     assert not out.value
+
+
+@pytest.mark.parametrize("mask", [0, 1, 2, 0b001100, 0b110000, 0b101010, 0b010101, 63])
+@pytest.mark.parametrize("n,p", [((3, 2, 2), 2), ((1, 1, 1), 4), ((1, 4, 2), 1), ((5, 3, 7), 3)])
+def test_layout_lengths_match_oracle_without_gpu(n, p, mask):
+    """hdg_layout (the host logic of the face numbering of hdg_create_ex)
+    against the oracle's layout for every kind of side set, including
+    meshes one element thick."""
+    import oracle
+    import paper_2007_11891_amd as pkg
+    L = oracle.Layout(n, p, mask)
+    got = pkg.layout(n, p, mask)
+    assert (got.n_free, got.n_all, got.n_vol) == (L.n_free, L.n_all, L.n_vol)
