@@ -78,7 +78,7 @@ typedef enum {
   HDG_EHIP = -2,         /* a HIP runtime call failed */
   HDG_ENOMEM = -3,       /* device or host allocation failed */
   HDG_ENOCONV = -4,      /* solver stopped at maxit; info is filled */
-  HDG_EUNSUPPORTED = -5  /* valid request this build does not implement */
+  HDG_EUNSUPPORTED = -5  /* valid request the library does not implement */
 } hdg_status;
 
 typedef enum { HDG_F64 = 0, HDG_F32 = 1 } hdg_dtype;
