@@ -84,9 +84,16 @@ hdg_status alloc_work(hdg_ctx* c, CgWork<T>& w) {
 }
 
 template <typename T>
+void drop_graphs(CgWork<T>& w) {
+  for (hipGraphExec_t* g : {&w.graph, &w.graph_tail}) {
+    if (*g) (void)hipGraphExecDestroy(*g);
+    *g = nullptr;
+  }
+}
+
+template <typename T>
 void free_work(CgWork<T>& w) {
-  if (w.graph) (void)hipGraphExecDestroy(w.graph);
-  w.graph = nullptr;
+  drop_graphs(w);
   dfree(w.x);
   dfree(w.z);
   dfree(w.p[0]);
@@ -115,11 +122,14 @@ float* dinv_of<float>(hdg_ctx* c) { return c->d_dinv32; }
 // apply + update pair, variant 10 + pc the nodal-basis CG with
 // preconditioner pc (FP64).
 template <typename T>
-hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters, int variant) {
-  if (w.graph && w.graph_iters == iters && w.graph_variant == variant) return HDG_OK;
-  if (w.graph) {
-    (void)hipGraphExecDestroy(w.graph);
-    w.graph = nullptr;
+hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters, int variant, bool tail = false) {
+  hipGraphExec_t& exec = tail ? w.graph_tail : w.graph;
+  int& ex_iters = tail ? w.tail_iters : w.graph_iters;
+  int& ex_variant = tail ? w.tail_variant : w.graph_variant;
+  if (exec && ex_iters == iters && ex_variant == variant) return HDG_OK;
+  if (exec) {
+    (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
   }
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -143,11 +153,11 @@ hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters, int variant) {
     return fail(HDG_EHIP, "kernel launch during capture failed: %s", hipGetErrorString(err));
   }
   HIP_TRY(e2);
-  hipError_t e3 = hipGraphInstantiate(&w.graph, g, nullptr, nullptr, 0);
+  hipError_t e3 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   HIP_TRY(e3);
-  w.graph_iters = iters;
-  w.graph_variant = variant;
+  ex_iters = iters;
+  ex_variant = variant;
   return HDG_OK;
 }
 
@@ -189,7 +199,12 @@ hdg_status cg_drive(hdg_ctx* c, CgWork<T>& w, int budget, int check_every, int v
   CgScalars* hs = c->h_scal;
   check_every = std::max(1, check_every);
   if (variant == 0) check_every += check_every & 1;   // launches alternate the state slot
+  // the tail graph: a few iterations, used once the residual history says
+  // the solve ends within the next big chunk (fewer no-op launches queued
+  // after convergence); the arithmetic is the same either way
+  const int tail = std::min(check_every, variant == 0 ? 4 : 2);
   ST_TRY(build_graph<T>(c, w, check_every, variant));
+  if (tail < check_every) ST_TRY(build_graph<T>(c, w, tail, variant, true));
   hipEvent_t ev[2] = {nullptr, nullptr};
   for (auto& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   struct EvGuard {
@@ -200,20 +215,38 @@ hdg_status cg_drive(hdg_ctx* c, CgWork<T>& w, int budget, int check_every, int v
     }
   } guard{ev};
   // the launch that detects the stop comes after the last iteration's
-  // launch(es); +2 chunks of slack
-  const int max_chunks = (std::max(1, budget) + check_every - 1) / check_every + 2;
-  bool seen_done = false;
-  for (int k = 0; k < max_chunks; ++k) {
-    HIP_TRY(hipGraphLaunch(w.graph, c->stream));
+  // launch(es): allow two big chunks of slack beyond the budget
+  const int64_t max_launched = (int64_t)std::max(1, budget) + 2 * (int64_t)check_every;
+  int64_t launched = 0;
+  bool seen_done = false, use_tail = false;
+  int chunk_len[2] = {0, 0};
+  int prev_iter = -1;
+  double prev_rr = 0.0;
+  for (int k = 0; launched < max_launched; ++k) {
+    const bool small = use_tail && tail < check_every;
+    HIP_TRY(hipGraphLaunch(small ? w.graph_tail : w.graph, c->stream));
+    chunk_len[k & 1] = small ? tail : check_every;
+    launched += chunk_len[k & 1];
     HIP_TRY(hipMemcpyAsync(&hs[k & 1], w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost,
                            c->stream));
     HIP_TRY(hipEventRecord(ev[k & 1], c->stream));
     if (k >= 1) {
       HIP_TRY(hipEventSynchronize(ev[(k - 1) & 1]));
-      if (hs[(k - 1) & 1].A.done) {
+      const CgState& st = hs[(k - 1) & 1].A;
+      if (st.done) {
         seen_done = true;
         break;
       }
+      // geometric estimate of the iterations still needed from the last two
+      // states; the chunk k now in flight covers chunk_len[k & 1] of them
+      if (!use_tail && prev_iter >= 0 && st.iter > prev_iter && st.rr > 0.0 &&
+          prev_rr > st.rr && st.rr_stop > 0.0 && st.rr > st.rr_stop) {
+        const double per_it = std::log(st.rr / prev_rr) / (double)(st.iter - prev_iter);
+        const double remaining = std::log(st.rr_stop / st.rr) / per_it;
+        if (remaining - chunk_len[k & 1] < check_every) use_tail = true;
+      }
+      prev_iter = st.iter;
+      prev_rr = st.rr;
     }
   }
   HIP_TRY(hipMemcpyAsync(&hs[0], w.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c->stream));
@@ -1169,14 +1202,10 @@ hdg_status hdg_set_tile(hdg_ctx* c, int variant) {
     return fail(HDG_EINVAL, "tile variant must be in [0, %d)", kNumTileVariants);
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->tile_variant = variant;
-  for (CgWork<double>* w : {&c->w64}) {
-    if (w->x) w->apply_blocks = std::max(1, elem_apply_blocks(c->np, c->n_elem, variant));
-    if (w->graph) (void)hipGraphExecDestroy(w->graph);
-    w->graph = nullptr;
-  }
+  if (c->w64.x) c->w64.apply_blocks = std::max(1, elem_apply_blocks(c->np, c->n_elem, variant));
   if (c->w32.x) c->w32.apply_blocks = std::max(1, elem_apply_blocks(c->np, c->n_elem, variant));
-  if (c->w32.graph) (void)hipGraphExecDestroy(c->w32.graph);
-  c->w32.graph = nullptr;
+  drop_graphs(c->w64);
+  drop_graphs(c->w32);
   return HDG_OK;
 }
 

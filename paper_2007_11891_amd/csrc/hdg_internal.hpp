@@ -102,6 +102,10 @@ struct CgWork {
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
   int graph_variant = -1;
+  // a short graph of the same iterations for the last chunks of a solve
+  hipGraphExec_t graph_tail = nullptr;
+  int tail_iters = 0;
+  int tail_variant = -1;
 };
 
 struct KernelConfig {
