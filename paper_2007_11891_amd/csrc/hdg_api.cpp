@@ -178,13 +178,7 @@ hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
   *done_out = 1;
   if (w.n == 0) return HDG_OK;
   w.dinv = dinv_of<T>(c);
-  CgScalars* hs = c->h_scal;
-  HIP_TRY(hipStreamSynchronize(c->stream));   // the upload slot is reused below
-  hs[2] = CgScalars{};
-  hs[2].A.rtol2 = rtol * rtol;
-  hs[2].A.maxit = std::max(1, maxit);
-  hs[2].A.rho = 1.0;
-  HIP_TRY(hipMemcpyAsync(w.sc, &hs[2], sizeof(CgScalars), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(launch_state_reset(w.sc, rtol * rtol, std::max(1, maxit), c->stream));
   if (variant == 0) HIP_TRY(launch_cgcg_init<T>(c, w, b, c->stream));
   else HIP_TRY(launch_cg_init<T>(c, w, b, c->stream));
   return cg_drive<T>(c, w, std::max(1, maxit), check_every, variant, iters_out, done_out);
@@ -306,10 +300,19 @@ hdg_status solve_eigen(hdg_ctx* c, const double* b, double* x_out, const hdg_sol
   auto t0 = std::chrono::steady_clock::now();
   ST_TRY(alloc_work(c, c->w64));
   double bb = 0.0;
-  ST_TRY(norm2_64(c, b, &bb));
+  if (o->mixed) {
+    ST_TRY(norm2_64(c, b, &bb));   // the FP32 scaling needs it now
+  } else if (c->n_free) {
+    // ||b||^2 read back with the final residual (one synchronisation); a
+    // zero b stops the CG at its first test with x = 0
+    HIP_TRY(launch_dot64(b, b, c->n_free, c->w64.partials, c->d_red + 1, c->w64.update_blocks,
+                         c->stream));
+    HIP_TRY(hipMemcpyAsync(c->h_red + 1, c->d_red + 1, sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  }
   inf.rhs_norm = std::sqrt(bb);
   hdg_status result = HDG_OK;
-  if (c->n_free == 0 || bb == 0.0) {
+  if (c->n_free == 0 || (o->mixed && bb == 0.0)) {
     if (c->n_free) HIP_TRY(launch_fill64(x_out, 0.0, c->n_free, c->stream));
     inf.rel_res = 0.0;
   } else if (!o->mixed) {
@@ -375,10 +378,14 @@ hdg_status solve_eigen(hdg_ctx* c, const double* b, double* x_out, const hdg_sol
     inf.outer_iters = outer;
     if (std::sqrt(rr) > o->rtol * inf.rhs_norm) result = HDG_ENOCONV;
   }
-  if (c->n_free && bb != 0.0) {
+  if (c->n_free && (!o->mixed || bb != 0.0)) {
     double rr = 0.0;
-    ST_TRY(residual64(c, b, x_out, &rr));
-    inf.rel_res = std::sqrt(rr) / inf.rhs_norm;
+    ST_TRY(residual64(c, b, x_out, &rr));   // synchronises: h_red[1] holds ||b||^2 too
+    if (!o->mixed) {
+      bb = c->h_red[1];
+      inf.rhs_norm = std::sqrt(bb);
+    }
+    inf.rel_res = bb > 0.0 ? std::sqrt(rr) / inf.rhs_norm : 0.0;
   }
   HIP_TRY(hipStreamSynchronize(c->stream));
   inf.t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -220,6 +220,8 @@ hipError_t launch_axpy_32_64(const float* in, double* out, double scale, int64_t
 hipError_t launch_fill64(double* out, double v, int64_t n, hipStream_t s);
 hipError_t launch_copy64(const double* in, double* out, int64_t n, hipStream_t s);
 hipError_t launch_add64(const double* in, double* out, int64_t n, hipStream_t s);   // out += in
+// both CG state slots zeroed, slot A with rtol^2, maxit and rho = 1
+hipError_t launch_state_reset(CgScalars* sc, double rtol2, int maxit, hipStream_t s);
 hipError_t launch_fill32(float* out, float v, int64_t n, hipStream_t s);
 hipError_t launch_recip_64_32(const double* diag, float* dinv32, double* dinv64, int64_t n,
                               hipStream_t s);

@@ -316,6 +316,22 @@ __global__ void copy64_kernel(int64_t n, const double* __restrict__ in, double* 
        g += (int64_t)gridDim.x * blockDim.x)
     out[g] = in[g];
 }
+// CG state before a solve, from kernel arguments (no host buffer to keep
+// alive, so the host needs no synchronisation before the next upload).
+__global__ void state_reset_kernel(CgScalars* sc, double rtol2, int maxit) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    CgScalars s{};
+    s.A.rtol2 = rtol2;
+    s.A.maxit = maxit;
+    s.A.rho = 1.0;
+    *sc = s;
+  }
+}
+hipError_t launch_state_reset(CgScalars* sc, double rtol2, int maxit, hipStream_t s) {
+  hipLaunchKernelGGL(state_reset_kernel, dim3(1), dim3(64), 0, s, sc, rtol2, maxit);
+  return hipGetLastError();
+}
+
 __global__ void add64_kernel(int64_t n, const double* __restrict__ in, double* __restrict__ out) {
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
        g += (int64_t)gridDim.x * blockDim.x)

@@ -332,3 +332,17 @@ def test_many_block_partials_at_full_size():
         assert info["rel_res"] < 1.5e-10
         assert abs(info["iters"] - info0["iters"]) <= 2
         assert rel_err(to_host(tr), ref) < 1e-8
+
+
+@pytest.mark.parametrize("opts", [dict(variant=0), dict(variant=1), dict(mixed=1), dict(precond=3)],
+                         ids=["one-kernel", "two-kernel", "mixed", "block"])
+def test_zero_right_hand_side_gives_zero_solution(opts):
+    """F = 0: every solver returns x = 0 at once with a zero residual."""
+    import paper_2007_11891_amd as pkg
+    o, c = _pair((3, 2, 2), 4)
+    nf = c.sizes.n_free
+    u = torch.full((nf,), 7.0, dtype=torch.float64, device="cuda")
+    u, info = c.solve(torch.zeros(nf, dtype=torch.float64, device="cuda"),
+                      opts=pkg.default_opts(**opts), u_free=u)
+    assert torch.count_nonzero(u) == 0, info
+    assert info["iters"] == 0 and info["rel_res"] == 0.0 and info["rhs_norm"] == 0.0, info
