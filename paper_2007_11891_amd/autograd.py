@@ -1,8 +1,8 @@
 """torch.autograd.Function around the HDG solve and its adjoint.
 
 Forward: u = U(lambda, f), the recovered element solution of the condensed
-HDG system for a per-element lambda field and nodal forcing f (Dirichlet data
-fixed).  Backward: one adjoint solve with the same symmetric condensed
+HDG system for a per-element lambda field and nodal forcing f (boundary data
+fixed: g_D, and g_N on the Neumann sides of a context that has them).  Backward: one adjoint solve with the same symmetric condensed
 operator plus the lambda-sensitivity kernel (``hdg_adjoint`` in the C ABI).
 Both run in the HIP library; this file only marshals tensors.
 """
@@ -42,5 +42,7 @@ class HdgSolveFn(torch.autograd.Function):
 
 
 def hdg_solve(lam, f, hdg: HdgContext, dirichlet_trace=None, opts=None):
-    """Differentiable u(lambda, f); gradients flow to lambda and f."""
+    """Differentiable u(lambda, f); gradients flow to lambda and f.
+    ``dirichlet_trace``: a full trace vector whose tail holds the boundary
+    data (g_D and the g_N block), or None for zero data."""
     return HdgSolveFn.apply(lam, f, hdg, dirichlet_trace, opts or default_opts())
