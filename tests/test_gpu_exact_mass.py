@@ -159,3 +159,30 @@ def test_exact_and_lumped_differ_and_converge_alike():
     (ul, ue), (um, _) = out
     assert np.abs(ul - um).max() > 1e-8
     assert np.abs(ul - ue).max() < 1e-3 and np.abs(um - ue).max() < 1e-3
+
+
+@pytest.mark.parametrize("p", [10, 12])
+def test_exact_mass_with_neumann_at_high_degree(p):
+    """Exact mass and four Neumann sides at p = 10 and 12 on a 2 x 2 x 2 mesh
+    (p = 16 is in the operator test above):
+    the operator and the right-hand side (nodal basis: the eigen basis of
+    each side carries its own rounding of S at this degree) and the whole
+    solution process against the oracle."""
+    import paper_2007_11891_amd as pkg
+    mask = 0b110011
+    o, c = _pair((2, 2, 2), p, mask)
+    L = o.layout
+    nf = L.n_free
+    Kff = o.assemble_K()[:nf, :nf].toarray()
+    x = W.random_trace(nf, 21)
+    assert rel_err(to_host(c.apply(to_dev(x), basis="nodal")), Kff @ x) < 1e-12
+    X = o.volume_coords()
+    f = W.f_sin3(*X.T, 1.0)
+    bc = bc_vector(L, W.u_sin3, W.grad_sin3, o.trace_coords(), o.trace_normals())
+    F = o.lifted_rhs(f, bc)
+    assert rel_err(to_host(c.rhs(to_dev(f), to_dev(bc), basis="nodal")), F) < 1e-12
+    ut = np.linalg.solve(Kff, F)
+    tr, uv, info = c.solve_forcing(to_dev(f), to_dev(bc),
+                                   opts=pkg.default_opts(rtol=1e-15, maxit=5000, check_every=9),
+                                   allow_noconv=True)
+    assert rel_err(to_host(tr)[:nf], ut) < 1e-11, info
