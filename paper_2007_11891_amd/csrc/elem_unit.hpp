@@ -14,9 +14,9 @@
 // intensity).  One thread per face-node column (q1,q2) walks q3 and keeps the
 // axis-2 reduction in registers; faces normal to x1, x2 and the element's u
 // go through LDS (u with an odd row pitch, so the axis-0 reduction is free of
-// bank conflicts).  For n_p >= 6 an element is owned by whole wavefronts (the
-// element record is wave-uniform and arrives through scalar loads); for
-// n_p <= 5 several elements share a wavefront.  Each interior face receives
+// bank conflicts).  For n_p = 7, 8 and n_p >= 10 an element is owned by whole
+// wavefronts (the element record is wave-uniform and arrives through scalar
+// loads); for n_p <= 6 and n_p = 9 several elements share a wavefront.  Each interior face receives
 // one contribution from the element below it (qa) and one from the element
 // above it (qb): plain stores, no atomics, deterministic sums.
 #pragma once
@@ -25,8 +25,12 @@
 namespace hdg {
 
 // ---- tile shapes ------------------------------------------------------------
+// n_p = 6 and 9 pack several elements into a wavefront instead (36 and 81
+// threads per element would leave 44 % and 37 % of the lanes of whole
+// wavefronts idle; measured 7-15 % faster CG iterations at p = 5 and 8,
+// while n_p = 7 measured faster as a group despite its idle lanes)
 template <int NP>
-__host__ __device__ constexpr bool is_group() { return NP >= 6; }
+__host__ __device__ constexpr bool is_group() { return NP >= 7 && NP != 9; }
 template <int NP>  // threads per element
 __host__ __device__ constexpr int tpe() { return is_group<NP>() ? round_up64(NP * NP) : NP * NP; }
 template <int NP>
