@@ -162,3 +162,16 @@ def test_layout_lengths_match_oracle_without_gpu(n, p, mask):
     L = oracle.Layout(n, p, mask)
     got = pkg.layout(n, p, mask)
     assert (got.n_free, got.n_all, got.n_vol) == (L.n_free, L.n_all, L.n_vol)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 exits with status 2 and a message,
+    before touching torch or the library."""
+    import subprocess
+    import sys
+    from pathlib import Path
+    root = Path(__file__).resolve().parents[1]
+    r = subprocess.run([sys.executable, str(root / "bench.py"), "--gpus", "2"], cwd=root,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
