@@ -105,10 +105,11 @@ def measured_traffic(kernel: str):
 
 def cg_iteration_roofline(c, W, torch, dev, fp32: bool, reps: int = 50):
     """Mean time of one CG iteration (HIP events, back-to-back launches) in
-    the CG form and tile shape the context uses, as an HBM roofline entry:
-    104 B per free DOF in FP64, 52 B in FP32."""
+    the CG form and tile shape the solve runs, as an HBM roofline entry:
+    104 B per free DOF in FP64, 52 B in FP32.  FP64: the context's CG form;
+    FP32: the two-kernel form, the one the mixed-precision inner CG uses."""
     nf = c.sizes.n_free
-    one = c.tile_shape()["cg_variant"] == 0
+    one = c.tile_shape()["cg_variant"] == 0 and not fp32
     which = (10 if fp32 else 9) if one else (3 if fp32 else 2)
     x = torch.as_tensor(W.random_trace(nf, 7), device=dev)
     if fp32:
