@@ -12,7 +12,7 @@ dense or sparse direct solver.
 Modules:
   basis     - GLL points, Lagrange basis, 1D standard matrices
   layout    - canonical trace / volume numbering and node coordinates
-  element   - dense element system, K_e, F_e, recovery
+  element   - dense element system and K_e (F_e and recovery: system)
   system    - global assembly, Dirichlet elimination, solve, adjoint
   fastdiag  - the paper's factorised operator, used only to pin its claims
   pcg       - the paper's nodal-basis CG solvers (no, diagonal, block

@@ -94,46 +94,3 @@ def element_operator(std: dict, h, lam: float) -> np.ndarray:
     """K_e = G_e - R_e^T A_e^-1 R_e (equation (hdg_operator))."""
     es = ElementSystem(std, h, lam)
     return es.G - es.R.T @ np.linalg.solve(es.A, es.R)
-
-
-def element_rhs(std: dict, h, lam: float, f_nodes: np.ndarray) -> np.ndarray:
-    """F_e = -R_e^T A_e^-1 [M_e f_e; 0] (no Neumann data)."""
-    es = ElementSystem(std, h, lam)
-    return -es.R.T @ np.linalg.solve(es.A, es.volume_rhs(es.Me @ f_nodes))
-
-
-def element_reconstruct(std: dict, h, lam: float, f_nodes, trace_local):
-    """[u; q1; q2; q3] = A_e^-1 ([M_e f_e; 0] - R_e u~_e); returns (u, q1, q2, q3)."""
-    es = ElementSystem(std, h, lam)
-    y = np.linalg.solve(es.A, es.volume_rhs(es.Me @ f_nodes) - es.R @ trace_local)
-    nv = es.nv
-    return y[:nv], y[nv:2 * nv], y[2 * nv:3 * nv], y[3 * nv:]
-
-
-class ElementCache:
-    """K_e and the element solves, cached per distinct (h1, h2, h3, lambda).
-
-    Identical elements have identical matrices, so caching only avoids
-    recomputing the same definition.
-    """
-
-    def __init__(self, p: int, tau: float, exact_mass: bool = False):
-        self.std = standard_matrices(p, tau, exact_mass=exact_mass)
-        self._sys = {}
-        self._K = {}
-
-    def _key(self, h, lam):
-        return (float(h[0]), float(h[1]), float(h[2]), float(lam))
-
-    def system(self, h, lam) -> ElementSystem:
-        key = self._key(h, lam)
-        if key not in self._sys:
-            self._sys[key] = ElementSystem(self.std, h, lam)
-        return self._sys[key]
-
-    def K(self, h, lam) -> np.ndarray:
-        key = self._key(h, lam)
-        if key not in self._K:
-            es = self.system(h, lam)
-            self._K[key] = es.G - es.R.T @ np.linalg.solve(es.A, es.R)
-        return self._K[key]

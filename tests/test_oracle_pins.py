@@ -14,7 +14,7 @@ import pytest
 import oracle
 import workloads as W
 from oracle.basis import gll_nodes_weights, standard_matrices
-from oracle.element import element_operator, element_rhs, ElementSystem, kron3
+from oracle.element import element_operator, ElementSystem, kron3
 from oracle.fastdiag import eigen_1d, factorized_element_operator, face_transform, b_s
 from oracle.layout import Layout
 
@@ -124,27 +124,50 @@ def test_element_operator_scaling_law(p):
 @pytest.mark.parametrize("p", [2, 4])
 def test_transformed_same_direction_block_is_diagonal(p):
     """In the face eigenbasis the face-to-opposite-face block of each direction
-    is diagonal in the two tangential indices (section on preconditioners)."""
+    is diagonal in the two tangential indices (section on preconditioners),
+    and its entries have the closed form of the factorised operator,
+
+        K^[(s,t),(s',t)] = d_a H[s,s'] - d_a^2 sum_k B_S[k,s] B_S[k,s'] / D_Z[k,t],
+
+    D_Z[k,t] = lambda d0 + d_a Lambda_k + d_b Lambda_tb + d_c Lambda_tc
+    (k the normal index, (tb, tc) the tangential pair).  The operator here is
+    the dense Schur complement of the element system, so a wrong sign, a
+    dropped face term or a transposed B_S in the closed form fails."""
     s = standard_matrices(p, 1.0)
-    K, info = factorized_element_operator(s, H_PERT, 1.0)
-    T = face_transform(info["S"], p + 1)
+    lam = 1.0
+    K = element_operator(s, H_PERT, lam)
+    S, Lam = eigen_1d(s)
+    BS = b_s(s, S)
+    Hm = s["G"] + s["C"].T @ np.linalg.inv(s["M"]) @ s["C"]
+    h1, h2, h3 = H_PERT
+    d0 = h1 * h2 * h3 / 8.0
+    d = [d0 * (2.0 / h1) ** 2, d0 * (2.0 / h2) ** 2, d0 * (2.0 / h3) ** 2]
+    T = face_transform(S, p + 1)
     Kh = T.T @ K @ T
     n = p + 1
     nf = 2 * n * n
     for a in range(3):
         blk = Kh[a * nf:(a + 1) * nf, a * nf:(a + 1) * nf]
-        # local face index -> (side, tangential pair)
+        # local face index -> (side, tangential pair (tb, tc), lower axis first)
         idx = np.arange(nf)
         if a == 0:
-            side, t = idx % 2, idx // 2
+            side, tb, tc = idx % 2, (idx // 2) % n, idx // (2 * n)
         elif a == 1:
-            side, t = (idx // n) % 2, (idx % n) + n * (idx // (2 * n))
+            side, tb, tc = (idx // n) % 2, idx % n, idx // (2 * n)
         else:
-            side, t = idx // (n * n), idx % (n * n)
+            side, tb, tc = idx // (n * n), idx % n, (idx // n) % n
+        t = tb + n * tc
         mask = t[:, None] != t[None, :]
         assert np.abs(blk[mask]).max() < 1e-12 * np.abs(blk).max()
-        # the diagonal block matches d H - d^2 sum_k B_S[k,s] B_S[k,s'] / D_Z
-    assert True
+        b, c = [ax for ax in range(3) if ax != a]
+        for i in range(nf):
+            for j in range(nf):
+                if t[i] != t[j]:
+                    continue
+                dz = lam * d0 + d[a] * Lam + d[b] * Lam[tb[i]] + d[c] * Lam[tc[i]]
+                ref = (d[a] * Hm[side[i], side[j]]
+                       - d[a] ** 2 * np.sum(BS[:, side[i]] * BS[:, side[j]] / dz))
+                assert abs(blk[i, j] - ref) < 1e-12 * np.abs(blk).max()
 
 
 def test_layout_counts_and_coverage():
@@ -263,17 +286,6 @@ def test_global_operator_spd_tiny():
     assert np.abs(o.apply_free(x) - Kff @ x).max() < 1e-13 * np.abs(Kff @ x).max()
 
 
-def test_rhs_consistency_with_element_system():
-    """F_e from the element system equals the direct elimination of u, q with
-    zero trace: the recovered u of a zero trace solves A [u;q] = [M f; 0]."""
-    s = standard_matrices(2, 1.0)
-    es = ElementSystem(s, H_PERT, 1.3)
-    f = np.random.default_rng(0).standard_normal(es.nv)
-    y = np.linalg.solve(es.A, es.volume_rhs(es.Me @ f))
-    F = element_rhs(s, H_PERT, 1.3, f)
-    assert np.abs(F + es.R.T @ y).max() < 1e-12
-
-
 def test_adjoint_matches_central_differences():
     """Oracle gradients dJ/dlambda_e and dJ/df against central differences of
     J = 1/2 ||u - u*||_M^2 computed by re-solving."""
@@ -303,3 +315,42 @@ def test_adjoint_matches_central_differences():
         fd = (J(lam + eps * vl, f + eps * vf) - J(lam - eps * vl, f - eps * vf)) / (2 * eps)
         an = dlam @ vl + df @ vf
         assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (fd, an)
+
+
+@pytest.mark.parametrize("neumann", [0, 0b100110])
+def test_apply_rows_and_faces_elements(neumann):
+    """The sampled-row operator of the oracle (used as the expected value of
+    full-size GPU checks) equals rows of the assembled K = sum_e Q_e^T K_e Q_e
+    (equation (hdg_system)), and the elements it sums are exactly the
+    elements whose closed box contains the face (one on a side of the box,
+    two inside), found from coordinates."""
+    n, p = (3, 2, 4), 2
+    widths = [np.array([0.2, 0.5, 0.3]), np.array([0.45, 0.55]), np.array([0.1, 0.2, 0.3, 0.4])]
+    o = oracle.HdgOracle(n, widths, p, 1.0, 1.3, neumann=neumann)
+    L = o.layout
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, L.n_all)
+    y_full = o.assemble_K() @ x
+    assert np.abs(o.apply(x) - y_full).max() < 1e-13 * np.abs(y_full).max()
+    npf = (p + 1) ** 2
+    faces = rng.choice(L.n_faces, size=12, replace=False)
+    rows = np.concatenate([f * npf + rng.choice(npf, size=3, replace=False) for f in faces])
+    rows = np.concatenate([rows, [0, L.n_free - 1, L.n_all - 1]])
+    got = o.apply_rows(x, rows)
+    assert np.abs(got - y_full[rows]).max() < 1e-13 * np.abs(y_full).max()
+    # elements of each face from geometry: the face's nodes lie on the
+    # element's closed box
+    T = o.trace_coords()
+    edges = [np.concatenate([[0.0], np.cumsum(w)]) for w in widths]
+    for f in faces:
+        pts = T[f * npf:(f + 1) * npf]
+        want = []
+        for e in range(L.n_elem):
+            ijk = L.elem_ijk(e)
+            lo = np.array([edges[a][ijk[a]] for a in range(3)])
+            hi = np.array([edges[a][ijk[a] + 1] for a in range(3)])
+            if ((pts >= lo - 1e-12) & (pts <= hi + 1e-12)).all():
+                want.append(e)
+        assert o.faces_elements([f]) == want
+        on_side = any(np.allclose(pts[:, a], v) for a in range(3) for v in (0.0, edges[a][-1]))
+        assert len(want) == (1 if on_side else 2)
