@@ -39,44 +39,125 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, budget_s: float):
-    """Oracle apply (dense Schur complement per element, then K_e x_e) on a
-    bounded sample of elements of the same workload, scaled to trace-DOF/s."""
-    import oracle
+def _blas_threads() -> int:
     try:
         from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        return int(max([d.get("num_threads", 1) for d in threadpool_info()] or [1]))
     except Exception:
-        threads = os.cpu_count() or 1
-    o = oracle.HdgOracle(prob.n, prob.widths, prob.p, prob.tau, prob.lam, cache_limit=1)
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(prob, budget_s: float, cg_iters: int):
+    """The oracle (dense element Schur complements, the definition of the
+    operator) timed on the host cores, as three separate parts:
+
+    * cfg1 (2^3, p = 4): setup (element systems and the assembled sparse K),
+      apply (CSR matvec of K_ff) and solve (sparse direct), all measured;
+    * the bench workload (16^3 perturbed, p = 7): setup of K_e for a random
+      sample of elements (dense LU of the element system), the element-by-
+      element apply y[Q_e] += K_e x[Q_e] over that sample with its K_e
+      precomputed, both scaled to the whole mesh, and the Jacobi-CG solve
+      estimated as (CG iterations of the GPU solve) x (apply + the vector
+      work of one iteration, timed on full-length numpy vectors).
+
+    `value` is the apply rate of the bench workload in trace-DOF/s."""
+    import oracle
+    import workloads as W
+    threads = _blas_threads()
     rng = np.random.default_rng(0)
-    x = rng.uniform(-1, 1, o.layout.n_all)
-    x[o.layout.n_free:] = 0.0
-    order = rng.permutation(o.layout.n_elem)
+    # ---- cfg1: everything measured --------------------------------------
+    tp = W.tiny()
+    t0 = time.perf_counter()
+    o1 = oracle.HdgOracle(tp.n, tp.widths, tp.p, tp.tau, tp.lam)
+    K1 = o1.assemble_K()
+    nf1 = o1.layout.n_free
+    Kff1 = K1[:nf1, :nf1].tocsr()
+    t_setup1 = time.perf_counter() - t0
+    x1 = rng.uniform(-1, 1, nf1)
+    ts = []
+    for _ in range(11):
+        t = time.perf_counter()
+        _ = Kff1 @ x1
+        ts.append(time.perf_counter() - t)
+    t_apply1 = statistics.median(ts[1:])
+    X = o1.volume_coords()
+    T = o1.trace_coords()
+    f1 = W.f_sin3(*X.T, 1.0)
+    g1 = W.u_sin3(*T.T)
+    ts = []
+    for _ in range(4):
+        t = time.perf_counter()
+        _ = o1.solve(f1, g1)
+        ts.append(time.perf_counter() - t)
+    t_solve1 = statistics.median(ts[1:])
+    # ---- bench workload: sampled setup and apply, estimated solve --------
+    o = oracle.HdgOracle(prob.n, prob.widths, prob.p, prob.tau, prob.lam, cache_limit=1 << 20)
+    ne, nf, na = o.layout.n_elem, o.layout.n_free, o.layout.n_all
+    order = rng.permutation(ne)
     t0 = time.perf_counter()
     m = 0
     for e in order:
-        mp = o.tmap(int(e))
-        _ = o.K_e(int(e)) @ x[mp]
+        o.K_e(int(e))
+        o.tmap(int(e))
         m += 1
-        if time.perf_counter() - t0 > budget_s and m >= 2:
+        if time.perf_counter() - t0 > 0.6 * budget_s and m >= 4:
             break
-    dt = time.perf_counter() - t0
-    per_apply_s = dt / m * o.layout.n_elem
-    return {"value": o.layout.n_free / per_apply_s, "unit": "trace-DOF/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{m} of {o.layout.n_elem} elements (dense element Schur complement + "
-                      f"matvec), {dt:.1f} s; scaled to one full apply = {per_apply_s:.0f} s"}
+    t_setup = (time.perf_counter() - t0) / m * ne
+    sample = [int(e) for e in order[:m]]
+    x = rng.uniform(-1, 1, na)
+    x[nf:] = 0.0
+    y = np.zeros(na)
+    ts = []
+    for _ in range(6):
+        t = time.perf_counter()
+        for e in sample:
+            mp = o.tmap(e)
+            y[mp] += o.K_e(e) @ x[mp]
+        ts.append(time.perf_counter() - t)
+    t_apply = statistics.median(ts[1:]) / m * ne
+    # vector work of one Jacobi-PCG iteration on N_tr(free)-long vectors
+    v = [rng.uniform(-1, 1, nf) for _ in range(5)]
+    xv, rv, pv, qv, dv = v
+    ts = []
+    for _ in range(6):
+        t = time.perf_counter()
+        al = 0.5 * float(rv @ rv) / float(pv @ qv)
+        xv += al * pv
+        rv -= al * qv
+        zv = dv * rv
+        be = float(rv @ zv) * 1e-3
+        pv *= be
+        pv += zv
+        ts.append(time.perf_counter() - t)
+    t_vec = statistics.median(ts[1:])
+    t_solve = cg_iters * (t_apply + t_vec)
+    return {"value": nf / t_apply, "unit": "trace-DOF/s", "cores": threads, "kind": "oracle",
+            "sample": (f"apply: y[Q_e] += K_e x[Q_e] over {m} of {ne} elements of the 16^3 p=7 "
+                       f"workload with K_e precomputed, scaled to the mesh; setup (dense K_e) "
+                       f"timed on the same sample"),
+            "bench_workload_s": {"setup": round(t_setup, 1), "apply": round(t_apply, 4),
+                                 "solve_est": round(t_solve, 1)},
+            "cfg1_s": {"setup": round(t_setup1, 4), "apply": t_apply1, "solve": round(t_solve1, 4)}}
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fused_cg_apply_perturbed16_p7_hbm_counters.md")
+# Algorithmic bytes of one FP64 Jacobi-PCG iteration per free trace DOF: the
+# operator reads its input and writes its output once (16 B) and the CG's
+# vector work takes about nine more passes over 8-byte vectors (72 B).  FP32
+# halves it.  The implementation's own per-DOF traffic is listed beside it.
+ALG_CG_BYTES = 88
+IMPL_CG_BYTES = {"one kernel": 104, "two kernels": 104}
+# committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries, one per workload
+TRAFFIC_PROFILES = {
+    "perturbed16_p7": os.path.join(ROOT, "profiles", "cg_iteration_perturbed16_p7_hbm_counters.md"),
+    "uniform32_p12": os.path.join(ROOT, "profiles", "cg_iteration_uniform32_p12_hbm_counters.md"),
+}
 KERNEL_SOURCES = ("paper_2007_11891_amd/csrc/elem_unit.hpp", "paper_2007_11891_amd/csrc/elem_kernels.hip",
                   "paper_2007_11891_amd/csrc/vec_kernels.hip",
                   "paper_2007_11891_amd/csrc/device_common.hpp")
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the sources of the fused CG apply kernel."""
+    """sha256 over the sources of the CG kernels."""
     import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
@@ -85,40 +166,74 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the
-    summary is missing, covers another kernel, or the kernel sources changed
-    since the counters were taken."""
+def measured_traffic(workload: str, kernels):
+    """HBM bytes per CG iteration (the sum over `kernels`, one launch each)
+    from the committed counter summary of `workload` (FETCH_SIZE +
+    WRITE_SIZE, each scaled by what it reads for a plain copy), or None when
+    the summary is missing, does not cover a kernel, or the kernel sources
+    changed since the counters were taken."""
     try:
-        with open(TRAFFIC_PROFILE) as fh:
+        with open(TRAFFIC_PROFILES[workload]) as fh:
             text = fh.read()
         block = text.split("```json", 1)[1].split("```", 1)[0]
         rec = json.loads(block)
-    except (OSError, IndexError, ValueError):
+    except (KeyError, OSError, IndexError, ValueError):
         return None
     if rec.get("source_sha256") != kernel_source_hash():
         return None
-    entry = rec.get("kernels", {}).get(kernel)
-    return None if entry is None else entry.get("traffic_bytes")
+    tot = 0
+    for k in kernels:
+        entry = rec.get("kernels", {}).get(k)
+        if entry is None:
+            return None
+        tot += entry["traffic_bytes"]
+    return tot
 
 
-def cg_iteration_roofline(c, W, torch, dev, fp32: bool, reps: int = 50):
-    """Mean time of one CG iteration (HIP events, back-to-back launches) in
-    the CG form and tile shape the solve runs, as an HBM roofline entry:
-    104 B per free DOF in FP64, 52 B in FP32.  FP64: the context's CG form;
-    FP32: the two-kernel form, the one the mixed-precision inner CG uses."""
+def cg_kernel_names(c, fp32: bool = False):
+    """Names (as rocprofv3 prints them) of the kernels of one CG iteration in
+    the context's CG form and tile shape."""
+    t = c.tile_shape()
+    typ = "float" if fp32 else "double"
+    np_, epu = c.p + 1, t["elems_per_unit"]
+    if t["cg_variant"] == 0 and not fp32:
+        return [f"elem_apply_kernel<{typ}, {np_}, {epu}, 2, 0>"]
+    units = -(-c.n_elem // epu)
+    upb = -(-units // min(units, 2048))
+    return [f"elem_apply_kernel<{typ}, {np_}, {epu}, 1, {1 if upb > 1 else 0}>",
+            f"cg_update_kernel<{typ}>"]
+
+
+def cg_iteration_roofline(c, W, torch, dev, fp32: bool = False, reps: int = 50,
+                          workload: str | None = None):
+    """One CG iteration in the CG form and tile shape the solve runs (FP32:
+    the two-kernel form of the mixed-precision inner CG), mean time per
+    iteration over back-to-back launches (HIP events on the context stream),
+    as an HBM roofline entry at the algorithmic 88 B per free DOF (44 in
+    FP32), with the implementation's own bytes and the counted traffic."""
+    import paper_2007_11891_amd as pkg
     nf = c.sizes.n_free
     one = c.tile_shape()["cg_variant"] == 0 and not fp32
-    which = (10 if fp32 else 9) if one else (3 if fp32 else 2)
+    form = "one kernel" if one else "two kernels"
+    if one:
+        which = pkg.TIME_CG1_ITER_F64
+    else:
+        which = pkg.TIME_CG2_ITER_F32 if fp32 else pkg.TIME_CG2_ITER_F64
     x = torch.as_tensor(W.random_trace(nf, 7), device=dev)
     if fp32:
         x = x.float()
     t = c.time_kernel(which, x, reps)
-    nbytes = (52 if fp32 else 104) * nf
-    gbs = nbytes / (t * 1e-3) / 1e9
-    return {"form": "one kernel" if one else "two kernels", "avg_us": round(t * 1e3, 3),
-            "bytes": nbytes, "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    scale = 0.5 if fp32 else 1.0
+    alg = ALG_CG_BYTES * scale * nf
+    impl = IMPL_CG_BYTES[form] * scale * nf
+    ach = alg / (t * 1e-3) / 1e9
+    kernels = cg_kernel_names(c, fp32)
+    traffic = None if (fp32 or workload is None) else measured_traffic(workload, kernels)
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernels": kernels, "cg_form": form, "avg_us": round(t * 1e3, 3),
+            "alg_bytes": int(alg), "impl_bytes": int(impl),
+            "impl_GBs": round(impl / (t * 1e-3) / 1e9, 1)}
 
 
 def bench_mixed(pkg, W, torch, dev, reps: int = 3):
@@ -402,7 +517,11 @@ def bench_batched(pkg, W, torch, dev, reps: int = 3):
     t1 = b.time_cg(1, reps=3)
     t21 = b.time_cg(21, reps=3)
     t_it = (t21 - t1) / 20.0                     # ms per CG iteration, all problems active
-    bytes_it = 104 * b.total_free                # fused apply 64 B + update 40 B per DOF
+    # algorithmic 88 B per free DOF and iteration; the two-phase form moves
+    # 104 B (apply phase 40 B: read z, p_old, write p, qa, qb; update phase
+    # 64 B: read z, qa, qb, D^-1, x, p, write z, x)
+    bytes_it = ALG_CG_BYTES * b.total_free
+    impl_it = 104 * b.total_free
     ach = bytes_it / (t_it * 1e-3) / 1e9
     log(f"[bench] batched: {len(probs)} problems, {b.total_free} free DOFs, wall {wall*1e3:.1f} ms, "
         f"max iters {iters.max()}, CG iteration {t_it*1e3:.1f} us, tiles {tiles}")
@@ -418,7 +537,8 @@ def bench_batched(pkg, W, torch, dev, reps: int = 3):
            "roofline": {"kernel": "batch_cg_kernel (persistent, one CG iteration of every problem)",
                         "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                        "bytes_per_iteration": bytes_it}}
+                        "alg_bytes": bytes_it, "impl_bytes": impl_it,
+                        "impl_GBs": round(impl_it / (t_it * 1e-3) / 1e9, 1)}}
     b.close()
     return out
 
@@ -473,6 +593,21 @@ def bench_adjoint(pkg, W, torch, dev, reps: int = 3):
     return out
 
 
+def hbm_size_iteration(pkg, W, torch, dev, p: int):
+    """The FP64 CG iteration on the 32^3 uniform unit-cube mesh at degree p
+    (lambda = 1): vectors of 66 MB (p = 8) and 137 MB (p = 12), past the
+    256 MB Infinity Cache once a few of them are live, so that the bytes come
+    from HBM."""
+    prob = W.mixed(p, 1.0)
+    c = pkg.HdgContext(prob.n, prob.widths, prob.p, prob.tau, 1.0)
+    c.autotune(reps=10)
+    r = cg_iteration_roofline(c, W, torch, dev, False, reps=50, workload=f"uniform32_p{p}")
+    r["workload"] = f"32^3 uniform, p={p}, lambda=1, N_tr(free)={c.sizes.n_free}"
+    c.close()
+    torch.cuda.empty_cache()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -490,6 +625,10 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-paper-case", action="store_true")
     ap.add_argument("--no-neumann", action="store_true")
+    ap.add_argument("--no-hbm-size", action="store_true")
+    ap.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
+                    help="file for the full record (every section); the last stdout line is the "
+                         "compact headline")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -501,29 +640,29 @@ def main():
     import paper_2007_11891_amd as pkg
 
     torch.cuda.set_device(0)
-    prob = W.perturbed(n=args.n, p=args.p, lam=10.0, seed=2)
-    log(f"[bench] workload perturbed n={prob.n} p={prob.p} lam=10 tau=1")
-    ctx = pkg.HdgContext(prob.n, prob.widths, prob.p, prob.tau, prob.lam)
-    nf, na, nv = ctx.sizes.n_free, ctx.sizes.n_all, ctx.sizes.n_vol
     dev = torch.device("cuda", 0)
-    f = torch.as_tensor(prob.f_values, device=dev)
-    trace = torch.zeros(na, dtype=torch.float64, device=dev)
-    u_vol = torch.empty(nv, dtype=torch.float64, device=dev)
-    opts = pkg.default_opts(rtol=1e-10)
-    variant, tile_times = ctx.autotune(reps=50)      # tile shape, chosen before timing
-    tile = ctx.tile_shape()
-    log(f"[bench] tile variant {variant} ({tile['elems_per_unit']} elements / "
-        f"{tile['threads_per_unit']} threads per unit), CG form {tile['cg_variant']}, "
-        f"times {[round(t * 1e3, 2) for t in tile_times]} us")
-
     if args.kernels_only:
+        # isolated kernels of one workload, for counter collection (rocprofv3
+        # --pmc): the bench mesh by default, --n 32 --p 12 for the uniform
+        # 32^3 mesh
+        if args.n == 16 and args.p == 7:
+            prob = W.perturbed(n=16, p=7, lam=10.0, seed=2)
+        else:
+            prob = W.mixed(args.p, 1.0) if args.n == 32 else W.perturbed(n=args.n, p=args.p,
+                                                                          lam=10.0, seed=2)
+        ctx = pkg.HdgContext(prob.n, prob.widths, prob.p, prob.tau, float(np.ravel(prob.lam)[0]))
+        variant, _ = ctx.autotune(reps=10)
+        tile = ctx.tile_shape()
+        log(f"[bench] kernels-only n={prob.n} p={prob.p}: tile variant {variant}, "
+            f"CG form {tile['cg_variant']}, kernels {cg_kernel_names(ctx)}")
+        nf = ctx.sizes.n_free
         x64 = torch.as_tensor(W.random_trace(nf, 1), device=dev)
         y64 = torch.empty_like(x64)
-        for which, name in ((0, "apply64"), (1, "apply32"), (4, "cg_apply64"),
-                            (5, "cg_update64"), (9, "cg_onekernel64"), (8, "copy64"),
-                            (13, "nodal_unprec64"), (14, "nodal_diag64"), (15, "nodal_block64")):
-            xin = x64.float() if which == 1 else x64
-            ms = ctx.time_kernel(which, xin, args.reps, y=y64 if which == 8 else None)
+        for which, name in ((pkg.TIME_APPLY_F64, "apply64"), (pkg.TIME_CG2_APPLY_F64, "cg_apply64"),
+                            (pkg.TIME_CG2_UPDATE_F64, "cg_update64"),
+                            (pkg.TIME_CG1_ITER_F64, "cg_onekernel64"), (pkg.TIME_COPY_F64, "copy64")):
+            ms = ctx.time_kernel(which, x64, args.reps,
+                                 y=y64 if which in (pkg.TIME_COPY_F64, pkg.TIME_APPLY_F64) else None)
             log(f"[bench] {name} {ms * 1e3:.3f} us")
         # plain copy of 256 MiB (larger than L2 and the infinity cache): the
         # reference dispatch for scaling HBM byte counters
@@ -534,6 +673,20 @@ def main():
         torch.cuda.synchronize()
         ctx.close()
         return
+
+    prob = W.perturbed(n=args.n, p=args.p, lam=10.0, seed=2)
+    log(f"[bench] workload perturbed n={prob.n} p={prob.p} lam=10 tau=1")
+    ctx = pkg.HdgContext(prob.n, prob.widths, prob.p, prob.tau, prob.lam)
+    nf, na, nv = ctx.sizes.n_free, ctx.sizes.n_all, ctx.sizes.n_vol
+    f = torch.as_tensor(prob.f_values, device=dev)
+    trace = torch.zeros(na, dtype=torch.float64, device=dev)
+    u_vol = torch.empty(nv, dtype=torch.float64, device=dev)
+    opts = pkg.default_opts(rtol=1e-10)
+    variant, tile_times = ctx.autotune(reps=50)      # tile shape, chosen before timing
+    tile = ctx.tile_shape()
+    log(f"[bench] tile variant {variant} ({tile['elems_per_unit']} elements / "
+        f"{tile['threads_per_unit']} threads per unit), CG form {tile['cg_variant']}, "
+        f"times {[round(t * 1e3, 2) for t in tile_times]} us")
 
     def step():
         trace.zero_()
@@ -555,80 +708,61 @@ def main():
     value = nf * applies / (elapsed / args.steps)
     log(f"[bench] step {ms_per_step:.3f} ms, CG iters {iters}, rel_res {infos[-1]['rel_res']:.2e}")
 
-    # ---- isolated kernels, HIP events on the context stream ----------------
+    # ---- the dominant kernel: one CG iteration (HIP events, context stream) --
+    roof = cg_iteration_roofline(ctx, W, torch, dev, False, reps=args.reps, workload="perturbed16_p7"
+                                 if (args.n, args.p) == (16, 7) else None)
+    log(f"[bench] CG iteration {roof['avg_us']:.2f} us ({roof['cg_form']}), "
+        f"{roof['achieved']:.0f} GB/s at 88 B/DOF, frac {roof['frac']:.3f}; "
+        f"{roof['impl_GBs']:.0f} GB/s at the implementation's bytes")
+    # ---- isolated kernels ---------------------------------------------------
     x64 = torch.as_tensor(W.random_trace(nf, 1), device=dev)
     x32 = x64.float()
-    reps = 200
-    t_apply64 = ctx.time_kernel(0, x64, reps)
-    t_apply32 = ctx.time_kernel(1, x32, reps)
-    t_cg_apply = ctx.time_kernel(4, x64, reps)
-    t_cg_update = ctx.time_kernel(5, x64, reps)
-    t_cg_iter = ctx.time_kernel(2, x64, reps)
-    t_cg_iter32 = ctx.time_kernel(3, x32, reps)
-    t_one = ctx.time_kernel(9, x64, reps)
-    t_one32 = ctx.time_kernel(10, x32, reps)
-    log(f"[bench] apply64 {t_apply64*1e3:.2f} us apply32 {t_apply32*1e3:.2f} us "
-        f"cg_apply {t_cg_apply*1e3:.2f} us cg_update {t_cg_update*1e3:.2f} us "
-        f"cg_iter {t_cg_iter*1e3:.2f} us cg_iter32 {t_cg_iter32*1e3:.2f} us")
-    # per free DOF and CG iteration (8 B each).  Two-kernel form: the fused
-    # apply reads z, p_old and writes p, qa, qb; the update reads z, qa, qb,
-    # D^-1, x, p and writes z, x.  One-kernel form: reads z, p, s, qa, qb,
-    # D^-1, x and writes z, p, s, x, qa, qb (104 B).  The roofline is reported
-    # for the dominant kernel of the CG form the solve uses.
-    cg_apply_bytes = 40 * nf
-    cg_update_bytes = 64 * nf
-    one_bytes = 104 * nf
-    # kernel names as rocprofv3 prints them: <type, n_p, elements per unit,
-    # mode, pipelined>; the fused apply is pipelined when a block has several
-    # units (grid capped at 2048 blocks)
-    epu = tile["elems_per_unit"]
-    units = -(-prob.n_elem // epu)
-    upb = -(-units // min(units, 2048))
-    apply_name = f"elem_apply_kernel<double, {prob.p + 1}, {epu}, 1, {1 if upb > 1 else 0}>"
-    one_name = f"elem_apply_kernel<double, {prob.p + 1}, {epu}, 2, 0>"
-    if tile["cg_variant"] == 0:
-        kname, kbytes, kt, kdesc = one_name, one_bytes, t_one, "one-kernel CG iteration"
-        it_us, it_kernels = t_one, [one_name]
-    else:
-        if t_cg_apply >= t_cg_update:
-            kname, kbytes, kt, kdesc = apply_name, cg_apply_bytes, t_cg_apply, "fused CG apply"
-        else:
-            kname, kbytes, kt, kdesc = ("cg_update_kernel<double>", cg_update_bytes, t_cg_update,
-                                        "CG update")
-        it_us, it_kernels = t_cg_iter, [apply_name, "cg_update_kernel<double>"]
-    achieved = kbytes / (kt * 1e-3) / 1e9
-    it_gbs = one_bytes / (it_us * 1e-3) / 1e9
-    roofline = {"kernel": f"{kname} ({kdesc})", "bound": "hbm",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(kname),
-                "bytes_per_launch": kbytes, "avg_launch_us": round(kt * 1e3, 3),
-                "cg_form": "one kernel per iteration" if tile["cg_variant"] == 0
-                           else "element + update kernel per iteration",
-                # the whole CG iteration (every kernel of the form in use)
-                "iteration": {"kernels": it_kernels, "bytes": one_bytes,
-                              "avg_us": round(it_us * 1e3, 3), "achieved": round(it_gbs, 1),
-                              "frac": round(it_gbs / HBM_PEAK_GBS, 4)}}
+    y64 = torch.empty_like(x64)
+    y32 = torch.empty_like(x32)
+    reps = args.reps
+    t_apply64 = ctx.time_kernel(pkg.TIME_APPLY_F64, x64, reps, y=y64)
+    t_apply32 = ctx.time_kernel(pkg.TIME_APPLY_F32, x32, reps, y=y32)
+    t_elem64 = ctx.time_kernel(pkg.TIME_ELEM_APPLY_F64, x64, reps)
+    t_cg_apply = ctx.time_kernel(pkg.TIME_CG2_APPLY_F64, x64, reps)
+    t_cg_update = ctx.time_kernel(pkg.TIME_CG2_UPDATE_F64, x64, reps)
+    t_cg_iter = ctx.time_kernel(pkg.TIME_CG2_ITER_F64, x64, reps)
+    t_cg_iter32 = ctx.time_kernel(pkg.TIME_CG2_ITER_F32, x32, reps)
+    t_one = ctx.time_kernel(pkg.TIME_CG1_ITER_F64, x64, reps)
+    t_one32 = ctx.time_kernel(pkg.TIME_CG1_ITER_F32, x32, reps)
+    log(f"[bench] apply64 {t_apply64*1e3:.2f} us (element kernel {t_elem64*1e3:.2f}) "
+        f"apply32 {t_apply32*1e3:.2f} us cg_apply {t_cg_apply*1e3:.2f} us "
+        f"cg_update {t_cg_update*1e3:.2f} us cg_iter {t_cg_iter*1e3:.2f} us "
+        f"cg_iter32 {t_cg_iter32*1e3:.2f} us one-kernel {t_one*1e3:.2f} us")
     # the paper's nodal-basis solvers at the same size: one CG iteration each
     nodal_iteration = {}
     for name, pc, tid, bpd in PAPER_SOLVERS[1:]:
         t_it = ctx.time_kernel(tid, x64, reps)
         gbs = bpd * nf / (t_it * 1e-3) / 1e9
-        nodal_iteration[name] = {"avg_us": round(t_it * 1e3, 3), "bytes": bpd * nf,
-                                 "achieved_GBs": round(gbs, 1),
-                                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        nodal_iteration[name] = {"avg_us": round(t_it * 1e3, 3), "impl_bytes": bpd * nf,
+                                 "impl_GBs": round(gbs, 1),
+                                 "impl_frac": round(gbs / HBM_PEAK_GBS, 4)}
     log("[bench] nodal-basis CG iteration: " + ", ".join(
-        f"{k} {v['avg_us']:.2f} us ({v['frac']:.3f})" for k, v in nodal_iteration.items()))
+        f"{k} {v['avg_us']:.2f} us ({v['impl_frac']:.3f})" for k, v in nodal_iteration.items()))
+    # hdg_apply in the eigen basis as it runs (element kernel + sum of the two
+    # face contributions); algorithmic 16 B per free DOF (8 in FP32)
     apply_bytes = 16 * nf
     apply_only = {"trace_dof_per_s_fp64": nf / (t_apply64 * 1e-3),
                   "trace_dof_per_s_fp32": nf / (t_apply32 * 1e-3),
-                  "avg_launch_us_fp64": round(t_apply64 * 1e3, 3),
-                  "avg_launch_us_fp32": round(t_apply32 * 1e3, 3),
-                  "algorithmic_GBs_fp64": round(apply_bytes / (t_apply64 * 1e-3) / 1e9, 1),
-                  "algorithmic_GBs_fp32": round(apply_bytes / 2 / (t_apply32 * 1e-3) / 1e9, 1)}
+                  "avg_us_fp64": round(t_apply64 * 1e3, 3),
+                  "avg_us_fp32": round(t_apply32 * 1e3, 3),
+                  "element_kernel_us_fp64": round(t_elem64 * 1e3, 3),
+                  "alg_GBs_fp64": round(apply_bytes / (t_apply64 * 1e-3) / 1e9, 1),
+                  "frac_fp64": round(apply_bytes / (t_apply64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "alg_GBs_fp32": round(apply_bytes / 2 / (t_apply32 * 1e-3) / 1e9, 1)}
+
+    hbm = {}
+    if not args.no_hbm_size:
+        for p in (8, 12):
+            hbm[f"p{p}"] = hbm_size_iteration(pkg, W, torch, dev, p)
+            log(f"[bench] 32^3 p={p} CG iteration {hbm[f'p{p}']['avg_us']:.1f} us "
+                f"({hbm[f'p{p}']['cg_form']}), frac {hbm[f'p{p}']['frac']:.3f} at 88 B/DOF")
 
     mixed = None if args.no_mixed else bench_mixed(pkg, W, torch, dev)
-
     batched = None if args.no_batch else bench_batched(pkg, W, torch, dev)
     adjoint = None if args.no_adjoint else bench_adjoint(pkg, W, torch, dev)
     paper_case = None if args.no_paper_case else bench_paper_case(pkg, W, torch, dev)
@@ -638,40 +772,77 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
-        cpu = cpu_baseline(prob, args.cpu_budget)
+        cpu = cpu_baseline(prob, args.cpu_budget, iters)
         log(f"[bench] cpu baseline {cpu['value']:.3e} trace-DOF/s on {cpu['cores']} threads")
 
-    out = {
+    config = {"workload": f"perturbed Cartesian {prob.n[0]}x{prob.n[1]}x{prob.n[2]}, p={prob.p}, "
+                          f"lambda=10, tau=1, f~U[-1,1], g_D=0; step = RHS + Jacobi-PCG to 1e-10 + "
+                          f"recovery",
+              "n_elem": prob.n_elem, "p": prob.p, "n_trace_free": nf, "n_trace_all": na,
+              "n_vol": nv, "cg_iters": iters, "rel_res": infos[-1]["rel_res"]}
+    head = {
         "metric": "trace-DOF/s of condensed HDG apply; time-to-1e-10 CG, mixed vs FP64",
         "value": value, "unit": "trace-DOF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"perturbed Cartesian {prob.n[0]}x{prob.n[1]}x{prob.n[2]}, "
-                               f"p={prob.p}, lambda=10, tau=1, f~U[-1,1], g_D=0; step = RHS + "
-                               f"Jacobi-PCG to 1e-10 + recovery",
-                   "n_elem": prob.n_elem, "p": prob.p, "n_trace_free": nf, "n_trace_all": na,
-                   "n_vol": nv, "cg_iters": iters, "rel_res": infos[-1]["rel_res"]},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "apply_only": apply_only,
-        "nodal_solver_iteration": nodal_iteration,
+        "config": config,
+    }
+    detail = dict(head)
+    detail.update({
+        "roofline": roof, "hbm_size_iteration": hbm, "cpu_baseline": cpu,
+        "apply_only": apply_only, "nodal_solver_iteration": nodal_iteration,
         "cg_iteration_us": {"two_kernel_fp64": round(t_cg_iter * 1e3, 3),
                             "two_kernel_fp32": round(t_cg_iter32 * 1e3, 3),
                             "fused_apply_fp64": round(t_cg_apply * 1e3, 3),
                             "update_fp64": round(t_cg_update * 1e3, 3),
                             "one_kernel_fp64": round(t_one * 1e3, 3),
                             "one_kernel_fp32": round(t_one32 * 1e3, 3)},
-        "mixed_precision": mixed,
         "tile": {"variant": variant, "elems_per_unit": tile["elems_per_unit"],
                  "threads_per_unit": tile["threads_per_unit"], "cg_variant": tile["cg_variant"],
                  "autotune_cg_iter_us": [round(t * 1e3, 3) for t in tile_times]},
-        "batched": batched,
-        "adjoint": adjoint,
-        "paper_case": paper_case,
-        "tau_sweep": tau_sweep,
-        "neumann": neumann,
-    }
-    print(json.dumps(out), flush=True)
+        "mixed_precision": mixed, "batched": batched, "adjoint": adjoint,
+        "paper_case": paper_case, "tau_sweep": tau_sweep, "neumann": neumann,
+    })
+    try:
+        os.makedirs(os.path.dirname(args.detail), exist_ok=True)
+        with open(args.detail, "w") as fh:
+            json.dump(detail, fh, indent=1)
+        log(f"[bench] full record: {args.detail}")
+    except OSError as exc:
+        log(f"[bench] could not write {args.detail}: {exc}")
+    # sections on stderr, one line each, for logs that keep only the streams
+    for k in ("apply_only", "mixed_precision", "batched", "adjoint", "neumann"):
+        if detail.get(k) is not None:
+            log(f"[bench] {k}: " + json.dumps(detail[k], separators=(",", ":"))[:4000])
+
+    # ---- compact headline: the last stdout line ----------------------------
+    keep = ("bound", "achieved", "peak", "unit", "frac", "traffic")
+    roofline = {k: roof[k] for k in keep}
+    roofline.update({"kernel": " + ".join(roof["kernels"]), "avg_launch_us": roof["avg_us"],
+                     "alg_bytes_per_dof": ALG_CG_BYTES,
+                     "impl_bytes_per_dof": IMPL_CG_BYTES[roof["cg_form"]],
+                     "impl_GBs": roof["impl_GBs"]})
+    if hbm:
+        roofline["hbm_size"] = {k: {"workload": v["workload"], "avg_us": v["avg_us"],
+                                    "achieved": v["achieved"], "frac": v["frac"],
+                                    "traffic": v["traffic"], "cg_form": v["cg_form"]}
+                                for k, v in hbm.items()}
+    extras = {"apply_only_fp64": {"trace_dof_per_s": round(apply_only["trace_dof_per_s_fp64"], 1),
+                                  "frac_16B": apply_only["frac_fp64"]}}
+    if mixed:
+        extras["mixed_geomean_speedup"] = mixed["geomean_speedup"]
+    if batched:
+        extras["batched"] = {"trace_dof_iters_per_s": round(batched["trace_dof_iters_per_s"], 1),
+                             "frac": batched["roofline"]["frac"]}
+    if adjoint:
+        extras["adjoint_gradients_per_s"] = round(adjoint["gradients_per_s"], 2)
+    head["config"] = {"workload": config["workload"], "n_trace_free": nf, "cg_iters": iters}
+    head["roofline"] = roofline
+    head["cpu_baseline"] = None if cpu is None else {
+        k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample", "bench_workload_s", "cfg1_s")}
+    head["extras"] = extras
+    line = json.dumps(head, separators=(",", ":"))
+    print(line, flush=True)
     ctx.close()
 
 

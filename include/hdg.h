@@ -344,19 +344,37 @@ hdg_status hdg_tile_shape(const hdg_ctx* ctx, int* variant, int* elems_per_unit,
 /* Diagonal of K^_ff (eigen basis), device double[n_free] output. */
 hdg_status hdg_diagonal(hdg_ctx* ctx, double* diag_free);
 
-/* Timing helper: launch the internal kernel `which` `reps` times
- * back-to-back on the context stream between two HIP events and return the
- * mean time per launch in *ms.  which: 0 = FP64 eigen-basis element apply
- * (x -> y), 1 = FP32 eigen-basis element apply, 2 = FP64 CG iteration
- * (fused apply + update), 3 = FP32 CG iteration, 4 / 5 = FP64 fused CG
- * apply / update alone, 6 / 7 = the same in FP32, 8 = plain FP64 copy
- * x -> y (reference traffic), 9 / 10 = one-kernel CG iteration (solver
- * variant 0) in FP64 / FP32, 11 / 12 = the same replayed from a captured
- * graph of reps (rounded up to even) launches, as the solver runs them,
- * 13 / 14 / 15 = one iteration of the nodal-basis CG with precond 0 / 2 / 3
- * (HDG-unprec / HDG-diag / HDG-block, FP64, x as the right-hand side).
- * x, y device buffers of n_free values of the matching type (x read; y
- * written only by 8).  Synchronises. */
+/* Kernels and kernel sequences that hdg_time_kernel can time. */
+typedef enum {
+  HDG_TIME_ELEM_APPLY_F64 = 0,     /* eigen-basis element kernel alone (x -> qa, qb) */
+  HDG_TIME_ELEM_APPLY_F32 = 1,
+  HDG_TIME_CG2_ITER_F64 = 2,       /* two-kernel CG iteration: fused apply + update */
+  HDG_TIME_CG2_ITER_F32 = 3,
+  HDG_TIME_CG2_APPLY_F64 = 4,      /* the fused CG apply alone */
+  HDG_TIME_CG2_UPDATE_F64 = 5,     /* the CG update alone */
+  HDG_TIME_CG2_APPLY_F32 = 6,
+  HDG_TIME_CG2_UPDATE_F32 = 7,
+  HDG_TIME_COPY_F64 = 8,           /* plain copy x -> y (reference traffic) */
+  HDG_TIME_CG1_ITER_F64 = 9,       /* one-kernel CG iteration (solver variant 0) */
+  HDG_TIME_CG1_ITER_F32 = 10,
+  HDG_TIME_CG1_GRAPH_F64 = 11,     /* the same, replayed from one captured graph */
+  HDG_TIME_CG1_GRAPH_F32 = 12,
+  HDG_TIME_NODAL_UNPREC_F64 = 13,  /* one nodal-basis CG iteration, precond 0 */
+  HDG_TIME_NODAL_DIAG_F64 = 14,    /* precond 2 */
+  HDG_TIME_NODAL_BLOCK_F64 = 15,   /* precond 3 */
+  HDG_TIME_APPLY_F64 = 16,         /* eigen-basis hdg_apply as it runs: element kernel + sum */
+  HDG_TIME_APPLY_F32 = 17
+} hdg_timed_kernel;
+
+/* Timing helper: launch the kernel or kernel sequence `which`
+ * (hdg_timed_kernel) `reps` times back-to-back on the context stream between
+ * two HIP events and return the mean time per launch in *ms.  The CG ids
+ * run one iteration of a solve that never converges (x as its right-hand
+ * side); the graph ids capture reps (rounded up to even) iterations once and
+ * time one replay, as the solver runs them.  x, y device buffers of n_free
+ * values of the matching type (x read; y written by HDG_TIME_COPY_F64 and
+ * HDG_TIME_APPLY_*, which need a y distinct from x).  Unknown ids give
+ * HDG_EINVAL.  Synchronises. */
 hdg_status hdg_time_kernel(hdg_ctx* ctx, int which, const void* x, void* y,
                            int reps, double* ms);
 

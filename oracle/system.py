@@ -182,6 +182,19 @@ class HdgOracle:
         es = self.system(e)
         return -es.R.T @ np.linalg.solve(es.A, es.volume_rhs(es.Me @ f_e))
 
+    def rhs_rows(self, f_vol, dof_ids):
+        """F[dof_ids] of F = sum_e Q_e^T F_e (no Dirichlet lift, no Neumann
+        load), summing only the elements that touch those DOFs."""
+        dof_ids = np.asarray(dof_ids, dtype=np.int64)
+        npf = self.layout.np_ ** 2
+        acc = {}
+        for e in self.faces_elements(np.unique(dof_ids // npf)):
+            m = self.tmap(e)
+            Fe = self.rhs_element(e, f_vol[self.vol_slice(e)])
+            for loc, g in enumerate(m):
+                acc[g] = acc.get(g, 0.0) + Fe[loc]
+        return np.array([acc.get(int(d), 0.0) for d in dof_ids])
+
     def assemble_F(self, f_vol):
         F = np.zeros(self.layout.n_all)
         for e in range(self.layout.n_elem):

@@ -11,4 +11,8 @@ from .hdg import (  # noqa: F401
     EXPORTS,
     TO_EIGEN_UNKNOWN, TO_EIGEN_RESIDUAL, TO_NODAL_UNKNOWN, TO_NODAL_RESIDUAL,
     PRECOND_NONE, PRECOND_EIGEN_JACOBI, PRECOND_NODAL_DIAG, PRECOND_NODAL_BLOCK,
+    TIME_ELEM_APPLY_F64, TIME_ELEM_APPLY_F32, TIME_CG2_ITER_F64, TIME_CG2_ITER_F32,
+    TIME_CG2_APPLY_F64, TIME_CG2_UPDATE_F64, TIME_CG2_APPLY_F32, TIME_CG2_UPDATE_F32, TIME_COPY_F64,
+    TIME_CG1_ITER_F64, TIME_CG1_ITER_F32, TIME_CG1_GRAPH_F64, TIME_CG1_GRAPH_F32,
+    TIME_NODAL_UNPREC_F64, TIME_NODAL_DIAG_F64, TIME_NODAL_BLOCK_F64, TIME_APPLY_F64, TIME_APPLY_F32,
 )

@@ -232,12 +232,16 @@ hdg_status cg_drive(hdg_ctx* c, CgWork<T>& w, int budget, int check_every, int v
         break;
       }
       // geometric estimate of the iterations still needed from the last two
-      // states; the chunk k now in flight covers chunk_len[k & 1] of them
-      if (!use_tail && prev_iter >= 0 && st.iter > prev_iter && st.rr > 0.0 &&
-          prev_rr > st.rr && st.rr_stop > 0.0 && st.rr > st.rr_stop) {
+      // states, recomputed at every check; the chunk k now in flight covers
+      // chunk_len[k & 1] of them.  Short graphs only while the estimate says
+      // the end is within the next big chunk (CG residuals are not monotone:
+      // a single large drop must not switch the rest of a solve to them).
+      use_tail = false;
+      if (prev_iter >= 0 && st.iter > prev_iter && st.rr > 0.0 && prev_rr > st.rr &&
+          st.rr_stop > 0.0 && st.rr > st.rr_stop) {
         const double per_it = std::log(st.rr / prev_rr) / (double)(st.iter - prev_iter);
         const double remaining = std::log(st.rr_stop / st.rr) / per_it;
-        if (remaining - chunk_len[k & 1] < check_every) use_tail = true;
+        use_tail = remaining - chunk_len[k & 1] < check_every;
       }
       prev_iter = st.iter;
       prev_rr = st.rr;
@@ -1270,23 +1274,30 @@ hdg_status hdg_diagonal(hdg_ctx* c, double* diag_free) {
 
 hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int reps, double* ms) {
   if (!c || !x || !ms || reps < 1) return fail(HDG_EINVAL, "invalid argument");
-  if (which < 0 || which > 15) return fail(HDG_EINVAL, "unknown kernel id %d", which);
-  if (which == 8 && (!y || y == x)) return fail(HDG_EINVAL, "copy needs a distinct y");
+  if (which < HDG_TIME_ELEM_APPLY_F64 || which > HDG_TIME_APPLY_F32)
+    return fail(HDG_EINVAL, "unknown kernel id %d", which);
+  const bool writes_y = which == HDG_TIME_COPY_F64 || which == HDG_TIME_APPLY_F64 ||
+                        which == HDG_TIME_APPLY_F32;
+  if (writes_y && (!y || y == x)) return fail(HDG_EINVAL, "kernel id %d needs a distinct y", which);
   if (c->n_free == 0) {
     *ms = 0.0;
     return HDG_OK;
   }
-  // 11 / 12: the one-kernel iteration replayed from a captured graph
-  const bool in_graph = (which == 11 || which == 12);
+  // the one-kernel iteration replayed from a captured graph
+  const bool in_graph = (which == HDG_TIME_CG1_GRAPH_F64 || which == HDG_TIME_CG1_GRAPH_F32);
   if (in_graph) which -= 2;
-  const bool f32 = (which == 1 || which == 3 || which == 6 || which == 7 || which == 10);
-  const bool one_kernel = (which == 9 || which == 10);
-  // 13 / 14 / 15: one iteration of the nodal-basis CG with preconditioner 0 / 2 / 3
-  const bool nodal = (which >= 13 && which <= 15);
-  const int npc = which == 13 ? 0 : (which == 14 ? 2 : 3);
+  const bool f32 = (which == HDG_TIME_ELEM_APPLY_F32 || which == HDG_TIME_CG2_ITER_F32 ||
+                    which == HDG_TIME_CG2_APPLY_F32 || which == HDG_TIME_CG2_UPDATE_F32 ||
+                    which == HDG_TIME_CG1_ITER_F32 || which == HDG_TIME_APPLY_F32);
+  const bool one_kernel = (which == HDG_TIME_CG1_ITER_F64 || which == HDG_TIME_CG1_ITER_F32);
+  // one iteration of the nodal-basis CG with preconditioner 0 / 2 / 3
+  const bool nodal = (which >= HDG_TIME_NODAL_UNPREC_F64 && which <= HDG_TIME_NODAL_BLOCK_F64);
+  const int npc = which == HDG_TIME_NODAL_UNPREC_F64 ? 0 : (which == HDG_TIME_NODAL_DIAG_F64 ? 2 : 3);
+  const bool cg_state = which >= HDG_TIME_CG2_ITER_F64 && which <= HDG_TIME_NODAL_BLOCK_F64 &&
+                        which != HDG_TIME_COPY_F64;
   if (f32) ST_TRY(alloc_work(c, c->w32));
   // CG-state kernels need an initialised run that never finishes
-  if (which >= 2) {
+  if (cg_state) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     CgScalars& init = c->h_scal[2];
     init = CgScalars{};
@@ -1330,35 +1341,51 @@ hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int re
   hipStream_t ls = c->stream;   // launch stream (the capture stream while capturing)
   auto launch = [&]() -> hipError_t {
     switch (which) {
-      case 0: return launch_elem_apply<double>(c, static_cast<const double*>(x), nullptr,
-                                               c->w64.qa, c->w64.qb, ls);
-      case 1: return launch_elem_apply<float>(c, static_cast<const float*>(x), nullptr,
-                                              c->w32.qa, c->w32.qb, ls);
-      case 2: {
+      case HDG_TIME_ELEM_APPLY_F64:
+        return launch_elem_apply<double>(c, static_cast<const double*>(x), nullptr, c->w64.qa,
+                                         c->w64.qb, ls);
+      case HDG_TIME_ELEM_APPLY_F32:
+        return launch_elem_apply<float>(c, static_cast<const float*>(x), nullptr, c->w32.qa,
+                                        c->w32.qb, ls);
+      case HDG_TIME_CG2_ITER_F64: {
         hipError_t e = launch_cg_apply<double>(c, c->w64, ls);
         return e == hipSuccess ? launch_cg_update<double>(c, c->w64, ls) : e;
       }
-      case 3: {
+      case HDG_TIME_CG2_ITER_F32: {
         hipError_t e = launch_cg_apply<float>(c, c->w32, ls);
         return e == hipSuccess ? launch_cg_update<float>(c, c->w32, ls) : e;
       }
-      case 4: return launch_cg_apply<double>(c, c->w64, ls);
-      case 5: return launch_cg_update<double>(c, c->w64, ls);
-      case 6: return launch_cg_apply<float>(c, c->w32, ls);
-      case 7: return launch_cg_update<float>(c, c->w32, ls);
-      case 9: {
+      case HDG_TIME_CG2_APPLY_F64: return launch_cg_apply<double>(c, c->w64, ls);
+      case HDG_TIME_CG2_UPDATE_F64: return launch_cg_update<double>(c, c->w64, ls);
+      case HDG_TIME_CG2_APPLY_F32: return launch_cg_apply<float>(c, c->w32, ls);
+      case HDG_TIME_CG2_UPDATE_F32: return launch_cg_update<float>(c, c->w32, ls);
+      case HDG_TIME_CG1_ITER_F64: {
         const int rd = parity;
         parity ^= 1;
         return launch_cgcg_iter<double>(c, c->w64, rd, ls);
       }
-      case 10: {
+      case HDG_TIME_CG1_ITER_F32: {
         const int rd = parity;
         parity ^= 1;
         return launch_cgcg_iter<float>(c, c->w32, rd, ls);
       }
-      case 13:
-      case 14:
-      case 15: return launch_ncg_iter(c, c->w64, npc, ls);
+      case HDG_TIME_NODAL_UNPREC_F64:
+      case HDG_TIME_NODAL_DIAG_F64:
+      case HDG_TIME_NODAL_BLOCK_F64: return launch_ncg_iter(c, c->w64, npc, ls);
+      case HDG_TIME_APPLY_F64: {           // what hdg_apply runs in the eigen basis
+        hipError_t e = launch_elem_apply<double>(c, static_cast<const double*>(x), nullptr,
+                                                 c->w64.qa, c->w64.qb, ls);
+        return e == hipSuccess ? launch_combine<double>(c->w64.qa, c->w64.qb,
+                                                        static_cast<double*>(y), c->n_free, ls)
+                               : e;
+      }
+      case HDG_TIME_APPLY_F32: {
+        hipError_t e = launch_elem_apply<float>(c, static_cast<const float*>(x), nullptr,
+                                                c->w32.qa, c->w32.qb, ls);
+        return e == hipSuccess ? launch_combine<float>(c->w32.qa, c->w32.qb,
+                                                       static_cast<float*>(y), c->n_free, ls)
+                               : e;
+      }
       default: return launch_copy64(static_cast<const double*>(x), static_cast<double*>(y),
                                     c->n_free, ls);
     }

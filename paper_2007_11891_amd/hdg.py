@@ -140,6 +140,15 @@ def _check(status: int, allow_noconv: bool = False):
 
 
 # SolveOpts.precond: the paper's solvers (section "Summary of solution method")
+# hdg_timed_kernel ids of hdg_time_kernel (include/hdg.h)
+TIME_ELEM_APPLY_F64, TIME_ELEM_APPLY_F32 = 0, 1
+TIME_CG2_ITER_F64, TIME_CG2_ITER_F32 = 2, 3
+TIME_CG2_APPLY_F64, TIME_CG2_UPDATE_F64, TIME_CG2_APPLY_F32, TIME_CG2_UPDATE_F32 = 4, 5, 6, 7
+TIME_COPY_F64 = 8
+TIME_CG1_ITER_F64, TIME_CG1_ITER_F32, TIME_CG1_GRAPH_F64, TIME_CG1_GRAPH_F32 = 9, 10, 11, 12
+TIME_NODAL_UNPREC_F64, TIME_NODAL_DIAG_F64, TIME_NODAL_BLOCK_F64 = 13, 14, 15
+TIME_APPLY_F64, TIME_APPLY_F32 = 16, 17
+
 PRECOND_NONE = 0          # HDG-unprec, nodal basis
 PRECOND_EIGEN_JACOBI = 1  # HDG-trans, eigen-face basis (default)
 PRECOND_NODAL_DIAG = 2    # HDG-diag, nodal basis

@@ -338,6 +338,10 @@ def test_apply_rows_and_faces_elements(neumann):
     rows = np.concatenate([rows, [0, L.n_free - 1, L.n_all - 1]])
     got = o.apply_rows(x, rows)
     assert np.abs(got - y_full[rows]).max() < 1e-13 * np.abs(y_full).max()
+    # the same rows of the assembled right-hand side
+    f = rng.uniform(-1, 1, L.n_vol)
+    F_full = o.assemble_F(f)
+    assert np.abs(o.rhs_rows(f, rows) - F_full[rows]).max() < 1e-13 * np.abs(F_full).max()
     # elements of each face from geometry: the face's nodes lie on the
     # element's closed box
     T = o.trace_coords()
