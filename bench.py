@@ -145,7 +145,12 @@ def cpu_baseline(prob, budget_s: float, cg_iters: int):
 # vector work takes about nine more passes over 8-byte vectors (72 B).  FP32
 # halves it.  The implementation's own per-DOF traffic is listed beside it.
 ALG_CG_BYTES = 88
-IMPL_CG_BYTES = {"one kernel": 104, "two kernels": 104}
+IMPL_CG_BYTES = {"one kernel": 104, "two kernels": 104,
+                 # pencil: element launch reads z, p_old, x and writes p, x and
+                 # the face contributions (two per face normal to x1 or x2,
+                 # one summed per face normal to x3); the update reads z,
+                 # D^-1 and those contributions and writes z
+                 "pencil": 91}
 # committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries, one per workload
 TRAFFIC_PROFILES = {
     "perturbed16_p7": os.path.join(ROOT, "profiles", "cg_iteration_perturbed16_p7_hbm_counters.md"),
@@ -198,6 +203,8 @@ def cg_kernel_names(c, fp32: bool = False):
     np_, epu = c.p + 1, t["elems_per_unit"]
     if t["cg_variant"] == 0 and not fp32:
         return [f"elem_apply_kernel<{typ}, {np_}, {epu}, 2, 0>"]
+    if t["cg_variant"] == 2 and not fp32:
+        return [f"pencil_apply_kernel<{typ}, {np_}, {epu}>", f"pencil_update_kernel<{typ}>"]
     units = -(-c.n_elem // epu)
     upb = -(-units // min(units, 2048))
     return [f"elem_apply_kernel<{typ}, {np_}, {epu}, 1, {1 if upb > 1 else 0}>",
@@ -213,12 +220,15 @@ def cg_iteration_roofline(c, W, torch, dev, fp32: bool = False, reps: int = 50,
     FP32), with the implementation's own bytes and the counted traffic."""
     import paper_2007_11891_amd as pkg
     nf = c.sizes.n_free
-    one = c.tile_shape()["cg_variant"] == 0 and not fp32
-    form = "one kernel" if one else "two kernels"
-    if one:
-        which = pkg.TIME_CG1_ITER_F64
+    cgv = c.tile_shape()["cg_variant"]
+    if fp32:
+        form, which = "two kernels", pkg.TIME_CG2_ITER_F32
+    elif cgv == 0:
+        form, which = "one kernel", pkg.TIME_CG1_ITER_F64
+    elif cgv == 2:
+        form, which = "pencil", pkg.TIME_PENCIL_ITER_F64
     else:
-        which = pkg.TIME_CG2_ITER_F32 if fp32 else pkg.TIME_CG2_ITER_F64
+        form, which = "two kernels", pkg.TIME_CG2_ITER_F64
     x = torch.as_tensor(W.random_trace(nf, 7), device=dev)
     if fp32:
         x = x.float()

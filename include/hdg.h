@@ -126,8 +126,13 @@ typedef struct {
   int variant;        /* CG form: 0 one kernel per iteration (Chronopoulos-
                          Gear form of the same PCG: one reduction point per
                          iteration); 1 textbook PCG, an element kernel and a
-                         vector update kernel per iteration; -1 the
-                         context's choice (hdg_autotune, or by mesh size)  */
+                         vector update kernel per iteration; 2 textbook PCG
+                         with the pencil element kernel (blocks march up x3,
+                         the faces between consecutive elements carried in
+                         registers; x updated in the element launch) and a
+                         vector update kernel; -1 the context's choice
+                         (hdg_autotune, or by mesh size).  Mixed precision
+                         runs its FP32 inner CG in form 1 whatever this is */
   int guess;          /* 0: CG from x0 = 0; 1: the unknowns passed in (u_free
                          of hdg_solve, the free part of trace in
                          hdg_solve_forcing) are the initial guess, e.g. from
@@ -326,7 +331,14 @@ hdg_status hdg_adjoint(hdg_ctx* ctx, const double* f, const double* trace,
  * (0, 1 or 2).  Synchronises the stream; invalidates captured CG graphs. */
 hdg_status hdg_set_tile(hdg_ctx* ctx, int variant);
 
-/* Autotuner: times one FP64 CG iteration in both CG forms (see
+/* Segment length of the pencil CG form (hdg_solve_opts.variant 2): its
+ * element blocks march up x3 through `ks` elements each (1 <= ks <= n3);
+ * 0 restores the automatic choice (whole columns when the rows of the mesh
+ * give enough blocks, shorter segments otherwise).  Synchronises the stream;
+ * invalidates captured CG graphs.  HDG_EINVAL for ks < 0 or ks > n3. */
+hdg_status hdg_set_cg_segment(hdg_ctx* ctx, int ks);
+
+/* Autotuner: times one FP64 CG iteration in each of the three CG forms (see
  * hdg_solve_opts.variant) for every tile variant on this context's mesh
  * (`reps` launches each, HIP events on the context stream), keeps the
  * fastest pair as the context's tile shape and CG form, returns the tile
@@ -336,7 +348,7 @@ hdg_status hdg_autotune(hdg_ctx* ctx, int reps, int* chosen, double* times_ms);
 
 /* Current tile shape: *variant (0..2), *elems_per_unit (elements of one
  * work unit), *threads_per_unit (threads of one FP64 work unit, a multiple
- * of 64), and the context's CG form *cg_variant (0 or 1); any pointer may
+ * of 64), and the context's CG form *cg_variant (0, 1 or 2); any pointer may
  * be NULL.  Host-only, no GPU work. */
 hdg_status hdg_tile_shape(const hdg_ctx* ctx, int* variant, int* elems_per_unit,
                           int* threads_per_unit, int* cg_variant);
@@ -363,7 +375,9 @@ typedef enum {
   HDG_TIME_NODAL_DIAG_F64 = 14,    /* precond 2 */
   HDG_TIME_NODAL_BLOCK_F64 = 15,   /* precond 3 */
   HDG_TIME_APPLY_F64 = 16,         /* eigen-basis hdg_apply as it runs: element kernel + sum */
-  HDG_TIME_APPLY_F32 = 17
+  HDG_TIME_APPLY_F32 = 17,
+  HDG_TIME_PENCIL_ITER_F64 = 18,   /* pencil CG iteration (solver variant 2): update + element */
+  HDG_TIME_PENCIL_ITER_F32 = 19
 } hdg_timed_kernel;
 
 /* Timing helper: launch the kernel or kernel sequence `which`

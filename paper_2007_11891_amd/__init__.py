@@ -15,4 +15,5 @@ from .hdg import (  # noqa: F401
     TIME_CG2_APPLY_F64, TIME_CG2_UPDATE_F64, TIME_CG2_APPLY_F32, TIME_CG2_UPDATE_F32, TIME_COPY_F64,
     TIME_CG1_ITER_F64, TIME_CG1_ITER_F32, TIME_CG1_GRAPH_F64, TIME_CG1_GRAPH_F32,
     TIME_NODAL_UNPREC_F64, TIME_NODAL_DIAG_F64, TIME_NODAL_BLOCK_F64, TIME_APPLY_F64, TIME_APPLY_F32,
+    TIME_PENCIL_ITER_F64, TIME_PENCIL_ITER_F32,
 )

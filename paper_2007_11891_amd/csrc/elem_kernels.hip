@@ -9,6 +9,7 @@
 // reduces p.q from element-local quadratic forms into one partial per block.
 // Everything that needs no face gather (the x and residual updates) is left
 // to the streaming update kernel.
+#include "cg_state.hpp"
 #include "elem_unit.hpp"
 
 namespace hdg {
@@ -44,48 +45,6 @@ struct ApplyIO {
   int rd;            // this launch reads state slot rd and writes slot rd ^ 1
   int n_parts;       // partials per slot written by the previous launch
 };
-
-// CG prologue of the fused apply, in two parts so that the first unit's
-// face loads and the partials' loads can be issued in between.  cg_head: a
-// finished solve skips the whole launch (x is already complete); otherwise
-// returns the iteration k.
-template <typename T>
-__device__ inline bool cg_head(const ApplyIO<T>& io, int* iter) {
-  *iter = io.sc->A.iter;
-  return io.sc->A.done != 0;                // uniform over the grid
-}
-
-// cg_scalars: reads slot A, sums the update partials (r.z and r.r, loads
-// already issued into ps), decides convergence, publishes slot B from block 0
-// and forms beta.
-template <typename T, int NT>
-__device__ inline void cg_scalars(const ApplyIO<T>& io, int it, PartialSums<NT, 2>& ps,
-                                  const double* const* pp, T* beta, bool* skip) {
-  const double rho_prev = io.sc->A.rho;
-  const double rtol2 = io.sc->A.rtol2;
-  const int maxit = io.sc->A.maxit;
-  double rr_stop = io.sc->A.rr_stop;
-  double sums[2];
-  ps.reduce(pp, io.n_upd, sums);
-  const double rho = sums[0], rr = sums[1];
-  if (it == 0) rr_stop = rtol2 * rr;
-  const double b = (it == 0) ? 0.0 : rho / rho_prev;
-  int done = 0;
-  if (!isfinite(rr) || !isfinite(b)) done = 3;
-  else if (rr <= rr_stop) done = 1;
-  else if (it >= maxit) done = 2;
-  *skip = done != 0;
-  *beta = (T)b;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    io.sc->B.rho = rho;
-    io.sc->B.rr = rr;
-    io.sc->B.rr_stop = rr_stop;
-    io.sc->B.iter = it;
-    io.sc->B.maxit = maxit;
-    io.sc->B.rtol2 = rtol2;
-    io.sc->B.done = done;
-  }
-}
 
 // Prologue of the one-kernel CG iteration (Chronopoulos-Gear form of the
 // preconditioned CG, one global reduction per iteration), in two parts so
@@ -249,7 +208,7 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
     // MODE 1: the state slot, then the first unit's loads, then the partial
     // sums and beta
     int iter;
-    if (cg_head(io, &iter)) return;
+    if (cg_head(io.sc, &iter)) return;
     u.z = io.z;
     u.p_in = (iter & 1) ? io.p0 : io.p1;     // iteration k reads p_{k-1}, writes p_k
     u.p_out = (iter & 1) ? io.p1 : io.p0;
@@ -262,7 +221,7 @@ elem_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, ApplyIO<T> io, int u
     auto scalars = [&]() -> bool {
       bool skip;
       T beta;
-      cg_scalars<T, NT>(io, iter, ps, pp, &beta, &skip);
+      cg_scalars<T, NT>(io.sc, io.n_upd, iter, ps, pp, &beta, &skip);
       u.beta = beta;
       return !skip;
     };

@@ -71,6 +71,12 @@ hdg_status alloc_work(hdg_ctx* c, CgWork<T>& w) {
   w.zz[0] = w.z;
   w.qq[0][0] = w.qa;
   w.qq[0][1] = w.qb;
+  w.pencil_blocks = std::max(1, pencil_blocks(c, c->tile_variant));
+  // the pencil form's most blocks: segments of one element (hdg_set_cg_segment)
+  for (int v = 0; v < kNumTileVariants; ++v) {
+    const int64_t e = tile_epb(c->np, v);
+    max_apply = (int)std::max<int64_t>(max_apply, (c->n[0] + e - 1) / e * c->n[1] * c->n[2]);
+  }
   w.pmax = std::max({max_apply, w.update_blocks, ncg_face_blocks(c->np, c->n_free_faces)});
   ST_TRY(dalloc(&w.partials, 6 * (int64_t)w.pmax));
   ST_TRY(dalloc(&w.sc, 1));
@@ -119,8 +125,8 @@ float* dinv_of<float>(hdg_ctx* c) { return c->d_dinv32; }
 
 // Capture `iters` CG iterations into a graph: variant 0 one launch per
 // iteration (state slot parity alternating, iters even), variant 1 the fused
-// apply + update pair, variant 10 + pc the nodal-basis CG with
-// preconditioner pc (FP64).
+// apply + update pair, variant 2 the pencil element launch + update pair,
+// variant 10 + pc the nodal-basis CG with preconditioner pc (FP64).
 template <typename T>
 hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters, int variant, bool tail = false) {
   hipGraphExec_t& exec = tail ? w.graph_tail : w.graph;
@@ -142,6 +148,9 @@ hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters, int variant, bool ta
         err = hipErrorInvalidValue;
     } else if (variant == 0) {
       err = launch_cgcg_iter<T>(c, w, it & 1, c->cap_stream);
+    } else if (variant == 2) {
+      err = launch_pencil_apply<T>(c, w, c->cap_stream);
+      if (err == hipSuccess) err = launch_pencil_update<T>(c, w, c->cap_stream);
     } else {
       err = launch_cg_apply<T>(c, w, c->cap_stream);
       if (err == hipSuccess) err = launch_cg_update<T>(c, w, c->cap_stream);
@@ -166,10 +175,17 @@ hdg_status build_graph(hdg_ctx* c, CgWork<T>& w, int iters, int variant, bool ta
 // keeps one graph in flight ahead of the convergence check, so a converged
 // solve costs at most one extra graph of no-op kernels.  variant 0: one
 // kernel per iteration (Chronopoulos-Gear recurrences); 1: textbook PCG
-// with an element kernel and an update kernel per iteration.
+// with an element kernel and an update kernel per iteration; 2: the same
+// with the pencil element kernel (faces normal to x3 carried along the
+// march, x updated in the element launch).
 template <typename T>
 hdg_status cg_drive(hdg_ctx* c, CgWork<T>& w, int budget, int check_every, int variant,
                     int* iters_out, int* done_out);
+
+// The pencil form addresses the trace with 32-bit offsets.
+bool pencil_fits(const hdg_ctx* c) {
+  return (c->n_faces + 1) * (int64_t)c->np * c->np < ((int64_t)1 << 31);
+}
 
 template <typename T>
 hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
@@ -177,6 +193,8 @@ hdg_status run_cg(hdg_ctx* c, CgWork<T>& w, const T* b, double rtol, int maxit,
   *iters_out = 0;
   *done_out = 1;
   if (w.n == 0) return HDG_OK;
+  if (variant == 2 && !pencil_fits(c))
+    return fail(HDG_EUNSUPPORTED, "the pencil CG form needs fewer than 2^31 trace values");
   w.dinv = dinv_of<T>(c);
   HIP_TRY(launch_state_reset(w.sc, rtol * rtol, std::max(1, maxit), c->stream));
   if (variant == 0) HIP_TRY(launch_cgcg_init<T>(c, w, b, c->stream));
@@ -266,7 +284,7 @@ int cg_variant_of(const hdg_ctx* c, const hdg_solve_opts* o) {
 hdg_status validate_opts(const hdg_solve_opts* o) {
   if (!(o->rtol > 0.0) || o->maxit < 1 || o->precond < 0 || o->precond > 3 ||
       o->guess < 0 || o->guess > 2 ||
-      (o->variant < -1 || o->variant > 1) ||
+      (o->variant < -1 || o->variant > 2) ||
       (o->mixed != 0 && o->mixed != 1) || o->check_every < 1 ||
       (o->mixed && (!(o->inner_rtol > 0.0) || o->inner_rtol >= 1.0 || o->max_outer < 1)))
     return fail(HDG_EINVAL, "invalid solver options");
@@ -1213,8 +1231,27 @@ hdg_status hdg_set_tile(hdg_ctx* c, int variant) {
     return fail(HDG_EINVAL, "tile variant must be in [0, %d)", kNumTileVariants);
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->tile_variant = variant;
-  if (c->w64.x) c->w64.apply_blocks = std::max(1, elem_apply_blocks(c->np, c->n_elem, variant));
-  if (c->w32.x) c->w32.apply_blocks = std::max(1, elem_apply_blocks(c->np, c->n_elem, variant));
+  for (CgWork<double>* w : {&c->w64}) {
+    if (!w->x) continue;
+    w->apply_blocks = std::max(1, elem_apply_blocks(c->np, c->n_elem, variant));
+    w->pencil_blocks = std::max(1, pencil_blocks(c, variant));
+  }
+  if (c->w32.x) {
+    c->w32.apply_blocks = std::max(1, elem_apply_blocks(c->np, c->n_elem, variant));
+    c->w32.pencil_blocks = std::max(1, pencil_blocks(c, variant));
+  }
+  drop_graphs(c->w64);
+  drop_graphs(c->w32);
+  return HDG_OK;
+}
+
+hdg_status hdg_set_cg_segment(hdg_ctx* c, int ks) {
+  if (!c) return fail(HDG_EINVAL, "ctx is NULL");
+  if (ks < 0 || ks > c->n[2]) return fail(HDG_EINVAL, "segment length %d not in [0, %d]", ks, c->n[2]);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->pencil_ks = ks;
+  if (c->w64.x) c->w64.pencil_blocks = std::max(1, pencil_blocks(c, c->tile_variant));
+  if (c->w32.x) c->w32.pencil_blocks = std::max(1, pencil_blocks(c, c->tile_variant));
   drop_graphs(c->w64);
   drop_graphs(c->w32);
   return HDG_OK;
@@ -1226,9 +1263,9 @@ hdg_status hdg_autotune(hdg_ctx* c, int reps, int* chosen, double* times_ms) {
     if (chosen) *chosen = c->tile_variant;
     return HDG_OK;
   }
-  // time one FP64 CG iteration in both forms (one kernel: id 9; element +
-  // update kernel: id 2) for every tile variant on this context's mesh and
-  // keep the fastest pair
+  // time one FP64 CG iteration in each form (one kernel, element + update
+  // kernel, pencil element + update kernel) for every tile variant on this
+  // context's mesh and keep the fastest pair
   double best = 1e300;
   int best_v = 0, best_cg = 0;
   double* x = c->d_tmp[1];
@@ -1236,9 +1273,11 @@ hdg_status hdg_autotune(hdg_ctx* c, int reps, int* chosen, double* times_ms) {
   for (int v = 0; v < kNumTileVariants; ++v) {
     ST_TRY(hdg_set_tile(c, v));
     double tv = 1e300;
-    for (int cg = 0; cg < 2; ++cg) {
+    for (int cg = 0; cg < (pencil_fits(c) ? 3 : 2); ++cg) {
+      const int id = cg == 0 ? HDG_TIME_CG1_ITER_F64
+                             : (cg == 1 ? HDG_TIME_CG2_ITER_F64 : HDG_TIME_PENCIL_ITER_F64);
       double ms = 0.0;
-      ST_TRY(hdg_time_kernel(c, cg == 0 ? 9 : 2, x, nullptr, reps, &ms));
+      ST_TRY(hdg_time_kernel(c, id, x, nullptr, reps, &ms));
       tv = std::min(tv, ms);
       if (ms < best) {
         best = ms;
@@ -1274,7 +1313,7 @@ hdg_status hdg_diagonal(hdg_ctx* c, double* diag_free) {
 
 hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int reps, double* ms) {
   if (!c || !x || !ms || reps < 1) return fail(HDG_EINVAL, "invalid argument");
-  if (which < HDG_TIME_ELEM_APPLY_F64 || which > HDG_TIME_APPLY_F32)
+  if (which < HDG_TIME_ELEM_APPLY_F64 || which > HDG_TIME_PENCIL_ITER_F32)
     return fail(HDG_EINVAL, "unknown kernel id %d", which);
   const bool writes_y = which == HDG_TIME_COPY_F64 || which == HDG_TIME_APPLY_F64 ||
                         which == HDG_TIME_APPLY_F32;
@@ -1288,13 +1327,17 @@ hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int re
   if (in_graph) which -= 2;
   const bool f32 = (which == HDG_TIME_ELEM_APPLY_F32 || which == HDG_TIME_CG2_ITER_F32 ||
                     which == HDG_TIME_CG2_APPLY_F32 || which == HDG_TIME_CG2_UPDATE_F32 ||
-                    which == HDG_TIME_CG1_ITER_F32 || which == HDG_TIME_APPLY_F32);
+                    which == HDG_TIME_CG1_ITER_F32 || which == HDG_TIME_APPLY_F32 ||
+                    which == HDG_TIME_PENCIL_ITER_F32);
+  const bool pencil = (which == HDG_TIME_PENCIL_ITER_F64 || which == HDG_TIME_PENCIL_ITER_F32);
   const bool one_kernel = (which == HDG_TIME_CG1_ITER_F64 || which == HDG_TIME_CG1_ITER_F32);
   // one iteration of the nodal-basis CG with preconditioner 0 / 2 / 3
   const bool nodal = (which >= HDG_TIME_NODAL_UNPREC_F64 && which <= HDG_TIME_NODAL_BLOCK_F64);
   const int npc = which == HDG_TIME_NODAL_UNPREC_F64 ? 0 : (which == HDG_TIME_NODAL_DIAG_F64 ? 2 : 3);
-  const bool cg_state = which >= HDG_TIME_CG2_ITER_F64 && which <= HDG_TIME_NODAL_BLOCK_F64 &&
-                        which != HDG_TIME_COPY_F64;
+  const bool cg_state = (which >= HDG_TIME_CG2_ITER_F64 && which <= HDG_TIME_NODAL_BLOCK_F64 &&
+                         which != HDG_TIME_COPY_F64) || pencil;
+  if (pencil && !pencil_fits(c))
+    return fail(HDG_EUNSUPPORTED, "the pencil CG form needs fewer than 2^31 trace values");
   if (f32) ST_TRY(alloc_work(c, c->w32));
   // CG-state kernels need an initialised run that never finishes
   if (cg_state) {
@@ -1332,6 +1375,9 @@ hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int re
     } else if (one_kernel) {
       if (f32) HIP_TRY(launch_cgcg_iter<float>(c, c->w32, 0, c->stream));
       else HIP_TRY(launch_cgcg_iter<double>(c, c->w64, 0, c->stream));
+    } else if (pencil) {
+      if (f32) HIP_TRY(launch_pencil_apply<float>(c, c->w32, c->stream));
+      else HIP_TRY(launch_pencil_apply<double>(c, c->w64, c->stream));
     } else {
       if (f32) HIP_TRY(launch_cg_apply<float>(c, c->w32, c->stream));
       else HIP_TRY(launch_cg_apply<double>(c, c->w64, c->stream));
@@ -1372,6 +1418,14 @@ hdg_status hdg_time_kernel(hdg_ctx* c, int which, const void* x, void* y, int re
       case HDG_TIME_NODAL_UNPREC_F64:
       case HDG_TIME_NODAL_DIAG_F64:
       case HDG_TIME_NODAL_BLOCK_F64: return launch_ncg_iter(c, c->w64, npc, ls);
+      case HDG_TIME_PENCIL_ITER_F64: {
+        hipError_t e = launch_pencil_update<double>(c, c->w64, ls);
+        return e == hipSuccess ? launch_pencil_apply<double>(c, c->w64, ls) : e;
+      }
+      case HDG_TIME_PENCIL_ITER_F32: {
+        hipError_t e = launch_pencil_update<float>(c, c->w32, ls);
+        return e == hipSuccess ? launch_pencil_apply<float>(c, c->w32, ls) : e;
+      }
       case HDG_TIME_APPLY_F64: {           // what hdg_apply runs in the eigen basis
         hipError_t e = launch_elem_apply<double>(c, static_cast<const double*>(x), nullptr,
                                                  c->w64.qa, c->w64.qb, ls);

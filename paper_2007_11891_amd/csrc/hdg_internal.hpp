@@ -99,6 +99,7 @@ struct CgWork {
   int64_t n = 0;
   int apply_blocks = 0;
   int update_blocks = 0;
+  int pencil_blocks = 0;       // element launches of the pencil CG form
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
   int graph_variant = -1;
@@ -119,6 +120,7 @@ struct hdg_ctx {
   int p = 0, np = 0;
   int tile_variant = 0;           // elements per work unit: epb_max >> variant
   int cg_variant = 1;             // CG form when the options leave it open
+  int pencil_ks = 0;              // pencil CG form: elements per x3 segment (0: automatic)
   double tau = 0.0;
   int neumann = 0;                // bit 2a+s: side s of axis a is a Neumann side
   int64_t n_elem = 0, n_free = 0, n_all = 0, n_vol = 0;
@@ -172,6 +174,13 @@ hipError_t launch_cg_update(const hdg_ctx* c, CgWork<T>& w, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_continue(const hdg_ctx* c, CgWork<T>& w, const T* b, int iter, double pscale,
                               hipStream_t s);
+// pencil form of the two-kernel CG (pencil_cg.hip): element launch and
+// update launch of one iteration; started by launch_cg_init
+template <typename T>
+hipError_t launch_pencil_apply(const hdg_ctx* c, CgWork<T>& w, hipStream_t s);
+template <typename T>
+hipError_t launch_pencil_update(const hdg_ctx* c, CgWork<T>& w, hipStream_t s);
+int pencil_blocks(const hdg_ctx* c, int variant);
 // one-kernel CG iteration (reads state slot rd, writes rd ^ 1) and its init
 template <typename T>
 hipError_t launch_cgcg_iter(const hdg_ctx* c, CgWork<T>& w, int rd, hipStream_t s);

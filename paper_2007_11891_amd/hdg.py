@@ -30,7 +30,8 @@ EXPORTS = (
     "hdg_sizes", "hdg_layout", "hdg_set_lambda", "hdg_tables", "hdg_coords", "hdg_apply", "hdg_face_transform",
     "hdg_rhs", "hdg_solve", "hdg_solve_forcing", "hdg_reconstruct", "hdg_hybridize",
     "hdg_adjoint",
-    "hdg_diagonal", "hdg_time_kernel", "hdg_set_tile", "hdg_autotune", "hdg_tile_shape",
+    "hdg_diagonal", "hdg_time_kernel", "hdg_set_tile", "hdg_set_cg_segment", "hdg_autotune",
+    "hdg_tile_shape",
     "hdg_batch_create", "hdg_batch_destroy", "hdg_batch_sizes", "hdg_batch_set_tile",
     "hdg_batch_tiles", "hdg_batch_set_form", "hdg_batch_form", "hdg_batch_autotune",
     "hdg_batch_time_cg", "hdg_batch_solve_forcing",
@@ -109,6 +110,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hdg_diagonal": (ctypes.c_int, [vp, vp]),
         "hdg_time_kernel": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int, dp]),
         "hdg_set_tile": (ctypes.c_int, [vp, ctypes.c_int]),
+        "hdg_set_cg_segment": (ctypes.c_int, [vp, ctypes.c_int]),
         "hdg_autotune": (ctypes.c_int, [vp, ctypes.c_int, ip, dp]),
         "hdg_tile_shape": (ctypes.c_int, [vp, ip, ip, ip, ip]),
         "hdg_batch_create": (ctypes.c_int, [ctypes.c_int, ip, ip, dp, ctypes.c_double, vp,
@@ -148,6 +150,7 @@ TIME_COPY_F64 = 8
 TIME_CG1_ITER_F64, TIME_CG1_ITER_F32, TIME_CG1_GRAPH_F64, TIME_CG1_GRAPH_F32 = 9, 10, 11, 12
 TIME_NODAL_UNPREC_F64, TIME_NODAL_DIAG_F64, TIME_NODAL_BLOCK_F64 = 13, 14, 15
 TIME_APPLY_F64, TIME_APPLY_F32 = 16, 17
+TIME_PENCIL_ITER_F64, TIME_PENCIL_ITER_F32 = 18, 19
 
 PRECOND_NONE = 0          # HDG-unprec, nodal basis
 PRECOND_EIGEN_JACOBI = 1  # HDG-trans, eigen-face basis (default)
@@ -409,6 +412,10 @@ class HdgContext:
         t = (ctypes.c_double * 3)()
         _check(self._lib.hdg_autotune(self._h, int(reps), ctypes.byref(ch), t))
         return ch.value, list(t)
+
+    def set_cg_segment(self, ks: int = 0):
+        """Elements per x3 segment of the pencil CG form (0: automatic)."""
+        _check(self._lib.hdg_set_cg_segment(self._h, int(ks)))
 
     def tile_shape(self) -> dict:
         v, e, t, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -67,7 +67,8 @@ def test_rhs_with_boundary_data(mask):
     assert rel_err(to_host(c.rhs(to_dev(f), to_dev(bc))), o.lifted_rhs(f, bc)) < 1e-12
 
 
-SOLVERS = [dict(precond=1, variant=0), dict(precond=1, variant=1), dict(precond=0),
+SOLVERS = [dict(precond=1, variant=0), dict(precond=1, variant=1), dict(precond=1, variant=2),
+           dict(precond=0),
            dict(precond=2), dict(precond=3)]
 
 

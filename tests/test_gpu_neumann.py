@@ -83,7 +83,8 @@ def test_rhs_with_dirichlet_and_neumann_data(mask):
     assert rel_err(got, ref) < 1e-12
 
 
-SOLVERS = [dict(precond=1, variant=0), dict(precond=1, variant=1), dict(precond=0),
+SOLVERS = [dict(precond=1, variant=0), dict(precond=1, variant=1), dict(precond=1, variant=2),
+           dict(precond=0),
            dict(precond=2), dict(precond=3)]
 
 

@@ -266,16 +266,18 @@ def test_every_tile_variant_matches_oracle(n, p):
         assert rel_err(to_host(tr)[:nf], ut_ref[:nf]) < 1e-12, (v, info)
     chosen, times = c.autotune(reps=5)
     assert chosen in (0, 1, 2) and all(t > 0 for t in times)
+    assert c.tile_shape()["cg_variant"] in (0, 1, 2)
     y = to_host(c.apply(to_dev(x), basis="nodal"))
     assert rel_err(y, y_ref) < 1e-12
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("n,p", [((4, 3, 3), 5), ((3, 2, 4), 2), ((2, 3, 2), 9)])
 def test_solver_variants_match_oracle(variant, n, p):
-    """Both CG forms (one kernel per iteration with the Chronopoulos-Gear
-    recurrences, and the textbook two-kernel form) reach the oracle's
-    solution at 1e-12 when run to stagnation."""
+    """Every CG form (one kernel per iteration with the Chronopoulos-Gear
+    recurrences, the textbook two-kernel form, and the textbook form with the
+    pencil element kernel marching up x3) reaches the oracle's solution at
+    1e-12 when run to stagnation."""
     import paper_2007_11891_amd as pkg
     print(f"[solver variant {variant}] n={n} p={p}", flush=True)
     o, c = _pair(n, p, seed=11)
@@ -293,22 +295,23 @@ def test_solver_variants_match_oracle(variant, n, p):
 
 
 def test_solver_variants_agree_at_full_size():
-    """Perturbed 16^3, p = 7, lambda = 10 (the bench workload): both CG forms
-    stop within two iterations of each other at 1e-10 with solutions equal
-    to 1e-8, and the reported residual is the true one."""
+    """Perturbed 16^3, p = 7, lambda = 10 (the bench workload): the three CG
+    forms stop within two iterations of each other at 1e-10 with solutions
+    equal to 1e-8, and the reported residual is the true one."""
     import paper_2007_11891_amd as pkg
     prob = W.perturbed(n=16, p=7, lam=10.0, seed=2)
     c = gpu_ctx(prob.n, prob.widths, prob.p, prob.tau, prob.lam)
     f = to_dev(prob.f_values)
     out = []
-    for variant in (0, 1):
+    for variant in (0, 1, 2):
         tr, _, info = c.solve_forcing(f, c.zeros_trace(), want_volume=False,
                                       opts=pkg.default_opts(rtol=1e-10, variant=variant))
         print(f"[variants full] variant {variant}: {info}", flush=True)
         assert info["rel_res"] < 1.5e-10
         out.append((to_host(tr), info["iters"]))
-    assert abs(out[0][1] - out[1][1]) <= 2
-    assert rel_err(out[0][0], out[1][0]) < 1e-8
+    for v in (1, 2):
+        assert abs(out[0][1] - out[v][1]) <= 2
+        assert rel_err(out[0][0], out[v][0]) < 1e-8
 
 
 def test_many_block_partials_at_full_size():
@@ -325,7 +328,7 @@ def test_many_block_partials_at_full_size():
                                     opts=pkg.default_opts(rtol=1e-10, variant=0))
     ref = to_host(ref)
     c.set_tile(2)
-    for variant in (0, 1):
+    for variant in (0, 1, 2):
         tr, _, info = c.solve_forcing(f, c.zeros_trace(), want_volume=False,
                                       opts=pkg.default_opts(rtol=1e-10, variant=variant))
         print(f"[many partials] variant {variant}: {info}", flush=True)
@@ -334,8 +337,9 @@ def test_many_block_partials_at_full_size():
         assert rel_err(to_host(tr), ref) < 1e-8
 
 
-@pytest.mark.parametrize("opts", [dict(variant=0), dict(variant=1), dict(mixed=1), dict(precond=3)],
-                         ids=["one-kernel", "two-kernel", "mixed", "block"])
+@pytest.mark.parametrize("opts", [dict(variant=0), dict(variant=1), dict(variant=2), dict(mixed=1),
+                                  dict(precond=3)],
+                         ids=["one-kernel", "two-kernel", "pencil", "mixed", "block"])
 def test_zero_right_hand_side_gives_zero_solution(opts):
     """F = 0: every solver returns x = 0 at once with a zero residual."""
     import paper_2007_11891_amd as pkg
@@ -346,3 +350,40 @@ def test_zero_right_hand_side_gives_zero_solution(opts):
                       opts=pkg.default_opts(**opts), u_free=u)
     assert torch.count_nonzero(u) == 0, info
     assert info["iters"] == 0 and info["rel_res"] == 0.0 and info["rhs_norm"] == 0.0, info
+
+
+PENCIL_CASES = [((3, 2, 5), 3), ((2, 3, 4), 5), ((2, 2, 6), 7), ((3, 2, 3), 8), ((1, 2, 4), 11)]
+
+
+@pytest.mark.parametrize("n,p", PENCIL_CASES)
+def test_pencil_form_every_tile_and_segment(n, p):
+    """The pencil CG form (blocks march up x3 in segments, the x3 faces
+    inside a segment summed in registers, x updated in the element launch)
+    reaches the oracle's solution at 1e-12 for every tile shape and segment
+    lengths from one element to the whole column (segment boundaries inside
+    the mesh, ragged last segment, the automatic choice)."""
+    import paper_2007_11891_amd as pkg
+    print(f"[pencil] n={n} p={p}", flush=True)
+    if p >= 10:
+        # widths perturbed along x3 only and one lambda: n3 distinct element
+        # systems keep the dense oracle affordable at this degree
+        widths = [W.uniform_widths(n[0]), W.uniform_widths(n[1]), perturbed_mesh(n, 13)[2]]
+        o, c = _pair(n, p, seed=13, lam=0.8, widths=widths)
+    else:
+        o, c = _pair(n, p, seed=13)
+    X = o.volume_coords()
+    f = W.f_sin3(*X.T, 1.0)
+    ut_ref = o.solve(f, np.zeros(o.layout.n_all))
+    nf = o.layout.n_free
+    for v in range(3):
+        c.set_tile(v)
+        for ks in sorted({0, 1, 2, n[2] - 1, n[2]} - {-1} if n[2] > 1 else {0, 1}):
+            if ks > n[2]:
+                continue
+            c.set_cg_segment(ks)
+            tr, _, info = c.solve_forcing(to_dev(f), c.zeros_trace(), want_volume=False,
+                                          opts=pkg.default_opts(rtol=1e-15, maxit=3000, variant=2,
+                                                                check_every=7),
+                                          allow_noconv=True)
+            assert rel_err(to_host(tr)[:nf], ut_ref[:nf]) < 1e-12, (v, ks, info)
+    c.set_cg_segment(0)
