@@ -64,8 +64,8 @@ struct PencilSmem {
 // Neumann side) has this element alone.  32-bit ids and offsets: the host
 // runs this form only when every trace offset fits.
 struct PencilRow {
-  int A[4], B[4];
-  int x3A, x3B, x3bot, x3top;
+  int A[4];            // faces normal to x1, x2 at k = 0
+  int ij;              // i + n1 j
   int freem, alonem;   // bits 0..3: faces normal to x1, x2; bits 4, 5: the
                        // boundary x3 faces (used at k = 0 and k = n3 - 1)
 };
@@ -78,56 +78,61 @@ __device__ inline void pencil_row(const MeshDev& m, int i, int j, PencilRow& R) 
     const int pl0 = i + s;
     if (pl0 >= 1 && pl0 <= m.n1 - 1) {
       R.A[s] = (int)m.foff[0] + (pl0 - 1) + (m.n1 - 1) * j;
-      R.B[s] = (m.n1 - 1) * m.n2;
       R.freem |= 1 << s;
     } else {
       R.A[s] = (int)m.boff[s] + j;
-      R.B[s] = m.n2;
       if (R.A[s] < nff) R.alonem |= 1 << s;
     }
     const int pl1 = j + s;
     if (pl1 >= 1 && pl1 <= m.n2 - 1) {
       R.A[2 + s] = (int)m.foff[1] + i + m.n1 * (pl1 - 1);
-      R.B[2 + s] = m.n1 * (m.n2 - 1);
       R.freem |= 4 << s;
     } else {
       R.A[2 + s] = (int)m.boff[2 + s] + i;
-      R.B[2 + s] = m.n1;
       if (R.A[2 + s] < nff) R.alonem |= 4 << s;
     }
   }
-  R.x3A = (int)m.foff[2] + i + m.n1 * j;
-  R.x3B = m.n1 * m.n2;
-  R.x3bot = (int)m.boff[4] + i + m.n1 * j;
-  R.x3top = (int)m.boff[5] + i + m.n1 * j;
-  if (R.x3bot < nff) R.alonem |= 16;
-  if (R.x3top < nff) R.alonem |= 32;
+  R.ij = i + m.n1 * j;
+  if ((int)m.boff[4] + R.ij < nff) R.alonem |= 16;
+  if ((int)m.boff[5] + R.ij < nff) R.alonem |= 32;
   R.freem |= R.alonem;
 }
 
 // Id of face f of the slot's element at k; *fr: free, *al: alone on it.
-__device__ inline int pencil_fid(const PencilRow& R, int n3, int k, int f, bool* fr, bool* al) {
+// Along the march a face normal to x1 moves by (n1 - 1) n2 ids per element
+// when interior and by n2 on a side of the box; normal to x2 by n1 (n2 - 1)
+// and n1; normal to x3 by n1 n2.
+__device__ inline int pencil_fid(const MeshDev& m, const PencilRow& R, int k, int f, bool* fr,
+                                 bool* al) {
   if (f < 4) {
+    const bool in = (R.freem >> f) & 1 & ~(R.alonem >> f);
+    const int step = f < 2 ? (in ? (m.n1 - 1) * m.n2 : m.n2) : (in ? m.n1 * (m.n2 - 1) : m.n1);
     *fr = (R.freem >> f) & 1;
     *al = (R.alonem >> f) & 1;
-    return R.A[f] + R.B[f] * k;
+    return R.A[f] + step * k;
   }
   const int pl = k + (f & 1);                  // plane of the x3 face
-  if (pl >= 1 && pl <= n3 - 1) {
+  if (pl >= 1 && pl <= m.n3 - 1) {
     *fr = true;
     *al = false;
-    return R.x3A + R.x3B * (pl - 1);
+    return (int)m.foff[2] + R.ij + m.n1 * m.n2 * (pl - 1);
   }
   *fr = (R.freem >> f) & 1;
   *al = *fr;
-  return f == 4 ? R.x3bot : R.x3top;
+  return (int)m.boff[f] + R.ij;
 }
 
 // Loads of one element of the march (issued one step ahead of its use).
+// Every lane loads from a valid address (faces that are not free, and idle
+// lanes, read the first free face) and the values of faces it does not use
+// are dropped where they are consumed: no conditional load writes a register
+// that an earlier load may still be filling, so the loads of the next
+// element stay in flight through the arithmetic of the current one.
 template <typename T>
 struct PencilLoads {
   T z[6], po[6];      // face 4 (low x3) only at the start of a segment
-  T d[4];             // lambda d0, d1, d2, d3
+  double d[4], lam;   // metric factors d0..d3 and lambda of the element
+  int use;            // bit f: face f free and read (lane active)
 };
 
 template <typename T, int NP>
@@ -135,27 +140,27 @@ __device__ inline void pencil_load(const MeshDev& m, const T* __restrict__ z,
                                    const T* __restrict__ pin, const PencilRow& R, int k, bool act,
                                    int col, int e, bool first, PencilLoads<T>& L) {
   constexpr int NF = NP * NP;
+  L.use = 0;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
-    L.z[f] = 0;
-    L.po[f] = 0;
-    bool fr, al;
-    const int fid = pencil_fid(R, m.n3, k, f, &fr, &al);
-    if (act && fr && (f != 4 || first)) {
-      const int g = fid * NF + col;
-      L.z[f] = z[g];
-      L.po[f] = pin[g];
+    if (f == 4 && !first) {
+      L.z[f] = L.po[f] = 0;
+      continue;
     }
+    bool fr, al;
+    const int fid = pencil_fid(m, R, k, f, &fr, &al);
+    const bool u = act && fr;
+    const int g = (u ? fid * NF : 0) + (act ? col : 0);
+    L.z[f] = z[g];
+    L.po[f] = pin[g];
+    L.use |= (int)u << f;
   }
-  if (act) {
-    const ElemInfo* ei = m.info + e;
-    L.d[0] = (T)(ei->d[0] * m.lam[e]);
-    L.d[1] = (T)ei->d[1];
-    L.d[2] = (T)ei->d[2];
-    L.d[3] = (T)ei->d[3];
-  } else {
-    L.d[0] = L.d[1] = L.d[2] = L.d[3] = 1;
-  }
+  const ElemInfo* ei = m.info + e;      // e is valid for every lane (idle slots clamped)
+  L.d[0] = ei->d[0];
+  L.d[1] = ei->d[1];
+  L.d[2] = ei->d[2];
+  L.d[3] = ei->d[3];
+  L.lam = m.lam[e];
 }
 
 // Element arithmetic on the input p (xf, faces 0..3 staged in LDS by the
@@ -229,45 +234,52 @@ __device__ inline void pencil_core(PencilSmem<T, NP, EPB>& sm, int sl, int q1, i
 template <typename T, int NP, int EPB>
 __device__ inline void pencil_step(T* __restrict__ pout, T* __restrict__ x, T* __restrict__ qa,
                                    T* __restrict__ qb, PencilSmem<T, NP, EPB>& sm,
-                                   const UnitLane& Ln, bool act, const PencilRow& R, int n3, int k,
+                                   const UnitLane& Ln, bool act, const MeshDev& m,
+                                   const PencilRow& R, int k,
                                    const PencilLoads<T>& L, bool first, bool last, T alpha,
                                    T beta, T H, T H11, T H01, T& carry_p, T& carry_w,
                                    double* dot) {
   constexpr int NF = NP * NP;
   const int col = Ln.col;
   // owned faces: the high face of each axis, and a free low face alone on a
-  // Neumann side; their x is read here and updated after the arithmetic
+  // Neumann side; their x is read here (valid address for every lane, as in
+  // pencil_load) and updated after the arithmetic
   T xo[6];
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     bool fr, al;
-    const int fid = pencil_fid(R, n3, k, f, &fr, &al);
-    xo[f] = 0;
-    if (act && fr && ((f & 1) || al)) xo[f] = x[fid * NF + col];
+    const int fid = pencil_fid(m, R, k, f, &fr, &al);
+    if ((f & 1) || f != 4 || first) {
+      const bool u = act && fr && ((f & 1) || al);
+      xo[f] = x[(u ? fid * NF : 0) + (act ? col : 0)];
+    } else {
+      xo[f] = 0;
+    }
   }
   T xf[6];
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     bool fr, al;
-    const int fid = pencil_fid(R, n3, k, f, &fr, &al);
+    const int fid = pencil_fid(m, R, k, f, &fr, &al);
     T v = 0;
     if (f == 4 && !first) {
       v = carry_p;
-    } else if (act && fr) {
+    } else if ((L.use >> f) & 1) {
       v = L.z[f] + beta * L.po[f];
       if ((f & 1) || al) pout[fid * NF + col] = v;
     }
     xf[f] = v;
     if (f < 4 && act) sm.face[Ln.sl][f][col] = v;
   }
+  const T d[4] = {(T)(L.d[0] * L.lam), (T)L.d[1], (T)L.d[2], (T)L.d[3]};
   T out[6];
-  pencil_core<T, NP, EPB>(sm, Ln.sl, Ln.q1, Ln.q2, col, act, L.d, xf, H, H11, H01, out);
+  pencil_core<T, NP, EPB>(sm, Ln.sl, Ln.q1, Ln.q2, col, act, d, xf, H, H11, H01, out);
   if (!act) return;
   double acc = 0.0;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     bool fr, al;
-    const int fid = pencil_fid(R, n3, k, f, &fr, &al);
+    const int fid = pencil_fid(m, R, k, f, &fr, &al);
     if (!fr) continue;
     const int g = fid * NF + col;
     if ((f & 1) || al) x[g] = xo[f] + alpha * L.po[f];
@@ -327,7 +339,6 @@ pencil_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, PencilIO<T> io) {
   const int ic = min(i, mesh.n1 - 1);       // idle slots past the end of x1 mirror the last
   const int rowe = mesh.n1 * j + ic;        // element index at k = 0
   const int plane = mesh.n1 * mesh.n2;
-  const int n3 = mesh.n3;
 
   // the first element's loads go out with the partials' loads
   PencilRow row;
@@ -356,7 +367,7 @@ pencil_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, PencilIO<T> io) {
 #pragma unroll
       for (int f = 0; f < 6; ++f) {
         bool fr, al;
-        const int fid = pencil_fid(row, n3, k, f, &fr, &al);
+        const int fid = pencil_fid(mesh, row, k, f, &fr, &al);
         if (!fr || !((f & 1) || al)) continue;
         const int g = fid * NF + Ln.col;
         x[g] = x[g] + alpha * pin[g];
@@ -367,16 +378,18 @@ pencil_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, PencilIO<T> io) {
   const T H = tab.H, H11 = tab.H11, H01 = tab.H01;
   T carry_p = 0, carry_w = 0;
   double dot = 0.0;
+  // two register sets: set B is loaded during the arithmetic on set A and
+  // the other way round; past the end of the segment the prefetch reloads
+  // the last element (cache hits), so that no load sits behind a branch
   for (int k = k0; k < k1; k += 2) {
-    const bool has_b = k + 1 < k1;
-    if (has_b)
-      pencil_load<T, NP>(mesh, z, pin, row, k + 1, act, Ln.col, rowe + plane * (k + 1), false, LB);
-    pencil_step<T, NP, EPB>(pout, x, qa, qb, sm, Ln, act, row, n3, k, LA, k == k0, !has_b, alpha,
-                            beta, H, H11, H01, carry_p, carry_w, &dot);
-    if (!has_b) break;
-    if (k + 2 < k1)
-      pencil_load<T, NP>(mesh, z, pin, row, k + 2, act, Ln.col, rowe + plane * (k + 2), false, LA);
-    pencil_step<T, NP, EPB>(pout, x, qa, qb, sm, Ln, act, row, n3, k + 1, LB, false, k + 2 >= k1,
+    const int kb = min(k + 1, k1 - 1);
+    pencil_load<T, NP>(mesh, z, pin, row, kb, act, Ln.col, rowe + plane * kb, false, LB);
+    pencil_step<T, NP, EPB>(pout, x, qa, qb, sm, Ln, act, mesh, row, k, LA, k == k0, k + 1 >= k1,
+                            alpha, beta, H, H11, H01, carry_p, carry_w, &dot);
+    if (k + 1 >= k1) break;
+    const int ka = min(k + 2, k1 - 1);
+    pencil_load<T, NP>(mesh, z, pin, row, ka, act, Ln.col, rowe + plane * ka, false, LA);
+    pencil_step<T, NP, EPB>(pout, x, qa, qb, sm, Ln, act, mesh, row, k + 1, LB, false, k + 2 >= k1,
                             alpha, beta, H, H11, H01, carry_p, carry_w, &dot);
   }
   // p_k . K^ p_k from the element-local quadratic forms, one partial per block
