@@ -670,7 +670,8 @@ def main():
         y64 = torch.empty_like(x64)
         for which, name in ((pkg.TIME_APPLY_F64, "apply64"), (pkg.TIME_CG2_APPLY_F64, "cg_apply64"),
                             (pkg.TIME_CG2_UPDATE_F64, "cg_update64"),
-                            (pkg.TIME_CG1_ITER_F64, "cg_onekernel64"), (pkg.TIME_COPY_F64, "copy64")):
+                            (pkg.TIME_CG1_ITER_F64, "cg_onekernel64"),
+                            (pkg.TIME_PENCIL_ITER_F64, "cg_pencil64"), (pkg.TIME_COPY_F64, "copy64")):
             ms = ctx.time_kernel(which, x64, args.reps,
                                  y=y64 if which in (pkg.TIME_COPY_F64, pkg.TIME_APPLY_F64) else None)
             log(f"[bench] {name} {ms * 1e3:.3f} us")

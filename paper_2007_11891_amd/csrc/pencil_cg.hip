@@ -22,9 +22,11 @@
 //   r.z and r.r partials.  The element launch that finds the solve finished
 // applies the last x update (x_k = x_{k-1} + alpha_{k-1} p_{k-1}) and stops.
 //
-// Loads of the next element of the march are issued before the arithmetic
-// of the current one (two register sets, alternating, so that no register
-// with a load in flight is ever copied); the 1D tables sit in LDS.
+// A step of the march first consumes the loaded face values of its element
+// (p and x updates and their stores, the input staged in LDS), then issues
+// the loads of the next element into the same registers, and then runs the
+// element arithmetic while those loads are in flight.  The 1D tables sit in
+// LDS.
 #include <algorithm>
 
 #include "cg_state.hpp"
@@ -122,38 +124,38 @@ __device__ inline int pencil_fid(const MeshDev& m, const PencilRow& R, int k, in
   return (int)m.boff[f] + R.ij;
 }
 
-// Loads of one element of the march (issued one step ahead of its use).
+// Loads of one element of the march (issued one step ahead of their use).
 // Every lane loads from a valid address (faces that are not free, and idle
 // lanes, read the first free face) and the values of faces it does not use
 // are dropped where they are consumed: no conditional load writes a register
-// that an earlier load may still be filling, so the loads of the next
-// element stay in flight through the arithmetic of the current one.
+// that an earlier load may still be filling.
 template <typename T>
 struct PencilLoads {
   T z[6], po[6];      // face 4 (low x3) only at the start of a segment
+  T xo[6];            // x on the owned faces (high faces; low faces alone on a Neumann side)
   double d[4], lam;   // metric factors d0..d3 and lambda of the element
-  int use;            // bit f: face f free and read (lane active)
 };
 
 template <typename T, int NP>
 __device__ inline void pencil_load(const MeshDev& m, const T* __restrict__ z,
-                                   const T* __restrict__ pin, const PencilRow& R, int k, bool act,
-                                   int col, int e, bool first, PencilLoads<T>& L) {
+                                   const T* __restrict__ pin, const T* __restrict__ x,
+                                   const PencilRow& R, int k, bool act, int col, int e, bool first,
+                                   PencilLoads<T>& L) {
   constexpr int NF = NP * NP;
-  L.use = 0;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
-    if (f == 4 && !first) {
-      L.z[f] = L.po[f] = 0;
-      continue;
-    }
     bool fr, al;
     const int fid = pencil_fid(m, R, k, f, &fr, &al);
+    if (f == 4 && !first) {
+      L.z[f] = L.po[f] = L.xo[f] = 0;
+      continue;
+    }
     const bool u = act && fr;
     const int g = (u ? fid * NF : 0) + (act ? col : 0);
     L.z[f] = z[g];
     L.po[f] = pin[g];
-    L.use |= (int)u << f;
+    if ((f & 1) || (R.alonem >> f) & 1) L.xo[f] = x[g];
+    else L.xo[f] = 0;
   }
   const ElemInfo* ei = m.info + e;      // e is valid for every lane (idle slots clamped)
   L.d[0] = ei->d[0];
@@ -226,36 +228,22 @@ __device__ inline void pencil_core(PencilSmem<T, NP, EPB>& sm, int sl, int q1, i
   __syncthreads();                          // LDS is reused by the next element
 }
 
-// One element of the march: the input p on its faces, the stores of p and x
-// on the faces it owns (x read at the start of the step, used after the
-// element arithmetic), the operator, and the stores of its contributions.
-// carry_p / carry_w: p and the contribution of the x3 face shared with the
-// previous element of the segment (in), and with the next one (out).
+// One element of the march.  In: L holds the loaded values of element k.
+// The input p on its faces, p and x on the faces it owns (stored), the input
+// staged in LDS; then the loads of element kn into L; then the operator and
+// the stores of the contributions.  carry_p / carry_w: p and the
+// contribution of the x3 face shared with the previous element of the
+// segment (in), and with the next one (out).
 template <typename T, int NP, int EPB>
-__device__ inline void pencil_step(T* __restrict__ pout, T* __restrict__ x, T* __restrict__ qa,
+__device__ inline void pencil_step(const T* __restrict__ z, const T* __restrict__ pin,
+                                   T* __restrict__ pout, T* __restrict__ x, T* __restrict__ qa,
                                    T* __restrict__ qb, PencilSmem<T, NP, EPB>& sm,
                                    const UnitLane& Ln, bool act, const MeshDev& m,
-                                   const PencilRow& R, int k,
-                                   const PencilLoads<T>& L, bool first, bool last, T alpha,
-                                   T beta, T H, T H11, T H01, T& carry_p, T& carry_w,
-                                   double* dot) {
+                                   const PencilRow& R, int k, int kn, int en, PencilLoads<T>& L,
+                                   bool first, bool last, T alpha, T beta, T H, T H11, T H01,
+                                   T& carry_p, T& carry_w, double* dot) {
   constexpr int NF = NP * NP;
   const int col = Ln.col;
-  // owned faces: the high face of each axis, and a free low face alone on a
-  // Neumann side; their x is read here (valid address for every lane, as in
-  // pencil_load) and updated after the arithmetic
-  T xo[6];
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    bool fr, al;
-    const int fid = pencil_fid(m, R, k, f, &fr, &al);
-    if ((f & 1) || f != 4 || first) {
-      const bool u = act && fr && ((f & 1) || al);
-      xo[f] = x[(u ? fid * NF : 0) + (act ? col : 0)];
-    } else {
-      xo[f] = 0;
-    }
-  }
   T xf[6];
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
@@ -264,14 +252,19 @@ __device__ inline void pencil_step(T* __restrict__ pout, T* __restrict__ x, T* _
     T v = 0;
     if (f == 4 && !first) {
       v = carry_p;
-    } else if ((L.use >> f) & 1) {
+    } else if (act && fr) {
       v = L.z[f] + beta * L.po[f];
-      if ((f & 1) || al) pout[fid * NF + col] = v;
+      if ((f & 1) || al) {                    // the face is this element's
+        pout[fid * NF + col] = v;
+        x[fid * NF + col] = L.xo[f] + alpha * L.po[f];
+      }
     }
     xf[f] = v;
     if (f < 4 && act) sm.face[Ln.sl][f][col] = v;
   }
   const T d[4] = {(T)(L.d[0] * L.lam), (T)L.d[1], (T)L.d[2], (T)L.d[3]};
+  // the next element's loads go out before the arithmetic of this one
+  pencil_load<T, NP>(m, z, pin, x, R, kn, act, col, en, false, L);
   T out[6];
   pencil_core<T, NP, EPB>(sm, Ln.sl, Ln.q1, Ln.q2, col, act, d, xf, H, H11, H01, out);
   if (!act) return;
@@ -282,7 +275,6 @@ __device__ inline void pencil_step(T* __restrict__ pout, T* __restrict__ x, T* _
     const int fid = pencil_fid(m, R, k, f, &fr, &al);
     if (!fr) continue;
     const int g = fid * NF + col;
-    if ((f & 1) || al) x[g] = xo[f] + alpha * L.po[f];
     acc += (double)(xf[f] * out[f]);
     if (f < 4) {
       if (f & 1) {
@@ -309,10 +301,16 @@ __device__ inline void pencil_step(T* __restrict__ pout, T* __restrict__ x, T* _
   *dot += acc;
 }
 
-// At most 128 VGPRs (four waves per SIMD): the march keeps enough blocks per
-// CU in flight to cover the memory latency.
+// Elements owned by whole wavefronts: at most 128 VGPRs (four waves per
+// SIMD), so that enough blocks per CU are in flight to cover the memory
+// latency; elements packed several per wavefront keep more registers per
+// lane (their face bookkeeping is per lane).
+template <int NP>
+constexpr int pencil_min_waves() { return is_group<NP>() ? 4 : 2; }
+
 template <typename T, int NP, int EPB>
 __global__ void __launch_bounds__((unit_threads<NP, EPB>()))
+__attribute__((amdgpu_waves_per_eu(pencil_min_waves<NP>())))
 pencil_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, PencilIO<T> io) {
   constexpr int NT = unit_threads<NP, EPB>();
   __shared__ PencilSmem<T, NP, EPB> sm;
@@ -343,8 +341,8 @@ pencil_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, PencilIO<T> io) {
   // the first element's loads go out with the partials' loads
   PencilRow row;
   pencil_row(mesh, ic, j, row);
-  PencilLoads<T> LA, LB;
-  pencil_load<T, NP>(mesh, z, pin, row, k0, act, Ln.col, rowe + plane * k0, true, LA);
+  PencilLoads<T> L;
+  pencil_load<T, NP>(mesh, z, pin, x, row, k0, act, Ln.col, rowe + plane * k0, true, L);
   const int k2 = iter & 1;
   const double* pp[2] = {io.partials + (size_t)(2 + k2) * io.pmax,
                          io.partials + (size_t)(4 + k2) * io.pmax};
@@ -378,19 +376,13 @@ pencil_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, PencilIO<T> io) {
   const T H = tab.H, H11 = tab.H11, H01 = tab.H01;
   T carry_p = 0, carry_w = 0;
   double dot = 0.0;
-  // two register sets: set B is loaded during the arithmetic on set A and
-  // the other way round; past the end of the segment the prefetch reloads
-  // the last element (cache hits), so that no load sits behind a branch
-  for (int k = k0; k < k1; k += 2) {
-    const int kb = min(k + 1, k1 - 1);
-    pencil_load<T, NP>(mesh, z, pin, row, kb, act, Ln.col, rowe + plane * kb, false, LB);
-    pencil_step<T, NP, EPB>(pout, x, qa, qb, sm, Ln, act, mesh, row, k, LA, k == k0, k + 1 >= k1,
-                            alpha, beta, H, H11, H01, carry_p, carry_w, &dot);
-    if (k + 1 >= k1) break;
-    const int ka = min(k + 2, k1 - 1);
-    pencil_load<T, NP>(mesh, z, pin, row, ka, act, Ln.col, rowe + plane * ka, false, LA);
-    pencil_step<T, NP, EPB>(pout, x, qa, qb, sm, Ln, act, mesh, row, k + 1, LB, false, k + 2 >= k1,
-                            alpha, beta, H, H11, H01, carry_p, carry_w, &dot);
+  // past the end of the segment the prefetch reloads the last element
+  // (cache hits), so that no load sits behind a branch
+  for (int k = k0; k < k1; ++k) {
+    const int kn = min(k + 1, k1 - 1);
+    pencil_step<T, NP, EPB>(z, pin, pout, x, qa, qb, sm, Ln, act, mesh, row, k, kn,
+                            rowe + plane * kn, L, k == k0, k + 1 == k1, alpha, beta, H, H11, H01,
+                            carry_p, carry_w, &dot);
   }
   // p_k . K^ p_k from the element-local quadratic forms, one partial per block
   const double bs = block_sum<NT>(dot, s_red);
@@ -399,20 +391,23 @@ pencil_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, PencilIO<T> io) {
 
 // ================================ update ====================================
 constexpr int kPencilVecThreads = 256;
-constexpr int kPencilUnroll = 4;
+// eight entries per thread in flight (four streams each): with fewer, the
+// update's loads per wave do not cover the HBM latency at 512 blocks
+constexpr int kPencilUnroll = 8;
 
 // Update of iteration k: alpha_k = rho_k / (p_k . w) with p.w summed from the
 // element launch's partials; z -= alpha_k D^-1 w with w = qa + qb, except on
 // the faces normal to x3 inside a segment, whose qa already holds the sum;
 // r.z and r.r partials for the next element launch.  Block 0 publishes A.
 // x3-face DOFs are [x3_lo, x3_hi), in planes of plane_dofs values; plane
-// pl = 1 .. n3 - 1 lies on a segment boundary when pl % ks == 0.
+// pl = 1 .. n3 - 1 lies on a segment boundary when pl % ks == 0.  32-bit
+// offsets within that range (the element launch needs them anyway).
 template <typename T>
 __global__ void __launch_bounds__(kPencilVecThreads)
 pencil_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ qb,
                      T* __restrict__ z, const T* __restrict__ dinv, double* __restrict__ partials,
                      int pmax, int n_apply, CgScalars* sc, int64_t x3_lo, int64_t x3_hi,
-                     int64_t plane_dofs, double inv_plane, int ks) {
+                     uint32_t plane_dofs, float inv_plane, uint32_t ks, float inv_ks) {
   const int done = sc->B.done;
   if (done) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -427,13 +422,19 @@ pencil_update_kernel(int64_t n, const T* __restrict__ qa, const T* __restrict__ 
   const int64_t stride = (int64_t)gridDim.x * kPencilVecThreads;
   int64_t g0 = (int64_t)blockIdx.x * kPencilVecThreads + threadIdx.x;
   T va[kPencilUnroll], vb[kPencilUnroll], vz[kPencilUnroll], vd[kPencilUnroll];
+  // plane q = r / plane_dofs and (q + 1) mod ks by float estimates corrected
+  // in 32-bit integers (r < 2^31: the estimate is within one of the quotient)
   auto need_b = [&](int64_t g) -> bool {
     if (g < x3_lo || g >= x3_hi) return true;
-    const int64_t r = g - x3_lo;
-    int64_t q = (int64_t)((double)r * inv_plane);
+    const uint32_t r = (uint32_t)(g - x3_lo);
+    uint32_t q = (uint32_t)((float)r * inv_plane);
     if (q * plane_dofs > r) --q;
     else if ((q + 1) * plane_dofs <= r) ++q;
-    return (q + 1) % ks == 0;
+    const uint32_t m = q + 1;
+    uint32_t t = (uint32_t)((float)m * inv_ks);
+    if (t * ks > m) --t;
+    else if ((t + 1) * ks <= m) ++t;
+    return m == t * ks;
   };
   auto load = [&](int64_t base) {
 #pragma unroll
@@ -588,7 +589,8 @@ hipError_t launch_pencil_update(const hdg_ctx* c, CgWork<T>& w, hipStream_t s) {
   const int64_t x3_hi = x3_lo + plane * (c->n[2] - 1);
   hipLaunchKernelGGL((pencil_update_kernel<T>), dim3(w.update_blocks), dim3(kPencilVecThreads), 0,
                      s, w.n, w.qa, w.qb, w.z, w.dinv, w.partials, w.pmax, w.pencil_blocks, w.sc,
-                     x3_lo, x3_hi, plane, 1.0 / (double)plane, ks);
+                     x3_lo, x3_hi, (uint32_t)plane, 1.0f / (float)plane, (uint32_t)ks,
+                     1.0f / (float)ks);
   return hipGetLastError();
 }
 
