@@ -51,11 +51,18 @@ struct PencilIO {
   int n_seg;          // segments along x3
 };
 
+// Two values read together from LDS (one 16-byte access in FP64).
+template <typename T>
+struct alignas(2 * sizeof(T)) PencilPair {
+  T lo, hi;
+};
+
 template <typename T, int NP, int EPB>
 struct PencilSmem {
-  T face[EPB][4][NP * NP];                  // faces normal to x1, x2 (input p)
+  PencilPair<T> face[EPB][2][NP * NP];      // faces normal to x1, x2 (input p), low and high
   T u[EPB][upitch<NP>() * NP * NP + 1];     // the element's u in the eigenspace
-  T bs0[NP], bs1[NP], lam[NP];
+  PencilPair<T> bs[NP];                     // B_S[k][0], B_S[k][1]
+  T lam[NP];
 };
 
 // Face ids of one slot's pencil (element (i, j, k) for the k of the march):
@@ -67,7 +74,8 @@ struct PencilSmem {
 // runs this form only when every trace offset fits.
 struct PencilRow {
   int A[4];            // faces normal to x1, x2 at k = 0
-  int ij;              // i + n1 j
+  int x3A;             // interior x3 face of plane 1 (foff[2] + i + n1 j)
+  int x3bot, x3top;    // the boundary x3 faces of the column
   int freem, alonem;   // bits 0..3: faces normal to x1, x2; bits 4, 5: the
                        // boundary x3 faces (used at k = 0 and k = n3 - 1)
 };
@@ -94,9 +102,12 @@ __device__ inline void pencil_row(const MeshDev& m, int i, int j, PencilRow& R) 
       if (R.A[2 + s] < nff) R.alonem |= 4 << s;
     }
   }
-  R.ij = i + m.n1 * j;
-  if ((int)m.boff[4] + R.ij < nff) R.alonem |= 16;
-  if ((int)m.boff[5] + R.ij < nff) R.alonem |= 32;
+  const int ij = i + m.n1 * j;
+  R.x3A = (int)m.foff[2] + ij;
+  R.x3bot = (int)m.boff[4] + ij;
+  R.x3top = (int)m.boff[5] + ij;
+  if (R.x3bot < nff) R.alonem |= 16;
+  if (R.x3top < nff) R.alonem |= 32;
   R.freem |= R.alonem;
 }
 
@@ -117,11 +128,11 @@ __device__ inline int pencil_fid(const MeshDev& m, const PencilRow& R, int k, in
   if (pl >= 1 && pl <= m.n3 - 1) {
     *fr = true;
     *al = false;
-    return (int)m.foff[2] + R.ij + m.n1 * m.n2 * (pl - 1);
+    return R.x3A + m.n1 * m.n2 * (pl - 1);
   }
   *fr = (R.freem >> f) & 1;
   *al = *fr;
-  return (int)m.boff[f] + R.ij;
+  return f == 4 ? R.x3bot : R.x3top;
 }
 
 // Loads of one element of the march (issued one step ahead of their use).
@@ -177,28 +188,29 @@ __device__ inline void pencil_core(PencilSmem<T, NP, EPB>& sm, int sl, int q1, i
   __syncthreads();
   T r2lo = 0, r2hi = 0;
   if (act) {
-    const T* f0lo = sm.face[sl][0];
-    const T* f0hi = sm.face[sl][1];
-    const T* f1lo = sm.face[sl][2];
-    const T* f1hi = sm.face[sl][3];
-    const T c0 = d[1] * sm.bs0[q1], c1 = d[1] * sm.bs1[q1];
-    const T c2 = d[2] * sm.bs0[q2], c3 = d[2] * sm.bs1[q2];
+    const PencilPair<T>* f0 = sm.face[sl][0];
+    const PencilPair<T>* f1 = sm.face[sl][1];
+    const PencilPair<T> b1 = sm.bs[q1], b2 = sm.bs[q2];
+    const T c0 = d[1] * b1.lo, c1 = d[1] * b1.hi;
+    const T c2 = d[2] * b2.lo, c3 = d[2] * b2.hi;
     const T x2lo = d[3] * xf[4], x2hi = d[3] * xf[5];
     const T dij = d[0] + d[1] * sm.lam[q1] + d[2] * sm.lam[q2];
     T* u = sm.u[sl] + q1 + P * q2;
 #pragma unroll 2
     for (int q3 = 0; q3 < NP; ++q3) {
-      const T b0 = sm.bs0[q3], b1 = sm.bs1[q3];
-      T F = c0 * f0lo[q2 + NP * q3];
-      F += c1 * f0hi[q2 + NP * q3];
-      F += c2 * f1lo[q1 + NP * q3];
-      F += c3 * f1hi[q1 + NP * q3];
-      F += b0 * x2lo;
-      F += b1 * x2hi;
+      const PencilPair<T> b = sm.bs[q3];
+      const PencilPair<T> a0 = f0[q2 + NP * q3];
+      const PencilPair<T> a1 = f1[q1 + NP * q3];
+      T F = c0 * a0.lo;
+      F += c1 * a0.hi;
+      F += c2 * a1.lo;
+      F += c3 * a1.hi;
+      F += b.lo * x2lo;
+      F += b.hi * x2hi;
       const T v = div_fast(F, dij + d[3] * sm.lam[q3]);
       u[P * NP * q3] = v;
-      r2lo += b0 * v;
-      r2hi += b1 * v;
+      r2lo += b.lo * v;
+      r2hi += b.hi * v;
     }
   }
   __syncthreads();
@@ -207,8 +219,9 @@ __device__ inline void pencil_core(PencilSmem<T, NP, EPB>& sm, int sl, int q1, i
     const T* ua = sm.u[sl] + P * col;             // axis 0: face node (q2, q3) = col
 #pragma unroll 4
     for (int a = 0; a < NP; ++a) {
-      lo += sm.bs0[a] * ua[a];
-      hi += sm.bs1[a] * ua[a];
+      const PencilPair<T> b = sm.bs[a];
+      lo += b.lo * ua[a];
+      hi += b.hi * ua[a];
     }
     out[0] = d[1] * (H * xf[0] + H01 * xf[1] - lo);
     out[1] = d[1] * (H11 * xf[1] + H01 * xf[0] - hi);
@@ -217,8 +230,9 @@ __device__ inline void pencil_core(PencilSmem<T, NP, EPB>& sm, int sl, int q1, i
     const T* ub = sm.u[sl] + q1 + P * NP * q2;    // axis 1: face node (q1, q3) = col
 #pragma unroll 4
     for (int b = 0; b < NP; ++b) {
-      lo += sm.bs0[b] * ub[P * b];
-      hi += sm.bs1[b] * ub[P * b];
+      const PencilPair<T> bb = sm.bs[b];
+      lo += bb.lo * ub[P * b];
+      hi += bb.hi * ub[P * b];
     }
     out[2] = d[2] * (H * xf[2] + H01 * xf[3] - lo);
     out[3] = d[2] * (H11 * xf[3] + H01 * xf[2] - hi);
@@ -260,7 +274,10 @@ __device__ inline void pencil_step(const T* __restrict__ z, const T* __restrict_
       }
     }
     xf[f] = v;
-    if (f < 4 && act) sm.face[Ln.sl][f][col] = v;
+  }
+  if (act) {
+    sm.face[Ln.sl][0][col] = PencilPair<T>{xf[0], xf[1]};
+    sm.face[Ln.sl][1][col] = PencilPair<T>{xf[2], xf[3]};
   }
   const T d[4] = {(T)(L.d[0] * L.lam), (T)L.d[1], (T)L.d[2], (T)L.d[3]};
   // the next element's loads go out before the arithmetic of this one
@@ -349,8 +366,7 @@ pencil_apply_kernel(const MeshDev mesh, const ElemTab<T> tab, PencilIO<T> io) {
   PartialSums<NT, 2> ps;
   ps.issue(pp, io.n_upd);
   if (threadIdx.x < NP) {
-    sm.bs0[threadIdx.x] = tab.bs0[threadIdx.x];
-    sm.bs1[threadIdx.x] = tab.bs1[threadIdx.x];
+    sm.bs[threadIdx.x] = PencilPair<T>{tab.bs0[threadIdx.x], tab.bs1[threadIdx.x]};
     sm.lam[threadIdx.x] = tab.lam[threadIdx.x];
   }
   bool skip;
