@@ -339,11 +339,13 @@ hdg_status hdg_set_tile(hdg_ctx* ctx, int variant);
 hdg_status hdg_set_cg_segment(hdg_ctx* ctx, int ks);
 
 /* Autotuner: times one FP64 CG iteration in each of the three CG forms (see
- * hdg_solve_opts.variant) for every tile variant on this context's mesh
- * (`reps` launches each, HIP events on the context stream), keeps the
- * fastest pair as the context's tile shape and CG form, returns the tile
- * variant in *chosen and, in times_ms (host double[3] or NULL), the best time
- * of each tile variant.  Synchronises the stream. */
+ * hdg_solve_opts.variant; the pencil form with its automatic segment length
+ * and with 16, 8, 4 and 2 elements per segment) for every tile variant on
+ * this context's mesh (`reps` launches each, HIP events on the context
+ * stream), keeps the fastest as the context's tile shape, CG form and
+ * segment length, returns the tile variant in *chosen and, in times_ms (host
+ * double[3] or NULL), the best time of each tile variant.  Synchronises the
+ * stream. */
 hdg_status hdg_autotune(hdg_ctx* ctx, int reps, int* chosen, double* times_ms);
 
 /* Current tile shape: *variant (0..2), *elems_per_unit (elements of one

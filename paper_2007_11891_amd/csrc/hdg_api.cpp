@@ -353,7 +353,8 @@ hdg_status solve_eigen(hdg_ctx* c, const double* b, double* x_out, const hdg_sol
     // FP32 correction, the FP64 residual is recomputed and replaces the FP32
     // one (normalised again), and the FP32 CG continues with its search
     // direction and previous r.z rescaled to the new normalisation instead of
-    // restarting.  The inner CG uses the two-kernel form.
+    // restarting.  The inner CG uses a two-kernel form: the pencil form when
+    // the FP64 solves of this context use it, else the plain one.
     float* b32 = reinterpret_cast<float*>(c->d_tmp[1]);   // n_free floats fit in n_free doubles
     double* xacc = x_out;
     CgWork<float>& w = c->w32;
@@ -367,7 +368,8 @@ hdg_status solve_eigen(hdg_ctx* c, const double* b, double* x_out, const hdg_sol
     // it: the device's iteration counter of the current FP32 run (buffer and
     // state-slot parities follow it); base: iterations of earlier runs
     int outer = 0, inner_total = 0, it = 0, done = 0, base = 0;
-    ST_TRY(run_cg<float>(c, w, b32, inner, o->maxit, o->check_every, 1, &it, &done));
+    const int v32 = (cg_variant_of(c, o) == 2 && pencil_fits(c)) ? 2 : 1;
+    ST_TRY(run_cg<float>(c, w, b32, inner, o->maxit, o->check_every, v32, &it, &done));
     for (;;) {
       inner_total = base + it;
       HIP_TRY(launch_axpy_32_64(w.x, xacc, sigma, c->n_free, c->stream));
@@ -387,13 +389,16 @@ hdg_status solve_eigen(hdg_ctx* c, const double* b, double* x_out, const hdg_sol
         hs[2].A.rtol2 = inner * inner;
         hs[2].A.maxit = it + std::max(1, o->maxit);
         hs[2].A.done = 0;
+        // the pencil form's element launch adds alpha_{k-1} p_{k-1} to x: that
+        // step is already in the finished segment's x, and x restarts at 0
+        hs[2].A.alpha = 0.0;
         HIP_TRY(hipMemcpyAsync(w.sc, &hs[2], sizeof(CgScalars), hipMemcpyHostToDevice,
                                c->stream));
-        ST_TRY(cg_drive<float>(c, w, std::max(1, o->maxit), o->check_every, 1, &it, &done));
+        ST_TRY(cg_drive<float>(c, w, std::max(1, o->maxit), o->check_every, v32, &it, &done));
       } else {
         // the segment hit its cap: restart from the replaced residual
         base += it;
-        ST_TRY(run_cg<float>(c, w, b32, inner, o->maxit, o->check_every, 1, &it, &done));
+        ST_TRY(run_cg<float>(c, w, b32, inner, o->maxit, o->check_every, v32, &it, &done));
       }
       sigma = sig_new;
     }
@@ -720,9 +725,10 @@ hdg_status hdg_create_ex(const int n_elem[3], const double* h1, const double* h2
   c->neumann = neumann_sides;
   c->n_elem = ne;
   // CG form before any autotuning: one kernel per iteration for meshes small
-  // enough that launch latency dominates, else the two-kernel form (the
-  // measured crossover on MI355X lies between n_elem n_p^2 = 2.6e5 and 6.8e5)
-  c->cg_variant = ne * (int64_t)(p + 1) * (p + 1) <= 400000 ? 0 : 1;
+  // enough that launch latency dominates, else the pencil form (the measured
+  // crossover on MI355X lies between n_elem n_p^2 = 2.6e5 and 8.2e5); the
+  // plain two-kernel form where the pencil form's 32-bit offsets do not fit
+  c->cg_variant = ne * (int64_t)(p + 1) * (p + 1) <= 400000 ? 0 : 2;
   const int n1 = n_elem[0], n2 = n_elem[1], n3 = n_elem[2];
   const int64_t nf0 = (int64_t)(n1 - 1) * n2 * n3, nf1 = (int64_t)n1 * (n2 - 1) * n3,
                 nf2 = (int64_t)n1 * n2 * (n3 - 1);
@@ -731,6 +737,7 @@ hdg_status hdg_create_ex(const int n_elem[3], const double* h1, const double* h2
   c->n_int_faces = fc.n_int;
   c->n_free_faces = fc.n_free_faces;
   c->n_faces = fc.n_faces;
+  if (c->cg_variant == 2 && !pencil_fits(c)) c->cg_variant = 1;
   c->n_neu_faces = c->n_free_faces - c->n_int_faces;
   const int64_t npf = (int64_t)c->np * c->np;
   c->n_free = c->n_free_faces * npf;
@@ -1265,16 +1272,25 @@ hdg_status hdg_autotune(hdg_ctx* c, int reps, int* chosen, double* times_ms) {
     return HDG_OK;
   }
   // time one FP64 CG iteration in each form (one kernel, element + update
-  // kernel, pencil element + update kernel) for every tile variant on this
-  // context's mesh and keep the fastest pair
+  // kernel, pencil element + update kernel with a few segment lengths) for
+  // every tile variant on this context's mesh and keep the fastest choice
   double best = 1e300;
-  int best_v = 0, best_cg = 0;
+  int best_v = 0, best_cg = 0, best_ks = 0;
   double* x = c->d_tmp[1];
   HIP_TRY(launch_fill64(x, 1.0, c->n_free, c->stream));
+  // segment lengths of the pencil form: the automatic choice, then 16, 8, 4, 2
+  // elements (the best measured lies among them on 16^3 .. 32^3 meshes)
+  std::vector<int> kss = {0};
+  for (int ks : {16, 8, 4, 2})
+    if (ks < c->n[2]) kss.push_back(ks);
   for (int v = 0; v < kNumTileVariants; ++v) {
     ST_TRY(hdg_set_tile(c, v));
     double tv = 1e300;
-    for (int cg = 0; cg < (pencil_fits(c) ? 3 : 2); ++cg) {
+    const int nforms = pencil_fits(c) ? 2 + (int)kss.size() : 2;
+    for (int form = 0; form < nforms; ++form) {
+      const int cg = form < 2 ? form : 2;
+      const int ks = form < 2 ? 0 : kss[form - 2];
+      if (cg == 2) ST_TRY(hdg_set_cg_segment(c, ks));
       const int id = cg == 0 ? HDG_TIME_CG1_ITER_F64
                              : (cg == 1 ? HDG_TIME_CG2_ITER_F64 : HDG_TIME_PENCIL_ITER_F64);
       double ms = 0.0;
@@ -1284,11 +1300,13 @@ hdg_status hdg_autotune(hdg_ctx* c, int reps, int* chosen, double* times_ms) {
         best = ms;
         best_v = v;
         best_cg = cg;
+        best_ks = ks;
       }
     }
     if (times_ms) times_ms[v] = tv;
   }
   ST_TRY(hdg_set_tile(c, best_v));
+  ST_TRY(hdg_set_cg_segment(c, best_cg == 2 ? best_ks : 0));
   c->cg_variant = best_cg;
   if (chosen) *chosen = best_v;
   return HDG_OK;

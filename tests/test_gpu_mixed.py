@@ -26,18 +26,24 @@ def _manufactured(c, lam):
     return vx, tx, f, g
 
 
+@pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("p", [4, 8])
 @pytest.mark.parametrize("lam", [1e-2, 1.0, 1e2])
-def test_mixed_precision_matches_oracle_submesh(p, lam):
+def test_mixed_precision_matches_oracle_submesh(p, lam, variant):
+    """The FP32 inner CG in the plain two-kernel form (variant 1) and in the
+    pencil form (variant 2, segments of two elements so that x3 faces are
+    summed inside segments and split at their ends)."""
     import paper_2007_11891_amd as pkg
     n = (4, 4, 4) if p == 4 else (3, 3, 3)
-    print(f"[mixed vs oracle] n={n} p={p} lam={lam}", flush=True)
+    print(f"[mixed vs oracle] n={n} p={p} lam={lam} variant={variant}", flush=True)
     widths = [W.uniform_widths(v) for v in n]
     c = gpu_ctx(n, widths, p, 1.0, lam)
+    c.set_cg_segment(2)
     vx, tx, f, g = _manufactured(c, lam)
     tr = to_dev(g)
     tr[:c.sizes.n_free] = 0
-    tr, uv, info = c.solve_forcing(to_dev(f), tr, opts=pkg.default_opts(rtol=1e-11, mixed=1))
+    tr, uv, info = c.solve_forcing(to_dev(f), tr, opts=pkg.default_opts(rtol=1e-11, mixed=1,
+                                                                          variant=variant))
     assert info["outer_iters"] >= 1 and info["rel_res"] <= 1e-11
     o = oracle.HdgOracle(n, widths, p, 1.0, lam)
     ut = o.solve(f, g)
