@@ -179,7 +179,7 @@ __device__ inline void pencil_load(const MeshDev& m, const T* __restrict__ z,
 // Element arithmetic on the input p (xf, faces 0..3 staged in LDS by the
 // caller before this call): expansion into the element eigenspace, division
 // by D_Z, reductions back to the faces, and the face term with the 2 x 2
-// matrix H = G + C^T M^-1 C of each axis.
+// matrix H = G + C^T M^-1 C of each axis.  Two barriers per element.
 template <typename T, int NP, int EPB>
 __device__ inline void pencil_core(PencilSmem<T, NP, EPB>& sm, int sl, int q1, int q2, int col,
                                    bool act, const T* d, const T* xf, T H, T H11, T H01,
@@ -239,7 +239,9 @@ __device__ inline void pencil_core(PencilSmem<T, NP, EPB>& sm, int sl, int q1, i
     out[4] = d[3] * (H * xf[4] + H01 * xf[5] - r2lo);
     out[5] = d[3] * (H11 * xf[5] + H01 * xf[4] - r2hi);
   }
-  __syncthreads();                          // LDS is reused by the next element
+  // no barrier here: the next element stages its faces (read above only
+  // before the second barrier) and writes u only after its first barrier,
+  // which every wave reaches after finishing these reductions
 }
 
 // One element of the march.  In: L holds the loaded values of element k.
