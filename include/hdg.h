@@ -246,6 +246,23 @@ hdg_status hdg_coords(hdg_ctx* ctx, double* vol_xyz, double* trace_xyz);
 hdg_status hdg_apply(hdg_ctx* ctx, const void* x, void* y, hdg_dtype dtype,
                      hdg_basis basis);
 
+/* hdg_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same y = K_ff x with the same arguments and kernels, but its per-face
+ * element contributions (and, in the nodal basis, the transformed input) sit
+ * in one file-scope device array of 48 MiB per GPU instead of context memory,
+ * so the call itself allocates nothing.  The array is held on each GPU the
+ * library runs on until the process ends; its device address is looked up
+ * once per device, at the first call on that device (the current device must
+ * be the context's).  Limit: 2 (eigen basis) or 3 (nodal basis) vectors of
+ * n_free values of dtype, each rounded up to 256 bytes, must fit in 48 MiB
+ * (n_free up to about 3.1M in FP64, eigen basis); larger sizes return
+ * HDG_EINVAL and launch nothing.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other contexts, other
+ * threads) race.  Nothing in the array needs clearing between calls. */
+hdg_status hdg_apply_noalloc(hdg_ctx* ctx, const void* x, void* y, hdg_dtype dtype,
+                             hdg_basis basis);
+
 /* Per-face transform (see hdg_transform) of n_faces consecutive faces
  * (n_faces * n_p^2 FP64 values, device; n_faces <= n_all / n_p^2); in == out
  * is allowed. */

@@ -34,6 +34,27 @@ hdg_status fail(hdg_status st, const char* fmt, ...) {
   return st;
 }
 
+// Per-face 1D transform matrices of the context by hdg_transform kind.
+const double* mat64(const hdg_ctx* c, int kind) {
+  // storage order: St, StM, S, MS, then S o S (entrywise square, used for the
+  // diagonal of the nodal block preconditioner)
+  const int npf = c->np * c->np;
+  switch (kind) {
+    case HDG_TO_EIGEN_UNKNOWN: return c->d_mats64 + npf;      // S^T M
+    case HDG_TO_EIGEN_RESIDUAL: return c->d_mats64;           // S^T
+    case HDG_TO_NODAL_UNKNOWN: return c->d_mats64 + 2 * npf;  // S
+    default: return c->d_mats64 + 3 * npf;                    // M S
+  }
+}
+const float* mat32(const hdg_ctx* c, int kind) {
+  const int npf = c->np * c->np;
+  switch (kind) {
+    case HDG_TO_EIGEN_UNKNOWN: return c->d_mats32 + npf;
+    case HDG_TO_EIGEN_RESIDUAL: return c->d_mats32;
+    case HDG_TO_NODAL_UNKNOWN: return c->d_mats32 + 2 * npf;
+    default: return c->d_mats32 + 3 * npf;
+  }
+
 }  // namespace hdg
 
 namespace {
@@ -439,25 +460,6 @@ hdg_status eigen_boundary(hdg_ctx* c, const double* trace, const double** out) {
   return HDG_OK;
 }
 
-const double* mat64(const hdg_ctx* c, int kind) {
-  // storage order: St, StM, S, MS, then S o S (entrywise square, used for the
-  // diagonal of the nodal block preconditioner)
-  const int npf = c->np * c->np;
-  switch (kind) {
-    case HDG_TO_EIGEN_UNKNOWN: return c->d_mats64 + npf;      // S^T M
-    case HDG_TO_EIGEN_RESIDUAL: return c->d_mats64;           // S^T
-    case HDG_TO_NODAL_UNKNOWN: return c->d_mats64 + 2 * npf;  // S
-    default: return c->d_mats64 + 3 * npf;                    // M S
-  }
-}
-const float* mat32(const hdg_ctx* c, int kind) {
-  const int npf = c->np * c->np;
-  switch (kind) {
-    case HDG_TO_EIGEN_UNKNOWN: return c->d_mats32 + npf;
-    case HDG_TO_EIGEN_RESIDUAL: return c->d_mats32;
-    case HDG_TO_NODAL_UNKNOWN: return c->d_mats32 + 2 * npf;
-    default: return c->d_mats32 + 3 * npf;
-  }
 }
 
 // Nodal-basis CG of the paper's solver comparison (HDG-unprec, HDG-diag,

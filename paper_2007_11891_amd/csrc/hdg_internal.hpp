@@ -221,6 +221,10 @@ hipError_t launch_volume(const hdg_ctx* c, int mode, int src_is_forcing,
                          double* qa, double* qb, double* out_vol, double* out_elem,
                          hipStream_t s);
 
+// the context's per-face 1D transform matrices by hdg_transform kind
+const double* mat64(const hdg_ctx* c, int kind);
+const float* mat32(const hdg_ctx* c, int kind);
+
 // misc vector kernels
 hipError_t launch_cast_scale_64_32(const double* in, float* out, double scale, int64_t n,
                                    hipStream_t s);

@@ -27,7 +27,8 @@ TO_EIGEN_UNKNOWN, TO_EIGEN_RESIDUAL, TO_NODAL_UNKNOWN, TO_NODAL_RESIDUAL = 0, 1,
 # every symbol include/hdg.h declares
 EXPORTS = (
     "hdg_default_opts", "hdg_create", "hdg_create_ex", "hdg_destroy", "hdg_last_error",
-    "hdg_sizes", "hdg_layout", "hdg_set_lambda", "hdg_tables", "hdg_coords", "hdg_apply", "hdg_face_transform",
+    "hdg_sizes", "hdg_layout", "hdg_set_lambda", "hdg_tables", "hdg_coords", "hdg_apply", "hdg_apply_noalloc",
+    "hdg_face_transform",
     "hdg_rhs", "hdg_solve", "hdg_solve_forcing", "hdg_reconstruct", "hdg_hybridize",
     "hdg_adjoint",
     "hdg_diagonal", "hdg_time_kernel", "hdg_set_tile", "hdg_set_cg_segment", "hdg_autotune",
@@ -97,6 +98,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hdg_tables": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp, dp, dp]),
         "hdg_coords": (ctypes.c_int, [vp, vp, vp]),
         "hdg_apply": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, ctypes.c_int]),
+        "hdg_apply_noalloc": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, ctypes.c_int]),
         "hdg_face_transform": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int64]),
         "hdg_rhs": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int]),
         "hdg_solve": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(SolveOpts),
@@ -300,6 +302,19 @@ class HdgContext:
     def set_lambda(self, lam):
         torch = _torch()
         _check(self._lib.hdg_set_lambda(self._h, _dptr(lam, self.n_elem, torch.float64, "lambda")))
+
+    def apply_noalloc(self, x, y, basis: str = "eigen"):
+        """hdg_apply_noalloc: the apply with its scratch in the library's
+        static device array (y must be given: nothing is allocated)."""
+        torch = _torch()
+        dt = x.dtype
+        if dt not in (torch.float64, torch.float32):
+            raise TypeError("x must be float64 or float32")
+        n = self.sizes.n_free
+        _check(self._lib.hdg_apply_noalloc(self._h, _dptr(x, n, dt, "x"), _dptr(y, n, dt, "y"),
+                                           F64 if dt == torch.float64 else F32,
+                                           EIGEN if basis == "eigen" else NODAL))
+        return y
 
     def apply(self, x, y=None, basis: str = "eigen"):
         torch = _torch()
