@@ -154,10 +154,12 @@ IMPL_CG_BYTES = {"one kernel": 104, "two kernels": 104,
 # committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries, one per workload
 TRAFFIC_PROFILES = {
     "perturbed16_p7": os.path.join(ROOT, "profiles", "cg_iteration_perturbed16_p7_hbm_counters.md"),
+    "uniform32_p8": os.path.join(ROOT, "profiles", "cg_iteration_uniform32_p8_hbm_counters.md"),
     "uniform32_p12": os.path.join(ROOT, "profiles", "cg_iteration_uniform32_p12_hbm_counters.md"),
 }
 KERNEL_SOURCES = ("paper_2007_11891_amd/csrc/elem_unit.hpp", "paper_2007_11891_amd/csrc/elem_kernels.hip",
-                  "paper_2007_11891_amd/csrc/vec_kernels.hip",
+                  "paper_2007_11891_amd/csrc/vec_kernels.hip", "paper_2007_11891_amd/csrc/pencil_cg.hip",
+                  "paper_2007_11891_amd/csrc/cg_state.hpp",
                   "paper_2007_11891_amd/csrc/device_common.hpp")
 
 
@@ -668,10 +670,13 @@ def main():
         nf = ctx.sizes.n_free
         x64 = torch.as_tensor(W.random_trace(nf, 1), device=dev)
         y64 = torch.empty_like(x64)
+        chosen = {0: pkg.TIME_CG1_ITER_F64, 1: pkg.TIME_CG2_ITER_F64,
+                  2: pkg.TIME_PENCIL_ITER_F64}[tile["cg_variant"]]
         for which, name in ((pkg.TIME_APPLY_F64, "apply64"), (pkg.TIME_CG2_APPLY_F64, "cg_apply64"),
                             (pkg.TIME_CG2_UPDATE_F64, "cg_update64"),
                             (pkg.TIME_CG1_ITER_F64, "cg_onekernel64"),
-                            (pkg.TIME_PENCIL_ITER_F64, "cg_pencil64"), (pkg.TIME_COPY_F64, "copy64")):
+                            (pkg.TIME_PENCIL_ITER_F64, "cg_pencil64"), (pkg.TIME_COPY_F64, "copy64"),
+                            (chosen, "chosen CG form, again")):
             ms = ctx.time_kernel(which, x64, args.reps,
                                  y=y64 if which in (pkg.TIME_COPY_F64, pkg.TIME_APPLY_F64) else None)
             log(f"[bench] {name} {ms * 1e3:.3f} us")

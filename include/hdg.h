@@ -463,8 +463,12 @@ hdg_status hdg_batch_tiles(const hdg_batch* batch, int* variants);
  * (element pass with the fused p update, then a vector update), two grid
  * barriers; 1 one element pass per iteration with the Chronopoulos-Gear
  * recurrences of the single-problem one-kernel CG (the same PCG iterates in
- * exact arithmetic), one barrier.  set_form synchronises the stream and drops
- * the graph; hdg_batch_form reports the current form. */
+ * exact arithmetic), one barrier; 2 two phases on the pencil march of the
+ * single-problem pencil form (whole columns along x3 per work item, the
+ * faces between consecutive elements of a column summed in registers, x
+ * updated in the element pass), two barriers.  set_form synchronises the
+ * stream, drops the graph and rebuilds the work schedule when switching to
+ * or from form 2; hdg_batch_form reports the current form. */
 hdg_status hdg_batch_set_form(hdg_batch* batch, int form);
 hdg_status hdg_batch_form(const hdg_batch* batch, int* form);
 

@@ -40,6 +40,9 @@ struct BatchProbDev {
   int maxit;
   int pad;
   double rtol2;
+  // pencil form: the problem's free x3 faces as a DOF range of its trace
+  // (relative to off); their contributions arrive summed in qa alone
+  int x3_lo, x3_hi;
 };
 
 struct BatchState {
@@ -89,7 +92,8 @@ struct BatchArgs {
   // iteration): second slots of z and of A z (qa, qb), the two slots of
   // s = D^-1 A p, and the per-segment partials of z.Az, r.z, r.r of both
   // parities: pcg[(slot * 3 + j) * max_segs + segment]
-  int form;                 // 0 two phases (apply, update), 1 one phase
+  int form;                 // 0 two phases (apply, update), 1 one phase, 2 two phases on
+                            // the pencil march (x updated in the apply phase)
   int max_segs;
   double* z1;
   double* s0;
@@ -97,9 +101,11 @@ struct BatchArgs {
   double* qa1;
   double* qb1;
   double* pcg;
+  const MeshDev* meshes;    // pencil form: per-problem mesh records
 };
 
-hipError_t batch_occupancy(int* blocks_per_cu);
+// co-resident blocks per CU of the persistent kernel of a form
+hipError_t batch_occupancy(int form, int* blocks_per_cu);
 hipError_t launch_batch_reset(BatchState* A, BatchState* B, GridBar* bar, unsigned* flags,
                               int n_probs, int nblocks, hipStream_t s);
 hipError_t launch_batch_cg(const BatchArgs& args, int nblocks, hipStream_t s);

@@ -50,10 +50,12 @@ struct hdg_batch {
   double* d_qb1 = nullptr;
   double* d_pcg = nullptr;          // [2 * 3 * max_segs]
   // schedule
-  int nblocks = 0;
-  int max_segs = 0;                 // bound on segments per phase: count + nblocks
+  int nblocks = 0;                  // persistent grid of the current form
+  int nblocks_form[3] = {0, 0, 0};  // co-resident grid of each form
+  int max_segs = 0;                 // bound on segments per phase: count + largest grid + 1
   std::vector<BatchProbDev> probs;
   BatchProbDev* d_probs = nullptr;
+  MeshDev* d_meshes = nullptr;      // per-problem mesh records (pencil form)
   BatchSeg* d_useg = nullptr;       // [max_segs]
   BatchSeg* d_vseg = nullptr;       // [max_segs]
   int* d_useg_range = nullptr;      // [nblocks + 1]
@@ -96,28 +98,36 @@ double unit_cost(int np) { return 8.0 + np; }
 // problem's segments are consecutive in both lists.
 hdg_status build_schedule(hdg_batch* b) {
   const int nb = b->nblocks;
+  // apply work items of each problem: element work units (forms 0, 1) or
+  // whole columns along x3 of EPB slots (pencil form), with their cost
   std::vector<int64_t> ubeg(b->count + 1, 0);
+  std::vector<double> ucost(b->count, 0.0);
   for (int i = 0; i < b->count; ++i) {
     const hdg_ctx* c = b->sub[i];
     BatchProbDev& P = b->probs[i];
     P.variant = b->variant[c->p];
     const int epb = tile_epb(c->np, P.variant);
-    ubeg[i + 1] = ubeg[i] + (c->n_elem + epb - 1) / epb;
+    if (b->form == 2) {
+      ubeg[i + 1] = ubeg[i] + (int64_t)((c->n[0] + epb - 1) / epb) * c->n[1];
+      ucost[i] = c->n[2] * unit_cost(c->np);
+    } else {
+      ubeg[i + 1] = ubeg[i] + (c->n_elem + epb - 1) / epb;
+      ucost[i] = unit_cost(c->np);
+    }
   }
-  // apply segments: unit u goes to the block holding the midpoint of its
-  // cost interval; ucut[k] is the first unit of block k
+  // apply segments: item u goes to the block holding the midpoint of its
+  // cost interval; ucut[k] is the first item of block k
   const int64_t U = ubeg[b->count];
   std::vector<int64_t> ucut(nb + 1, U);
   {
     double total = 0.0;
-    for (int i = 0; i < b->count; ++i)
-      total += (double)(ubeg[i + 1] - ubeg[i]) * unit_cost(b->sub[i]->np);
+    for (int i = 0; i < b->count; ++i) total += (double)(ubeg[i + 1] - ubeg[i]) * ucost[i];
     const double per = total > 0.0 ? total / nb : 1.0;
     double acc = 0.0;
     int next = 1;
     ucut[0] = 0;
     for (int i = 0; i < b->count; ++i) {
-      const double w = unit_cost(b->sub[i]->np);
+      const double w = ucost[i];
       for (int64_t u = ubeg[i]; u < ubeg[i + 1]; ++u) {
         const int blk = std::min(nb - 1, (int)((acc + 0.5 * w) / per));
         while (next <= blk) ucut[next++] = u;
@@ -235,6 +245,7 @@ BatchArgs make_args(const hdg_batch* b, int max_iters) {
   a.bar = b->d_bar;
   a.flags = b->d_flags;
   a.tabs = b->d_tabs;
+  a.meshes = b->d_meshes;
   return a;
 }
 
@@ -353,6 +364,7 @@ hdg_status hdg_batch_destroy(hdg_batch* b) {
                      &b->d_qa1, &b->d_qb1, &b->d_pcg})
     dfree(*p);
   dfree(b->d_probs);
+  dfree(b->d_meshes);
   dfree(b->d_useg);
   dfree(b->d_vseg);
   dfree(b->d_useg_range);
@@ -428,25 +440,31 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
                                     hipMemcpyDeviceToDevice, b->stream) != hipSuccess)
       return cleanup(fail(HDG_EHIP, "diagonal copy failed"));
   }
-  // persistent grid: every block resident (cooperative launch)
-  int per_cu = 0, n_cu = 0;
-  if (batch_occupancy(&per_cu) != hipSuccess || per_cu < 1)
-    return cleanup(fail(HDG_EHIP, "occupancy query of the persistent kernel failed"));
+  // persistent grid of each form: every block resident (cooperative launch)
+  int n_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
     return cleanup(fail(HDG_EHIP, "device attribute query failed"));
-  b->nblocks = std::min(per_cu, 4) * n_cu;
+  int nb_max = 0;
+  for (int form = 0; form < 3; ++form) {
+    int per_cu = 0;
+    if (batch_occupancy(form, &per_cu) != hipSuccess || per_cu < 1)
+      return cleanup(fail(HDG_EHIP, "occupancy query of the persistent kernel failed"));
+    b->nblocks_form[form] = std::min(per_cu, 4) * n_cu;
+    nb_max = std::max(nb_max, b->nblocks_form[form]);
+  }
+  b->nblocks = b->nblocks_form[0];
   // each block range splits into at most one more segment than problems it touches
-  b->max_segs = count + b->nblocks + 1;
+  b->max_segs = count + nb_max + 1;
   const int ms = b->max_segs;
   if ((st = dalloc(&b->d_probs, count)) != HDG_OK || (st = dalloc(&b->d_useg, ms)) != HDG_OK ||
       (st = dalloc(&b->d_vseg, ms)) != HDG_OK ||
-      (st = dalloc(&b->d_useg_range, b->nblocks + 1)) != HDG_OK ||
-      (st = dalloc(&b->d_vseg_range, b->nblocks + 1)) != HDG_OK ||
+      (st = dalloc(&b->d_useg_range, nb_max + 1)) != HDG_OK ||
+      (st = dalloc(&b->d_vseg_range, nb_max + 1)) != HDG_OK ||
       (st = dalloc(&b->d_ppq, ms)) != HDG_OK || (st = dalloc(&b->d_prz, ms)) != HDG_OK ||
       (st = dalloc(&b->d_prr, ms)) != HDG_OK || (st = dalloc(&b->d_pcg, 6 * ms)) != HDG_OK ||
       (st = dalloc(&b->d_A, count)) != HDG_OK ||
       (st = dalloc(&b->d_B, count)) != HDG_OK || (st = dalloc(&b->d_bar, 1)) != HDG_OK ||
-      (st = dalloc(&b->d_flags, 2 * (int64_t)b->nblocks * kFlagStride)) != HDG_OK)
+      (st = dalloc(&b->d_flags, 2 * (int64_t)nb_max * kFlagStride)) != HDG_OK)
     return cleanup(st);
   if (hipHostMalloc(reinterpret_cast<void**>(&b->h_A), sizeof(BatchState) * count,
                     hipHostMallocDefault) != hipSuccess ||
@@ -466,6 +484,11 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
     P.np = c->np;
     P.off = b->off[i];
     P.n = c->n_free;
+    // the free faces normal to x3 (all interior: batched problems are
+    // Dirichlet on every side), as a DOF range of the problem's trace
+    const int64_t npf = (int64_t)c->np * c->np;
+    P.x3_lo = (int)(c->mesh.foff[2] * npf);
+    P.x3_hi = (int)((c->mesh.foff[2] + (int64_t)c->n[0] * c->n[1] * (c->n[2] - 1)) * npf);
     // per-degree tables (one tau_hat for the whole batch)
     const int o = batch_tab_off(c->np);
     for (int k = 0; k < c->np; ++k) {
@@ -474,6 +497,14 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
       b->tabs[o + 2 * c->np + k] = c->et64.lam[k];
     }
     b->tabs[o + 3 * c->np] = c->et64.H;
+  }
+  {
+    std::vector<MeshDev> meshes(count);
+    for (int i = 0; i < count; ++i) meshes[i] = b->sub[i]->mesh;
+    if ((st = dalloc(&b->d_meshes, count)) != HDG_OK) return cleanup(st);
+    if (hipMemcpy(b->d_meshes, meshes.data(), sizeof(MeshDev) * count, hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return cleanup(fail(HDG_EHIP, "mesh record upload failed"));
   }
   if ((st = dalloc(&b->d_tabs, kBatchTabWords)) != HDG_OK) return cleanup(st);
   if (hipMemcpy(b->d_tabs, b->tabs.data(), sizeof(double) * kBatchTabWords,
@@ -515,11 +546,15 @@ hdg_status hdg_batch_set_tile(hdg_batch* b, int p, int variant) {
 
 hdg_status hdg_batch_set_form(hdg_batch* b, int form) {
   if (!b) return fail(HDG_EINVAL, "batch is NULL");
-  if (form != 0 && form != 1) return fail(HDG_EINVAL, "form must be 0 or 1, got %d", form);
+  if (form < 0 || form > 2) return fail(HDG_EINVAL, "form must be 0, 1 or 2, got %d", form);
   HIP_TRY(hipStreamSynchronize(b->stream));
+  // a change of grid or of work item (columns instead of units) needs a new
+  // schedule
+  const bool resched = (form == 2) != (b->form == 2) || b->nblocks_form[form] != b->nblocks;
   b->form = form;
+  b->nblocks = b->nblocks_form[form];
   drop_graphs(b);
-  return HDG_OK;
+  return resched ? build_schedule(b) : HDG_OK;
 }
 
 hdg_status hdg_batch_form(const hdg_batch* b, int* form) {
@@ -589,7 +624,7 @@ hdg_status hdg_batch_autotune(hdg_batch* b, int iters, int reps, int* variants) 
   double best_all = 1e300;
   int best_form = 0;
   int best_var[kMaxNP + 1];
-  for (int form = 0; form <= 1; ++form) {
+  for (int form = 0; form <= 2; ++form) {
     ST_TRY(hdg_batch_set_form(b, form));
     ST_TRY(hdg_batch_set_tile(b, 0, 0));
     double best = 0.0;

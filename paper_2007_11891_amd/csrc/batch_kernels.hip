@@ -25,6 +25,7 @@
 // flag and every block returns, so the grid always drains.
 #include "batch.hpp"
 #include "elem_unit.hpp"
+#include "pencil_unit.hpp"
 
 namespace hdg {
 
@@ -40,6 +41,17 @@ constexpr int kBatchLdsWords =
          cmax(cmax(cmax(unit_lds_words<6>(), unit_lds_words<7>()), cmax(unit_lds_words<8>(), unit_lds_words<9>())),
               cmax(unit_lds_words<10>(), unit_lds_words<11>())));
 static_assert(kBatchLdsWords * 8 <= 40000, "batched LDS budget");
+template <int NP>
+__host__ __device__ constexpr int pencil_lds_words() {
+  return (int)((sizeof(PencilSmem<double, NP, epb_max<NP>()>) + 7) / 8);
+}
+constexpr int kBatchPencilLdsWords =
+    cmax(cmax(cmax(pencil_lds_words<2>(), pencil_lds_words<3>()),
+              cmax(pencil_lds_words<4>(), pencil_lds_words<5>())),
+         cmax(cmax(cmax(pencil_lds_words<6>(), pencil_lds_words<7>()),
+                   cmax(pencil_lds_words<8>(), pencil_lds_words<9>())),
+              cmax(pencil_lds_words<10>(), pencil_lds_words<11>())));
+static_assert(kBatchPencilLdsWords * 8 <= 40000, "batched pencil LDS budget");
 
 // Grid barrier.  Block i (> 0) publishes its arrival epoch in line i of
 // `arrive`; block 0 polls all arrival lines (its threads in parallel), then
@@ -209,6 +221,86 @@ __device__ inline double dispatch_units(int np, int variant, const UnitIO<double
     HDG_UCASE(2) HDG_UCASE(3) HDG_UCASE(4) HDG_UCASE(5) HDG_UCASE(6) HDG_UCASE(7)
     HDG_UCASE(8) HDG_UCASE(9) HDG_UCASE(10) HDG_UCASE(11)
 #undef HDG_UCASE
+    default: return 0.0;
+  }
+}
+
+// Pencil form: columns [pen0, pen1) of one problem (column pen = ig + n_ig j,
+// whole columns along x3) through the pencil march of pencil_unit.hpp at
+// degree NP - 1 and EPB slots; with final_x only the last x update of a
+// finished solve.  Tables from the batch table buffer into LDS (after a
+// barrier: the previous run, possibly of another degree, shares the LDS).
+template <int NP, int EPB>
+__device__ inline double run_pencils(const BatchArgs& a, const MeshDev& m, double* smem, int tid,
+                                     int64_t off, int it, int pen0, int pen1, double alpha,
+                                     double beta, bool final_x) {
+  constexpr int o = batch_tab_off(NP);
+  const double* tp = a.tabs;
+  asm volatile("" : "+s"(tp));
+  cdouble* ct = (cdouble*)tp;
+  auto& sm = *reinterpret_cast<PencilSmem<double, NP, EPB>*>(smem);
+  __syncthreads();
+  if (tid < NP) {
+    sm.bs[tid] = PencilPair<double>{ct[o + tid], ct[o + NP + tid]};
+    sm.lam[tid] = ct[o + 2 * NP + tid];
+  }
+  const double H = ct[o + 3 * NP];
+  const UnitLane Ln = unit_lane<NP, EPB>(tid);
+  const int n_ig = (m.n1 + EPB - 1) / EPB;
+  const double* __restrict__ z = a.z + off;
+  const double* __restrict__ pin = ((it & 1) ? a.p0 : a.p1) + off;   // p_{k-1}
+  double* __restrict__ pout = ((it & 1) ? a.p1 : a.p0) + off;        // p_k
+  double* __restrict__ x = a.x + off;
+  double* __restrict__ qa = a.qa + off;
+  double* __restrict__ qb = a.qb + off;
+  const int plane = m.n1 * m.n2;
+  double dot = 0.0;
+  for (int pen = pen0; pen < pen1; ++pen) {
+    const int ig = pen % n_ig, j = pen / n_ig;
+    const int i = ig * EPB + Ln.slot;
+    const bool act = Ln.slot < EPB && i < m.n1 && Ln.colok;
+    const int ic = min(i, m.n1 - 1);
+    PencilRow row;
+    pencil_row(m, ic, j, row);
+    if (final_x) {
+      pencil_final_x<double, NP>(m, row, act, Ln.col, 0, m.n3, alpha, pin, x);
+      continue;
+    }
+    const int rowe = m.n1 * j + ic;
+    PencilLoads<double> L;
+    pencil_load<double, NP>(m, z, pin, x, row, 0, act, Ln.col, rowe, true, L);
+    double carry_p = 0, carry_w = 0;
+    for (int k = 0; k < m.n3; ++k) {
+      const int kn = min(k + 1, m.n3 - 1);
+      pencil_step<double, NP, EPB>(z, pin, pout, x, qa, qb, sm, Ln, act, m, row, k, kn,
+                                   rowe + plane * kn, L, k == 0, k + 1 == m.n3, alpha, beta, H, H,
+                                   0.0, carry_p, carry_w, &dot);
+    }
+  }
+  return dot;
+}
+
+__device__ inline double dispatch_pencils(int np, int variant, const BatchArgs& a,
+                                          const MeshDev& m, double* smem, int64_t off, int it,
+                                          int pen0, int pen1, double alpha, double beta,
+                                          bool final_x) {
+  // the thread index through an empty asm (see run_units)
+  int tid = (int)threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  switch (np * 4 + variant) {
+#define HDG_PCASE(N)                                                                           \
+  case N * 4 + 0:                                                                              \
+    return run_pencils<N, epb_var<N, 0>()>(a, m, smem, tid, off, it, pen0, pen1, alpha, beta,  \
+                                           final_x);                                           \
+  case N * 4 + 1:                                                                              \
+    return run_pencils<N, epb_var<N, 1>()>(a, m, smem, tid, off, it, pen0, pen1, alpha, beta,  \
+                                           final_x);                                           \
+  case N * 4 + 2:                                                                              \
+    return run_pencils<N, epb_var<N, 2>()>(a, m, smem, tid, off, it, pen0, pen1, alpha, beta,  \
+                                           final_x);
+    HDG_PCASE(2) HDG_PCASE(3) HDG_PCASE(4) HDG_PCASE(5) HDG_PCASE(6) HDG_PCASE(7)
+    HDG_PCASE(8) HDG_PCASE(9) HDG_PCASE(10) HDG_PCASE(11)
+#undef HDG_PCASE
     default: return 0.0;
   }
 }
@@ -505,6 +597,157 @@ __global__ void __launch_bounds__(kBT, 3) batch_cgcg_kernel(BatchArgs a) {
   }
 }
 
+// Two-phase form on the pencil march (form 2): the apply phase walks the
+// block's column segments (a problem and a range of its whole columns along
+// x3), forms beta and the convergence decision per problem as the two-phase
+// form does, updates p and x (x += alpha_{k-1} p_{k-1}) on the faces its
+// columns own and applies the operator, the x3 faces of a column summed in
+// registers; the update phase forms alpha and z -= alpha D^-1 w with w = qa +
+// qb, except on a problem's free x3 faces, whose qa holds the sum.  A problem
+// that finishes gets its last x update in the apply phase that detects it.
+// Two blocks per CU: the pencil paths of all degrees in one kernel need more
+// than the 168 registers of three blocks per CU (they spilled there).
+__global__ void __launch_bounds__(kBT, 3) batch_pencil_kernel(BatchArgs a) {
+  __shared__ double smem[kBatchPencilLdsWords];
+  __shared__ double s_red[kBT / 64];
+  const int bid = blockIdx.x;
+  unsigned epoch = 0;
+
+  // ---- init: z = D^-1 b, x = 0, p_{-1} = 0, partials of iteration 0 -------
+  for (int s = a.vseg_range[bid]; s < a.vseg_range[bid + 1]; ++s) {
+    const BatchSeg sg = a.vseg[s];
+    const int64_t off = a.probs[sg.prob].off;
+    double rz = 0.0, rr = 0.0;
+    for (int64_t g = off + sg.begin + threadIdx.x; g < off + sg.end; g += kBT) {
+      const double v = a.b[g];
+      const double zv = a.dinv[g] * v;
+      a.z[g] = zv;
+      a.x[g] = 0.0;
+      a.p1[g] = 0.0;
+      rz += v * zv;
+      rr += v * v;
+    }
+    const double brz = block_sum<kBT>(rz, s_red);
+    const double brr = block_sum<kBT>(rr, s_red);
+    if (threadIdx.x == 0) {
+      a.prz[s] = brz;
+      a.prr[s] = brr;
+    }
+  }
+  if (!grid_sync(a, ++epoch)) return;
+
+  for (int it = 0; it < a.max_iters; ++it) {
+    // ------------------------------ apply -----------------------------------
+    for (int s = a.useg_range[bid]; s < a.useg_range[bid + 1]; ++s) {
+      const BatchSeg sg = a.useg[s];
+      const int pb = uni_int(sg.prob);
+      const BatchProbDev* P = a.probs + pb;
+      if (a.A[pb].done != 0) continue;
+      const double rho_prev = a.A[pb].rho;
+      const double alpha = uni_f64(a.A[pb].alpha);   // alpha_{k-1}, 0 before the first update
+      double rr_stop = a.A[pb].rr_stop;
+      double rho, rr;
+      sum_partials2<kBT>(a.prz + P->vseg_begin, a.prr + P->vseg_begin, P->n_vsegs, s_red, &rho,
+                         &rr);
+      if (it == 0) rr_stop = P->rtol2 * rr;
+      const double bb = (it == 0) ? 0.0 : rho / rho_prev;
+      int done = 0;
+      if (!isfinite(rr) || !isfinite(bb)) done = 3;
+      else if (rr <= rr_stop) done = 1;
+      else if (it >= P->maxit) done = 2;
+      if (s == P->useg_begin && threadIdx.x == 0) {
+        a.B[pb].rho = rho;
+        a.B[pb].rr = rr;
+        a.B[pb].rr_stop = rr_stop;
+        a.B[pb].iter = it;
+        a.B[pb].done = done;
+      }
+      const double dot = dispatch_pencils(uni_int(P->np), uni_int(P->variant), a, a.meshes[pb],
+                                          smem, P->off, it, sg.begin, sg.end, alpha,
+                                          uni_f64(bb), done != 0);
+      if (done) continue;                     // the last x update is in
+      const double bs = block_sum<kBT>(dot, s_red);
+      if (threadIdx.x == 0) a.ppq[s] = bs;
+    }
+    if (!grid_sync(a, ++epoch)) return;
+    // ------------------------------ update ----------------------------------
+    for (int s = a.vseg_range[bid]; s < a.vseg_range[bid + 1]; ++s) {
+      const BatchSeg sg = a.vseg[s];
+      const int pb = uni_int(sg.prob);
+      const BatchProbDev* P = a.probs + pb;
+      const int bdone = a.B[pb].done;
+      const bool owner = (s == P->vseg_begin) && threadIdx.x == 0;
+      if (bdone == 0 && a.A[pb].done != 0) continue;   // broke down in an earlier update
+      if (bdone) {
+        if (owner && a.A[pb].done == 0) {               // finished in this iteration's apply
+          a.A[pb].done = bdone;
+          a.A[pb].iter = a.B[pb].iter;
+          a.A[pb].rr = a.B[pb].rr;
+          a.A[pb].rr_stop = a.B[pb].rr_stop;
+          atomicAdd(&a.bar->done_count, 1u);
+        }
+        continue;
+      }
+      const double pq = sum_partials<kBT>(a.ppq + P->useg_begin, P->n_usegs, 1, 0, s_red);
+      const double rho = a.B[pb].rho;
+      const double alpha = rho / pq;
+      if (!(pq > 0.0) || !isfinite(alpha)) {
+        if (owner) {
+          a.A[pb].done = 3;
+          a.A[pb].iter = it;
+          atomicAdd(&a.bar->done_count, 1u);
+        }
+        continue;
+      }
+      if (owner) {
+        a.A[pb].rho = rho;
+        a.A[pb].alpha = alpha;
+        a.A[pb].rr_stop = a.B[pb].rr_stop;
+        a.A[pb].rr = a.B[pb].rr;
+        a.A[pb].iter = it + 1;
+      }
+      const int64_t off = P->off;
+      const int x3_lo = P->x3_lo, x3_hi = P->x3_hi;
+      double rz = 0.0, rr = 0.0;
+      // eight entries per thread with all their loads in flight together
+      // (entries past the segment read its first entry and are dropped)
+      constexpr int U = 8;
+      for (int r0 = sg.begin + (int)threadIdx.x; r0 < sg.end; r0 += U * kBT) {
+        double d[U], w[U], zv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int r = r0 + u * kBT;
+          const int64_t g = off + (r < sg.end ? r : sg.begin);
+          d[u] = a.dinv[g];
+          zv[u] = a.z[g];
+          w[u] = a.qa[g];
+          if (r < x3_lo || r >= x3_hi) w[u] += a.qb[g];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int r = r0 + u * kBT;
+          if (r >= sg.end) continue;
+          const double zn = zv[u] - alpha * (d[u] * w[u]);
+          a.z[off + r] = zn;
+          const double rn = div_fast(zn, d[u]);
+          rz += zn * rn;
+          rr += rn * rn;
+        }
+      }
+      const double brz = block_sum<kBT>(rz, s_red);
+      const double brr = block_sum<kBT>(rr, s_red);
+      if (threadIdx.x == 0) {
+        a.prz[s] = brz;
+        a.prr[s] = brr;
+      }
+    }
+    if (!grid_sync(a, ++epoch)) return;
+    if (__hip_atomic_load(&a.bar->done_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+        (unsigned)a.n_probs)
+      break;
+  }
+}
+
 // State reset before every batched solve (a kernel, so that it can sit in the
 // captured graph next to the solver).
 __global__ void batch_reset_kernel(BatchState* A, BatchState* B, GridBar* bar, unsigned* flags,
@@ -527,13 +770,12 @@ __global__ void batch_reset_kernel(BatchState* A, BatchState* B, GridBar* bar, u
   }
 }
 
-hipError_t batch_occupancy(int* blocks_per_cu) {
-  // the grid must be co-resident for both forms
-  int a = 0, b = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, batch_cg_kernel, kBT, 0);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, batch_cgcg_kernel, kBT, 0);
-  *blocks_per_cu = a < b ? a : b;
-  return e;
+hipError_t batch_occupancy(int form, int* blocks_per_cu) {
+  // the grid must be co-resident
+  const void* fn = form == 1   ? reinterpret_cast<const void*>(batch_cgcg_kernel)
+                   : form == 2 ? reinterpret_cast<const void*>(batch_pencil_kernel)
+                               : reinterpret_cast<const void*>(batch_cg_kernel);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kBT, 0);
 }
 
 hipError_t launch_batch_reset(BatchState* A, BatchState* B, GridBar* bar, unsigned* flags,
@@ -549,8 +791,9 @@ hipError_t launch_batch_cg(const BatchArgs& args, int nblocks, hipStream_t s) {
   if (nblocks < 1 || nblocks > kBT * kMaxBlocksPerThread) return hipErrorInvalidValue;
   BatchArgs a = args;
   void* params[] = {&a};
-  const void* fn = a.form == 1 ? reinterpret_cast<const void*>(batch_cgcg_kernel)
-                               : reinterpret_cast<const void*>(batch_cg_kernel);
+  const void* fn = a.form == 1   ? reinterpret_cast<const void*>(batch_cgcg_kernel)
+                  : a.form == 2 ? reinterpret_cast<const void*>(batch_pencil_kernel)
+                                : reinterpret_cast<const void*>(batch_cg_kernel);
   return hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kBT), params, 0, s);
 }
 
