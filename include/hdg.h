@@ -467,8 +467,9 @@ hdg_status hdg_batch_tiles(const hdg_batch* batch, int* variants);
  * single-problem pencil form (whole columns along x3 per work item, the
  * faces between consecutive elements of a column summed in registers, x
  * updated in the element pass), two barriers.  set_form synchronises the
- * stream, drops the graph and rebuilds the work schedule when switching to
- * or from form 2; hdg_batch_form reports the current form. */
+ * stream, drops the graph and rebuilds the work schedule (each form has its
+ * own grid, work item and cost model); hdg_batch_form reports the current
+ * form. */
 hdg_status hdg_batch_set_form(hdg_batch* batch, int form);
 hdg_status hdg_batch_form(const hdg_batch* batch, int* form);
 

@@ -84,10 +84,19 @@ struct hdg_batch {
 
 namespace {
 
-// Relative cost of one work unit in the apply phase: a unit keeps a whole
-// block busy for a time that grows with the column length n_p, whatever the
-// number of elements in it.
-double unit_cost(int np) { return 8.0 + np; }
+// Relative cost of one apply work item, from per-segment timings of the
+// persistent kernel at three blocks per CU on the 256-problem batch (p = 2..10):
+// an element work unit keeps its block busy for 5.5-6.3 us in the two-phase
+// form and 11-13 us in the one-phase form, almost whatever its degree (the
+// unit is bound by the latency of its dependent loads, not by its bytes); an
+// element of a pencil column row takes 5-7 us.
+double item_cost(int form, int np) {
+  switch (form) {
+    case 1: return 10.2 + 0.25 * np;
+    case 2: return 4.6 + 0.22 * np;
+    default: return 5.3 + 0.09 * np;
+  }
+}
 
 // Splits the problems' work into per-block segments.  Apply phase: the
 // global list of work units (problem-major) is cut into nb contiguous ranges
@@ -109,10 +118,10 @@ hdg_status build_schedule(hdg_batch* b) {
     const int epb = tile_epb(c->np, P.variant);
     if (b->form == 2) {
       ubeg[i + 1] = ubeg[i] + (int64_t)((c->n[0] + epb - 1) / epb) * c->n[1];
-      ucost[i] = c->n[2] * unit_cost(c->np);
+      ucost[i] = c->n[2] * item_cost(2, c->np);
     } else {
       ubeg[i + 1] = ubeg[i] + (c->n_elem + epb - 1) / epb;
-      ucost[i] = unit_cost(c->np);
+      ucost[i] = item_cost(b->form, c->np);
     }
   }
   // apply segments: item u goes to the block holding the midpoint of its
@@ -548,13 +557,11 @@ hdg_status hdg_batch_set_form(hdg_batch* b, int form) {
   if (!b) return fail(HDG_EINVAL, "batch is NULL");
   if (form < 0 || form > 2) return fail(HDG_EINVAL, "form must be 0, 1 or 2, got %d", form);
   HIP_TRY(hipStreamSynchronize(b->stream));
-  // a change of grid or of work item (columns instead of units) needs a new
-  // schedule
-  const bool resched = (form == 2) != (b->form == 2) || b->nblocks_form[form] != b->nblocks;
+  // every form has its own grid, work item and item cost: a new schedule
   b->form = form;
   b->nblocks = b->nblocks_form[form];
   drop_graphs(b);
-  return resched ? build_schedule(b) : HDG_OK;
+  return build_schedule(b);
 }
 
 hdg_status hdg_batch_form(const hdg_batch* b, int* form) {

@@ -1,23 +1,25 @@
 // Batched Jacobi-PCG for many independent condensed-HDG problems of uneven
 // sizes and degrees in one persistent launch.
 //
-// All problems iterate in lockstep phases separated by grid-wide barriers:
-//   apply  : every block walks its apply segments (a problem and a range of
-//            its element work units); per segment it re-sums the previous
-//            update's partials (r.z, r.r) of that problem in a fixed order,
-//            decides convergence, forms p = z + beta p_old on the units'
-//            faces (z = D^-1 r), applies the transformed operator (the same
+// Each CG iteration of a problem is one or two phases over its segments:
+//   apply  : element segments (a problem and a range of its element work
+//            units); per segment the previous update's partials (r.z, r.r)
+//            of that problem are re-summed in a fixed order, convergence is
+//            decided, p = z + beta p_old is formed on the units' faces
+//            (z = D^-1 r), the transformed operator is applied (the same
 //            `apply_unit` as the single-problem kernels, selected by degree
-//            and tile shape) and writes one p.q partial per segment;
-//   update : every block walks its vector segments (a problem and a range of
-//            its free trace); per segment it re-sums the problem's apply
-//            partials, forms alpha, updates z and x, and writes one r.z and
-//            one r.r partial per segment.
-// Converged problems drop out; the kernel returns when every problem is done.
-// Per-problem state lives in two slots (A: read by apply, written by update;
-// B: the reverse), written by the block that owns the problem's first
-// segment of the phase.  Every reduction is a fixed-order sum, identical in
-// every block, so the result does not depend on timing.
+//            and tile shape) and one p.q partial is written per segment;
+//   update : vector segments (a problem and a range of its free trace); per
+//            segment the problem's apply partials are re-summed, alpha is
+//            formed, z and x are updated and one r.z and one r.r partial
+//            are written per segment.
+// The one-phase form fuses both into one element pass per iteration, and the
+// pencil form marches element columns (see below).  Converged problems drop
+// out; the kernel returns when every problem is done.  Per-problem state
+// lives in two slots (A: read by apply, written by update; B: the reverse),
+// written by whichever block runs the problem's first segment of the phase.
+// Every reduction is a fixed-order sum over per-segment partials, so the
+// result depends neither on timing nor on which block ran which segment.
 //
 // Grid barrier: each block publishes an arrival epoch in its own cache line;
 // block 0 waits for all of them and then releases every block through its
@@ -305,160 +307,178 @@ __device__ inline double dispatch_pencils(int np, int variant, const BatchArgs& 
   }
 }
 
-__global__ void __launch_bounds__(kBT, 3) batch_cg_kernel(BatchArgs a) {
-  __shared__ double smem[kBatchLdsWords];
-  __shared__ double s_red[kBT / 64];
-  const int bid = blockIdx.x;
-  unsigned epoch = 0;
+// ---- the work of one segment in each phase ----------------------------------
+// Every function below handles one segment of one phase of CG iteration `it`.
 
-  // ---- init: z = D^-1 b, x = 0, p_{-1} = 0, partials of iteration 0 -------
-  for (int s = a.vseg_range[bid]; s < a.vseg_range[bid + 1]; ++s) {
-    const BatchSeg sg = a.vseg[s];
-    const int64_t off = a.probs[sg.prob].off;
-    double rz = 0.0, rr = 0.0;
-    for (int64_t g = off + sg.begin + threadIdx.x; g < off + sg.end; g += kBT) {
-      const double v = a.b[g];
-      const double zv = a.dinv[g] * v;
-      a.z[g] = zv;
-      a.x[g] = 0.0;
-      a.p1[g] = 0.0;
-      rz += v * zv;
-      rr += v * v;
+// Two-phase forms, start: z = D^-1 b, x = 0, p_{-1} = 0 on vector segment s,
+// and the segment's partials of r.z and r.r for iteration 0.
+__device__ __forceinline__ void init_seg_two_phase(const BatchArgs& a, int s, double* s_red) {
+  const BatchSeg sg = a.vseg[s];
+  const int64_t off = a.probs[sg.prob].off;
+  double rz = 0.0, rr = 0.0;
+  for (int64_t g = off + sg.begin + threadIdx.x; g < off + sg.end; g += kBT) {
+    const double v = a.b[g];
+    const double zv = a.dinv[g] * v;
+    a.z[g] = zv;
+    a.x[g] = 0.0;
+    a.p1[g] = 0.0;
+    rz += v * zv;
+    rr += v * v;
+  }
+  const double brz = block_sum<kBT>(rz, s_red);
+  const double brr = block_sum<kBT>(rr, s_red);
+  if (threadIdx.x == 0) {
+    a.prz[s] = brz;
+    a.prr[s] = brr;
+  }
+}
+
+// One-phase form, start: z_0 = D^-1 b in slot 0, x = 0, p_{-1} = s_{-1} = 0
+// (slot 1) on vector segment s.
+__device__ __forceinline__ void init_seg_one_phase(const BatchArgs& a, int s) {
+  const BatchSeg sg = a.vseg[s];
+  const int64_t off = a.probs[sg.prob].off;
+  for (int64_t g = off + sg.begin + threadIdx.x; g < off + sg.end; g += kBT) {
+    a.z[g] = a.dinv[g] * a.b[g];
+    a.x[g] = 0.0;
+    a.p1[g] = 0.0;
+    a.s1[g] = 0.0;
+  }
+}
+
+// Two-phase form, apply phase: re-sum the problem's r.z and r.r partials of
+// the previous update in a fixed order, decide convergence (the owner of the
+// problem's first segment records it in slot B), form p = z + beta p_old on
+// the segment's units and apply the operator; one p.q partial per segment.
+__device__ __forceinline__ void apply_seg(const BatchArgs& a, int s, int it, double* smem, double* s_red) {
+  const BatchSeg sg = a.useg[s];
+  const int pb = uni_int(sg.prob);
+  const BatchProbDev* P = a.probs + pb;
+  if (a.A[pb].done != 0) return;
+  const double rho_prev = a.A[pb].rho;
+  double rr_stop = a.A[pb].rr_stop;
+  double rho, rr;
+  sum_partials2<kBT>(a.prz + P->vseg_begin, a.prr + P->vseg_begin, P->n_vsegs, s_red, &rho, &rr);
+  if (it == 0) rr_stop = P->rtol2 * rr;
+  const double bb = (it == 0) ? 0.0 : rho / rho_prev;
+  int done = 0;
+  if (!isfinite(rr) || !isfinite(bb)) done = 3;
+  else if (rr <= rr_stop) done = 1;
+  else if (it >= P->maxit) done = 2;
+  if (s == P->useg_begin && threadIdx.x == 0) {
+    a.B[pb].rho = rho;
+    a.B[pb].rr = rr;
+    a.B[pb].rr_stop = rr_stop;
+    a.B[pb].iter = it;
+    a.B[pb].done = done;
+  }
+  if (done) return;                       // x is complete: nothing left to apply
+  const int64_t off = P->off;
+  UnitIO<double> io{};
+  io.info = uni_ptr(P->info);
+  io.lam = uni_ptr(P->lam);
+  io.n_elem = uni_int(P->n_elem);
+  io.nff = uni_int(P->nff);
+  io.qa = uni_ptr(a.qa + off);
+  io.qb = uni_ptr(a.qb + off);
+  io.z = uni_ptr(a.z + off);
+  io.p_in = uni_ptr(((it & 1) ? a.p0 : a.p1) + off);
+  io.p_out = uni_ptr(((it & 1) ? a.p1 : a.p0) + off);
+  io.beta = uni_f64(bb);
+  const double dot =
+      dispatch_units(uni_int(P->np), uni_int(P->variant), io, a.tabs, smem, sg.begin, sg.end);
+  const double bs = block_sum<kBT>(dot, s_red);
+  if (threadIdx.x == 0) a.ppq[s] = bs;
+}
+
+// Update-phase bookkeeping shared by the two-phase forms: decisions read slot
+// B (slot A is written in this phase).  Returns false when the segment has
+// nothing to update (problem finished or broken down), else true with alpha.
+__device__ __forceinline__ bool update_alpha(const BatchArgs& a, int s, int it, double* s_red,
+                                             double* alpha_out) {
+  const BatchSeg sg = a.vseg[s];
+  const int pb = uni_int(sg.prob);
+  const BatchProbDev* P = a.probs + pb;
+  const int bdone = a.B[pb].done;
+  const bool owner = (s == P->vseg_begin) && threadIdx.x == 0;
+  if (bdone == 0 && a.A[pb].done != 0) return false;   // broke down in an earlier update
+  if (bdone) {
+    if (owner && a.A[pb].done == 0) {                 // finished in this iteration's apply
+      a.A[pb].done = bdone;
+      a.A[pb].iter = a.B[pb].iter;
+      a.A[pb].rr = a.B[pb].rr;
+      a.A[pb].rr_stop = a.B[pb].rr_stop;
+      atomicAdd(&a.bar->done_count, 1u);
     }
-    const double brz = block_sum<kBT>(rz, s_red);
-    const double brr = block_sum<kBT>(rr, s_red);
-    if (threadIdx.x == 0) {
-      a.prz[s] = brz;
-      a.prr[s] = brr;
+    return false;
+  }
+  const double pq = sum_partials<kBT>(a.ppq + P->useg_begin, P->n_usegs, 1, 0, s_red);
+  const double rho = a.B[pb].rho;
+  const double alpha = rho / pq;
+  if (!(pq > 0.0) || !isfinite(alpha)) {
+    if (owner) {
+      a.A[pb].done = 3;
+      a.A[pb].iter = it;
+      atomicAdd(&a.bar->done_count, 1u);
+    }
+    return false;
+  }
+  if (owner) {
+    a.A[pb].rho = rho;
+    a.A[pb].alpha = alpha;
+    a.A[pb].rr_stop = a.B[pb].rr_stop;
+    a.A[pb].rr = a.B[pb].rr;
+    a.A[pb].iter = it + 1;
+  }
+  *alpha_out = alpha;
+  return true;
+}
+
+// Two-phase form, update phase: alpha from the problem's p.q partials, then
+// z -= alpha D^-1 (qa + qb), x += alpha p and the segment's r.z, r.r partials.
+__device__ __forceinline__ void update_seg(const BatchArgs& a, int s, int it, double* s_red) {
+  double alpha;
+  if (!update_alpha(a, s, it, s_red, &alpha)) return;
+  const BatchSeg sg = a.vseg[s];
+  const BatchProbDev* P = a.probs + uni_int(sg.prob);
+  const int64_t lo = P->off + sg.begin, hi = P->off + sg.end;
+  const double* __restrict__ pk = (it & 1) ? a.p1 : a.p0;   // p of this iteration
+  double rz = 0.0, rr = 0.0;
+  int64_t g = lo + threadIdx.x;
+  for (; g + 3 * kBT < hi; g += 4 * kBT) {
+    double zv[4], q[4], d[4], xv[4], pv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      zv[k] = a.z[g + k * kBT];
+      q[k] = a.qa[g + k * kBT] + a.qb[g + k * kBT];
+      d[k] = a.dinv[g + k * kBT];
+      xv[k] = a.x[g + k * kBT];
+      pv[k] = pk[g + k * kBT];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double zn = zv[k] - alpha * (d[k] * q[k]);
+      a.z[g + k * kBT] = zn;
+      a.x[g + k * kBT] = xv[k] + alpha * pv[k];
+      const double rn = div_fast(zn, d[k]);
+      rz += zn * rn;
+      rr += rn * rn;
     }
   }
-  if (!grid_sync(a, ++epoch)) return;
-
-  for (int it = 0; it < a.max_iters; ++it) {
-    // ------------------------------ apply -----------------------------------
-    for (int s = a.useg_range[bid]; s < a.useg_range[bid + 1]; ++s) {
-      const BatchSeg sg = a.useg[s];
-      const int pb = uni_int(sg.prob);
-      const BatchProbDev* P = a.probs + pb;
-      if (a.A[pb].done != 0) continue;
-      const double rho_prev = a.A[pb].rho;
-      double rr_stop = a.A[pb].rr_stop;
-      double rho, rr;
-      sum_partials2<kBT>(a.prz + P->vseg_begin, a.prr + P->vseg_begin, P->n_vsegs, s_red, &rho,
-                         &rr);
-      if (it == 0) rr_stop = P->rtol2 * rr;
-      const double bb = (it == 0) ? 0.0 : rho / rho_prev;
-      int done = 0;
-      if (!isfinite(rr) || !isfinite(bb)) done = 3;
-      else if (rr <= rr_stop) done = 1;
-      else if (it >= P->maxit) done = 2;
-      if (s == P->useg_begin && threadIdx.x == 0) {
-        a.B[pb].rho = rho;
-        a.B[pb].rr = rr;
-        a.B[pb].rr_stop = rr_stop;
-        a.B[pb].iter = it;
-        a.B[pb].done = done;
-      }
-      if (done) continue;                     // x is complete: nothing left to apply
-      const int64_t off = P->off;
-      UnitIO<double> io{};
-      io.info = uni_ptr(P->info);
-      io.lam = uni_ptr(P->lam);
-      io.n_elem = uni_int(P->n_elem);
-      io.nff = uni_int(P->nff);
-      io.qa = uni_ptr(a.qa + off);
-      io.qb = uni_ptr(a.qb + off);
-      io.z = uni_ptr(a.z + off);
-      io.p_in = uni_ptr(((it & 1) ? a.p0 : a.p1) + off);
-      io.p_out = uni_ptr(((it & 1) ? a.p1 : a.p0) + off);
-      io.beta = uni_f64(bb);
-      const double dot = dispatch_units(uni_int(P->np), uni_int(P->variant), io, a.tabs, smem,
-                                        sg.begin, sg.end);
-      const double bs = block_sum<kBT>(dot, s_red);
-      if (threadIdx.x == 0) a.ppq[s] = bs;
-    }
-    if (!grid_sync(a, ++epoch)) return;
-    // ------------------------------ update ----------------------------------
-    for (int s = a.vseg_range[bid]; s < a.vseg_range[bid + 1]; ++s) {
-      const BatchSeg sg = a.vseg[s];
-      const int pb = uni_int(sg.prob);
-      const BatchProbDev* P = a.probs + pb;
-      // decisions read slot B (slot A is written in this phase)
-      const int bdone = a.B[pb].done;
-      const bool owner = (s == P->vseg_begin) && threadIdx.x == 0;
-      if (bdone == 0 && a.A[pb].done != 0) continue;   // broke down in an earlier update
-      if (bdone) {
-        if (owner && a.A[pb].done == 0) {               // finished in this iteration's apply
-          a.A[pb].done = bdone;
-          a.A[pb].iter = a.B[pb].iter;
-          a.A[pb].rr = a.B[pb].rr;
-          a.A[pb].rr_stop = a.B[pb].rr_stop;
-          atomicAdd(&a.bar->done_count, 1u);
-        }
-        continue;
-      }
-      const double pq = sum_partials<kBT>(a.ppq + P->useg_begin, P->n_usegs, 1, 0, s_red);
-      const double rho = a.B[pb].rho;
-      const double alpha = rho / pq;
-      if (!(pq > 0.0) || !isfinite(alpha)) {
-        if (owner) {
-          a.A[pb].done = 3;
-          a.A[pb].iter = it;
-          atomicAdd(&a.bar->done_count, 1u);
-        }
-        continue;
-      }
-      if (owner) {
-        a.A[pb].rho = rho;
-        a.A[pb].alpha = alpha;
-        a.A[pb].rr_stop = a.B[pb].rr_stop;
-        a.A[pb].rr = a.B[pb].rr;
-        a.A[pb].iter = it + 1;
-      }
-      const int64_t lo = P->off + sg.begin, hi = P->off + sg.end;
-      const double* __restrict__ pk = (it & 1) ? a.p1 : a.p0;   // p of this iteration
-      double rz = 0.0, rr = 0.0;
-      int64_t g = lo + threadIdx.x;
-      for (; g + 3 * kBT < hi; g += 4 * kBT) {
-        double zv[4], q[4], d[4], xv[4], pv[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          zv[k] = a.z[g + k * kBT];
-          q[k] = a.qa[g + k * kBT] + a.qb[g + k * kBT];
-          d[k] = a.dinv[g + k * kBT];
-          xv[k] = a.x[g + k * kBT];
-          pv[k] = pk[g + k * kBT];
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const double zn = zv[k] - alpha * (d[k] * q[k]);
-          a.z[g + k * kBT] = zn;
-          a.x[g + k * kBT] = xv[k] + alpha * pv[k];
-          const double rn = div_fast(zn, d[k]);
-          rz += zn * rn;
-          rr += rn * rn;
-        }
-      }
-      for (; g < hi; g += kBT) {
-        const double d = a.dinv[g];
-        const double zn = a.z[g] - alpha * (d * (a.qa[g] + a.qb[g]));
-        a.z[g] = zn;
-        a.x[g] += alpha * pk[g];
-        const double rn = div_fast(zn, d);
-        rz += zn * rn;
-        rr += rn * rn;
-      }
-      const double brz = block_sum<kBT>(rz, s_red);
-      const double brr = block_sum<kBT>(rr, s_red);
-      if (threadIdx.x == 0) {
-        a.prz[s] = brz;
-        a.prr[s] = brr;
-      }
-    }
-    if (!grid_sync(a, ++epoch)) return;
-    if (__hip_atomic_load(&a.bar->done_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
-        (unsigned)a.n_probs)
-      break;
+  for (; g < hi; g += kBT) {
+    const double d = a.dinv[g];
+    const double zn = a.z[g] - alpha * (d * (a.qa[g] + a.qb[g]));
+    a.z[g] = zn;
+    a.x[g] += alpha * pk[g];
+    const double rn = div_fast(zn, d);
+    rz += zn * rn;
+    rr += rn * rn;
+  }
+  const double brz = block_sum<kBT>(rz, s_red);
+  const double brr = block_sum<kBT>(rr, s_red);
+  if (threadIdx.x == 0) {
+    a.prz[s] = brz;
+    a.prr[s] = brr;
   }
 }
 
@@ -468,284 +488,242 @@ __global__ void __launch_bounds__(kBT, 3) batch_cg_kernel(BatchArgs a) {
 // iterate k - 1, parity slot (k - 1) & 1) are re-summed in a fixed order,
 // convergence is decided and alpha_{k-1}, beta_{k-1} formed; then each unit
 // updates s, z and, on the faces it owns, p and x, and applies the operator
-// to the new z.  One grid barrier per iteration.  Slots alternate with the
-// parity rd = k & 1 exactly as the single-problem launches do; the state
-// slot read is A for even k, B for odd k.
-__global__ void __launch_bounds__(kBT, 3) batch_cgcg_kernel(BatchArgs a) {
-  __shared__ double smem[kBatchLdsWords];
-  __shared__ double s_red[kBT / 64];
-  // consecutive ranges on one XCD: neighbouring elements of a problem,
-  // whose shared faces both read, meet in the same L2
-  const int bid = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-  unsigned epoch = 0;
-
-  // ---- init: z_0 = D^-1 b in slot 0, x = 0, p_{-1} = s_{-1} = 0 (slot 1) ---
-  for (int s = a.vseg_range[bid]; s < a.vseg_range[bid + 1]; ++s) {
-    const BatchSeg sg = a.vseg[s];
-    const int64_t off = a.probs[sg.prob].off;
-    for (int64_t g = off + sg.begin + threadIdx.x; g < off + sg.end; g += kBT) {
-      a.z[g] = a.dinv[g] * a.b[g];
-      a.x[g] = 0.0;
-      a.p1[g] = 0.0;
-      a.s1[g] = 0.0;
-    }
+// to the new z.  Slots alternate with the parity rd = k & 1 exactly as the
+// single-problem launches do; the state slot read is A for even k, B for odd.
+__device__ __forceinline__ void pass_seg(const BatchArgs& a, int s, int it, double* smem, double* s_red) {
+  const int rd = it & 1;
+  double* const zs[2] = {a.z, a.z1};
+  double* const ps_[2] = {a.p0, a.p1};
+  double* const ss[2] = {a.s0, a.s1};
+  double* const qas[2] = {a.qa, a.qa1};
+  double* const qbs[2] = {a.qb, a.qb1};
+  const double* prev = a.pcg + (size_t)(rd ^ 1) * 3 * a.max_segs;
+  double* cur = a.pcg + (size_t)rd * 3 * a.max_segs;
+  const BatchSeg sg = a.useg[s];
+  const int pb = uni_int(sg.prob);
+  const BatchProbDev* P = a.probs + pb;
+  BatchState* R = rd ? a.B + pb : a.A + pb;
+  BatchState* W = rd ? a.A + pb : a.B + pb;
+  const bool owner = (s == P->useg_begin) && threadIdx.x == 0;
+  const int rdone = R->done;
+  if (rdone) {                              // finished earlier: keep both slots equal
+    if (owner && W->done == 0) *W = *R;
+    return;
   }
-  if (!grid_sync(a, ++epoch)) return;
-
-  int it = 0;
-  for (; it < a.max_iters; ++it) {
-    const int rd = it & 1;
-    double* const zs[2] = {a.z, a.z1};
-    double* const ps_[2] = {a.p0, a.p1};
-    double* const ss[2] = {a.s0, a.s1};
-    double* const qas[2] = {a.qa, a.qa1};
-    double* const qbs[2] = {a.qb, a.qb1};
-    const double* prev = a.pcg + (size_t)(rd ^ 1) * 3 * a.max_segs;
-    double* cur = a.pcg + (size_t)rd * 3 * a.max_segs;
-    for (int s = a.useg_range[bid]; s < a.useg_range[bid + 1]; ++s) {
-      const BatchSeg sg = a.useg[s];
-      const int pb = uni_int(sg.prob);
-      const BatchProbDev* P = a.probs + pb;
-      BatchState* R = rd ? a.B + pb : a.A + pb;
-      BatchState* W = rd ? a.A + pb : a.B + pb;
-      const bool owner = (s == P->useg_begin) && threadIdx.x == 0;
-      const int rdone = R->done;
-      if (rdone) {                            // finished earlier: keep both slots equal
-        if (owner && W->done == 0) *W = *R;
-        continue;
-      }
-      const int k = R->iter;
-      double alpha = 0.0, beta = 0.0;
-      if (k == 0) {
-        if (owner) {
-          W->iter = 1;
-          W->done = 0;
-        }
+  const int k = R->iter;
+  double alpha = 0.0, beta = 0.0;
+  if (k == 0) {
+    if (owner) {
+      W->iter = 1;
+      W->done = 0;
+    }
+  } else {
+    double del = 0.0, gam = 0.0, rr = 0.0;
+    sum_partials2<kBT>(prev + P->useg_begin, prev + a.max_segs + P->useg_begin, P->n_usegs, s_red,
+                       &del, &gam);
+    rr = sum_partials<kBT>(prev + 2 * a.max_segs + P->useg_begin, P->n_usegs, 1, 0, s_red);
+    const double rr_stop = (k == 1) ? P->rtol2 * rr : R->rr_stop;
+    int done = 0;
+    if (!isfinite(rr) || !isfinite(gam)) done = 3;
+    else if (rr <= rr_stop) done = 1;
+    else if (k - 1 >= P->maxit) done = 2;
+    else {
+      beta = (k == 1) ? 0.0 : gam / R->rho;
+      alpha = (k == 1) ? gam / del : gam / (del - beta * gam / R->alpha);
+      if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta)) done = 3;
+    }
+    if (owner) {
+      W->rr = rr;
+      W->rr_stop = rr_stop;
+      W->done = done;
+      if (done) {
+        W->iter = k - 1;                    // x_{k-1} is the result
+        atomicAdd(&a.bar->done_count, 1u);
       } else {
-        double del = 0.0, gam = 0.0, rr = 0.0;
-        sum_partials2<kBT>(prev + P->useg_begin, prev + a.max_segs + P->useg_begin, P->n_usegs,
-                           s_red, &del, &gam);
-        rr = sum_partials<kBT>(prev + 2 * a.max_segs + P->useg_begin, P->n_usegs, 1, 0, s_red);
-        const double rr_stop = (k == 1) ? P->rtol2 * rr : R->rr_stop;
-        int done = 0;
-        if (!isfinite(rr) || !isfinite(gam)) done = 3;
-        else if (rr <= rr_stop) done = 1;
-        else if (k - 1 >= P->maxit) done = 2;
-        else {
-          beta = (k == 1) ? 0.0 : gam / R->rho;
-          alpha = (k == 1) ? gam / del : gam / (del - beta * gam / R->alpha);
-          if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta)) done = 3;
-        }
-        if (owner) {
-          W->rr = rr;
-          W->rr_stop = rr_stop;
-          W->done = done;
-          if (done) {
-            W->iter = k - 1;                  // x_{k-1} is the result
-            atomicAdd(&a.bar->done_count, 1u);
-          } else {
-            W->rho = gam;
-            W->alpha = alpha;
-            W->iter = k + 1;
-          }
-        }
-        if (done) continue;
-      }
-      const int64_t off = P->off;
-      UnitIO<double> io{};
-      io.info = uni_ptr(P->info);
-      io.lam = uni_ptr(P->lam);
-      io.n_elem = uni_int(P->n_elem);
-      io.nff = uni_int(P->nff);
-      io.first = k == 0;
-      io.z_old = uni_ptr((k == 0 ? zs[rd] : zs[rd ^ 1]) + off);
-      io.z_new = uni_ptr(zs[rd] + off);
-      io.p_in = uni_ptr(ps_[rd] + off);
-      io.p_out = uni_ptr(ps_[rd ^ 1] + off);
-      io.s_old = uni_ptr(ss[rd] + off);
-      io.s_new = uni_ptr(ss[rd ^ 1] + off);
-      io.w_a = uni_ptr(qas[rd ^ 1] + off);
-      io.w_b = uni_ptr(qbs[rd ^ 1] + off);
-      io.qa = uni_ptr(qas[rd] + off);
-      io.qb = uni_ptr(qbs[rd] + off);
-      io.dinv = uni_ptr(a.dinv + off);
-      io.x = uni_ptr(a.x + off);
-      io.alpha = uni_f64(alpha);
-      io.beta = uni_f64(beta);
-      double acc[3] = {0.0, 0.0, 0.0};
-      dispatch_units_cgcg(uni_int(P->np), uni_int(P->variant), io, a.tabs, smem, sg.begin, sg.end,
-                          acc);
-      block_sums<kBT, 3>(acc);
-      if (threadIdx.x == 0) {
-        cur[s] = acc[0];
-        cur[a.max_segs + s] = acc[1];
-        cur[2 * a.max_segs + s] = acc[2];
+        W->rho = gam;
+        W->alpha = alpha;
+        W->iter = k + 1;
       }
     }
-    if (!grid_sync(a, ++epoch)) return;
-    if (__hip_atomic_load(&a.bar->done_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
-        (unsigned)a.n_probs)
-      break;
+    if (done) return;
   }
-  // the result slot: a problem decided in an odd pass wrote slot A, in an
-  // even pass slot B; the host reads A
-  for (int s = a.useg_range[bid]; s < a.useg_range[bid + 1]; ++s) {
-    const BatchSeg sg = a.useg[s];
-    const BatchProbDev* P = a.probs + sg.prob;
-    if (s == P->useg_begin && threadIdx.x == 0 && a.A[sg.prob].done == 0 && a.B[sg.prob].done != 0)
-      a.A[sg.prob] = a.B[sg.prob];
+  const int64_t off = P->off;
+  UnitIO<double> io{};
+  io.info = uni_ptr(P->info);
+  io.lam = uni_ptr(P->lam);
+  io.n_elem = uni_int(P->n_elem);
+  io.nff = uni_int(P->nff);
+  io.first = k == 0;
+  io.z_old = uni_ptr((k == 0 ? zs[rd] : zs[rd ^ 1]) + off);
+  io.z_new = uni_ptr(zs[rd] + off);
+  io.p_in = uni_ptr(ps_[rd] + off);
+  io.p_out = uni_ptr(ps_[rd ^ 1] + off);
+  io.s_old = uni_ptr(ss[rd] + off);
+  io.s_new = uni_ptr(ss[rd ^ 1] + off);
+  io.w_a = uni_ptr(qas[rd ^ 1] + off);
+  io.w_b = uni_ptr(qbs[rd ^ 1] + off);
+  io.qa = uni_ptr(qas[rd] + off);
+  io.qb = uni_ptr(qbs[rd] + off);
+  io.dinv = uni_ptr(a.dinv + off);
+  io.x = uni_ptr(a.x + off);
+  io.alpha = uni_f64(alpha);
+  io.beta = uni_f64(beta);
+  double acc[3] = {0.0, 0.0, 0.0};
+  dispatch_units_cgcg(uni_int(P->np), uni_int(P->variant), io, a.tabs, smem, sg.begin, sg.end,
+                      acc);
+  block_sums<kBT, 3>(acc);
+  if (threadIdx.x == 0) {
+    cur[s] = acc[0];
+    cur[a.max_segs + s] = acc[1];
+    cur[2 * a.max_segs + s] = acc[2];
   }
 }
 
-// Two-phase form on the pencil march (form 2): the apply phase walks the
-// block's column segments (a problem and a range of its whole columns along
-// x3), forms beta and the convergence decision per problem as the two-phase
-// form does, updates p and x (x += alpha_{k-1} p_{k-1}) on the faces its
-// columns own and applies the operator, the x3 faces of a column summed in
-// registers; the update phase forms alpha and z -= alpha D^-1 w with w = qa +
-// qb, except on a problem's free x3 faces, whose qa holds the sum.  A problem
-// that finishes gets its last x update in the apply phase that detects it.
-// Two blocks per CU: the pencil paths of all degrees in one kernel need more
-// than the 168 registers of three blocks per CU (they spilled there).
-__global__ void __launch_bounds__(kBT, 3) batch_pencil_kernel(BatchArgs a) {
-  __shared__ double smem[kBatchPencilLdsWords];
-  __shared__ double s_red[kBT / 64];
-  const int bid = blockIdx.x;
-  unsigned epoch = 0;
+// One-phase form, after the last pass: a problem decided in an odd pass wrote
+// slot A, in an even pass slot B; the host reads A.
+__device__ __forceinline__ void pass_result(const BatchArgs& a, int s) {
+  const BatchSeg sg = a.useg[s];
+  const BatchProbDev* P = a.probs + sg.prob;
+  if (s == P->useg_begin && threadIdx.x == 0 && a.A[sg.prob].done == 0 && a.B[sg.prob].done != 0)
+    a.A[sg.prob] = a.B[sg.prob];
+}
 
-  // ---- init: z = D^-1 b, x = 0, p_{-1} = 0, partials of iteration 0 -------
-  for (int s = a.vseg_range[bid]; s < a.vseg_range[bid + 1]; ++s) {
-    const BatchSeg sg = a.vseg[s];
-    const int64_t off = a.probs[sg.prob].off;
-    double rz = 0.0, rr = 0.0;
-    for (int64_t g = off + sg.begin + threadIdx.x; g < off + sg.end; g += kBT) {
-      const double v = a.b[g];
-      const double zv = a.dinv[g] * v;
-      a.z[g] = zv;
-      a.x[g] = 0.0;
-      a.p1[g] = 0.0;
-      rz += v * zv;
-      rr += v * v;
+// Two-phase form on the pencil march (form 2), apply phase: as apply_seg,
+// but the segment is a range of whole columns along x3; p and x (x +=
+// alpha_{k-1} p_{k-1}) are updated on the faces the columns own and the x3
+// faces of a column are summed in registers.  The apply that detects the
+// stop still makes the last x update.
+__device__ __forceinline__ void pencil_apply_seg(const BatchArgs& a, int s, int it, double* smem,
+                                        double* s_red) {
+  const BatchSeg sg = a.useg[s];
+  const int pb = uni_int(sg.prob);
+  const BatchProbDev* P = a.probs + pb;
+  if (a.A[pb].done != 0) return;
+  const double rho_prev = a.A[pb].rho;
+  const double alpha = uni_f64(a.A[pb].alpha);   // alpha_{k-1}, 0 before the first update
+  double rr_stop = a.A[pb].rr_stop;
+  double rho, rr;
+  sum_partials2<kBT>(a.prz + P->vseg_begin, a.prr + P->vseg_begin, P->n_vsegs, s_red, &rho, &rr);
+  if (it == 0) rr_stop = P->rtol2 * rr;
+  const double bb = (it == 0) ? 0.0 : rho / rho_prev;
+  int done = 0;
+  if (!isfinite(rr) || !isfinite(bb)) done = 3;
+  else if (rr <= rr_stop) done = 1;
+  else if (it >= P->maxit) done = 2;
+  if (s == P->useg_begin && threadIdx.x == 0) {
+    a.B[pb].rho = rho;
+    a.B[pb].rr = rr;
+    a.B[pb].rr_stop = rr_stop;
+    a.B[pb].iter = it;
+    a.B[pb].done = done;
+  }
+  const double dot = dispatch_pencils(uni_int(P->np), uni_int(P->variant), a, a.meshes[pb], smem,
+                                      P->off, it, sg.begin, sg.end, alpha, uni_f64(bb), done != 0);
+  if (done) return;                         // the last x update is in
+  const double bs = block_sum<kBT>(dot, s_red);
+  if (threadIdx.x == 0) a.ppq[s] = bs;
+}
+
+// Pencil form, update phase: z -= alpha D^-1 w with w = qa + qb, except on
+// the problem's free x3 faces, whose qa holds the sum.
+__device__ __forceinline__ void pencil_update_seg(const BatchArgs& a, int s, int it, double* s_red) {
+  double alpha;
+  if (!update_alpha(a, s, it, s_red, &alpha)) return;
+  const BatchSeg sg = a.vseg[s];
+  const BatchProbDev* P = a.probs + uni_int(sg.prob);
+  const int64_t off = P->off;
+  const int x3_lo = P->x3_lo, x3_hi = P->x3_hi;
+  double rz = 0.0, rr = 0.0;
+  // eight entries per thread with all their loads in flight together
+  // (entries past the segment read its first entry and are dropped)
+  constexpr int U = 8;
+  for (int r0 = sg.begin + (int)threadIdx.x; r0 < sg.end; r0 += U * kBT) {
+    double d[U], w[U], zv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + u * kBT;
+      const int64_t g = off + (r < sg.end ? r : sg.begin);
+      d[u] = a.dinv[g];
+      zv[u] = a.z[g];
+      w[u] = a.qa[g];
+      if (r < x3_lo || r >= x3_hi) w[u] += a.qb[g];
     }
-    const double brz = block_sum<kBT>(rz, s_red);
-    const double brr = block_sum<kBT>(rr, s_red);
-    if (threadIdx.x == 0) {
-      a.prz[s] = brz;
-      a.prr[s] = brr;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + u * kBT;
+      if (r >= sg.end) continue;
+      const double zn = zv[u] - alpha * (d[u] * w[u]);
+      a.z[off + r] = zn;
+      const double rn = div_fast(zn, d[u]);
+      rz += zn * rn;
+      rr += rn * rn;
     }
   }
-  if (!grid_sync(a, ++epoch)) return;
+  const double brz = block_sum<kBT>(rz, s_red);
+  const double brr = block_sum<kBT>(rr, s_red);
+  if (threadIdx.x == 0) {
+    a.prz[s] = brz;
+    a.prr[s] = brr;
+  }
+}
 
+template <int FORM>
+struct FormTraits {
+  static constexpr int phases = FORM == 1 ? 1 : 2;
+  static constexpr int lds_words = FORM == 2 ? kBatchPencilLdsWords : kBatchLdsWords;
+};
+
+template <int FORM>
+__device__ __forceinline__ void init_seg(const BatchArgs& a, int s, double* s_red) {
+  if constexpr (FORM == 1) init_seg_one_phase(a, s);
+  else init_seg_two_phase(a, s, s_red);
+}
+
+// Phase 0: the element segments; phase 1 (two-phase forms): the vector segments.
+template <int FORM>
+__device__ __forceinline__ void run_seg(const BatchArgs& a, int phase, int s, int it, double* smem,
+                               double* s_red) {
+  if constexpr (FORM == 0) {
+    if (phase == 0) apply_seg(a, s, it, smem, s_red);
+    else update_seg(a, s, it, s_red);
+  } else if constexpr (FORM == 1) {
+    pass_seg(a, s, it, smem, s_red);
+  } else {
+    if (phase == 0) pencil_apply_seg(a, s, it, smem, s_red);
+    else pencil_update_seg(a, s, it, s_red);
+  }
+}
+
+// ---- the persistent kernel ----------------------------------------------------
+// Every block owns one contiguous range of segments per phase; all problems
+// iterate in lockstep phases separated by grid barriers; converged problems
+// drop out and the kernel returns when every problem is done.  The one-phase
+// form numbers its blocks so that consecutive ranges sit on one XCD
+// (neighbouring elements of a problem, whose shared faces both read, meet in
+// the same L2).
+template <int FORM>
+__global__ void __launch_bounds__(kBT, 3) batch_cg_kernel(BatchArgs a) {
+  __shared__ double smem[FormTraits<FORM>::lds_words];
+  __shared__ double s_red[kBT / 64];
+  const int bid = FORM == 1 ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  unsigned epoch = 0;
+  for (int s = a.vseg_range[bid]; s < a.vseg_range[bid + 1]; ++s) init_seg<FORM>(a, s, s_red);
+  if (!grid_sync(a, ++epoch)) return;
   for (int it = 0; it < a.max_iters; ++it) {
-    // ------------------------------ apply -----------------------------------
-    for (int s = a.useg_range[bid]; s < a.useg_range[bid + 1]; ++s) {
-      const BatchSeg sg = a.useg[s];
-      const int pb = uni_int(sg.prob);
-      const BatchProbDev* P = a.probs + pb;
-      if (a.A[pb].done != 0) continue;
-      const double rho_prev = a.A[pb].rho;
-      const double alpha = uni_f64(a.A[pb].alpha);   // alpha_{k-1}, 0 before the first update
-      double rr_stop = a.A[pb].rr_stop;
-      double rho, rr;
-      sum_partials2<kBT>(a.prz + P->vseg_begin, a.prr + P->vseg_begin, P->n_vsegs, s_red, &rho,
-                         &rr);
-      if (it == 0) rr_stop = P->rtol2 * rr;
-      const double bb = (it == 0) ? 0.0 : rho / rho_prev;
-      int done = 0;
-      if (!isfinite(rr) || !isfinite(bb)) done = 3;
-      else if (rr <= rr_stop) done = 1;
-      else if (it >= P->maxit) done = 2;
-      if (s == P->useg_begin && threadIdx.x == 0) {
-        a.B[pb].rho = rho;
-        a.B[pb].rr = rr;
-        a.B[pb].rr_stop = rr_stop;
-        a.B[pb].iter = it;
-        a.B[pb].done = done;
-      }
-      const double dot = dispatch_pencils(uni_int(P->np), uni_int(P->variant), a, a.meshes[pb],
-                                          smem, P->off, it, sg.begin, sg.end, alpha,
-                                          uni_f64(bb), done != 0);
-      if (done) continue;                     // the last x update is in
-      const double bs = block_sum<kBT>(dot, s_red);
-      if (threadIdx.x == 0) a.ppq[s] = bs;
-    }
+    for (int s = a.useg_range[bid]; s < a.useg_range[bid + 1]; ++s)
+      run_seg<FORM>(a, 0, s, it, smem, s_red);
     if (!grid_sync(a, ++epoch)) return;
-    // ------------------------------ update ----------------------------------
-    for (int s = a.vseg_range[bid]; s < a.vseg_range[bid + 1]; ++s) {
-      const BatchSeg sg = a.vseg[s];
-      const int pb = uni_int(sg.prob);
-      const BatchProbDev* P = a.probs + pb;
-      const int bdone = a.B[pb].done;
-      const bool owner = (s == P->vseg_begin) && threadIdx.x == 0;
-      if (bdone == 0 && a.A[pb].done != 0) continue;   // broke down in an earlier update
-      if (bdone) {
-        if (owner && a.A[pb].done == 0) {               // finished in this iteration's apply
-          a.A[pb].done = bdone;
-          a.A[pb].iter = a.B[pb].iter;
-          a.A[pb].rr = a.B[pb].rr;
-          a.A[pb].rr_stop = a.B[pb].rr_stop;
-          atomicAdd(&a.bar->done_count, 1u);
-        }
-        continue;
-      }
-      const double pq = sum_partials<kBT>(a.ppq + P->useg_begin, P->n_usegs, 1, 0, s_red);
-      const double rho = a.B[pb].rho;
-      const double alpha = rho / pq;
-      if (!(pq > 0.0) || !isfinite(alpha)) {
-        if (owner) {
-          a.A[pb].done = 3;
-          a.A[pb].iter = it;
-          atomicAdd(&a.bar->done_count, 1u);
-        }
-        continue;
-      }
-      if (owner) {
-        a.A[pb].rho = rho;
-        a.A[pb].alpha = alpha;
-        a.A[pb].rr_stop = a.B[pb].rr_stop;
-        a.A[pb].rr = a.B[pb].rr;
-        a.A[pb].iter = it + 1;
-      }
-      const int64_t off = P->off;
-      const int x3_lo = P->x3_lo, x3_hi = P->x3_hi;
-      double rz = 0.0, rr = 0.0;
-      // eight entries per thread with all their loads in flight together
-      // (entries past the segment read its first entry and are dropped)
-      constexpr int U = 8;
-      for (int r0 = sg.begin + (int)threadIdx.x; r0 < sg.end; r0 += U * kBT) {
-        double d[U], w[U], zv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int r = r0 + u * kBT;
-          const int64_t g = off + (r < sg.end ? r : sg.begin);
-          d[u] = a.dinv[g];
-          zv[u] = a.z[g];
-          w[u] = a.qa[g];
-          if (r < x3_lo || r >= x3_hi) w[u] += a.qb[g];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int r = r0 + u * kBT;
-          if (r >= sg.end) continue;
-          const double zn = zv[u] - alpha * (d[u] * w[u]);
-          a.z[off + r] = zn;
-          const double rn = div_fast(zn, d[u]);
-          rz += zn * rn;
-          rr += rn * rn;
-        }
-      }
-      const double brz = block_sum<kBT>(rz, s_red);
-      const double brr = block_sum<kBT>(rr, s_red);
-      if (threadIdx.x == 0) {
-        a.prz[s] = brz;
-        a.prr[s] = brr;
-      }
+    if constexpr (FormTraits<FORM>::phases == 2) {
+      for (int s = a.vseg_range[bid]; s < a.vseg_range[bid + 1]; ++s)
+        run_seg<FORM>(a, 1, s, it, smem, s_red);
+      if (!grid_sync(a, ++epoch)) return;
     }
-    if (!grid_sync(a, ++epoch)) return;
     if (__hip_atomic_load(&a.bar->done_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
         (unsigned)a.n_probs)
       break;
   }
+  if constexpr (FORM == 1)
+    for (int s = a.useg_range[bid]; s < a.useg_range[bid + 1]; ++s) pass_result(a, s);
 }
 
 // State reset before every batched solve (a kernel, so that it can sit in the
@@ -770,12 +748,18 @@ __global__ void batch_reset_kernel(BatchState* A, BatchState* B, GridBar* bar, u
   }
 }
 
+namespace {
+const void* batch_kernel_fn(int form) {
+  return form == 1   ? reinterpret_cast<const void*>(batch_cg_kernel<1>)
+         : form == 2 ? reinterpret_cast<const void*>(batch_cg_kernel<2>)
+                     : reinterpret_cast<const void*>(batch_cg_kernel<0>);
+}
+}  // namespace
+
 hipError_t batch_occupancy(int form, int* blocks_per_cu) {
   // the grid must be co-resident
-  const void* fn = form == 1   ? reinterpret_cast<const void*>(batch_cgcg_kernel)
-                   : form == 2 ? reinterpret_cast<const void*>(batch_pencil_kernel)
-                               : reinterpret_cast<const void*>(batch_cg_kernel);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kBT, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel_fn(form), kBT,
+                                                      0);
 }
 
 hipError_t launch_batch_reset(BatchState* A, BatchState* B, GridBar* bar, unsigned* flags,
@@ -789,12 +773,11 @@ hipError_t launch_batch_reset(BatchState* A, BatchState* B, GridBar* bar, unsign
 
 hipError_t launch_batch_cg(const BatchArgs& args, int nblocks, hipStream_t s) {
   if (nblocks < 1 || nblocks > kBT * kMaxBlocksPerThread) return hipErrorInvalidValue;
+  if (args.form < 0 || args.form > 2) return hipErrorInvalidValue;
   BatchArgs a = args;
   void* params[] = {&a};
-  const void* fn = a.form == 1   ? reinterpret_cast<const void*>(batch_cgcg_kernel)
-                  : a.form == 2 ? reinterpret_cast<const void*>(batch_pencil_kernel)
-                                : reinterpret_cast<const void*>(batch_cg_kernel);
-  return hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kBT), params, 0, s);
+  return hipLaunchCooperativeKernel(batch_kernel_fn(a.form), dim3(nblocks), dim3(kBT), params, 0,
+                                    s);
 }
 
 }  // namespace hdg
