@@ -159,7 +159,7 @@ TRAFFIC_PROFILES = {
 }
 KERNEL_SOURCES = ("paper_2007_11891_amd/csrc/elem_unit.hpp", "paper_2007_11891_amd/csrc/elem_kernels.hip",
                   "paper_2007_11891_amd/csrc/vec_kernels.hip", "paper_2007_11891_amd/csrc/pencil_cg.hip",
-                  "paper_2007_11891_amd/csrc/cg_state.hpp",
+                  "paper_2007_11891_amd/csrc/pencil_unit.hpp", "paper_2007_11891_amd/csrc/cg_state.hpp",
                   "paper_2007_11891_amd/csrc/device_common.hpp")
 
 
