@@ -237,6 +237,14 @@ hdg_status hdg_tables(int p, double tau_hat, double* x, double* w, double* D,
  * (computed on the host, copied on the stream). */
 hdg_status hdg_coords(hdg_ctx* ctx, double* vol_xyz, double* trace_xyz);
 
+/* Place the mesh corner at origin[3] (host doubles, finite; default 0, 0, 0)
+ * for hdg_coords.  The condensed operator, the right-hand side and the
+ * recovery depend on the element widths only (the metric factors of the
+ * transformed element operator, paper section "Product factorization of the
+ * HDG operator"), so the origin moves nothing but the coordinates a caller
+ * evaluates f and the boundary data at. */
+hdg_status hdg_set_origin(hdg_ctx* ctx, const double origin[3]);
+
 /* y = K_ff x (paper: Alg. "HDG_Op_3D", nodal basis, or the transformed
  * Alg. with product factorization, eigen basis), on the free trace:
  * x, y device arrays of n_free values of type dtype, not overlapping.

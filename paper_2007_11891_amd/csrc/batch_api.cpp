@@ -394,19 +394,7 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
                             double tau_hat, void* stream, hdg_batch** out) {
   if (!out) return fail(HDG_EINVAL, "out is NULL");
   *out = nullptr;
-  if (count < 1 || count > (1 << 16)) return fail(HDG_EINVAL, "count must be in [1, 65536]");
-  if (!n_elem3 || !p || !lambda) return fail(HDG_EINVAL, "NULL argument");
-  if (!(tau_hat > 0.0) || !std::isfinite(tau_hat)) return fail(HDG_EINVAL, "tau_hat must be > 0");
-  for (int i = 0; i < count; ++i) {
-    for (int a = 0; a < 3; ++a)
-      if (n_elem3[3 * i + a] < 1 || n_elem3[3 * i + a] > 4096)
-        return fail(HDG_EINVAL, "problem %d: n_elem[%d] = %d out of [1, 4096]", i, a,
-                    n_elem3[3 * i + a]);
-    if (p[i] < 1 || p[i] > 10)
-      return fail(HDG_EINVAL, "problem %d: batched degrees must be in [1, 10], got %d", i, p[i]);
-    if (!(lambda[i] >= 0.0) || !std::isfinite(lambda[i]))
-      return fail(HDG_EINVAL, "problem %d: lambda must be finite and >= 0", i);
-  }
+  ST_TRY(validate_batch_create(count, n_elem3, p, lambda, tau_hat));
   hdg_batch* b = new (std::nothrow) hdg_batch();
   if (!b) return fail(HDG_ENOMEM, "host allocation failed");
   auto cleanup = [&](hdg_status st) {

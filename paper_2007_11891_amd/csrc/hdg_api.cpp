@@ -22,18 +22,6 @@ using namespace hdg;
 
 namespace hdg {
 
-thread_local std::string g_err;
-
-hdg_status fail(hdg_status st, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
-  va_end(ap);
-  g_err = buf;
-  return st;
-}
-
 // Per-face 1D transform matrices of the context by hdg_transform kind.
 const double* mat64(const hdg_ctx* c, int kind) {
   // storage order: St, StM, S, MS, then S o S (entrywise square, used for the
@@ -595,32 +583,6 @@ hdg_status solve_from_guess(hdg_ctx* c, const double* bhat, double* xhat, const 
   return st;
 }
 
-// Face counts of the trace layout: interior faces, then the Neumann sides
-// (free), then the Dirichlet sides, each side in the order (0,0), (0,1),
-// (1,0), ... (2,1).  side_off[k] is the first face id of side k.
-struct FaceCounts {
-  int64_t n_int, n_free_faces, n_faces, n_neu;
-  int64_t side_off[6];
-};
-FaceCounts face_counts(const int n[3], int neumann_sides) {
-  FaceCounts fc{};
-  const int64_t n1 = n[0], n2 = n[1], n3 = n[2];
-  const int64_t tb[3] = {n2 * n3, n1 * n3, n1 * n2};
-  fc.n_int = (n1 - 1) * n2 * n3 + n1 * (n2 - 1) * n3 + n1 * n2 * (n3 - 1);
-  int64_t off = fc.n_int;
-  for (int pass = 1; pass >= 0; --pass) {
-    for (int k = 0; k < 6; ++k)
-      if (((neumann_sides >> k) & 1) == pass) {
-        fc.side_off[k] = off;
-        off += tb[k >> 1];
-      }
-    if (pass == 1) fc.n_free_faces = off;
-  }
-  fc.n_faces = off;
-  fc.n_neu = fc.n_free_faces - fc.n_int;
-  return fc;
-}
-
 hdg_status upload_lambda_and_diag(hdg_ctx* c) {
   HIP_TRY(launch_diag(c, c->d_diag, c->stream));
   HIP_TRY(launch_recip_64_32(c->d_diag, c->d_dinv32, c->d_tmp[3], c->n_free, c->stream));
@@ -630,37 +592,6 @@ hdg_status upload_lambda_and_diag(hdg_ctx* c) {
 }  // namespace
 
 extern "C" {
-
-void hdg_default_opts(hdg_solve_opts* o) {
-  if (!o) return;
-  o->rtol = 1e-10;
-  o->maxit = 20000;
-  o->precond = 1;
-  o->mixed = 0;
-  o->inner_rtol = 1e-2;
-  o->max_outer = 12;
-  o->check_every = 25;
-  o->variant = -1;
-  o->guess = 0;
-}
-
-const char* hdg_last_error(void) { return g_err.c_str(); }
-
-hdg_status hdg_tables(int p, double tau_hat, double* x, double* w, double* D, double* S,
-                      double* Lam, double* BS, double* H) {
-  if (p < 1 || p > 16) return fail(HDG_EINVAL, "p must be in [1, 16], got %d", p);
-  if (!(tau_hat > 0.0)) return fail(HDG_EINVAL, "tau_hat must be > 0");
-  Tables1D t = make_tables(p, tau_hat);
-  const int n = t.np;
-  if (x) std::memcpy(x, t.x.data(), sizeof(double) * n);
-  if (w) std::memcpy(w, t.w.data(), sizeof(double) * n);
-  if (D) std::memcpy(D, t.D.data(), sizeof(double) * n * n);
-  if (S) std::memcpy(S, t.S.data(), sizeof(double) * n * n);
-  if (Lam) std::memcpy(Lam, t.Lam.data(), sizeof(double) * n);
-  if (BS) std::memcpy(BS, t.BS.data(), sizeof(double) * n * 2);
-  if (H) *H = t.H;
-  return HDG_OK;
-}
 
 hdg_status hdg_create(const int n_elem[3], const double* h1, const double* h2, const double* h3,
                       int p, double tau_hat, const double* lambda_host, double lambda_const,
@@ -675,42 +606,10 @@ hdg_status hdg_create_ex(const int n_elem[3], const double* h1, const double* h2
                          hdg_ctx** out) {
   if (!out) return fail(HDG_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!n_elem) return fail(HDG_EINVAL, "n_elem is NULL");
-  const double* hs[3] = {h1, h2, h3};
-  for (int a = 0; a < 3; ++a) {
-    if (n_elem[a] < 1 || n_elem[a] > (1 << 20))
-      return fail(HDG_EINVAL, "n_elem[%d] = %d out of range", a, n_elem[a]);
-    if (!hs[a]) return fail(HDG_EINVAL, "width array %d is NULL", a);
-    for (int i = 0; i < n_elem[a]; ++i)
-      if (!(hs[a][i] > 0.0) || !std::isfinite(hs[a][i]))
-        return fail(HDG_EINVAL, "width h%d[%d] must be finite and > 0", a + 1, i);
-  }
-  if (p < 1 || p > 16) return fail(HDG_EINVAL, "p must be in [1, 16], got %d", p);
-  if (!(tau_hat > 0.0) || !std::isfinite(tau_hat)) return fail(HDG_EINVAL, "tau_hat must be > 0");
+  ST_TRY(validate_create(n_elem, h1, h2, h3, p, tau_hat, lambda_host, lambda_const, neumann_sides,
+                         exact_mass));
   const int64_t ne = (int64_t)n_elem[0] * n_elem[1] * n_elem[2];
-  if (ne > (int64_t)1 << 28) return fail(HDG_EINVAL, "more than 2^28 elements");
-  if (lambda_host) {
-    for (int64_t e = 0; e < ne; ++e)
-      if (!(lambda_host[e] >= 0.0) || !std::isfinite(lambda_host[e]))
-        return fail(HDG_EINVAL, "lambda[%lld] must be finite and >= 0", (long long)e);
-  } else if (!(lambda_const >= 0.0) || !std::isfinite(lambda_const)) {
-    return fail(HDG_EINVAL, "lambda_const must be finite and >= 0");
-  }
-  if (exact_mass != 0 && exact_mass != 1)
-    return fail(HDG_EINVAL, "exact_mass must be 0 or 1, got %d", exact_mass);
-  if (neumann_sides < 0 || neumann_sides > 63)
-    return fail(HDG_EINVAL, "neumann_sides must be a mask of bits 0..5, got %d", neumann_sides);
-  if (neumann_sides == 63) {
-    bool any = false;
-    if (lambda_host) {
-      for (int64_t e = 0; e < ne && !any; ++e) any = lambda_host[e] > 0.0;
-    } else {
-      any = lambda_const > 0.0;
-    }
-    if (!any)
-      return fail(HDG_EINVAL, "every side Neumann with lambda = 0: the condensed operator is "
-                              "singular (constants are in its kernel)");
-  }
+  const double* hs[3] = {h1, h2, h3};
 
   hdg_ctx* c = new (std::nothrow) hdg_ctx();
   if (!c) return fail(HDG_ENOMEM, "host allocation failed");
@@ -909,23 +808,6 @@ hdg_status hdg_destroy(hdg_ctx* c) {
   return HDG_OK;
 }
 
-hdg_status hdg_layout(const int n_elem[3], int p, int neumann_sides, int64_t* n_free,
-                      int64_t* n_all, int64_t* n_vol) {
-  if (!n_elem) return fail(HDG_EINVAL, "n_elem is NULL");
-  for (int a = 0; a < 3; ++a)
-    if (n_elem[a] < 1 || n_elem[a] > (1 << 20))
-      return fail(HDG_EINVAL, "n_elem[%d] = %d out of range", a, n_elem[a]);
-  if (p < 1 || p > 16) return fail(HDG_EINVAL, "p must be in [1, 16], got %d", p);
-  if (neumann_sides < 0 || neumann_sides > 63)
-    return fail(HDG_EINVAL, "neumann_sides must be a mask of bits 0..5, got %d", neumann_sides);
-  const FaceCounts fc = face_counts(n_elem, neumann_sides);
-  const int64_t npf = (int64_t)(p + 1) * (p + 1);
-  if (n_free) *n_free = fc.n_free_faces * npf;
-  if (n_all) *n_all = (fc.n_faces + fc.n_neu) * npf;
-  if (n_vol) *n_vol = (int64_t)n_elem[0] * n_elem[1] * n_elem[2] * npf * (p + 1);
-  return HDG_OK;
-}
-
 hdg_status hdg_sizes(const hdg_ctx* c, int64_t* n_free, int64_t* n_all, int64_t* n_vol) {
   if (!c) return fail(HDG_EINVAL, "ctx is NULL");
   if (n_free) *n_free = c->n_free;
@@ -941,12 +823,20 @@ hdg_status hdg_set_lambda(hdg_ctx* c, const double* lambda_dev) {
   return upload_lambda_and_diag(c);
 }
 
+hdg_status hdg_set_origin(hdg_ctx* c, const double origin[3]) {
+  if (!c || !origin) return fail(HDG_EINVAL, "NULL argument");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(origin[a])) return fail(HDG_EINVAL, "origin[%d] is not finite", a);
+  for (int a = 0; a < 3; ++a) c->origin[a] = origin[a];
+  return HDG_OK;
+}
+
 hdg_status hdg_coords(hdg_ctx* c, double* vol_xyz, double* trace_xyz) {
   if (!c) return fail(HDG_EINVAL, "ctx is NULL");
   const int np = c->np;
   std::vector<double> X[3];
   for (int a = 0; a < 3; ++a) {
-    X[a].assign(c->n[a] + 1, 0.0);
+    X[a].assign(c->n[a] + 1, c->origin[a]);
     for (int i = 0; i < c->n[a]; ++i) X[a][i + 1] = X[a][i] + c->h_host[a][i];
   }
   auto coord = [&](int a, int el, int q) {

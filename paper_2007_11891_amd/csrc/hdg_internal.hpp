@@ -132,6 +132,7 @@ struct hdg_ctx {
   hdg::Tables1D tab;
   hdg::MeshDev mesh{};
   std::vector<double> h_host[3];
+  double origin[3] = {0.0, 0.0, 0.0};   // coordinates of the mesh corner (hdg_coords only)
   std::vector<double> lam_host;
   // device buffers
   double* d_h[3] = {nullptr, nullptr, nullptr};

@@ -1,16 +1,14 @@
-// Host-side helpers shared by the API translation units: error reporting
-// (thread-local message read by hdg_last_error) and device allocation.
+// Host-side helpers shared by the API translation units: device allocation
+// and the HIP / status propagation macros (error reporting: host_setup.hpp).
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 #include "../../include/hdg.h"
+#include "host_setup.hpp"
 
 namespace hdg {
-
-// Records a printf-style message for hdg_last_error and returns st.
-hdg_status fail(hdg_status st, const char* fmt, ...);
 
 template <typename T>
 hdg_status dalloc(T** p, int64_t n) {

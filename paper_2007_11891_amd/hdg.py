@@ -27,7 +27,8 @@ TO_EIGEN_UNKNOWN, TO_EIGEN_RESIDUAL, TO_NODAL_UNKNOWN, TO_NODAL_RESIDUAL = 0, 1,
 # every symbol include/hdg.h declares
 EXPORTS = (
     "hdg_default_opts", "hdg_create", "hdg_create_ex", "hdg_destroy", "hdg_last_error",
-    "hdg_sizes", "hdg_layout", "hdg_set_lambda", "hdg_tables", "hdg_coords", "hdg_apply", "hdg_apply_noalloc",
+    "hdg_sizes", "hdg_layout", "hdg_set_lambda", "hdg_tables", "hdg_coords", "hdg_set_origin",
+    "hdg_apply", "hdg_apply_noalloc",
     "hdg_face_transform",
     "hdg_rhs", "hdg_solve", "hdg_solve_forcing", "hdg_reconstruct", "hdg_hybridize",
     "hdg_adjoint",
@@ -97,6 +98,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "hdg_set_lambda": (ctypes.c_int, [vp, vp]),
         "hdg_tables": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, dp, dp, dp, dp, dp, dp, dp]),
         "hdg_coords": (ctypes.c_int, [vp, vp, vp]),
+        "hdg_set_origin": (ctypes.c_int, [vp, dp]),
         "hdg_apply": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, ctypes.c_int]),
         "hdg_apply_noalloc": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, ctypes.c_int]),
         "hdg_face_transform": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int64]),
@@ -298,6 +300,11 @@ class HdgContext:
         _check(self._lib.hdg_coords(self._h, ctypes.c_void_p(v.data_ptr()),
                                     ctypes.c_void_p(t.data_ptr())))
         return v.view(-1, 3), t.view(-1, 3)
+
+    def set_origin(self, origin):
+        """Coordinates of the mesh corner for coords() (default 0, 0, 0)."""
+        o = (ctypes.c_double * 3)(*(float(v) for v in origin))
+        _check(self._lib.hdg_set_origin(self._h, o))
 
     def set_lambda(self, lam):
         torch = _torch()

@@ -96,6 +96,34 @@ def test_coordinates_match_oracle():
     assert np.abs(to_host(tx) - o.trace_coords()).max() < 1e-15
 
 
+def test_origin_moves_coordinates_only():
+    """hdg_set_origin: every node moves by the origin (exactly, up to the
+    rounding of the sum); a polynomial of degree p placed on the moved mesh
+    is still reproduced; non-finite origins are refused."""
+    import paper_2007_11891_amd as pkg
+    n, p = (3, 2, 2), 3
+    o, c = _pair(n, p, lam=np.ones(n[0] * n[1] * n[2]))
+    org = (0.25, -1.5, 3.0)
+    c.set_origin(org)
+    vx, tx = c.coords()
+    vx, tx = to_host(vx), to_host(tx)
+    assert np.abs(vx - (o.volume_coords() + np.array(org))).max() < 1e-14
+    assert np.abs(tx - (o.trace_coords() + np.array(org))).max() < 1e-14
+    coef = np.random.default_rng(7).standard_normal((p + 1,) * 3)
+    u, f = W.poly_tensor(coef)
+    fv = f(*vx.T, np.full(len(vx), 1.0))
+    g = u(*tx.T)
+    tr = to_dev(g)
+    tr[:c.sizes.n_free] = 0
+    tr, uv, info = c.solve_forcing(to_dev(fv), tr, opts=pkg.default_opts(rtol=1e-14, maxit=2000,
+                                                                          check_every=10),
+                                   allow_noconv=True)
+    assert max_rel(to_host(tr), g) < 1e-11, info
+    assert max_rel(to_host(uv), u(*vx.T)) < 1e-11
+    with pytest.raises(pkg.HdgError, match="EINVAL"):
+        c.set_origin((0.0, float("nan"), 0.0))
+
+
 @pytest.mark.parametrize("n,p", [((3, 2, 4), 2), ((2, 3, 2), 5)])
 def test_diagonal_matches_transformed_operator(n, p):
     o, c = _pair(n, p)
