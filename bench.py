@@ -205,7 +205,7 @@ def cg_kernel_names(c, fp32: bool = False):
     np_, epu = c.p + 1, t["elems_per_unit"]
     if t["cg_variant"] == 0 and not fp32:
         return [f"elem_apply_kernel<{typ}, {np_}, {epu}, 2, 0>"]
-    if t["cg_variant"] == 2 and not fp32:
+    if t["cg_variant"] == 2:   # the FP32 inner CG follows the FP64 pencil form
         return [f"pencil_apply_kernel<{typ}, {np_}, {epu}>", f"pencil_update_kernel<{typ}>"]
     units = -(-c.n_elem // epu)
     upb = -(-units // min(units, 2048))
@@ -216,7 +216,8 @@ def cg_kernel_names(c, fp32: bool = False):
 def cg_iteration_roofline(c, W, torch, dev, fp32: bool = False, reps: int = 50,
                           workload: str | None = None):
     """One CG iteration in the CG form and tile shape the solve runs (FP32:
-    the two-kernel form of the mixed-precision inner CG), mean time per
+    the form of the mixed-precision inner CG, the pencil form when the FP64
+    CG runs it, else the two-kernel form), mean time per
     iteration over back-to-back launches (HIP events on the context stream),
     as an HBM roofline entry at the algorithmic 88 B per free DOF (44 in
     FP32), with the implementation's own bytes and the counted traffic."""
@@ -224,7 +225,8 @@ def cg_iteration_roofline(c, W, torch, dev, fp32: bool = False, reps: int = 50,
     nf = c.sizes.n_free
     cgv = c.tile_shape()["cg_variant"]
     if fp32:
-        form, which = "two kernels", pkg.TIME_CG2_ITER_F32
+        form, which = (("pencil", pkg.TIME_PENCIL_ITER_F32) if cgv == 2 else
+                       ("two kernels", pkg.TIME_CG2_ITER_F32))
     elif cgv == 0:
         form, which = "one kernel", pkg.TIME_CG1_ITER_F64
     elif cgv == 2:
