@@ -533,9 +533,10 @@ def bench_batched(pkg, W, torch, dev, reps: int = 3):
     t_it = (t21 - t1) / 20.0                     # ms per CG iteration, all problems active
     # algorithmic 88 B per free DOF and iteration; the two-phase form moves
     # 104 B (apply phase 40 B: read z, p_old, write p, qa, qb; update phase
-    # 64 B: read z, qa, qb, D^-1, x, p, write z, x)
+    # 64 B: read z, qa, qb, D^-1, x, p, write z, x), the one-phase form 104 B,
+    # the pencil form 91 B (as the single-problem forms)
     bytes_it = ALG_CG_BYTES * b.total_free
-    impl_it = 104 * b.total_free
+    impl_it = (IMPL_CG_BYTES["pencil"] if b.form() == 2 else 104) * b.total_free
     ach = bytes_it / (t_it * 1e-3) / 1e9
     log(f"[bench] batched: {len(probs)} problems, {b.total_free} free DOFs, wall {wall*1e3:.1f} ms, "
         f"max iters {iters.max()}, CG iteration {t_it*1e3:.1f} us, tiles {tiles}")
@@ -546,7 +547,8 @@ def bench_batched(pkg, W, torch, dev, reps: int = 3):
            "wall_ms": round(wall * 1e3, 3), "gpu_ms": round(statistics.median(gpus), 3),
            "iters_min": int(iters.min()), "iters_max": int(iters.max()),
            "iters_sum": int(iters.sum()), "tiles_by_p": tiles,
-           "cg_form": "one element pass per iteration" if b.form() == 1 else "two phases per iteration",
+           "cg_form": {0: "two phases per iteration", 1: "one element pass per iteration",
+                       2: "two phases on the pencil march"}[b.form()],
            "cg_iteration_us": round(t_it * 1e3, 2),
            "roofline": {"kernel": "batch_cg_kernel (persistent, one CG iteration of every problem)",
                         "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
@@ -635,7 +637,15 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the isolated kernel timings (for counter collection)")
     ap.add_argument("--reps", type=int, default=200)
+    ap.add_argument("--tile", type=int, default=0,
+                    help="--kernels-only: tile variant (no autotuning, so that every counter pass "
+                         "times the same launches)")
+    ap.add_argument("--ks", type=int, default=0,
+                    help="--kernels-only: pencil segment length (0: whole columns)")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched persistent CG timed over 1 and 21 iterations, form 0, "
+                         "tile variant 0 (for counter collection)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-paper-case", action="store_true")
     ap.add_argument("--no-neumann", action="store_true")
@@ -665,21 +675,27 @@ def main():
             prob = W.mixed(args.p, 1.0) if args.n == 32 else W.perturbed(n=args.n, p=args.p,
                                                                           lam=10.0, seed=2)
         ctx = pkg.HdgContext(prob.n, prob.widths, prob.p, prob.tau, float(np.ravel(prob.lam)[0]))
-        variant, _ = ctx.autotune(reps=10)
+        ctx.set_tile(args.tile)
+        ctx.set_cg_segment(args.ks)
         tile = ctx.tile_shape()
-        log(f"[bench] kernels-only n={prob.n} p={prob.p}: tile variant {variant}, "
-            f"CG form {tile['cg_variant']}, kernels {cg_kernel_names(ctx)}")
+        log(f"[bench] kernels-only n={prob.n} p={prob.p}: tile variant {args.tile}, pencil segment "
+            f"{args.ks or 'whole columns'}, CG form {tile['cg_variant']}, kernels "
+            f"{cg_kernel_names(ctx)}")
         nf = ctx.sizes.n_free
         x64 = torch.as_tensor(W.random_trace(nf, 1), device=dev)
         y64 = torch.empty_like(x64)
         chosen = {0: pkg.TIME_CG1_ITER_F64, 1: pkg.TIME_CG2_ITER_F64,
                   2: pkg.TIME_PENCIL_ITER_F64}[tile["cg_variant"]]
+        x32 = x64.float()
         for which, name in ((pkg.TIME_APPLY_F64, "apply64"), (pkg.TIME_CG2_APPLY_F64, "cg_apply64"),
                             (pkg.TIME_CG2_UPDATE_F64, "cg_update64"),
                             (pkg.TIME_CG1_ITER_F64, "cg_onekernel64"),
                             (pkg.TIME_PENCIL_ITER_F64, "cg_pencil64"), (pkg.TIME_COPY_F64, "copy64"),
-                            (chosen, "chosen CG form, again")):
-            ms = ctx.time_kernel(which, x64, args.reps,
+                            (chosen, "chosen CG form, again"),
+                            (pkg.TIME_CG2_ITER_F32, "cg_iter32 (two kernels)"),
+                            (pkg.TIME_PENCIL_ITER_F32, "cg_pencil32")):
+            x = x32 if which in (pkg.TIME_CG2_ITER_F32, pkg.TIME_PENCIL_ITER_F32) else x64
+            ms = ctx.time_kernel(which, x, args.reps,
                                  y=y64 if which in (pkg.TIME_COPY_F64, pkg.TIME_APPLY_F64) else None)
             log(f"[bench] {name} {ms * 1e3:.3f} us")
         # plain copy of 256 MiB (larger than L2 and the infinity cache): the
@@ -690,6 +706,22 @@ def main():
             big2.copy_(big)
         torch.cuda.synchronize()
         ctx.close()
+        return
+
+    if args.batch_only:
+        # the persistent batched CG alone, for counter collection: the
+        # dispatches are the warm-up and 3 timed launches of 1 iteration, then
+        # of 21 iterations (bytes per iteration = difference / 20)
+        probs = W.batched()
+        b = pkg.HdgBatch([pr.n for pr in probs], [pr.p for pr in probs],
+                         [float(pr.lam[0]) for pr in probs], tau=1.0)
+        b.set_form(0)
+        b.set_tile(0, 0)
+        t1 = b.time_cg(1, reps=3)
+        t21 = b.time_cg(21, reps=3)
+        log(f"[bench] batch-only: {b.total_free} free DOFs, one CG iteration of every problem "
+            f"{(t21 - t1) / 20 * 1e3:.1f} us")
+        b.close()
         return
 
     prob = W.perturbed(n=args.n, p=args.p, lam=10.0, seed=2)
