@@ -701,6 +701,10 @@ __device__ __forceinline__ void run_seg(const BatchArgs& a, int phase, int s, in
 // form numbers its blocks so that consecutive ranges sit on one XCD
 // (neighbouring elements of a problem, whose shared faces both read, meet in
 // the same L2).
+// three blocks per CU for every form: four fit the one-phase form's paths in
+// 128 registers (a 100-byte spill) but measured slower (630 against 583 us per
+// iteration of the 256-problem batch); the two-phase forms spill 300-400
+// bytes per lane at four
 template <int FORM>
 __global__ void __launch_bounds__(kBT, 3) batch_cg_kernel(BatchArgs a) {
   __shared__ double smem[FormTraits<FORM>::lds_words];

@@ -56,7 +56,7 @@ def test_mixed_precision_matches_oracle_submesh(p, lam, variant):
 @pytest.mark.parametrize("lam", [1e-2, 1.0, 1e2])
 def test_mixed_precision_matches_fp64_full_size(p, lam):
     """32^3 mesh: FP32-inner / FP64-outer to relative residual 1e-10 agrees
-    with the FP64 CG solve to 1e-9 (both are 1e-10-residual solutions)."""
+    with the FP64 CG solve to 1e-8 (both are 1e-10-residual solutions)."""
     import paper_2007_11891_amd as pkg
     print(f"[mixed vs fp64] 32^3 p={p} lam={lam}", flush=True)
     prob = W.mixed(p, lam)
