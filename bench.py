@@ -532,11 +532,11 @@ def bench_batched(pkg, W, torch, dev, reps: int = 3):
     t21 = b.time_cg(21, reps=3)
     t_it = (t21 - t1) / 20.0                     # ms per CG iteration, all problems active
     # algorithmic 88 B per free DOF and iteration; the two-phase form moves
-    # 104 B (apply phase 40 B: read z, p_old, write p, qa, qb; update phase
-    # 64 B: read z, qa, qb, D^-1, x, p, write z, x), the one-phase form 104 B,
-    # the pencil form 91 B (as the single-problem forms)
+    # 96 B (apply phase 56 B: read z, p_old, x, write p, x, qa, qb; update
+    # phase 40 B: read z, qa, qb, D^-1, write z), the one-phase form 104 B,
+    # the pencil form 91 B (as the single-problem pencil form)
     bytes_it = ALG_CG_BYTES * b.total_free
-    impl_it = (IMPL_CG_BYTES["pencil"] if b.form() == 2 else 104) * b.total_free
+    impl_it = {0: 96, 1: 104, 2: IMPL_CG_BYTES["pencil"]}[b.form()] * b.total_free
     ach = bytes_it / (t_it * 1e-3) / 1e9
     log(f"[bench] batched: {len(probs)} problems, {b.total_free} free DOFs, wall {wall*1e3:.1f} ms, "
         f"max iters {iters.max()}, CG iteration {t_it*1e3:.1f} us, tiles {tiles}")

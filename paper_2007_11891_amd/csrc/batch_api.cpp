@@ -86,15 +86,16 @@ namespace {
 
 // Relative cost of one apply work item, from per-segment timings of the
 // persistent kernel at three blocks per CU on the 256-problem batch (p = 2..10):
-// an element work unit keeps its block busy for 5.5-6.3 us in the two-phase
-// form and 11-13 us in the one-phase form, almost whatever its degree (the
-// unit is bound by the latency of its dependent loads, not by its bytes); an
-// element of a pencil column row takes 5-7 us.
+// an element work unit keeps its block busy for 6.8-7.4 us in the two-phase
+// form (9.1 us at n_p = 11, whose code path spills registers) and 11-13 us in
+// the one-phase form, almost whatever its degree otherwise (the unit is bound
+// by the latency of its dependent loads, not by its bytes); an element of a
+// pencil column row takes 5-7 us.
 double item_cost(int form, int np) {
   switch (form) {
     case 1: return 10.2 + 0.25 * np;
     case 2: return 4.6 + 0.22 * np;
-    default: return 5.3 + 0.09 * np;
+    default: return np >= 11 ? 9.1 : 7.0 + 0.03 * np;
   }
 }
 

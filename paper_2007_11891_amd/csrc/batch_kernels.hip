@@ -177,8 +177,44 @@ __device__ inline double run_units(const UnitIO<double>& io, const double* tabs,
   int tid = (int)threadIdx.x;
   asm volatile("" : "+v"(tid));
   double acc[3] = {0.0, 0.0, 0.0};
-  run_units_pipelined<double, NP, EPB, 1>(io, tab, sm, u0, u1, acc, tid);
+  run_units_pipelined<double, NP, EPB, 3>(io, tab, sm, u0, u1, acc, tid);
   return acc[0];
+}
+
+// The last x step of a finished solve, x += alpha p_old on the faces the
+// units [u0, u1) own (their high faces; batched problems have no Neumann
+// side).
+template <int NP, int EPB>
+__device__ inline void final_x_units(const UnitIO<double>& io, int u0, int u1, int tid) {
+  constexpr int NF = NP * NP;
+  const UnitLane L = unit_lane<NP, EPB>(tid);
+  for (int u = u0; u < u1; ++u) {
+    UnitRegs<double> R;
+    unit_info<double, NP, EPB>(io, L, u, R);
+    if (!R.active || !L.colok) continue;
+#pragma unroll
+    for (int f = 1; f < 6; f += 2)
+      if (R.fid[f] < io.nff) {
+        const int64_t g = (int64_t)R.fid[f] * NF + L.col;
+        io.x[g] += io.alpha * io.p_in[g];
+      }
+  }
+}
+
+__device__ inline void dispatch_final_x(int np, int variant, const UnitIO<double>& io, int u0,
+                                        int u1) {
+  int tid = (int)threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  switch (np * 4 + variant) {
+#define HDG_FCASE(N)                                                           \
+  case N * 4 + 0: final_x_units<N, epb_var<N, 0>()>(io, u0, u1, tid); return; \
+  case N * 4 + 1: final_x_units<N, epb_var<N, 1>()>(io, u0, u1, tid); return; \
+  case N * 4 + 2: final_x_units<N, epb_var<N, 2>()>(io, u0, u1, tid); return;
+    HDG_FCASE(2) HDG_FCASE(3) HDG_FCASE(4) HDG_FCASE(5) HDG_FCASE(6) HDG_FCASE(7)
+    HDG_FCASE(8) HDG_FCASE(9) HDG_FCASE(10) HDG_FCASE(11)
+#undef HDG_FCASE
+    default: return;
+  }
 }
 
 // The one-phase form: units [u0, u1) of one problem through the one-kernel
@@ -349,7 +385,9 @@ __device__ __forceinline__ void init_seg_one_phase(const BatchArgs& a, int s) {
 // Two-phase form, apply phase: re-sum the problem's r.z and r.r partials of
 // the previous update in a fixed order, decide convergence (the owner of the
 // problem's first segment records it in slot B), form p = z + beta p_old on
-// the segment's units and apply the operator; one p.q partial per segment.
+// the segment's units, make the previous iteration's x step x += alpha p_old
+// on the faces they own, and apply the operator; one p.q partial per
+// segment.  The apply that detects the stop only makes that last x step.
 __device__ __forceinline__ void apply_seg(const BatchArgs& a, int s, int it, double* smem, double* s_red) {
   const BatchSeg sg = a.useg[s];
   const int pb = uni_int(sg.prob);
@@ -372,17 +410,22 @@ __device__ __forceinline__ void apply_seg(const BatchArgs& a, int s, int it, dou
     a.B[pb].iter = it;
     a.B[pb].done = done;
   }
-  if (done) return;                       // x is complete: nothing left to apply
   const int64_t off = P->off;
   UnitIO<double> io{};
   io.info = uni_ptr(P->info);
   io.lam = uni_ptr(P->lam);
   io.n_elem = uni_int(P->n_elem);
   io.nff = uni_int(P->nff);
+  io.p_in = uni_ptr(((it & 1) ? a.p0 : a.p1) + off);   // p_{k-1}
+  io.x = uni_ptr(a.x + off);
+  io.alpha = uni_f64(a.A[pb].alpha);                     // alpha_{k-1}, 0 before the first update
+  if (done) {                             // the last x step, then the solve is complete
+    dispatch_final_x(uni_int(P->np), uni_int(P->variant), io, sg.begin, sg.end);
+    return;
+  }
   io.qa = uni_ptr(a.qa + off);
   io.qb = uni_ptr(a.qb + off);
   io.z = uni_ptr(a.z + off);
-  io.p_in = uni_ptr(((it & 1) ? a.p0 : a.p1) + off);
   io.p_out = uni_ptr(((it & 1) ? a.p1 : a.p0) + off);
   io.beta = uni_f64(bb);
   const double dot =
@@ -435,31 +478,29 @@ __device__ __forceinline__ bool update_alpha(const BatchArgs& a, int s, int it, 
 }
 
 // Two-phase form, update phase: alpha from the problem's p.q partials, then
-// z -= alpha D^-1 (qa + qb), x += alpha p and the segment's r.z, r.r partials.
+// z -= alpha D^-1 (qa + qb) and the segment's r.z, r.r partials (x takes its
+// step alpha p in the next apply phase).
 __device__ __forceinline__ void update_seg(const BatchArgs& a, int s, int it, double* s_red) {
   double alpha;
   if (!update_alpha(a, s, it, s_red, &alpha)) return;
   const BatchSeg sg = a.vseg[s];
   const BatchProbDev* P = a.probs + uni_int(sg.prob);
   const int64_t lo = P->off + sg.begin, hi = P->off + sg.end;
-  const double* __restrict__ pk = (it & 1) ? a.p1 : a.p0;   // p of this iteration
   double rz = 0.0, rr = 0.0;
   int64_t g = lo + threadIdx.x;
-  for (; g + 3 * kBT < hi; g += 4 * kBT) {
-    double zv[4], q[4], d[4], xv[4], pv[4];
+  constexpr int U = 8;
+  for (; g + (U - 1) * kBT < hi; g += U * kBT) {
+    double zv[U], q[U], d[U];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < U; ++k) {
       zv[k] = a.z[g + k * kBT];
       q[k] = a.qa[g + k * kBT] + a.qb[g + k * kBT];
       d[k] = a.dinv[g + k * kBT];
-      xv[k] = a.x[g + k * kBT];
-      pv[k] = pk[g + k * kBT];
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < U; ++k) {
       const double zn = zv[k] - alpha * (d[k] * q[k]);
       a.z[g + k * kBT] = zn;
-      a.x[g + k * kBT] = xv[k] + alpha * pv[k];
       const double rn = div_fast(zn, d[k]);
       rz += zn * rn;
       rr += rn * rn;
@@ -469,7 +510,6 @@ __device__ __forceinline__ void update_seg(const BatchArgs& a, int s, int it, do
     const double d = a.dinv[g];
     const double zn = a.z[g] - alpha * (d * (a.qa[g] + a.qb[g]));
     a.z[g] = zn;
-    a.x[g] += alpha * pk[g];
     const double rn = div_fast(zn, d);
     rz += zn * rn;
     rr += rn * rn;

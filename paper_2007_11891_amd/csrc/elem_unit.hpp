@@ -68,7 +68,9 @@ struct UnitIO {
   const T* x_bdry;         // may be null
   T* qa;
   T* qb;
-  // fused CG apply (MODE 1): p = z + beta p_old
+  // fused CG apply (MODE 1): p = z + beta p_old; MODE 3 also makes the
+  // previous iteration's x step on the faces the unit owns, x += alpha p_old
+  // (alpha and x below), so that the vector update need not touch x and p
   const T* z;              // z = D^-1 r
   const T* p_in;
   T* p_out;
@@ -130,7 +132,8 @@ __device__ inline UnitLane unit_lane(int tid) {
 }
 
 // Registers of one unit between its loads and its arithmetic: the element
-// record and the raw face values (MODE 0: the input x; MODE 1: z and p_old).
+// record and the raw face values (MODE 0: the input x; MODES 1, 3: z and
+// p_old; MODE 3 also x on the three faces the unit owns, c[f / 2]).
 template <typename T>
 struct UnitRegs {
   bool active;
@@ -139,6 +142,7 @@ struct UnitRegs {
   T d[4];
   T a[6];
   T b[6];
+  T c[3];
 };
 
 // Element record of the lane's element in unit `unit`.
@@ -159,8 +163,8 @@ __device__ inline void unit_info(const UnitIO<T>& io, const UnitLane& L, int uni
   }
 }
 
-// Issues the face loads of a unit (MODES 0 and 1); no arithmetic on them, so
-// that they can stay in flight while another unit computes.
+// Issues the face loads of a unit (MODES 0, 1 and 3); no arithmetic on them,
+// so that they can stay in flight while another unit computes.
 template <typename T, int NP, int MODE>
 __device__ inline void unit_data(const UnitIO<T>& io, const UnitLane& L, UnitRegs<T>& R) {
   constexpr int NF = NP * NP;
@@ -176,6 +180,9 @@ __device__ inline void unit_data(const UnitIO<T>& io, const UnitLane& L, UnitReg
         } else {
           R.a[f] = io.z[g];
           R.b[f] = io.p_in[g];
+          // MODE 3 runs without Neumann sides: the unit owns its high faces
+          if constexpr (MODE == 3)
+            if (f & 1) R.c[f >> 1] = io.x[g];
         }
       } else if (MODE == 0 && io.x_bdry != nullptr) {
         R.a[f] = io.x_bdry[(int64_t)(R.fid[f] - io.nff) * NF + L.col];
@@ -190,7 +197,7 @@ __device__ inline void unit_data(const UnitIO<T>& io, const UnitLane& L, UnitReg
 // kernels measured as fast or faster with plain stores.
 template <int MODE, typename T>
 __device__ inline void put(T* p, T v) {
-  if constexpr (MODE == 1) __builtin_nontemporal_store(v, p);
+  if constexpr (MODE == 1 || MODE == 3) __builtin_nontemporal_store(v, p);
   else *p = v;
 }
 
@@ -291,9 +298,10 @@ __device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T
   __syncthreads();                          // LDS is reused by the next unit
 }
 
-// MODES 0 and 1 from loaded registers: forms the input (MODE 1:
-// p = z + beta p_old, written by the element below each face), stages it and
-// runs the element arithmetic.
+// MODES 0, 1 and 3 from loaded registers: forms the input (MODES 1, 3:
+// p = z + beta p_old, written by the element below each face, which in MODE 3
+// also writes x + alpha p_old there), stages it and runs the element
+// arithmetic.
 template <typename T, int NP, int EPB, int MODE, typename Tab>
 __device__ inline void unit_compute(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
                                     const UnitLane& L, const UnitRegs<T>& R, double* acc) {
@@ -308,6 +316,14 @@ __device__ inline void unit_compute(const UnitIO<T>& io, const Tab& tab, UnitSme
       const bool own_lo = TabTraits<Tab>::neumann && ((R.nm >> f) & 1);
       if (((f & 1) || own_lo) && R.active && L.colok && R.fid[f] < io.nff)
         put<MODE>(io.p_out + (int64_t)R.fid[f] * NF + L.col, v);
+    } else if constexpr (MODE == 3) {
+      static_assert(!TabTraits<Tab>::neumann, "MODE 3 is for meshes without Neumann sides");
+      v = R.a[f] + io.beta * R.b[f];
+      if ((f & 1) && R.active && L.colok && R.fid[f] < io.nff) {
+        const int64_t g = (int64_t)R.fid[f] * NF + L.col;
+        put<MODE>(io.p_out + g, v);
+        put<MODE>(io.x + g, R.c[f >> 1] + io.alpha * R.b[f]);
+      }
     }
     xf[f] = v;
     if (f < 4 && R.active && L.colok) sm.face[L.sl][f][L.col] = v;
