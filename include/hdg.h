@@ -468,8 +468,9 @@ hdg_status hdg_batch_set_tile(hdg_batch* batch, int p, int variant);
 hdg_status hdg_batch_tiles(const hdg_batch* batch, int* variants);
 
 /* CG form of the persistent kernel: 0 (default) two phases per iteration
- * (element pass with the fused p update, then a vector update), two grid
- * barriers; 1 one element pass per iteration with the Chronopoulos-Gear
+ * (element pass with the fused p update and the previous iteration's x
+ * step, then a vector update of z), two grid barriers; 1 one element pass
+ * per iteration with the Chronopoulos-Gear
  * recurrences of the single-problem one-kernel CG (the same PCG iterates in
  * exact arithmetic), one barrier; 2 two phases on the pencil march of the
  * single-problem pencil form (whole columns along x3 per work item, the
