@@ -6,18 +6,19 @@
 //            units); per segment the previous update's partials (r.z, r.r)
 //            of that problem are re-summed in a fixed order, convergence is
 //            decided, p = z + beta p_old is formed on the units' faces
-//            (z = D^-1 r), the transformed operator is applied (the same
-//            `apply_unit` as the single-problem kernels, selected by degree
-//            and tile shape) and one p.q partial is written per segment;
+//            (z = D^-1 r) and x takes the previous iteration's step on the
+//            faces they own, the transformed operator is applied (the work
+//            unit of the single-problem kernels, selected by degree and tile
+//            shape) and one p.q partial is written per segment;
 //   update : vector segments (a problem and a range of its free trace); per
 //            segment the problem's apply partials are re-summed, alpha is
-//            formed, z and x are updated and one r.z and one r.r partial
-//            are written per segment.
+//            formed, z is updated and one r.z and one r.r partial are
+//            written per segment.
 // The one-phase form fuses both into one element pass per iteration, and the
 // pencil form marches element columns (see below).  Converged problems drop
 // out; the kernel returns when every problem is done.  Per-problem state
 // lives in two slots (A: read by apply, written by update; B: the reverse),
-// written by whichever block runs the problem's first segment of the phase.
+// written by the block that owns the problem's first segment of the phase.
 // Every reduction is a fixed-order sum over per-segment partials, so the
 // result depends neither on timing nor on which block ran which segment.
 //
