@@ -450,7 +450,9 @@ typedef struct {
  *   tau_hat   penalty scale > 0 (all problems)
  *   stream    hipStream_t (as void*) for all work of the batch
  * Tile variants start at 0 for every degree.  *out owns device memory until
- * hdg_batch_destroy. */
+ * hdg_batch_destroy.  HDG_EINVAL also when a problem's free trace holds
+ * 2^28 values or more (the element pass addresses it with 32-bit byte
+ * offsets). */
 hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const double* lambda,
                             double tau_hat, void* stream, hdg_batch** out);
 hdg_status hdg_batch_destroy(hdg_batch* batch);

@@ -420,8 +420,11 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
     if ((st = hdg_create(ne, h[0].data(), h[1].data(), h[2].data(), p[i], tau_hat, nullptr,
                          lambda[i], stream, &b->sub[i])) != HDG_OK)
       return cleanup(st);
-    if (b->sub[i]->n_free > INT32_MAX || b->sub[i]->n_elem > INT32_MAX)
-      return cleanup(fail(HDG_EINVAL, "problem %d too large for the batched solver", i));
+    // the element pass addresses a problem's trace vectors with 32-bit byte
+    // offsets below 2^31
+    if (b->sub[i]->n_free >= ((int64_t)1 << 28) || b->sub[i]->n_elem > INT32_MAX)
+      return cleanup(fail(HDG_EINVAL, "problem %d too large for the batched solver "
+                                      "(free trace of 2^28 values or more)", i));
     b->off[i] = b->total_free;
     b->voff[i] = b->total_vol;
     b->total_free += b->sub[i]->n_free;

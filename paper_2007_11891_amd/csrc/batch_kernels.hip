@@ -178,7 +178,7 @@ __device__ inline double run_units(const UnitIO<double>& io, const double* tabs,
   int tid = (int)threadIdx.x;
   asm volatile("" : "+v"(tid));
   double acc[3] = {0.0, 0.0, 0.0};
-  run_units_pipelined<double, NP, EPB, 3>(io, tab, sm, u0, u1, acc, tid);
+  run_units_ranged<NP, EPB>(io, tab, sm, u0, u1, acc, tid);
   return acc[0];
 }
 

@@ -133,7 +133,9 @@ __device__ inline UnitLane unit_lane(int tid) {
 
 // Registers of one unit between its loads and its arithmetic: the element
 // record and the raw face values (MODE 0: the input x; MODES 1, 3: z and
-// p_old; MODE 3 also x on the three faces the unit owns, c[f / 2]).
+// p_old; MODE 3 also x on the three faces the unit owns, c[f / 2]).  MODE 3
+// keeps lambda_e apart from d[0] (so that no arithmetic waits on the record
+// loads) and the lane's byte offset into the trace vectors of each face.
 template <typename T>
 struct UnitRegs {
   bool active;
@@ -143,6 +145,8 @@ struct UnitRegs {
   T a[6];
   T b[6];
   T c[3];
+  T lam;
+  uint32_t off[6];
 };
 
 // Element record of the lane's element in unit `unit`.
@@ -163,10 +167,11 @@ __device__ inline void unit_info(const UnitIO<T>& io, const UnitLane& L, int uni
   }
 }
 
-// Issues the face loads of a unit (MODES 0, 1 and 3); no arithmetic on them,
+// Issues the face loads of a unit (MODES 0 and 1); no arithmetic on them,
 // so that they can stay in flight while another unit computes.
 template <typename T, int NP, int MODE>
 __device__ inline void unit_data(const UnitIO<T>& io, const UnitLane& L, UnitRegs<T>& R) {
+  static_assert(MODE == 0 || MODE == 1, "MODE 3 loads through unit_data_ranged");
   constexpr int NF = NP * NP;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
@@ -180,9 +185,6 @@ __device__ inline void unit_data(const UnitIO<T>& io, const UnitLane& L, UnitReg
         } else {
           R.a[f] = io.z[g];
           R.b[f] = io.p_in[g];
-          // MODE 3 runs without Neumann sides: the unit owns its high faces
-          if constexpr (MODE == 3)
-            if (f & 1) R.c[f >> 1] = io.x[g];
         }
       } else if (MODE == 0 && io.x_bdry != nullptr) {
         R.a[f] = io.x_bdry[(int64_t)(R.fid[f] - io.nff) * NF + L.col];
@@ -197,8 +199,95 @@ __device__ inline void unit_data(const UnitIO<T>& io, const UnitLane& L, UnitReg
 // kernels measured as fast or faster with plain stores.
 template <int MODE, typename T>
 __device__ inline void put(T* p, T v) {
-  if constexpr (MODE == 1 || MODE == 3) __builtin_nontemporal_store(v, p);
+  if constexpr (MODE == 1) __builtin_nontemporal_store(v, p);
   else *p = v;
+}
+
+// ---- range-checked trace access (MODE 3, FP64) -------------------------------
+// A raw buffer resource spans one trace vector of the problem (under 2 GiB,
+// which the batch set-up checks).  The memory unit checks every access
+// against that range: one at kOutOfRange reads zero and writes nothing.
+// Masked lanes take that offset instead of a branch, so every path through a
+// unit issues the same loads and stores, and the compiler's wait for a unit's
+// face data counts exactly the memory operations issued after them: the loads
+// of the next unit stay in flight through the arithmetic of this one (with
+// branches around them the count differs between paths and the wait falls
+// back to all of them).
+constexpr uint32_t kOutOfRange = 0x80000000u;
+struct UnitBufs {
+  __amdgpu_buffer_rsrc_t z, p_in, x, qa, qb, p_out;
+};
+__device__ inline __amdgpu_buffer_rsrc_t trace_rsrc(const void* p, uint32_t bytes) {
+  // word 3: 32-bit data format, which untyped buffer accesses need on gfx9
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+template <int NP>
+__device__ inline UnitBufs unit_bufs(const UnitIO<double>& io) {
+  const uint32_t n = (uint32_t)io.nff * (uint32_t)(NP * NP) * 8u;
+  return {trace_rsrc(io.z, n),  trace_rsrc(io.p_in, n), trace_rsrc(io.x, n),
+          trace_rsrc(io.qa, n), trace_rsrc(io.qb, n),   trace_rsrc(io.p_out, n)};
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ inline double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+// non-temporal (cache policy bit 1): nothing reads these in the same phase
+__device__ inline void buf_store_nt(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 2);
+}
+
+// Element record of unit `unit` (valid: the unit is one to compute) loaded
+// without a branch: a lane without an element reads element 0's record and
+// is marked inactive.  Nothing is computed from the loads here.
+template <int NP, int EPB>
+__device__ inline void unit_info_ranged(const UnitIO<double>& io, const UnitLane& L, int unit,
+                                        bool valid, UnitRegs<double>& R) {
+  // global address space: generic (flat) loads would make every later wait
+  // for memory a wait for all of it
+  typedef const __attribute__((address_space(1))) ElemInfo GInfo;
+  typedef const __attribute__((address_space(1))) double GDouble;
+  const int e = unit * EPB + L.slot;
+  R.active = valid && L.slot < EPB && e < io.n_elem;
+  const int ec = R.active ? e : 0;
+  GInfo* ei = (GInfo*)io.info + ec;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) R.d[k] = ei->d[k];
+  R.lam = ((GDouble*)io.lam)[ec];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) R.fid[f] = ei->fid[f];
+  R.nm = 0;
+}
+
+// Face loads of a unit in MODE 3: z and p_old on every face, x on the three
+// faces the unit owns (its high faces: batched problems have no Neumann side).
+template <int NP>
+__device__ inline void unit_data_ranged(const UnitBufs& B, const UnitIO<double>& io,
+                                        const UnitLane& L, UnitRegs<double>& R) {
+  constexpr int NF = NP * NP;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const bool on = R.active && L.colok && R.fid[f] < io.nff;
+    R.off[f] = on ? ((uint32_t)R.fid[f] * NF + (uint32_t)L.col) * 8u : kOutOfRange;
+    R.a[f] = buf_load(B.z, R.off[f]);
+    R.b[f] = buf_load(B.p_in, R.off[f]);
+    if (f & 1) R.c[f >> 1] = buf_load(B.x, R.off[f]);
+  }
+}
+
+// The 1D table entries a lane needs at its face-node column (q1, q2).  A
+// caller that runs many units can load them once: in the batched kernel the
+// tables are device memory, and loads issued inside a unit would wait behind
+// the next unit's face loads.
+template <typename T>
+struct LaneTab {
+  T bs0q1, bs1q1, bs0q2, bs1q2, lamq1, lamq2;
+};
+template <typename T, typename Tab>
+__device__ inline LaneTab<T> lane_tab(const Tab& tab, const UnitLane& L) {
+  // a lane past the last column (q2 >= n_p) reads entry 0
+  const int q1 = L.colok ? L.q1 : 0, q2 = L.colok ? L.q2 : 0;
+  return {(T)tab.bs0[q1], (T)tab.bs1[q1], (T)tab.bs0[q2],
+          (T)tab.bs1[q2], (T)tab.lam[q1], (T)tab.lam[q2]};
 }
 
 // Element arithmetic of one unit given its input face values xf (already in
@@ -206,11 +295,15 @@ __device__ inline void put(T* p, T v) {
 // barrier): expansion into the element eigenspace, reductions back to the
 // faces, stores of qa / qb, and the quadratic form xf.out into *dot.  A face
 // in nm (on a Neumann side of the box) has no second element: its other
-// slot is written with zero, so that qa + qb is the face's sum.
+// slot is written with zero, so that qa + qb is the face's sum.  MODE 3
+// takes the lane's table entries (lt) and its face offsets into the ranged
+// trace vectors (bufs, off) from the caller.
 template <typename T, int NP, int EPB, int MODE, typename Tab>
 __device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
                                  const UnitLane& L, bool active, const int* fid, int nm,
-                                 const T* d, const T* xf, double* dot) {
+                                 const T* d, const T* xf, double* dot,
+                                 const UnitBufs* bufs = nullptr, const uint32_t* off = nullptr,
+                                 const LaneTab<T>* lt = nullptr) {
   constexpr int NF = NP * NP;
   constexpr int P = upitch<NP>();
   const int sl = L.sl, q1 = L.q1, q2 = L.q2, col = L.col;
@@ -225,10 +318,13 @@ __device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T
     const T* f0hi = sm.face[sl][1];
     const T* f1lo = sm.face[sl][2];
     const T* f1hi = sm.face[sl][3];
-    const T c0 = d[1] * tab.bs0[q1], c1 = d[1] * tab.bs1[q1];
-    const T c2 = d[2] * tab.bs0[q2], c3 = d[2] * tab.bs1[q2];
+    LaneTab<T> t;
+    if constexpr (MODE == 3) t = *lt;
+    else t = {tab.bs0[q1], tab.bs1[q1], tab.bs0[q2], tab.bs1[q2], tab.lam[q1], tab.lam[q2]};
+    const T c0 = d[1] * t.bs0q1, c1 = d[1] * t.bs1q1;
+    const T c2 = d[2] * t.bs0q2, c3 = d[2] * t.bs1q2;
     const T x2lo = d[3] * xf[4], x2hi = d[3] * xf[5];
-    const T dij = d[0] + d[1] * tab.lam[q1] + d[2] * tab.lam[q2];
+    const T dij = d[0] + d[1] * t.lamq1 + d[2] * t.lamq2;
 #pragma unroll
     for (int q3 = 0; q3 < NP; ++q3) {
       T F = c0 * f0lo[q2 + NP * q3];
@@ -246,8 +342,10 @@ __device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T
   __syncthreads();
 
   // reductions back to the faces and the face-diagonal term
+  T out[6];
+  if constexpr (MODE == 3)
+    for (int f = 0; f < 6; ++f) out[f] = 0;
   if (active && L.colok) {
-    T out[6];
     {
       // axis 0: face node (q2,q3) = col
       const T* u = sm.u[sl] + P * col;
@@ -289,19 +387,25 @@ __device__ inline void unit_core(const UnitIO<T>& io, const Tab& tab, UnitSmem<T
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       if (fid[f] >= io.nff) continue;
-      const int64_t g = (int64_t)fid[f] * NF + col;
-      put<MODE>((f & 1) ? io.qa + g : io.qb + g, out[f]);
-      if ((nm >> f) & 1) put<MODE>((f & 1) ? io.qb + g : io.qa + g, (T)0);
+      if constexpr (MODE != 3) {
+        const int64_t g = (int64_t)fid[f] * NF + col;
+        put<MODE>((f & 1) ? io.qa + g : io.qb + g, out[f]);
+        if ((nm >> f) & 1) put<MODE>((f & 1) ? io.qb + g : io.qa + g, (T)0);
+      }
       if constexpr (MODE != 0) *dot += (double)(xf[f] * out[f]);
     }
+  }
+  if constexpr (MODE == 3) {
+    // every lane stores; off is out of range where the lane has no face
+#pragma unroll
+    for (int f = 0; f < 6; ++f) buf_store_nt((f & 1) ? bufs->qa : bufs->qb, off[f], out[f]);
   }
   __syncthreads();                          // LDS is reused by the next unit
 }
 
-// MODES 0, 1 and 3 from loaded registers: forms the input (MODES 1, 3:
-// p = z + beta p_old, written by the element below each face, which in MODE 3
-// also writes x + alpha p_old there), stages it and runs the element
-// arithmetic.
+// MODES 0 and 1 from loaded registers: forms the input (MODE 1:
+// p = z + beta p_old, written by the element below each face), stages it and
+// runs the element arithmetic.
 template <typename T, int NP, int EPB, int MODE, typename Tab>
 __device__ inline void unit_compute(const UnitIO<T>& io, const Tab& tab, UnitSmem<T, NP, EPB>& sm,
                                     const UnitLane& L, const UnitRegs<T>& R, double* acc) {
@@ -316,14 +420,6 @@ __device__ inline void unit_compute(const UnitIO<T>& io, const Tab& tab, UnitSme
       const bool own_lo = TabTraits<Tab>::neumann && ((R.nm >> f) & 1);
       if (((f & 1) || own_lo) && R.active && L.colok && R.fid[f] < io.nff)
         put<MODE>(io.p_out + (int64_t)R.fid[f] * NF + L.col, v);
-    } else if constexpr (MODE == 3) {
-      static_assert(!TabTraits<Tab>::neumann, "MODE 3 is for meshes without Neumann sides");
-      v = R.a[f] + io.beta * R.b[f];
-      if ((f & 1) && R.active && L.colok && R.fid[f] < io.nff) {
-        const int64_t g = (int64_t)R.fid[f] * NF + L.col;
-        put<MODE>(io.p_out + g, v);
-        put<MODE>(io.x + g, R.c[f >> 1] + io.alpha * R.b[f]);
-      }
     }
     xf[f] = v;
     if (f < 4 && R.active && L.colok) sm.face[L.sl][f][L.col] = v;
@@ -457,7 +553,7 @@ template <typename T, int NP, int EPB, int MODE, typename Tab, typename Between 
 __device__ inline bool run_units_pipelined(const UnitIO<T>& io, const Tab& tab,
                                            UnitSmem<T, NP, EPB>& sm, int u0, int u1, double* acc,
                                            int tid = (int)threadIdx.x, Between between = {}) {
-  static_assert(MODE != 2, "the one-kernel CG iteration is not pipelined");
+  static_assert(MODE == 0 || MODE == 1, "MODE 3 runs through run_units_ranged");
   if (u0 >= u1) return between();
   const UnitLane L = unit_lane<NP, EPB>(tid);
   UnitRegs<T> cur, nxt;
@@ -475,6 +571,59 @@ __device__ inline bool run_units_pipelined(const UnitIO<T>& io, const Tab& tab,
     unit_compute<T, NP, EPB, MODE>(io, tab, sm, L, c, acc);
   }
   return true;
+}
+
+// MODE 3 from loaded registers: p = z + beta p_old on every face; on the
+// faces the unit owns (its high faces) p and the previous iteration's x step
+// x + alpha p_old are stored; then the element arithmetic.
+template <int NP, int EPB, typename Tab>
+__device__ inline void unit_compute_ranged(const UnitBufs& B, const UnitIO<double>& io,
+                                           const Tab& tab, const LaneTab<double>& lt,
+                                           UnitSmem<double, NP, EPB>& sm,
+                                           const UnitLane& L, const UnitRegs<double>& R,
+                                           double* acc) {
+  static_assert(!TabTraits<Tab>::neumann, "MODE 3 is for meshes without Neumann sides");
+  double xf[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const double v = R.a[f] + io.beta * R.b[f];
+    if (f & 1) {
+      buf_store_nt(B.p_out, R.off[f], v);
+      buf_store_nt(B.x, R.off[f], R.c[f >> 1] + io.alpha * R.b[f]);
+    }
+    xf[f] = v;
+    if (f < 4 && R.active && L.colok) sm.face[L.sl][f][L.col] = v;
+  }
+  const double d[4] = {R.d[0] * R.lam, R.d[1], R.d[2], R.d[3]};
+  double dot = 0.0;
+  unit_core<double, NP, EPB, 3>(io, tab, sm, L, R.active, R.fid, 0, d, xf, &dot, &B, R.off, &lt);
+  acc[0] += dot;
+}
+
+// Units [u0, u1) in MODE 3 with the face loads of unit u + 1 and the element
+// record of unit u + 2 in flight during the arithmetic of unit u.  Every load
+// and store is issued unconditionally (a unit beyond u1 is inactive: its
+// record is element 0's and its face accesses are out of range), so that no
+// path through the loop changes the count of memory operations in flight.
+template <int NP, int EPB, typename Tab>
+__device__ inline void run_units_ranged(const UnitIO<double>& io, const Tab& tab,
+                                        UnitSmem<double, NP, EPB>& sm, int u0, int u1,
+                                        double* acc, int tid) {
+  if (u0 >= u1) return;
+  const UnitLane L = unit_lane<NP, EPB>(tid);
+  const UnitBufs B = unit_bufs<NP>(io);
+  const LaneTab<double> lt = lane_tab<double>(tab, L);
+  UnitRegs<double> cur, nxt;
+  unit_info_ranged<NP, EPB>(io, L, u0, true, cur);
+  unit_data_ranged<NP>(B, io, L, cur);
+  unit_info_ranged<NP, EPB>(io, L, u0 + 1, u0 + 1 < u1, nxt);
+  for (int u = u0; u < u1; ++u) {
+    const UnitRegs<double> c = cur;
+    unit_data_ranged<NP>(B, io, L, nxt);
+    cur = nxt;
+    unit_info_ranged<NP, EPB>(io, L, u + 2, u + 2 < u1, nxt);
+    unit_compute_ranged<NP, EPB>(B, io, tab, lt, sm, L, c, acc);
+  }
 }
 
 }  // namespace hdg
