@@ -51,6 +51,7 @@ struct hdg_batch {
   double* d_pcg = nullptr;          // [2 * 3 * max_segs]
   // schedule
   int nblocks = 0;                  // persistent grid of the current form
+  int n_cu = 0;                     // compute units of the device
   int nblocks_form[3] = {0, 0, 0};  // co-resident grid of each form
   int max_segs = 0;                 // bound on segments per phase: count + largest grid + 1
   std::vector<BatchProbDev> probs;
@@ -86,28 +87,62 @@ namespace {
 
 // Relative cost of one apply work item, from per-segment timings of the
 // persistent kernel at three blocks per CU on the 256-problem batch (p = 2..10):
-// an element work unit keeps its block busy for 6.8-7.4 us in the two-phase
-// form (9.1 us at n_p = 11, whose code path spills registers) and 11-13 us in
-// the one-phase form, almost whatever its degree otherwise (the unit is bound
-// by the latency of its dependent loads, not by its bytes); an element of a
-// pencil column row takes 5-7 us.
+// an element work unit keeps its block busy for nearly the same time in the
+// two-phase form whatever its degree (the unit is bound by the latency of its
+// dependent loads, not by its bytes; 12 % more from n_p = 8 on), and 11-13 us
+// in the one-phase form; an element of a pencil column row takes 5-7 us.  A
+// segment adds about two units' worth in the two-phase form (its partial
+// sums and decisions): kSegCost, charged at the first unit of each problem.
+constexpr double kSegCost = 14.0;
 double item_cost(int form, int np) {
   switch (form) {
     case 1: return 10.2 + 0.25 * np;
     case 2: return 4.6 + 0.22 * np;
-    default: return np >= 11 ? 9.1 : 7.0 + 0.03 * np;
+    default: return np >= 8 ? 7.85 : 7.0;
   }
+}
+
+// Share of a phase's work for the s-th block on a compute unit in the
+// two-phase form (its blocks run in launch order, and the co-resident launch
+// places blocks k, k + n_cu, k + 2 n_cu on one CU).  The SIMDs issue from
+// older waves first, so that the first block on a CU outruns the later ones:
+// with equal shares, per-block timers of the 256-problem batch at three
+// blocks per CU gave 4.1, 6.1 and 7.6 us per element work unit for the three
+// slots, and each CU ran its last block alone for the last quarter of the
+// apply phase.  While all three run, their rates in the apply phase are about
+// 1 : 0.53 : 0.29; the streaming vector phase is much less uneven.  The
+// shares make the blocks of a CU finish together.  (The pencil form measured
+// slower with unequal shares and the one-phase form remaps its blocks: both
+// keep equal shares.)
+double slot_share(int form, bool apply, int slot) {
+  static const double wa[3] = {1.0, 0.556, 0.305};
+  static const double wv[3] = {1.0, 0.98, 0.97};
+  if (form != 0 || slot < 0) return 1.0;
+  return (apply ? wa : wv)[slot < 3 ? slot : 2];
 }
 
 // Splits the problems' work into per-block segments.  Apply phase: the
 // global list of work units (problem-major) is cut into nb contiguous ranges
-// of about equal cost, each range into one segment per problem it touches.
-// Vector phases: the concatenated free trace is cut into nb ranges of about
-// equal length (multiples of 64 entries), likewise; a problem without free
-// entries gets one empty segment.  Segments are listed block by block, so a
-// problem's segments are consecutive in both lists.
+// of about equal time (cost times the block's share), each range into one
+// segment per problem it touches.  Vector phases: the concatenated free
+// trace is cut into nb ranges in the same shares (multiples of 64 entries),
+// likewise; a problem without free entries gets one empty segment.  Segments
+// are listed block by block, so a problem's segments are consecutive in both
+// lists.
 hdg_status build_schedule(hdg_batch* b) {
   const int nb = b->nblocks;
+  // cumulative shares: block k's part of the apply (vector) phase is
+  // [wcum[k], wcum[k + 1]) ([vcum[k], vcum[k + 1]))
+  std::vector<double> wcum(nb + 1, 0.0), vcum(nb + 1, 0.0);
+  for (int k = 0; k < nb; ++k) {
+    const int slot = b->n_cu > 0 ? k / b->n_cu : -1;
+    wcum[k + 1] = wcum[k] + slot_share(b->form, true, slot);
+    vcum[k + 1] = vcum[k] + slot_share(b->form, false, slot);
+  }
+  for (int k = 0; k <= nb; ++k) {
+    wcum[k] /= wcum[nb];
+    vcum[k] /= vcum[nb];
+  }
   // apply work items of each problem: element work units (forms 0, 1) or
   // whole columns along x3 of EPB slots (pencil form), with their cost
   std::vector<int64_t> ubeg(b->count + 1, 0);
@@ -131,15 +166,18 @@ hdg_status build_schedule(hdg_batch* b) {
   std::vector<int64_t> ucut(nb + 1, U);
   {
     double total = 0.0;
-    for (int i = 0; i < b->count; ++i) total += (double)(ubeg[i + 1] - ubeg[i]) * ucost[i];
-    const double per = total > 0.0 ? total / nb : 1.0;
+    const double seg = b->form == 0 ? kSegCost : 0.0;
+    for (int i = 0; i < b->count; ++i)
+      total += (double)(ubeg[i + 1] - ubeg[i]) * ucost[i] + (ubeg[i + 1] > ubeg[i] ? seg : 0.0);
+    if (!(total > 0.0)) total = 1.0;
     double acc = 0.0;
-    int next = 1;
+    int blk = 0, next = 1;
     ucut[0] = 0;
     for (int i = 0; i < b->count; ++i) {
-      const double w = ucost[i];
       for (int64_t u = ubeg[i]; u < ubeg[i + 1]; ++u) {
-        const int blk = std::min(nb - 1, (int)((acc + 0.5 * w) / per));
+        const double w = ucost[i] + (u == ubeg[i] ? seg : 0.0);
+        const double mid = (acc + 0.5 * w) / total;
+        while (blk + 1 < nb && wcum[blk + 1] <= mid) ++blk;
         while (next <= blk) ucut[next++] = u;
         acc += w;
       }
@@ -164,7 +202,8 @@ hdg_status build_schedule(hdg_batch* b) {
   // vector segments: cut points on the concatenated free trace
   const int64_t N = b->total_free;
   std::vector<int64_t> vcut(nb + 1);
-  for (int k = 0; k <= nb; ++k) vcut[k] = std::min<int64_t>(N, (N * k / nb + 32) / 64 * 64);
+  for (int k = 0; k <= nb; ++k)
+    vcut[k] = std::min<int64_t>(N, ((int64_t)std::llround((double)N * vcum[k]) + 32) / 64 * 64);
   vcut[0] = 0;
   vcut[nb] = N;
   int blk = 0;
@@ -454,6 +493,7 @@ hdg_status hdg_batch_create(int count, const int* n_elem3, const int* p, const d
     nb_max = std::max(nb_max, b->nblocks_form[form]);
   }
   b->nblocks = b->nblocks_form[0];
+  b->n_cu = n_cu;
   // each block range splits into at most one more segment than problems it touches
   b->max_segs = count + nb_max + 1;
   const int ms = b->max_segs;
