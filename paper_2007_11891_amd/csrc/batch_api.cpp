@@ -104,18 +104,19 @@ double item_cost(int form, int np) {
 
 // Share of a phase's work for the s-th block on a compute unit in the
 // two-phase form (its blocks run in launch order, and the co-resident launch
-// places blocks k, k + n_cu, k + 2 n_cu on one CU).  The SIMDs issue from
-// older waves first, so that the first block on a CU outruns the later ones:
-// with equal shares, per-block timers of the 256-problem batch at three
-// blocks per CU gave 4.1, 6.1 and 7.6 us per element work unit for the three
-// slots, and each CU ran its last block alone for the last quarter of the
-// apply phase.  While all three run, their rates in the apply phase are about
-// 1 : 0.53 : 0.29; the streaming vector phase is much less uneven.  The
-// shares make the blocks of a CU finish together.  (The pencil form measured
-// slower with unequal shares and the one-phase form remaps its blocks: both
-// keep equal shares.)
+// places blocks k, k + n_cu, ... on one CU).  The SIMDs issue from older
+// waves first, so that the first block on a CU outruns the later ones: with
+// equal shares at three blocks per CU, per-block timers of the 256-problem
+// batch gave 4.1, 6.1 and 7.6 us per element work unit for the three slots,
+// and each CU ran its last block alone for the last quarter of the apply
+// phase.  At the two blocks per CU the form now runs, apply shares 1 : 0.70
+// measured fastest (1 : 0.78 evens the mean end times of the two slots but
+// measured 0.4 % slower: the phase ends with its slowest block, and blocks of
+// one slot spread more than the slots differ); the streaming vector phase is
+// barely uneven.  (The pencil form measured slower with unequal shares and
+// the one-phase form remaps its blocks: both keep equal shares.)
 double slot_share(int form, bool apply, int slot) {
-  static const double wa[3] = {1.0, 0.556, 0.305};
+  static const double wa[3] = {1.0, 0.70, 0.55};
   static const double wv[3] = {1.0, 0.98, 0.97};
   if (form != 0 || slot < 0) return 1.0;
   return (apply ? wa : wv)[slot < 3 ? slot : 2];

@@ -742,12 +742,15 @@ __device__ __forceinline__ void run_seg(const BatchArgs& a, int phase, int s, in
 // form numbers its blocks so that consecutive ranges sit on one XCD
 // (neighbouring elements of a problem, whose shared faces both read, meet in
 // the same L2).
-// three blocks per CU for every form: four fit the one-phase form's paths in
-// 128 registers (a 100-byte spill) but measured slower (630 against 583 us per
-// iteration of the 256-problem batch); the two-phase forms spill 300-400
-// bytes per lane at four
+// Blocks per CU: two for the two-phase form (201 registers, no spill; with
+// its element pass keeping the next unit's loads in flight it measured 470
+// against 490 us per iteration of the 256-problem batch at three, where it
+// spilled 84 bytes per lane), three for the others: four fit the one-phase
+// form's paths in 128 registers (a 100-byte spill) but measured slower (630
+// against 583 us), and the pencil form measured slower at two (615 against
+// 578 us).
 template <int FORM>
-__global__ void __launch_bounds__(kBT, 3) batch_cg_kernel(BatchArgs a) {
+__global__ void __launch_bounds__(kBT, FORM == 0 ? 2 : 3) batch_cg_kernel(BatchArgs a) {
   __shared__ double smem[FormTraits<FORM>::lds_words];
   __shared__ double s_red[kBT / 64];
   const int bid = FORM == 1 ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
