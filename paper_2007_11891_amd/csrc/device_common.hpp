@@ -27,9 +27,11 @@ __device__ inline int xcd_remap(int bid, int nb) {
 }
 
 // a / b through the hardware reciprocal (about 2^-24 relative error on
-// gfx950), one Newton step (about 10 ulp) and one residual correction of the
-// quotient, which leaves it within one ulp of the IEEE quotient (measured on
-// 2^20 random operands); no IEEE division sequence.
+// gfx950), one Newton step (reciprocal then within about 2^-48) and one
+// residual correction of the quotient, q + r (a - b q) with fused
+// multiply-adds, which by that error analysis leaves it within about one ulp
+// of the IEEE quotient; not an IEEE division sequence, and not claimed to be
+// correctly rounded.
 __device__ inline double div_fast(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
   const double e = __builtin_fma(-b, r, 1.0);

@@ -15,8 +15,9 @@
 // axis-2 reduction in registers; faces normal to x1, x2 and the element's u
 // go through LDS (u with an odd row pitch, so the axis-0 reduction is free of
 // bank conflicts).  For n_p = 7, 8 and n_p >= 10 an element is owned by whole
-// wavefronts (the element record is wave-uniform and arrives through scalar
-// loads); for n_p <= 6 and n_p = 9 several elements share a wavefront.  Each interior face receives
+// wavefronts (the element record is wave-uniform; the single-problem kernels
+// read it with scalar loads); for n_p <= 6 and n_p = 9 several elements share
+// a wavefront.  Each interior face receives
 // one contribution from the element below it (qa) and one from the element
 // above it (qb): plain stores, no atomics, deterministic sums.
 #pragma once
